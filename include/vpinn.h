@@ -1,0 +1,200 @@
+/*
+ * vpinn.h -- C ABI of the MI355X (gfx950) FastVPINNs training hot path.
+ *
+ * The library evaluates, on one GPU, the variational PINN loss of FastVPINNs
+ * (arXiv 2404.12063) and its gradient with respect to the network weights:
+ *
+ *   R[e,k] = eps * sum_q ( u_x G_x + u_y G_y )[e,k,q] - F[e,k]          (Alg. 3)
+ *   L      = c_v sum_{e,k} R[e,k]^2 + tau  mean_b (u(x_b) - g_b)^2
+ *                                    + gamma mean_s (u(x_s) - d_s)^2     (Sec. 2.3, 4.7)
+ *
+ * where u is a tanh multilayer perceptron (Sec. 2.2), G_x, G_y are the
+ * premultiplied test-function gradients of Sec. 4.4 (quadrature weight times
+ * det J times the physical gradient of test function k at quadrature point q
+ * of element e) and F is the forcing matrix of Appendix A.2.
+ *
+ * Conventions shared by every call
+ *  - Status codes are returned; nothing throws across the ABI.  On error,
+ *    vpinn_last_error() gives a message for the calling thread.
+ *  - "device" pointers are HIP device memory of the current device (for
+ *    example torch CUDA tensors' data_ptr()), contiguous, caller-owned.
+ *  - "host" pointers are ordinary host memory, read during the call only.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *    Kernel launches are asynchronous on it; argument errors are reported
+ *    synchronously, device faults at the caller's next synchronisation.
+ *  - Network parameters use one flat float32 layout (width H, L hidden layers):
+ *      W1[H][2], b1[H], then for l = 2..L: W_l[H][H], b_l[H], then
+ *      W_out[H], b_out                       (vpinn_n_params(H, L) floats)
+ *    all matrices row-major with the output neuron as the row index.
+ *  - Distinct problem objects may be used from different threads; one object
+ *    must not be used by two calls at once.
+ */
+#ifndef VPINN_H
+#define VPINN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vpinn_status;
+#define VPINN_OK 0
+#define VPINN_E_INVALID (-1)     /* bad argument: null pointer, order out of range, size mismatch */
+#define VPINN_E_MESH (-2)        /* bad mesh: vertex index out of range, det J <= 0 (clockwise or
+                                    non-convex element); the message names the element */
+#define VPINN_E_NOMEM (-3)       /* device or host allocation failed */
+#define VPINN_E_NONFINITE (-4)   /* the forcing function returned a NaN or an infinity */
+#define VPINN_E_DEVICE (-5)      /* a HIP runtime call failed */
+#define VPINN_E_UNSUPPORTED (-6) /* a configuration outside the compiled kernels' limits */
+
+/* limits of the compiled kernels */
+#define VPINN_MAX_WIDTH 32       /* hidden width H (padded to 32 inside the kernels) */
+#define VPINN_MAX_HIDDEN 4       /* hidden layers L */
+#define VPINN_MAX_QUAD_ORDER 100 /* GLL points per direction n (N_quad = n^2) */
+#define VPINN_MAX_TEST_ORDER 30  /* test functions per direction N_t (N_test = N_t^2) */
+
+/* ------------------------------------------------------------------------ */
+/* Mesh (Sec. 3.2 and Appendix A.1): quadrilaterals given by 4 vertex ids,   */
+/* counter-clockwise, matched in order to the reference corners (-1,-1),     */
+/* (1,-1), (1,1), (-1,1) of the bilinear map.                                */
+/* ------------------------------------------------------------------------ */
+typedef struct vpinn_mesh {
+    int64_t n_nodes;
+    const double *xy;      /* host, [n_nodes][2] vertex coordinates */
+    int64_t n_elem;
+    const int32_t *quad;   /* host, [n_elem][4] vertex ids */
+} vpinn_mesh;
+
+/* Forcing f of -Lap u = f (Sec. 2.1). */
+typedef double (*vpinn_scalar_fn)(double x, double y, void *user);
+#define VPINN_FORCING_CALLBACK 0 /* f = fn(x, y, user), called on the host once per quadrature point */
+#define VPINN_FORCING_SINSIN 1   /* f = amp * sin(kx x) * sin(ky y), evaluated on the device in FP64 */
+typedef struct vpinn_forcing {
+    int32_t kind;
+    double amp, kx, ky;
+    vpinn_scalar_fn fn;
+    void *user;
+} vpinn_forcing;
+
+typedef struct vpinn_problem vpinn_problem;
+
+/*
+ * vpinn_assemble -- one-time precomputation of the premultiplied tensors
+ * (Sec. 4.2 and 4.4, Appendix A.2).  Builds, in FP64 on the device, and
+ * stores in FP32 in device memory owned by the returned problem:
+ *   G_x, G_y [n_elem][N_test][N_quad]   w_q * det J * (d v_k / dx, d v_k / dy) at point q
+ *   F        [n_elem][N_test]           sum_q w_q det J f(x_q) v_k(x_q)
+ *   X        [n_elem][N_quad][2]        physical quadrature points
+ * with Gauss-Lobatto-Legendre quadrature of quad_order points per direction
+ * (q = j*n + i, i the xi index) and test functions
+ * v_k = phi_r(xi) phi_s(eta), phi_r = P_{r+1} - P_{r-1}, r, s = 1..test_order,
+ * k = (s-1)*test_order + (r-1).
+ * Errors: VPINN_E_INVALID (null pointers, quad_order outside 2..100,
+ * test_order outside 1..30, n_elem < 1), VPINN_E_MESH (vertex id out of range or
+ * det J <= 0 at a corner, with the element id in the message), VPINN_E_NONFINITE,
+ * VPINN_E_NOMEM, VPINN_E_DEVICE.  Synchronous: returns after the tensors are built.
+ * On success *out owns all device memory; free it with vpinn_problem_free.
+ */
+vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order,
+                            const vpinn_forcing *forcing, void *stream, vpinn_problem **out);
+
+/*
+ * Dirichlet points x_b and values g_b of the boundary term (Sec. 2.2), and
+ * sensor points x_s with observations d_s of the data term of the inverse
+ * problem (Sec. 4.7).  Host arrays xy [n][2] and values [n] are copied to the
+ * device (as FP32); a later call replaces the previous set; n = 0 clears it.
+ * Synchronous.  Errors: VPINN_E_INVALID, VPINN_E_NOMEM, VPINN_E_DEVICE.
+ */
+vpinn_status vpinn_set_boundary(vpinn_problem *p, int64_t n, const double *xy, const double *g);
+vpinn_status vpinn_set_sensors(vpinn_problem *p, int64_t n, const double *xy, const double *d);
+
+typedef struct vpinn_problem_info {
+    int64_t n_elem, n_quad, n_test;  /* N_elem, N_quad = n^2, N_test = N_t^2 */
+    int64_t n_points;                /* N_elem * N_quad interior quadrature points */
+    int64_t n_boundary, n_sensors;
+    int32_t quad_order, test_order;
+} vpinn_problem_info;
+
+vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info);
+
+/* Copy one assembled tensor to host memory: which = 0 G_x, 1 G_y, 2 F, 3 X.
+ * `count` must equal the tensor's element count (floats).  Synchronous. */
+#define VPINN_TENSOR_GX 0
+#define VPINN_TENSOR_GY 1
+#define VPINN_TENSOR_F 2
+#define VPINN_TENSOR_X 3
+vpinn_status vpinn_read_tensor(const vpinn_problem *p, int32_t which, float *host_dst, int64_t count);
+
+/* ------------------------------------------------------------------------ */
+/* Loss and gradient (Algorithm 3 with its backward pass)                    */
+/* ------------------------------------------------------------------------ */
+#define VPINN_PATH_FUSED 0 /* one fused forward + contraction + adjoint launch and a reduction */
+#define VPINN_PATH_PLAIN 1 /* unfused kernel sequence that materialises every intermediate */
+#define VPINN_NORM_TEST 0  /* c_v = 1/N_test: mean over test functions, sum over elements (Alg. 3) */
+#define VPINN_NORM_ELEM 1  /* c_v = 1/N_elem: the variational-loss equation of Sec. 2.3 */
+
+typedef struct vpinn_loss_cfg {
+    int32_t n_hidden;  /* L, 1..VPINN_MAX_HIDDEN */
+    int32_t width;     /* H, 1..VPINN_MAX_WIDTH */
+    float tau;         /* boundary weight */
+    float gamma;       /* sensor weight */
+    int32_t loss_norm; /* VPINN_NORM_TEST or VPINN_NORM_ELEM */
+    int32_t path;      /* VPINN_PATH_FUSED or VPINN_PATH_PLAIN */
+} vpinn_loss_cfg;
+
+int64_t vpinn_n_params(int32_t width, int32_t n_hidden);
+
+/*
+ * vpinn_loss_and_grad -- one forward + adjoint evaluation.
+ *   d_params   device, vpinn_n_params(width, n_hidden) floats
+ *   d_eps      device, 1 float: the diffusion coefficient eps of -eps Lap u = f
+ *              (Sec. 4.7.1); NULL means eps = 1
+ *   d_loss     device, 4 floats written: L, L_v, L_b, L_s (L_b and L_s are the
+ *              unweighted means; L = L_v + tau L_b + gamma L_s)
+ *   d_grad     device, vpinn_n_params floats written: dL/dtheta; NULL skips the
+ *              backward pass
+ *   d_grad_eps device, 1 float written: dL/deps; may be NULL
+ * The problem keeps a device workspace that the first call of each path
+ * allocates (and a call with more boundary or sensor points grows); later calls
+ * allocate nothing.  Deterministic: fixed-order reductions, no float atomics.
+ */
+vpinn_status vpinn_loss_and_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
+                                 const float *d_eps, float *d_loss, float *d_grad, float *d_grad_eps,
+                                 void *stream);
+
+/*
+ * vpinn_residual -- the residual matrix alone: d_R device [n_elem][N_test] floats,
+ * R = eps * sum_q (u_x G_x + u_y G_y) - F at the given parameters.
+ */
+vpinn_status vpinn_residual(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
+                            const float *d_eps, float *d_R, void *stream);
+
+/*
+ * vpinn_eval_network -- u, du/dx, du/dy of the network (Sec. 2.2) at n points.
+ *   d_xy device [n][2] floats; d_u, d_ux, d_uy device [n] floats (any may be NULL).
+ */
+vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_params, int64_t n,
+                                const float *d_xy, float *d_u, float *d_ux, float *d_uy, void *stream);
+
+/*
+ * vpinn_adam_step -- Kingma-Ba Adam (Algorithm 1 of that paper, the optimiser of
+ * Sec. 4.6.3), in place on n device floats:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   theta -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+ * `step` counts from 1.  Errors: VPINN_E_INVALID (n < 0, step < 1, null pointer).
+ */
+vpinn_status vpinn_adam_step(int64_t n, float *d_params, const float *d_grad, float *d_m, float *d_v,
+                             int64_t step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Release every device buffer of the problem.  NULL is a no-op. */
+void vpinn_problem_free(vpinn_problem *p);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *vpinn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VPINN_H */

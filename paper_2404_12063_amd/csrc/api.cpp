@@ -1,0 +1,326 @@
+// Host side of the C ABI declared in include/vpinn.h: argument and mesh
+// validation, ownership of device buffers, and dispatch to the kernels.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace vp {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+vpinn_status fail(vpinn_status code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+// selects the problem's device for the duration of a call
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// mesh checks on the host, before any device work.  det J of the bilinear map
+// is affine in (xi, eta), so its minimum over the reference square is attained
+// at a corner; at corner c it equals the cross product of the two edges
+// leaving vertex c (up to the positive factor 1/4).
+static vpinn_status validate_mesh(const vpinn_mesh *m) {
+    if (!m || !m->xy || !m->quad) return fail(VPINN_E_INVALID, "mesh or its arrays are null");
+    if (m->n_nodes < 4 || m->n_elem < 1) return fail(VPINN_E_INVALID, "mesh needs >= 4 nodes and >= 1 element");
+    for (int64_t i = 0; i < 2 * m->n_nodes; ++i)
+        if (!std::isfinite(m->xy[i])) return fail(VPINN_E_MESH, "vertex " + std::to_string(i / 2) + " is not finite");
+    for (int64_t e = 0; e < m->n_elem; ++e) {
+        double x[4], y[4];
+        for (int c = 0; c < 4; ++c) {
+            const int32_t id = m->quad[4 * e + c];
+            if (id < 0 || id >= m->n_nodes)
+                return fail(VPINN_E_MESH, "element " + std::to_string(e) + ": vertex id " + std::to_string(id) +
+                                              " out of range");
+            x[c] = m->xy[2 * (int64_t)id];
+            y[c] = m->xy[2 * (int64_t)id + 1];
+        }
+        for (int c = 0; c < 4; ++c) {
+            const int nx = (c + 1) & 3, pv = (c + 3) & 3;
+            const double cross = (x[nx] - x[c]) * (y[pv] - y[c]) - (y[nx] - y[c]) * (x[pv] - x[c]);
+            if (!(cross > 0.0))
+                return fail(VPINN_E_MESH, "element " + std::to_string(e) +
+                                              ": det J <= 0 at a corner (vertices must be counter-clockwise and "
+                                              "the quadrilateral convex)");
+        }
+    }
+    return VPINN_OK;
+}
+
+static vpinn_status rebuild_points(vpinn_problem *p, const std::vector<float> &bxy, const std::vector<float> &bg,
+                                   const std::vector<float> &sxy, const std::vector<float> &sd, int64_t nb,
+                                   int64_t ns) {
+    DevBuf npts, ntgt;
+    const int64_t total = p->n_pts + nb + ns;
+    VP_HIP(npts.reserve(sizeof(float2) * total));
+    VP_HIP(hipMemcpy(npts.ptr, p->pts.ptr, sizeof(float2) * p->n_pts, hipMemcpyDeviceToDevice));
+    if (nb) VP_HIP(hipMemcpy(npts.as<float2>() + p->n_pts, bxy.data(), sizeof(float2) * nb, hipMemcpyHostToDevice));
+    if (ns)
+        VP_HIP(hipMemcpy(npts.as<float2>() + p->n_pts + nb, sxy.data(), sizeof(float2) * ns, hipMemcpyHostToDevice));
+    if (nb + ns) {
+        VP_HIP(ntgt.reserve(sizeof(float) * (nb + ns)));
+        if (nb) VP_HIP(hipMemcpy(ntgt.ptr, bg.data(), sizeof(float) * nb, hipMemcpyHostToDevice));
+        if (ns) VP_HIP(hipMemcpy(ntgt.as<float>() + nb, sd.data(), sizeof(float) * ns, hipMemcpyHostToDevice));
+    }
+    std::swap(p->pts.ptr, npts.ptr);
+    std::swap(p->pts.bytes, npts.bytes);
+    std::swap(p->tgt.ptr, ntgt.ptr);
+    std::swap(p->tgt.bytes, ntgt.bytes);
+    p->n_bnd = nb;
+    p->n_sen = ns;
+    return VPINN_OK;
+}
+
+}  // namespace vp
+
+// host copies of the boundary and sensor sets (so either can be replaced alone)
+struct vpinn_point_sets {
+    std::vector<float> bxy, bg, sxy, sd;
+};
+
+namespace {
+struct ProblemWithSets : vpinn_problem {
+    vpinn_point_sets sets;
+};
+
+vpinn_status convert_set(int64_t n, const double *xy, const double *val, std::vector<float> &oxy,
+                         std::vector<float> &oval, const char *what) {
+    if (n < 0) return vp::fail(VPINN_E_INVALID, std::string(what) + ": negative count");
+    if (n > 0 && (!xy || !val)) return vp::fail(VPINN_E_INVALID, std::string(what) + ": null array");
+    oxy.resize(2 * n);
+    oval.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(xy[2 * i]) || !std::isfinite(xy[2 * i + 1]) || !std::isfinite(val[i]))
+            return vp::fail(VPINN_E_INVALID, std::string(what) + ": point " + std::to_string(i) + " is not finite");
+        oxy[2 * i] = (float)xy[2 * i];
+        oxy[2 * i + 1] = (float)xy[2 * i + 1];
+        oval[i] = (float)val[i];
+    }
+    return VPINN_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int64_t vpinn_n_params(int32_t width, int32_t n_hidden) {
+    if (width < 1 || n_hidden < 1) return -1;
+    return (int64_t)width * 2 + width + (int64_t)(n_hidden - 1) * ((int64_t)width * width + width) + width + 1;
+}
+
+const char *vpinn_last_error(void) { return vp::g_err.c_str(); }
+
+vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order,
+                            const vpinn_forcing *forcing, void *stream, vpinn_problem **out) {
+    using namespace vp;
+    if (!out) return fail(VPINN_E_INVALID, "out is null");
+    *out = nullptr;
+    if (quad_order < 2 || quad_order > VPINN_MAX_QUAD_ORDER)
+        return fail(VPINN_E_INVALID, "quad_order must be in 2.." + std::to_string(VPINN_MAX_QUAD_ORDER));
+    if (test_order < 1 || test_order > VPINN_MAX_TEST_ORDER)
+        return fail(VPINN_E_INVALID, "test_order must be in 1.." + std::to_string(VPINN_MAX_TEST_ORDER));
+    if (!forcing) return fail(VPINN_E_INVALID, "forcing is null");
+    if (forcing->kind == VPINN_FORCING_CALLBACK) {
+        if (!forcing->fn) return fail(VPINN_E_INVALID, "callback forcing without a function");
+    } else if (forcing->kind == VPINN_FORCING_SINSIN) {
+        if (!std::isfinite(forcing->amp) || !std::isfinite(forcing->kx) || !std::isfinite(forcing->ky))
+            return fail(VPINN_E_NONFINITE, "forcing coefficients are not finite");
+    } else {
+        return fail(VPINN_E_INVALID, "unknown forcing kind");
+    }
+    vpinn_status st = validate_mesh(mesh);
+    if (st) return st;
+    const int64_t nq = (int64_t)quad_order * quad_order, ntest = (int64_t)test_order * test_order;
+    const int64_t n_elem = mesh->n_elem;
+    if (n_elem > (int64_t(1) << 40) / (nq * ntest)) return fail(VPINN_E_INVALID, "tensor size overflows");
+
+    ProblemWithSets *p = new (std::nothrow) ProblemWithSets();
+    if (!p) return fail(VPINN_E_NOMEM, "host allocation failed");
+    auto bail = [&](vpinn_status s) {
+        delete p;
+        return s;
+    };
+    if (hipGetDevice(&p->device) != hipSuccess) return bail(fail(VPINN_E_DEVICE, "no HIP device"));
+    p->n_elem = n_elem;
+    p->n = quad_order;
+    p->nt = test_order;
+    p->nq = (int)nq;
+    p->ntest = (int)ntest;
+    p->n_pts = n_elem * nq;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t gbytes = sizeof(float) * (size_t)(n_elem * ntest * nq);
+    if (p->Gx.reserve(gbytes) != hipSuccess || p->Gy.reserve(gbytes) != hipSuccess ||
+        p->F.reserve(sizeof(float) * n_elem * ntest) != hipSuccess ||
+        p->pts.reserve(sizeof(float2) * p->n_pts) != hipSuccess)
+        return bail(fail(VPINN_E_NOMEM, "device allocation of the assembled tensors failed"));
+    DevBuf d_nodes, d_quad;
+    if (d_nodes.reserve(sizeof(double) * 2 * mesh->n_nodes) != hipSuccess ||
+        d_quad.reserve(sizeof(int32_t) * 4 * n_elem) != hipSuccess)
+        return bail(fail(VPINN_E_NOMEM, "device allocation of the mesh failed"));
+    if (hipMemcpy(d_nodes.ptr, mesh->xy, sizeof(double) * 2 * mesh->n_nodes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_quad.ptr, mesh->quad, sizeof(int32_t) * 4 * n_elem, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(VPINN_E_DEVICE, "mesh upload failed"));
+    st = assemble_device(p, d_nodes.as<double>(), mesh->n_nodes, d_quad.as<int32_t>(), forcing, s);
+    if (st) return bail(st);
+    *out = p;
+    return VPINN_OK;
+}
+
+vpinn_status vpinn_set_boundary(vpinn_problem *pp, int64_t n, const double *xy, const double *g) {
+    using namespace vp;
+    if (!pp) return fail(VPINN_E_INVALID, "problem is null");
+    auto *p = static_cast<ProblemWithSets *>(pp);
+    std::vector<float> bxy, bg;
+    vpinn_status st = convert_set(n, xy, g, bxy, bg, "boundary");
+    if (st) return st;
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
+    st = rebuild_points(p, bxy, bg, p->sets.sxy, p->sets.sd, n, p->n_sen);
+    if (st) return st;
+    p->sets.bxy.swap(bxy);
+    p->sets.bg.swap(bg);
+    return VPINN_OK;
+}
+
+vpinn_status vpinn_set_sensors(vpinn_problem *pp, int64_t n, const double *xy, const double *d) {
+    using namespace vp;
+    if (!pp) return fail(VPINN_E_INVALID, "problem is null");
+    auto *p = static_cast<ProblemWithSets *>(pp);
+    std::vector<float> sxy, sd;
+    vpinn_status st = convert_set(n, xy, d, sxy, sd, "sensors");
+    if (st) return st;
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
+    st = rebuild_points(p, p->sets.bxy, p->sets.bg, sxy, sd, p->n_bnd, n);
+    if (st) return st;
+    p->sets.sxy.swap(sxy);
+    p->sets.sd.swap(sd);
+    return VPINN_OK;
+}
+
+vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info) {
+    using namespace vp;
+    if (!p || !info) return fail(VPINN_E_INVALID, "null argument");
+    info->n_elem = p->n_elem;
+    info->n_quad = p->nq;
+    info->n_test = p->ntest;
+    info->n_points = p->n_pts;
+    info->n_boundary = p->n_bnd;
+    info->n_sensors = p->n_sen;
+    info->quad_order = p->n;
+    info->test_order = p->nt;
+    return VPINN_OK;
+}
+
+vpinn_status vpinn_read_tensor(const vpinn_problem *p, int32_t which, float *host_dst, int64_t count) {
+    using namespace vp;
+    if (!p || !host_dst) return fail(VPINN_E_INVALID, "null argument");
+    const void *src = nullptr;
+    int64_t want = 0;
+    switch (which) {
+    case VPINN_TENSOR_GX: src = p->Gx.ptr; want = p->n_elem * p->ntest * p->nq; break;
+    case VPINN_TENSOR_GY: src = p->Gy.ptr; want = p->n_elem * p->ntest * p->nq; break;
+    case VPINN_TENSOR_F: src = p->F.ptr; want = p->n_elem * p->ntest; break;
+    case VPINN_TENSOR_X: src = p->pts.ptr; want = 2 * p->n_pts; break;
+    default: return fail(VPINN_E_INVALID, "unknown tensor id");
+    }
+    if (count != want) return fail(VPINN_E_INVALID, "count must be " + std::to_string(want));
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
+    VP_HIP(hipMemcpy(host_dst, src, sizeof(float) * count, hipMemcpyDeviceToHost));
+    return VPINN_OK;
+}
+
+static vpinn_status check_cfg(const vpinn_loss_cfg *cfg) {
+    using namespace vp;
+    if (!cfg) return fail(VPINN_E_INVALID, "cfg is null");
+    if (cfg->n_hidden < 1 || cfg->n_hidden > VPINN_MAX_HIDDEN)
+        return fail(VPINN_E_UNSUPPORTED, "n_hidden must be in 1.." + std::to_string(VPINN_MAX_HIDDEN));
+    if (cfg->width < 1 || cfg->width > VPINN_MAX_WIDTH)
+        return fail(VPINN_E_UNSUPPORTED, "width must be in 1.." + std::to_string(VPINN_MAX_WIDTH));
+    if (cfg->loss_norm != VPINN_NORM_TEST && cfg->loss_norm != VPINN_NORM_ELEM)
+        return fail(VPINN_E_INVALID, "unknown loss_norm");
+    if (cfg->path != VPINN_PATH_FUSED && cfg->path != VPINN_PATH_PLAIN) return fail(VPINN_E_INVALID, "unknown path");
+    if (!std::isfinite(cfg->tau) || !std::isfinite(cfg->gamma) || cfg->tau < 0 || cfg->gamma < 0)
+        return fail(VPINN_E_INVALID, "tau and gamma must be finite and >= 0");
+    return VPINN_OK;
+}
+
+vpinn_status vpinn_loss_and_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
+                                 const float *d_eps, float *d_loss, float *d_grad, float *d_grad_eps, void *stream) {
+    using namespace vp;
+    if (!p || !d_params) return fail(VPINN_E_INVALID, "problem or params is null");
+    if (!d_loss && !d_grad && !d_grad_eps) return fail(VPINN_E_INVALID, "nothing to compute");
+    vpinn_status st = check_cfg(cfg);
+    if (st) return st;
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
+    hipStream_t s = (hipStream_t)stream;
+    if (cfg->path == VPINN_PATH_PLAIN) return plain_loss_grad(p, cfg, d_params, d_eps, d_loss, d_grad, d_grad_eps,
+                                                              nullptr, s);
+    return fused_loss_grad(p, cfg, d_params, d_eps, d_loss, d_grad, d_grad_eps, s);
+}
+
+vpinn_status vpinn_residual(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params, const float *d_eps,
+                            float *d_R, void *stream) {
+    using namespace vp;
+    if (!p || !d_params || !d_R) return fail(VPINN_E_INVALID, "null argument");
+    vpinn_status st = check_cfg(cfg);
+    if (st) return st;
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
+    return plain_loss_grad(p, cfg, d_params, d_eps, nullptr, nullptr, nullptr, d_R, (hipStream_t)stream);
+}
+
+vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_params, int64_t n, const float *d_xy,
+                                float *d_u, float *d_ux, float *d_uy, void *stream) {
+    using namespace vp;
+    if (width < 1 || width > VPINN_MAX_WIDTH || n_hidden < 1 || n_hidden > VPINN_MAX_HIDDEN)
+        return fail(VPINN_E_UNSUPPORTED, "width or n_hidden out of range");
+    if (!d_params || (n > 0 && !d_xy) || n < 0) return fail(VPINN_E_INVALID, "null argument or negative n");
+    static thread_local DevBuf wpad;
+    static thread_local int wpad_dev = -1;
+    int dev = 0;
+    VP_HIP(hipGetDevice(&dev));
+    if (wpad_dev != dev) {
+        wpad.release();
+        wpad_dev = dev;
+    }
+    VP_HIP(wpad.reserve(sizeof(float) * kMaxPadded));
+    hipStream_t s = (hipStream_t)stream;
+    vpinn_status st = pack_params(d_params, width, n_hidden, wpad.as<float>(), s);
+    if (st) return st;
+    return eval_network(n_hidden, wpad.as<float>(), n, reinterpret_cast<const float2 *>(d_xy), d_u, d_ux, d_uy, s);
+}
+
+vpinn_status vpinn_adam_step(int64_t n, float *d_params, const float *d_grad, float *d_m, float *d_v, int64_t step,
+                             float lr, float beta1, float beta2, float eps, void *stream) {
+    using namespace vp;
+    if (n < 0 || step < 1) return fail(VPINN_E_INVALID, "n must be >= 0 and step >= 1");
+    if (n > 0 && (!d_params || !d_grad || !d_m || !d_v)) return fail(VPINN_E_INVALID, "null argument");
+    return adam_step(n, d_params, d_grad, d_m, d_v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+void vpinn_problem_free(vpinn_problem *p) {
+    if (!p) return;
+    vp::DeviceGuard dg(p->device);
+    delete static_cast<ProblemWithSets *>(p);
+}
+
+}  // extern "C"

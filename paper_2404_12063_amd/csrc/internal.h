@@ -1,0 +1,107 @@
+// Internal declarations shared by the host API and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/vpinn.h"
+
+namespace vp {
+
+// ---------------------------------------------------------------------------
+// padded parameter layout used inside every kernel: width padded to 32, so
+// weight rows are 32 floats and padded neurons carry zero weights and biases
+// (their activation is tanh(0) = 0 and they feed nothing).
+//   W1 [32][2] at 0, b1 [32] at 64,
+//   layer l = 2..L: W_l [32][32] at 96 + (l-2)*1056, b_l [32] right after,
+//   W_out [32] at 96 + (L-1)*1056, b_out after it.
+// ---------------------------------------------------------------------------
+constexpr int PW = 32;
+constexpr int kOffB1 = 64;
+constexpr int kLayerStride = PW * PW + PW;  // 1056
+__host__ __device__ constexpr int off_w(int l) { return l == 1 ? 0 : 96 + (l - 2) * kLayerStride; }
+__host__ __device__ constexpr int off_b(int l) { return l == 1 ? kOffB1 : off_w(l) + PW * PW; }
+__host__ __device__ constexpr int off_wout(int L) { return 96 + (L - 1) * kLayerStride; }
+__host__ __device__ constexpr int n_padded(int L) { return off_wout(L) + PW + 1; }
+constexpr int kMaxPadded = n_padded(VPINN_MAX_HIDDEN);
+
+// flat (unpadded) layout offsets for width H
+__host__ __device__ inline int64_t hoff_w(int H, int l) {
+    return l == 1 ? 0 : (int64_t)3 * H + (int64_t)(l - 2) * (H * H + H);
+}
+
+// status helpers ------------------------------------------------------------
+void set_error(const std::string &msg);
+vpinn_status fail(vpinn_status code, const std::string &msg);
+#define VP_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return ::vp::fail(VPINN_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// device buffer that frees itself --------------------------------------------
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    // grow to at least `b` bytes (contents are not preserved)
+    hipError_t reserve(size_t b) {
+        if (b <= bytes) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&ptr, b);
+        if (e == hipSuccess) bytes = b;
+        else ptr = nullptr;
+        return e;
+    }
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+}  // namespace vp
+
+struct vpinn_problem {
+    int device = 0;
+    int64_t n_elem = 0;
+    int n = 0, nt = 0, nq = 0, ntest = 0;
+    int64_t n_pts = 0;       // interior points n_elem * nq
+    int64_t n_bnd = 0, n_sen = 0;
+    vp::DevBuf Gx, Gy, F;    // float
+    vp::DevBuf pts;          // float2 [n_pts + n_bnd + n_sen]: interior, boundary, sensors
+    vp::DevBuf tgt;          // float [n_bnd + n_sen]: g_b then d_s
+    // workspace (grown on demand)
+    vp::DevBuf wpad;         // float [kMaxPadded]: padded parameters
+    vp::DevBuf u, ux, uy;    // float [all points]
+    vp::DevBuf act;          // float [(32 + 96 (L-1))][all points]: stored activations (plain path)
+    vp::DevBuf uxb, uyb;     // float [n_pts]: adjoint of the contraction
+    vp::DevBuf A, R;         // float [n_elem * ntest]
+    vp::DevBuf loss_e;       // double [n_elem]: per-element sum_k R^2 (or per-block partials)
+    vp::DevBuf gpart;        // float [blocks][kMaxPadded]: per-block gradient partials
+    vp::DevBuf eps_part;     // double [blocks]
+    int64_t all_pts() const { return n_pts + n_bnd + n_sen; }
+};
+
+namespace vp {
+
+// kernel launchers (defined in the .hip files) --------------------------------
+vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_nodes, const int32_t *d_quad,
+                             const vpinn_forcing *f, hipStream_t s);
+vpinn_status pack_params(const float *d_params, int H, int L, float *d_wpad, hipStream_t s);
+vpinn_status eval_network(int L, const float *d_wpad, int64_t n, const float2 *d_xy, float *d_u,
+                          float *d_ux, float *d_uy, hipStream_t s);
+vpinn_status plain_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
+                             const float *d_eps, float *d_loss, float *d_grad, float *d_grad_eps,
+                             float *d_R_out, hipStream_t s);
+vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
+                             const float *d_eps, float *d_loss, float *d_grad, float *d_grad_eps,
+                             hipStream_t s);
+vpinn_status adam_step(int64_t n, float *p, const float *g, float *m, float *v, int64_t step, float lr,
+                       float b1, float b2, float eps, hipStream_t s);
+
+}  // namespace vp

@@ -1,0 +1,224 @@
+"""ctypes binding of libvpinn.so (include/vpinn.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  torch supplies device memory and streams; device arguments are torch
+CUDA tensors (float32, contiguous) and host arguments are numpy arrays.
+Functions keep the C names.  A missing library raises immediately: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvpinn.so")
+
+VPINN_OK = 0
+VPINN_E_INVALID = -1
+VPINN_E_MESH = -2
+VPINN_E_NOMEM = -3
+VPINN_E_NONFINITE = -4
+VPINN_E_DEVICE = -5
+VPINN_E_UNSUPPORTED = -6
+
+VPINN_FORCING_CALLBACK = 0
+VPINN_FORCING_SINSIN = 1
+VPINN_PATH_FUSED = 0
+VPINN_PATH_PLAIN = 1
+VPINN_NORM_TEST = 0
+VPINN_NORM_ELEM = 1
+VPINN_TENSOR_GX, VPINN_TENSOR_GY, VPINN_TENSOR_F, VPINN_TENSOR_X = 0, 1, 2, 3
+
+SCALAR_FN = C.CFUNCTYPE(C.c_double, C.c_double, C.c_double, C.c_void_p)
+
+
+class vpinn_mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xy", C.POINTER(C.c_double)),
+                ("n_elem", C.c_int64), ("quad", C.POINTER(C.c_int32))]
+
+
+class vpinn_forcing(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("amp", C.c_double), ("kx", C.c_double), ("ky", C.c_double),
+                ("fn", SCALAR_FN), ("user", C.c_void_p)]
+
+
+class vpinn_problem_info(C.Structure):
+    _fields_ = [("n_elem", C.c_int64), ("n_quad", C.c_int64), ("n_test", C.c_int64),
+                ("n_points", C.c_int64), ("n_boundary", C.c_int64), ("n_sensors", C.c_int64),
+                ("quad_order", C.c_int32), ("test_order", C.c_int32)]
+
+
+class vpinn_loss_cfg(C.Structure):
+    _fields_ = [("n_hidden", C.c_int32), ("width", C.c_int32), ("tau", C.c_float), ("gamma", C.c_float),
+                ("loss_norm", C.c_int32), ("path", C.c_int32)]
+
+
+class VpinnError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vpinn error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# every symbol of include/vpinn.h with its (restype, argtypes)
+_SIGNATURES = {
+    "vpinn_assemble": (C.c_int32, [C.POINTER(vpinn_mesh), C.c_int32, C.c_int32, C.POINTER(vpinn_forcing),
+                                   C.c_void_p, C.POINTER(C.c_void_p)]),
+    "vpinn_set_boundary": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "vpinn_set_sensors": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "vpinn_get_info": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_problem_info)]),
+    "vpinn_read_tensor": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
+    "vpinn_n_params": (C.c_int64, [C.c_int32, C.c_int32]),
+    "vpinn_loss_and_grad": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_loss_cfg), C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vpinn_residual": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_loss_cfg), C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]),
+    "vpinn_eval_network": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vpinn_adam_step": (C.c_int32, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]),
+    "vpinn_problem_free": (None, [C.c_void_p]),
+    "vpinn_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libvpinn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback implementation)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != VPINN_OK:
+        raise VpinnError(rc, lib().vpinn_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    """Device address of a torch tensor (float32, contiguous) or None."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def vpinn_last_error() -> str:
+    return lib().vpinn_last_error().decode()
+
+
+def vpinn_n_params(width: int, n_hidden: int) -> int:
+    return int(lib().vpinn_n_params(width, n_hidden))
+
+
+class Problem:
+    """Owner of a vpinn_problem handle (device G_x, G_y, F, points)."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.vpinn_problem_free(self.handle)
+            self.handle = None
+
+    def info(self) -> vpinn_problem_info:
+        return vpinn_get_info(self)
+
+
+def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0, kx: float = 0.0,
+                   ky: float = 0.0, fn=None, stream=None) -> Problem:
+    """xy: host [n_nodes, 2] float64; quad: host [n_elem, 4] int32.  Forcing is amp*sin(kx x)sin(ky y),
+    or the Python callable fn(x, y) evaluated on the host (kind VPINN_FORCING_CALLBACK)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    quad = np.ascontiguousarray(quad, dtype=np.int32)
+    mesh = vpinn_mesh(xy.shape[0], xy.ctypes.data_as(C.POINTER(C.c_double)), quad.shape[0],
+                      quad.ctypes.data_as(C.POINTER(C.c_int32)))
+    if fn is None:
+        cb = SCALAR_FN(0)
+        f = vpinn_forcing(VPINN_FORCING_SINSIN, amp, kx, ky, cb, None)
+    else:
+        cb = SCALAR_FN(lambda x, y, u: float(fn(x, y)))
+        f = vpinn_forcing(VPINN_FORCING_CALLBACK, 0.0, 0.0, 0.0, cb, None)
+    out = C.c_void_p()
+    _check(lib().vpinn_assemble(C.byref(mesh), quad_order, test_order, C.byref(f), _stream(stream), C.byref(out)))
+    return Problem(out.value)
+
+
+def vpinn_set_boundary(p: Problem, xy, g):
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    _check(lib().vpinn_set_boundary(p.handle, xy.shape[0], xy.ctypes.data, g.ctypes.data))
+
+
+def vpinn_set_sensors(p: Problem, xy, d):
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    _check(lib().vpinn_set_sensors(p.handle, xy.shape[0], xy.ctypes.data, d.ctypes.data))
+
+
+def vpinn_get_info(p: Problem) -> vpinn_problem_info:
+    info = vpinn_problem_info()
+    _check(lib().vpinn_get_info(p.handle, C.byref(info)))
+    return info
+
+
+def vpinn_read_tensor(p: Problem, which: int) -> np.ndarray:
+    info = vpinn_get_info(p)
+    shapes = {VPINN_TENSOR_GX: (info.n_elem, info.n_test, info.n_quad),
+              VPINN_TENSOR_GY: (info.n_elem, info.n_test, info.n_quad),
+              VPINN_TENSOR_F: (info.n_elem, info.n_test),
+              VPINN_TENSOR_X: (info.n_elem, info.n_quad, 2)}
+    out = np.empty(shapes[which], dtype=np.float32)
+    _check(lib().vpinn_read_tensor(p.handle, which, out.ctypes.data, out.size))
+    return out
+
+
+def loss_cfg(width: int = 30, n_hidden: int = 3, tau: float = 10.0, gamma: float = 0.0,
+             loss_norm: int = VPINN_NORM_TEST, path: int = VPINN_PATH_FUSED) -> vpinn_loss_cfg:
+    return vpinn_loss_cfg(n_hidden, width, tau, gamma, loss_norm, path)
+
+
+def vpinn_loss_and_grad(p: Problem, cfg: vpinn_loss_cfg, params, eps=None, loss=None, grad=None,
+                        grad_eps=None, stream=None):
+    _check(lib().vpinn_loss_and_grad(p.handle, C.byref(cfg), _ptr(params), _ptr(eps), _ptr(loss), _ptr(grad),
+                                     _ptr(grad_eps), _stream(stream)))
+
+
+def vpinn_residual(p: Problem, cfg: vpinn_loss_cfg, params, R, eps=None, stream=None):
+    _check(lib().vpinn_residual(p.handle, C.byref(cfg), _ptr(params), _ptr(eps), _ptr(R), _stream(stream)))
+
+
+def vpinn_eval_network(width: int, n_hidden: int, params, xy, u=None, ux=None, uy=None, stream=None):
+    n = xy.shape[0]
+    _check(lib().vpinn_eval_network(width, n_hidden, _ptr(params), n, _ptr(xy), _ptr(u), _ptr(ux), _ptr(uy),
+                                    _stream(stream)))
+
+
+def vpinn_adam_step(params, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                    eps: float = 1e-8, stream=None):
+    _check(lib().vpinn_adam_step(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1,
+                                 beta2, eps, _stream(stream)))
