@@ -1,0 +1,231 @@
+"""Training-step throughput of the FastVPINNs hot path on one MI355X.
+
+A step is one full epoch of Algorithm 3 on the 32x32 skewed-quad Poisson workload
+(1,024 elements, 10x10 GLL points, 5x5 test functions, u* = sin(8 pi x) sin(8 pi y),
+1,600 boundary points, 2-30-30-30-1 tanh network): forward values and tangents at
+every quadrature point, contraction with G_x/G_y and F, loss, adjoint through the
+contraction and the network, and an Adam update.  Inputs (premultiplied tensors,
+points, parameters) are resident in device memory before the timed region.
+
+Prints one JSON line (rank 0).  --gpus above 1 is rejected: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 (vector and matrix) peak
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+
+
+def flops_per_epoch(prob) -> float:
+    """Algorithmic FLOPs of one forward+adjoint epoch: 2 x the multiply-adds of the dense products.
+
+    interior point: forward 2H + 3(L-1)H^2 + 2H, backward 2H + 6(L-1)H^2 + 4H, contraction 4 N_test;
+    boundary/sensor point (value stream only): forward 3H + (L-1)H^2, backward 3H + 2(L-1)H^2.
+    """
+    H, L = prob.width, prob.n_hidden
+    nt = prob.test_order ** 2
+    mac_int = (2 * H + 3 * (L - 1) * H * H + 2 * H) + (2 * H + 6 * (L - 1) * H * H + 4 * H) + 4 * nt
+    mac_bnd = (3 * H + (L - 1) * H * H) + (3 * H + 2 * (L - 1) * H * H)
+    n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
+    return 2.0 * (prob.n_points * mac_int + n_extra * mac_bnd)
+
+
+def bytes_per_epoch(prob) -> float:
+    """Algorithmic HBM bytes: G_x and G_y once, F, quadrature and boundary points, parameters."""
+    nt = prob.test_order ** 2
+    n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
+    return (8.0 * nt * prob.n_points + 4.0 * nt * prob.n_elem + 8.0 * prob.n_points + 12.0 * n_extra)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2404_12063_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    entry = rec.get(kernel)
+    if not entry or entry.get("source_digest") != source_digest():
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
+    dev = torch.device("cuda:0")
+    n = V.vpinn_n_params(prob.width, prob.n_hidden)
+    th = torch.tensor(theta, dtype=torch.float32, device=dev)
+    m = torch.zeros(n, dtype=torch.float32, device=dev)
+    v = torch.zeros(n, dtype=torch.float32, device=dev)
+    g = torch.zeros(n, dtype=torch.float32, device=dev)
+    loss = torch.zeros(4, dtype=torch.float32, device=dev)
+    cfg = V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma, V.VPINN_NORM_TEST, path)
+    stream = torch.cuda.current_stream()
+    t = 0
+    for _ in range(warmup):
+        t += 1
+        V.vpinn_loss_and_grad(p, cfg, th, loss=loss, grad=g, stream=stream)
+        V.vpinn_adam_step(th, g, m, v, t, lr=1e-3, stream=stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(steps):
+        t += 1
+        ev[i][0].record(stream)
+        V.vpinn_loss_and_grad(p, cfg, th, loss=loss, grad=g, stream=stream)
+        ev[i][1].record(stream)
+        V.vpinn_adam_step(th, g, m, v, t, lr=1e-3, stream=stream)
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    lg = sorted(a.elapsed_time(b) for a, b, _ in ev)
+    st = sorted(a.elapsed_time(c) for a, _, c in ev)
+    q = lambda xs, f: xs[min(len(xs) - 1, int(f * len(xs)))]  # noqa: E731
+    return {"wall_s": wall, "lg_ms_mean": sum(lg) / len(lg), "lg_ms_p50": q(lg, 0.5),
+            "step_ms_p10": q(st, 0.1), "step_ms_p50": q(st, 0.5), "step_ms_p90": q(st, 0.9),
+            "final_loss": float(loss[0].item()), "theta0": theta}
+
+
+def cpu_baseline(prob, theta, seconds: float):
+    """The FP64 oracle (single-threaded C) on full epochs of the same workload, as many as fit in ~seconds."""
+    from oracle import oracle as O
+    import numpy as np
+    asm = O.assemble_problem(prob)
+    th = theta.copy()
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    n_ep = 0
+    first = None
+    t0 = time.perf_counter()
+    while True:
+        r = O.problem_loss_grad(prob, asm, th)
+        if first is None:
+            first = r.loss[0]
+        O.adam(th, r.grad, m, v, n_ep + 1, lr=1e-3)
+        n_ep += 1
+        el = time.perf_counter() - t0
+        if n_ep >= 2 and el >= seconds:
+            break
+    return {"value": n_ep / el, "unit": "epochs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_ep} full epochs (loss+grad+Adam, FP64, single-threaded C) of the same workload in "
+                      f"{el:.1f} s; assembly not timed"}, first
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--path", choices=["fused", "plain"], default="fused")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_12063_amd import vpinn as V
+    import vpinn_inputs as gen
+
+    assert torch.cuda.is_available(), "needs a HIP device"
+    prob = gen.config_c2()
+    theta = prob.params()
+    p = V.vpinn_assemble(prob.mesh.xy, prob.mesh.quad, prob.quad_order, prob.test_order,
+                         prob.f_amp, prob.f_kx, prob.f_ky)
+    V.vpinn_set_boundary(p, prob.bnd_xy, prob.bnd_g)
+    print(f"[bench] workload c2: {prob.n_elem} elements, {prob.n_points} quadrature points, "
+          f"{len(prob.bnd_xy)} boundary points", file=sys.stderr, flush=True)
+
+    main_path = V.VPINN_PATH_FUSED if args.path == "fused" else V.VPINN_PATH_PLAIN
+    res = time_path(V, torch, p, prob, theta, main_path, args.steps, args.warmup)
+    print(f"[bench] {args.path}: {res['wall_s'] / args.steps * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
+    plain = None
+    if not args.no_plain and main_path != V.VPINN_PATH_PLAIN:
+        plain = time_path(V, torch, p, prob, theta, V.VPINN_PATH_PLAIN, min(args.steps, 300), 20)
+        print(f"[bench] plain: {plain['wall_s'] / min(args.steps, 300) * 1e3:.4f} ms/step", file=sys.stderr,
+              flush=True)
+
+    # loss parity at the initial parameters (one extra evaluation outside the timed region)
+    dev = torch.device("cuda:0")
+    loss0 = torch.zeros(4, dtype=torch.float32, device=dev)
+    V.vpinn_loss_and_grad(p, V.loss_cfg(prob.width, prob.n_hidden, prob.tau, 0.0, 0, main_path),
+                          torch.tensor(theta, dtype=torch.float32, device=dev), loss=loss0)
+    torch.cuda.synchronize()
+    gpu_loss0 = float(loss0[0].item())
+
+    ms = res["wall_s"] / args.steps * 1e3
+    eps_s = 1e3 / ms
+    flops = flops_per_epoch(prob)
+    kernel = "vpinn_fused" if main_path == V.VPINN_PATH_FUSED else "vpinn_plain_sequence"
+    lg_s = res["lg_ms_mean"] * 1e-3
+    achieved_tf = flops / lg_s / 1e12
+    traffic = traffic_from_profile(kernel)
+    out = {
+        "metric": "epochs/s and Mquadpts/s fwd+adjoint, fused batched vs plain HIP, loss err<=1e-5",
+        "value": round(eps_s, 3),
+        "unit": "epochs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c2: Poisson -Lap u = f on [0,1]^2, 32x32 quad mesh with interior nodes "
+                               "jittered +-20% h, 10x10 GLL points, 5x5 test functions, u*=sin(8pi x)sin(8pi y), "
+                               "1600 boundary points, MLP 2-30-30-30-1 tanh, Adam lr 1e-3",
+                   "path": args.path, "n_elem": prob.n_elem, "quad_points": prob.n_points,
+                   "boundary_points": len(prob.bnd_xy), "parallelism": "single GPU"},
+        "mquadpts_per_s": round(prob.n_points * eps_s / 1e6, 2),
+        "step_ms_p10_p50_p90": [round(res["step_ms_p10"], 5), round(res["step_ms_p50"], 5),
+                                round(res["step_ms_p90"], 5)],
+        "roofline": {"bound": "mfma" if main_path == V.VPINN_PATH_FUSED else "alu",
+                     "kernel": kernel,
+                     "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic,
+                     "algorithmic_flop_per_launch": flops,
+                     "algorithmic_bytes_per_launch": bytes_per_epoch(prob),
+                     "launch_ms_mean": round(res["lg_ms_mean"], 5),
+                     "achieved_hbm_gbs": round(bytes_per_epoch(prob) / lg_s / 1e9, 1)},
+    }
+    if plain is not None:
+        pms = plain["wall_s"] / min(args.steps, 300) * 1e3
+        out["plain_hip"] = {"ms_per_step": round(pms, 5), "epochs_per_s": round(1e3 / pms, 3),
+                            "loss_and_grad_ms_mean": round(plain["lg_ms_mean"], 5)}
+        out["speedup_vs_plain"] = round(pms / ms, 3)
+    if not args.no_cpu_baseline:
+        cb, oracle_loss0 = cpu_baseline(prob, theta, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["loss_rel_err_vs_oracle"] = abs(gpu_loss0 - oracle_loss0) / abs(oracle_loss0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -84,7 +84,12 @@ struct vpinn_problem {
     vp::DevBuf loss_e;       // double [n_elem]: per-element sum_k R^2 (or per-block partials)
     vp::DevBuf gpart;        // float [blocks][kMaxPadded]: per-block gradient partials
     vp::DevBuf eps_part;     // double [blocks]
+    void *fused_ws = nullptr;              // fused-path workspace (owned)
+    void (*fused_ws_free)(void *) = nullptr;
     int64_t all_pts() const { return n_pts + n_bnd + n_sen; }
+    ~vpinn_problem() {
+        if (fused_ws && fused_ws_free) fused_ws_free(fused_ws);
+    }
 };
 
 namespace vp {
