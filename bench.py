@@ -132,6 +132,93 @@ def cpu_baseline(prob, theta, seconds: float):
                       f"{el:.1f} s; assembly not timed"}, first
 
 
+def bench_batched(args, V, torch, gen):
+    """64 independent Poisson instances (log-uniform sizes, mixed orders), one batched step per epoch,
+    replayed from a captured HIP graph; the unfused path loops over the instances as the comparator."""
+    probs = gen.batched_instances(64, seed=0)
+    gp = []
+    for pr in probs:
+        p = V.vpinn_assemble(pr.mesh.xy, pr.mesh.quad, pr.quad_order, pr.test_order, pr.f_amp, pr.f_kx, pr.f_ky)
+        V.vpinn_set_boundary(p, pr.bnd_xy, pr.bnd_g)
+        gp.append(p)
+    P = sum(pr.n_points for pr in probs)
+    print(f"[bench] workload c5: 64 instances, {sum(pr.n_elem for pr in probs)} elements, {P} quadrature points",
+          file=sys.stderr, flush=True)
+    cfg = V.loss_cfg(30, 3, 10.0, 0.0)
+    b = V.vpinn_batch_create(gp, cfg)
+    dev = torch.device("cuda:0")
+    import numpy as np
+    th = np.stack([pr.params() for pr in probs])
+    T = torch.tensor(th, dtype=torch.float32, device=dev)
+    M = torch.zeros_like(T)
+    Vv = torch.zeros_like(T)
+    step = torch.zeros(1, dtype=torch.int64, device=dev)
+    losses = torch.zeros((64, 4), device=dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        V.vpinn_batch_capture(b, T, M, Vv, step, lr=1e-3, losses=losses, stream=s)
+        for _ in range(args.warmup):
+            V.vpinn_batch_replay(b, stream=s)
+        s.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(s)
+            V.vpinn_batch_replay(b, stream=s)
+            ev[i][1].record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+    st = sorted(a.elapsed_time(c) for a, c in ev)
+    ms = wall / args.steps * 1e3
+    # unfused comparator: each instance's plain loss/grad and Adam, in a loop
+    pcfg = V.loss_cfg(30, 3, 10.0, 0.0, path=V.VPINN_PATH_PLAIN)
+    Ts = [torch.tensor(th[i], dtype=torch.float32, device=dev) for i in range(64)]
+    Ms = [torch.zeros_like(t) for t in Ts]
+    Vs = [torch.zeros_like(t) for t in Ts]
+    g = torch.zeros(T.shape[1], device=dev)
+    l1 = torch.zeros(4, device=dev)
+    n_plain = max(3, min(20, args.steps // 10))
+    for t in range(1, 3):
+        for i in range(64):
+            V.vpinn_loss_and_grad(gp[i], pcfg, Ts[i], loss=l1, grad=g)
+            V.vpinn_adam_step(Ts[i], g, Ms[i], Vs[i], t)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for t in range(3, 3 + n_plain):
+        for i in range(64):
+            V.vpinn_loss_and_grad(gp[i], pcfg, Ts[i], loss=l1, grad=g)
+            V.vpinn_adam_step(Ts[i], g, Ms[i], Vs[i], t)
+    torch.cuda.synchronize()
+    pms = (time.perf_counter() - w0) / n_plain * 1e3
+    eps_s = 1e3 / ms
+    flops = sum(flops_per_epoch(pr) for pr in probs)
+    achieved = flops / (st[len(st) // 2] * 1e-3) / 1e12
+    out = {
+        "metric": "epochs/s and Mquadpts/s fwd+adjoint, fused batched vs plain HIP, loss err<=1e-5",
+        "value": round(eps_s, 3), "unit": "epochs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c5: 64 independent Poisson instances on +-20% jittered square meshes, element "
+                               "counts log-uniform in [256,16384], GLL n in {4,6,10}, test N_t in {3,5}, "
+                               "k in 1..16, each with its own 2-30-30-30-1 tanh MLP; one batched "
+                               "forward+adjoint+Adam step per epoch replayed from a HIP graph",
+                   "instances": 64, "quad_points": P, "parallelism": "single GPU"},
+        "mquadpts_per_s": round(P * eps_s / 1e6, 2),
+        "step_ms_p10_p50_p90": [round(st[len(st) // 10], 4), round(st[len(st) // 2], 4),
+                                round(st[(9 * len(st)) // 10], 4)],
+        "roofline": {"bound": "mfma", "kernel": "k_fused (batched step incl. reduction+Adam)",
+                     "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "algorithmic_flop_per_launch": flops,
+                     "algorithmic_bytes_per_launch": sum(bytes_per_epoch(pr) for pr in probs)},
+        "plain_hip": {"ms_per_step": round(pms, 4), "epochs_per_s": round(1e3 / pms, 3),
+                      "note": "64 x (unfused loss/grad + Adam) per step"},
+        "speedup_vs_plain": round(pms / ms, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +228,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
+    ap.add_argument("--workload", choices=["c2", "c5"], default="c2")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -152,6 +240,9 @@ def main():
     import vpinn_inputs as gen
 
     assert torch.cuda.is_available(), "needs a HIP device"
+    if args.workload == "c5":
+        bench_batched(args, V, torch, gen)
+        return
     prob = gen.config_c2()
     theta = prob.params()
     p = V.vpinn_assemble(prob.mesh.xy, prob.mesh.quad, prob.quad_order, prob.test_order,

@@ -187,6 +187,63 @@ vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_
 vpinn_status vpinn_adam_step(int64_t n, float *d_params, const float *d_grad, float *d_m, float *d_v,
                              int64_t step, float lr, float beta1, float beta2, float eps, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent problems (each with its own mesh, orders and    */
+/* network) trained together, one fused launch per step for all of them.    */
+/* ------------------------------------------------------------------------ */
+typedef struct vpinn_batch vpinn_batch;
+
+/*
+ * vpinn_batch_create -- plan a batch over n >= 1 assembled problems that share
+ * the network shape and loss weighting in `cfg` (cfg->path is ignored: batches
+ * always use the fused kernel).  The batch borrows the problems' device data:
+ * they must outlive it, and a later vpinn_set_boundary/vpinn_set_sensors on
+ * any of them requires a new batch.  Work is split into items balanced by
+ * point count over the device's compute units.  Allocates its workspace here;
+ * later batch calls allocate nothing.
+ */
+vpinn_status vpinn_batch_create(int32_t n, vpinn_problem *const *problems, const vpinn_loss_cfg *cfg,
+                                vpinn_batch **out);
+
+/*
+ * vpinn_batch_loss_and_grad -- loss and gradient of every problem.
+ *   d_params   device [n][vpinn_n_params(width, n_hidden)] floats, problem-major
+ *   d_eps      device [n] floats or NULL (eps = 1 for all)
+ *   d_losses   device [n][4] floats (L, L_v, L_b, L_s per problem), may be NULL
+ *   d_grads    device [n][n_params] floats, may be NULL (then no backward pass
+ *              unless d_grad_eps is given)
+ *   d_grad_eps device [n] floats or NULL
+ * Each problem's results equal its own vpinn_loss_and_grad up to FP32 rounding
+ * order.
+ */
+vpinn_status vpinn_batch_loss_and_grad(vpinn_batch *b, const float *d_params, const float *d_eps, float *d_losses,
+                                       float *d_grads, float *d_grad_eps, void *stream);
+
+/*
+ * vpinn_batch_step -- one training step of every problem: the fused forward +
+ * adjoint launch, then a reduction kernel that applies Adam (as in
+ * vpinn_adam_step) to each problem's parameters in place.  d_step is a device
+ * int64 step counter: the launch increments it and Adam uses the new value, so
+ * the first step after *d_step = 0 is step 1 and a captured step replays
+ * correctly.  d_m, d_v are device [n][n_params]; d_losses (may be NULL) gets
+ * the losses at the parameters before the update.
+ */
+vpinn_status vpinn_batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
+                              float beta1, float beta2, float eps, float *d_losses, void *stream);
+
+/*
+ * vpinn_batch_capture -- record one vpinn_batch_step with these arguments into
+ * a HIP graph owned by the batch (stream must not be NULL; the capture is
+ * thread-local); vpinn_batch_replay launches it.  The graph holds kernel nodes
+ * only.  Capturing again replaces the previous graph.
+ */
+vpinn_status vpinn_batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
+                                 float beta1, float beta2, float eps, float *d_losses, void *stream);
+vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream);
+
+/* Release the batch (not the problems).  NULL is a no-op. */
+void vpinn_batch_free(vpinn_batch *b);
+
 /* Release every device buffer of the problem.  NULL is a no-op. */
 void vpinn_problem_free(vpinn_problem *p);
 

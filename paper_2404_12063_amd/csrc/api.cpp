@@ -317,6 +317,74 @@ vpinn_status vpinn_adam_step(int64_t n, float *d_params, const float *d_grad, fl
     return adam_step(n, d_params, d_grad, d_m, d_v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
 }
 
+vpinn_status vpinn_batch_create(int32_t n, vpinn_problem *const *problems, const vpinn_loss_cfg *cfg,
+                                vpinn_batch **out) {
+    using namespace vp;
+    if (!out) return fail(VPINN_E_INVALID, "out is null");
+    *out = nullptr;
+    if (n < 1 || !problems) return fail(VPINN_E_INVALID, "need n >= 1 problems");
+    for (int i = 0; i < n; ++i) {
+        if (!problems[i]) return fail(VPINN_E_INVALID, "problem " + std::to_string(i) + " is null");
+        if (problems[i]->device != problems[0]->device)
+            return fail(VPINN_E_INVALID, "all problems of a batch must live on one device");
+    }
+    vpinn_status st = check_cfg(cfg);
+    if (st) return st;
+    DeviceGuard dg(problems[0]->device);
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problems' device");
+    return batch_create(n, problems, cfg, out);
+}
+
+vpinn_status vpinn_batch_loss_and_grad(vpinn_batch *b, const float *d_params, const float *d_eps, float *d_losses,
+                                       float *d_grads, float *d_grad_eps, void *stream) {
+    using namespace vp;
+    if (!b || !d_params) return fail(VPINN_E_INVALID, "batch or params is null");
+    if (!d_losses && !d_grads && !d_grad_eps) return fail(VPINN_E_INVALID, "nothing to compute");
+    DeviceGuard dg(batch_device(b));
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the batch's device");
+    return batch_loss_and_grad(b, d_params, d_eps, d_losses, d_grads, d_grad_eps, (hipStream_t)stream);
+}
+
+static vpinn_status check_step_args(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step) {
+    using namespace vp;
+    if (!b || !d_params || !d_m || !d_v || !d_step) return fail(VPINN_E_INVALID, "null argument");
+    return VPINN_OK;
+}
+
+vpinn_status vpinn_batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
+                              float beta1, float beta2, float eps, float *d_losses, void *stream) {
+    using namespace vp;
+    vpinn_status st = check_step_args(b, d_params, d_m, d_v, d_step);
+    if (st) return st;
+    DeviceGuard dg(batch_device(b));
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the batch's device");
+    return batch_step(b, d_params, d_m, d_v, d_step, lr, beta1, beta2, eps, d_losses, (hipStream_t)stream);
+}
+
+vpinn_status vpinn_batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
+                                 float beta1, float beta2, float eps, float *d_losses, void *stream) {
+    using namespace vp;
+    vpinn_status st = check_step_args(b, d_params, d_m, d_v, d_step);
+    if (st) return st;
+    DeviceGuard dg(batch_device(b));
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the batch's device");
+    return batch_capture(b, d_params, d_m, d_v, d_step, lr, beta1, beta2, eps, d_losses, (hipStream_t)stream);
+}
+
+vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream) {
+    using namespace vp;
+    if (!b) return fail(VPINN_E_INVALID, "batch is null");
+    DeviceGuard dg(batch_device(b));
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the batch's device");
+    return batch_replay(b, (hipStream_t)stream);
+}
+
+void vpinn_batch_free(vpinn_batch *b) {
+    if (!b) return;
+    vp::DeviceGuard dg(vp::batch_device(b));
+    vp::batch_destroy(b);
+}
+
 void vpinn_problem_free(vpinn_problem *p) {
     if (!p) return;
     vp::DeviceGuard dg(p->device);

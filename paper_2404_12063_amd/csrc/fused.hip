@@ -35,7 +35,10 @@
 // from registers to registers.  Only the weight-gradient products, which
 // contract over points, need the vectors transposed; that goes through a small
 // per-wavefront LDS tile.
+#include <algorithm>
 #include <cstdint>
+#include <new>
+#include <vector>
 
 #include "device_common.h"
 #include "internal.h"
@@ -81,35 +84,44 @@ struct FusedShared {
     double lp[kFWaves][4];
 };
 
-struct FusedArgs {
-    const float *params;  // flat layout, width H
-    int H;
+// static description of one problem instance (device resident)
+struct InstDesc {
     const float *Gx, *Gy, *F;
-    const float2 *pts;    // interior points then boundary then sensors
-    const float *tgt;     // boundary values then sensor observations
-    const float *eps_ptr;
+    const float2 *pts;        // interior points then boundary then sensors
+    const float *tgt;         // boundary values then sensor observations
     int64_t n_elem, n_pts, n_bnd, n_sen;
+    int64_t n_items, item0;   // items item0 .. item0 + n_items - 1 of the global list
     int nq, ntest;
-    int64_t n_items;
-    float two_cv, wb2, ws2;  // 2 c_v, 2 tau / N_D, 2 gamma / N_s
-    double cv;
+    int fast;                 // nq <= kFThreads and ntest <= kKB: G stays in registers
+    int row0, blk0, n_rows;   // partial rows row0.. (one per block blk0 .. blk0 + n_rows - 1)
+    float two_cv, wb2, ws2;   // 2 c_v, 2 tau / N_D, 2 gamma / N_s
     float tau, gamma;
-    int want_grad;
-    int64_t n_params_flat;
-    int item_cap_pts;        // LDS capacity for item points
-    int fast_contract;       // nq <= kFThreads and ntest <= kKB: G stays in registers
-    float *gpart;            // [blocks][kMaxPadded]
-    double *lpart;           // [blocks][4]
+    double cv;
 };
 
-// element and extra-point ranges of item i (even split, no work list needed)
-__device__ __forceinline__ void item_range(const FusedArgs &A, int64_t i, int64_t &e0, int64_t &e1, int64_t &x0,
+struct FusedArgs {
+    const InstDesc *inst;
+    const int *item_inst;       // [items] instance of each global item (instance-major order)
+    const int64_t *blk_items;   // [blocks + 1] global item range of each block
+    const float *params;        // [n_inst][param_stride] flat layout, width H
+    int64_t param_stride;
+    const float *eps;           // [n_inst] or null (eps = 1)
+    int H;
+    int want_grad;
+    int item_cap_pts;           // LDS capacity for item points
+    float *gpart;               // [rows][kMaxPadded]
+    double *lpart;              // [rows][4]
+    int64_t *step;              // optional step counter, incremented once per launch
+};
+
+// element and extra-point ranges of item i of an instance (even split, no work list needed)
+__device__ __forceinline__ void item_range(const InstDesc &I, int64_t i, int64_t &e0, int64_t &e1, int64_t &x0,
                                            int64_t &x1) {
-    const int64_t nx = A.n_bnd + A.n_sen;
-    e0 = i * A.n_elem / A.n_items;
-    e1 = (i + 1) * A.n_elem / A.n_items;
-    x0 = i * nx / A.n_items;
-    x1 = (i + 1) * nx / A.n_items;
+    const int64_t nx = I.n_bnd + I.n_sen;
+    e0 = i * I.n_elem / I.n_items;
+    e1 = (i + 1) * I.n_elem / I.n_items;
+    x0 = i * nx / I.n_items;
+    x1 = (i + 1) * nx / I.n_items;
 }
 
 // ---------------------------------------------------------------------------
@@ -373,42 +385,33 @@ __device__ __forceinline__ void tile_backward(const FusedShared<L> &S, float (*T
 // ---------------------------------------------------------------------------
 // the fused kernel
 // ---------------------------------------------------------------------------
+// weights of one instance -> LDS (padded to 32, fragment order for the MFMA A operands)
 template <int L>
-__global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A) {
-    __shared__ FusedShared<L> S;
-    extern __shared__ float dyn[];  // item data: float2 per item point, then 2 c_v R per (element, test)
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int H = A.H;
-
+__device__ __forceinline__ void load_weights(FusedShared<L> &S, const float *__restrict__ P, int H, int tid) {
     // weights -> LDS (padded to 32, fragment order for the MFMA A operands)
     for (int t = tid; t < PW * 2; t += kFThreads) {
         const int o = t >> 1, i = t & 1;
-        S.w1[o][i] = o < H ? A.params[o * 2 + i] : 0.f;
+        S.w1[o][i] = o < H ? P[o * 2 + i] : 0.f;
     }
     for (int t = tid; t < L * PW; t += kFThreads) {
         const int l = t / PW + 1, o = t % PW;
         const int64_t off = (l == 1) ? 2 * H : hoff_w(H, l) + (int64_t)H * H;
-        S.b[l - 1][o] = o < H ? A.params[off + o] : 0.f;
+        S.b[l - 1][o] = o < H ? P[off + o] : 0.f;
     }
-    for (int t = tid; t < PW; t += kFThreads) S.wo[t] = t < H ? A.params[hoff_w(H, L + 1) + t] : 0.f;
-    if (tid == 0) S.bo = A.params[hoff_w(H, L + 1) + H];
+    for (int t = tid; t < PW; t += kFThreads) S.wo[t] = t < H ? P[hoff_w(H, L + 1) + t] : 0.f;
+    if (tid == 0) S.bo = P[hoff_w(H, L + 1) + H];
     for (int t = tid; t < (L - 1) * 2 * 2 * 8 * 64; t += kFThreads) {
         const int ln = t & 63, s = (t >> 6) & 7, mt = (t >> 9) & 1, dir = (t >> 10) & 1, l = 2 + (t >> 11);
         const int m = s >> 2, r = s & 3;
         // forward: W[16 mt + ln % 16][16 m + 4 (ln / 16) + r]; backward: W[16 m + 4 (ln / 16) + r][16 mt + ln % 16]
         const int o = dir == 0 ? 16 * mt + (ln & 15) : 16 * m + 4 * (ln >> 4) + r;
         const int i = dir == 0 ? 16 * m + 4 * (ln >> 4) + r : 16 * mt + (ln & 15);
-        S.wf[l - 2][dir][mt][s][ln] = (o < H && i < H) ? A.params[hoff_w(H, l) + (int64_t)o * H + i] : 0.f;
+        S.wf[l - 2][dir][mt][s][ln] = (o < H && i < H) ? P[hoff_w(H, l) + (int64_t)o * H + i] : 0.f;
     }
-    __syncthreads();
+}
 
-    const float eps = A.eps_ptr ? *A.eps_ptr : 1.0f;
-    float2 *uxy = reinterpret_cast<float2 *>(dyn);
-    float *rbar = dyn + 2 * A.item_cap_pts;
-    float(*T0)[kTs] = S.tt[wave][0];
-    float(*T1)[kTs] = S.tt[wave][1];
-
-    GradAcc<L> G;
+template <int L>
+__device__ __forceinline__ void zero_acc(GradAcc<L> &G) {
 #pragma unroll
     for (int l = 0; l < (L > 1 ? L - 1 : 1); ++l)
 #pragma unroll
@@ -416,217 +419,13 @@ __global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A)
 #pragma unroll
     for (int l = 0; l < L; ++l) G.b[l] = 0.f;
     G.w1c0 = G.w1c1 = G.wo = G.bo = 0.f;
-    double lrr = 0.0, lra = 0.0, lbb = 0.0, lss = 0.0;  // per-thread loss partials
+}
 
-    for (int64_t item = blockIdx.x; item < A.n_items; item += gridDim.x) {
-        int64_t e0, e1, x0, x1;
-        item_range(A, item, e0, e1, x0, x1);
-        const int ne = (int)(e1 - e0);
-        const int n_int = ne * A.nq;                 // interior points of the item
-        const int n_all = n_int + (int)(x1 - x0);     // plus boundary/sensor points
-        const int n_tiles = (n_all + 15) >> 4;
-        auto point_xy = [&](int idx) -> float2 {
-            if (idx < n_int) return A.pts[e0 * A.nq + idx];
-            return A.pts[A.n_pts + x0 + (idx - n_int)];
-        };
-
-        // tiles go to wavefronts starting at a block-dependent offset, so the two
-        // blocks sharing a CU put their ragged extra tiles on different SIMDs
-        const int wrot = (wave + (int)(blockIdx.x + item) % kFWaves) % kFWaves;
-        // 1. forward
-        for (int t = wrot; t < n_tiles; t += kFWaves) {
-            const int idx = 16 * t + (lane & 15);
-            const bool valid = idx < n_all;
-            const float2 p = valid ? point_xy(idx) : make_float2(0.f, 0.f);
-            Vec a, tx, ty;
-            Acts<L> unused;
-            tile_forward<L, false>(S, lane, p.x, p.y, a, tx, ty, unused);
-            float u, ux, uy;
-            tile_outputs<L>(S, lane, a, tx, ty, u, ux, uy);
-            if (valid && lane < 16) uxy[idx] = idx < n_int ? make_float2(ux, uy) : make_float2(u, 0.f);
-        }
-        __syncthreads();
-
-        if (A.fast_contract) {
-            // 2+3. chunks of whole elements, thread (element, q); G of all tests in registers
-            float *cbuf = rbar + ne * A.ntest;  // [kKB][kCbs] per-point terms
-            const int epc = kFThreads / A.nq;
-            for (int c0 = 0; c0 < ne; c0 += epc) {
-                const int ce = min(epc, ne - c0);
-                const int el = c0 + tid / A.nq, q = tid - (tid / A.nq) * A.nq;
-                const bool act = tid < ce * A.nq;
-                const int64_t gbase = ((e0 + el) * A.ntest) * (int64_t)A.nq + q;
-                float gx[kKB], gy[kKB];
-#pragma unroll
-                for (int k = 0; k < kKB; ++k) {
-                    const bool ok = act && k < A.ntest;
-                    gx[k] = ok ? A.Gx[gbase + (int64_t)k * A.nq] : 0.f;
-                    gy[k] = ok ? A.Gy[gbase + (int64_t)k * A.nq] : 0.f;
-                }
-                const float2 d = act ? uxy[el * A.nq + q] : make_float2(0.f, 0.f);
-#pragma unroll
-                for (int k = 0; k < kKB; ++k)
-                    if (k < A.ntest) cbuf[k * kCbs + tid] = fmaf(d.x, gx[k], d.y * gy[k]);
-                __syncthreads();
-                // row sums, 8 lanes per (element, test) row
-                for (int r8 = tid; r8 < 8 * ce * A.ntest; r8 += kFThreads) {
-                    const int r = r8 >> 3, part = r8 & 7;
-                    const int e2 = r / A.ntest, k = r - e2 * A.ntest;
-                    const float *row = cbuf + k * kCbs + e2 * A.nq;
-                    float a = 0.f;
-                    for (int qq = part; qq < A.nq; qq += 8) a += row[qq];
-                    a += __shfl_xor(a, 4, 8);
-                    a += __shfl_xor(a, 2, 8);
-                    a += __shfl_xor(a, 1, 8);
-                    if (part == 0) {
-                        const float R = eps * a - A.F[(e0 + c0 + e2) * A.ntest + k];
-                        rbar[(c0 + e2) * A.ntest + k] = A.two_cv * R;
-                        lrr += (double)R * (double)R;
-                        lra += (double)R * (double)a;
-                    }
-                }
-                __syncthreads();
-                if (A.want_grad && act) {
-                    // reload G (cache hits) rather than keep 2 kKB registers live across the barrier
-                    const float *rb = rbar + el * A.ntest;
-#pragma unroll
-                    for (int k = 0; k < kKB; ++k) {
-                        const bool ok = k < A.ntest;
-                        gx[k] = ok ? A.Gx[gbase + (int64_t)k * A.nq] : 0.f;
-                        gy[k] = ok ? A.Gy[gbase + (int64_t)k * A.nq] : 0.f;
-                    }
-                    float bx = 0.f, by = 0.f;
-#pragma unroll
-                    for (int k = 0; k < kKB; ++k)
-                        if (k < A.ntest) {
-                            bx = fmaf(rb[k], gx[k], bx);
-                            by = fmaf(rb[k], gy[k], by);
-                        }
-                    uxy[el * A.nq + q] = make_float2(eps * bx, eps * by);
-                }
-            }
-        } else {
-        // 2. contraction: rows (element, test function), 16 lanes per row, two rows per
-            //    batch, every load of a batch in flight before the first use
-            {
-                constexpr int kRG = kFThreads / 16;
-                const int rg = tid >> 4, rl = tid & 15;
-                const int n_rows = ne * A.ntest;
-                for (int r0 = 0; r0 < n_rows; r0 += 2 * kRG) {
-                    float acc[2] = {0.f, 0.f}, fv[2];
-                    int row[2];
-                    int64_t base[2];
-                    int el[2];
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        row[i] = r0 + rg + i * kRG;
-                        el[i] = row[i] / A.ntest;
-                        const int k = row[i] - el[i] * A.ntest;
-                        base[i] = ((e0 + el[i]) * A.ntest + k) * (int64_t)A.nq;
-                        fv[i] = row[i] < n_rows ? A.F[(e0 + el[i]) * A.ntest + k] : 0.f;
-                    }
-                    for (int qc = 0; qc < A.nq; qc += 128) {
-                        float gx[2][8], gy[2][8];
-#pragma unroll
-                        for (int i = 0; i < 2; ++i)
-#pragma unroll
-                            for (int t = 0; t < 8; ++t) {
-                                const int q = qc + rl + 16 * t;
-                                const bool ok = row[i] < n_rows && q < A.nq;
-                                gx[i][t] = ok ? A.Gx[base[i] + q] : 0.f;
-                                gy[i][t] = ok ? A.Gy[base[i] + q] : 0.f;
-                            }
-#pragma unroll
-                        for (int i = 0; i < 2; ++i)
-#pragma unroll
-                            for (int t = 0; t < 8; ++t) {
-                                const int q = qc + rl + 16 * t;
-                                if (row[i] < n_rows && q < A.nq) {
-                                    const float2 d = uxy[el[i] * A.nq + q];
-                                    acc[i] = fmaf(d.x, gx[i][t], fmaf(d.y, gy[i][t], acc[i]));
-                                }
-                            }
-                    }
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        float a = acc[i];
-                        a += __shfl_xor(a, 8, 16);
-                        a += __shfl_xor(a, 4, 16);
-                        a += __shfl_xor(a, 2, 16);
-                        a += __shfl_xor(a, 1, 16);
-                        if (rl == 0 && row[i] < n_rows) {
-                            const float R = eps * a - fv[i];
-                            rbar[row[i]] = A.two_cv * R;
-                            lrr += (double)R * (double)R;
-                            lra += (double)R * (double)a;
-                        }
-                    }
-                }
-            }
-        }
-        for (int idx = n_int + tid; idx < n_all; idx += kFThreads) {
-            const int64_t xi = x0 + (idx - n_int);
-            const float d = uxy[idx].x - A.tgt[xi];
-            const bool bnd = xi < A.n_bnd;
-            if (bnd) lbb += (double)d * (double)d;
-            else lss += (double)d * (double)d;
-            uxy[idx] = make_float2((bnd ? A.wb2 : A.ws2) * d, 0.f);
-        }
-        __syncthreads();
-        if (!A.want_grad) {
-            __syncthreads();
-            continue;
-        }
-
-        // 3. adjoint of the contraction (generic path), thread per point, 16 tests per batch
-        for (int idx = tid; idx < (A.fast_contract ? 0 : n_int); idx += kFThreads) {
-            const int el = idx / A.nq, q = idx - el * A.nq;
-            const int64_t e = e0 + el;
-            const float *rb = rbar + el * A.ntest;
-            float bx = 0.f, by = 0.f;
-            for (int k0 = 0; k0 < A.ntest; k0 += 16) {
-                float gx[16], gy[16];
-#pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    const int k = k0 + t;
-                    const int64_t o = (e * A.ntest + k) * (int64_t)A.nq + q;
-                    gx[t] = k < A.ntest ? A.Gx[o] : 0.f;
-                    gy[t] = k < A.ntest ? A.Gy[o] : 0.f;
-                }
-#pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    const float r = (k0 + t < A.ntest) ? rb[k0 + t] : 0.f;
-                    bx = fmaf(r, gx[t], bx);
-                    by = fmaf(r, gy[t], by);
-                }
-            }
-            uxy[idx] = make_float2(eps * bx, eps * by);
-        }
-        __syncthreads();
-
-        // 4. backward with recompute
-        for (int t = wrot; t < n_tiles; t += kFWaves) {
-            const int idx = 16 * t + (lane & 15);
-            const bool valid = idx < n_all;
-            const float2 p = valid ? point_xy(idx) : make_float2(0.f, 0.f);
-            float ub = 0.f, uxb = 0.f, uyb = 0.f;
-            if (valid) {
-                const float2 d = uxy[idx];
-                if (idx < n_int) {
-                    uxb = d.x;
-                    uyb = d.y;
-                } else {
-                    ub = d.x;
-                }
-            }
-            Acts<L> K;
-            Vec a, tx, ty;
-            tile_forward<L, true>(S, lane, p.x, p.y, a, tx, ty, K);
-            tile_backward<L>(S, T0, T1, lane, p.x, p.y, ub, uxb, uyb, K, G);
-        }
-        __syncthreads();
-    }
-
+// the block's sums for one instance -> partial row `row`; accumulators reset
+template <int L>
+__device__ __forceinline__ void flush(FusedShared<L> &S, float *dyn, const FusedArgs &A, int64_t row, GradAcc<L> &G,
+                                      double &lrr, double &lra, double &lbb, double &lss, int tid, int wave,
+                                      int lane) {
     // ---- block partial: loss terms (double) and the padded gradient row ----
     {
         double v0 = wave_sum(lrr), v1 = wave_sum(lra), v2 = wave_sum(lbb), v3 = wave_sum(lss);
@@ -685,32 +484,293 @@ __global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A)
     }
     const int NP = n_padded(L);
     if (A.want_grad)
-        for (int j = tid; j < NP; j += kFThreads) A.gpart[(int64_t)blockIdx.x * kMaxPadded + j] = red[j];
+        for (int j = tid; j < NP; j += kFThreads) A.gpart[(int64_t)row * kMaxPadded + j] = red[j];
     if (tid < 4) {
         double s = 0.0;
         for (int w = 0; w < kFWaves; ++w) s += S.lp[w][tid];
-        A.lpart[blockIdx.x * 4 + tid] = s;
+        A.lpart[(int64_t)row * 4 + tid] = s;
     }
+    zero_acc<L>(G);
+    lrr = lra = lbb = lss = 0.0;
+    __syncthreads();
+}
+
+template <int L>
+__global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A) {
+    __shared__ FusedShared<L> S;
+    extern __shared__ float dyn[];  // item data: float2 per item point, then 2 c_v R per (element, test)
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int H = A.H;
+    if (A.step && blockIdx.x == 0 && tid == 0) *A.step += 1;
+
+    float2 *uxy = reinterpret_cast<float2 *>(dyn);
+    float *rbar = dyn + 2 * A.item_cap_pts;
+    float(*T0)[kTs] = S.tt[wave][0];
+    float(*T1)[kTs] = S.tt[wave][1];
+
+    GradAcc<L> G;
+    zero_acc<L>(G);
+    double lrr = 0.0, lra = 0.0, lbb = 0.0, lss = 0.0;  // per-thread loss partials
+    int cur = -1;
+    InstDesc I;
+    float eps = 1.0f;
+    const int64_t it_begin = A.blk_items[blockIdx.x], it_end = A.blk_items[blockIdx.x + 1];
+    for (int64_t git = it_begin; git < it_end; ++git) {
+        const int inst = A.item_inst[git];
+        if (inst != cur) {
+            if (cur >= 0) flush<L>(S, dyn, A, I.row0 + (int64_t)(blockIdx.x - I.blk0), G, lrr, lra, lbb, lss, tid,
+                                   wave, lane);
+            cur = inst;
+            I = A.inst[inst];
+            eps = A.eps ? A.eps[inst] : 1.0f;
+            __syncthreads();
+            load_weights<L>(S, A.params + (int64_t)inst * A.param_stride, H, tid);
+            __syncthreads();
+        }
+        const int64_t item = git - I.item0;
+        int64_t e0, e1, x0, x1;
+        item_range(I, item, e0, e1, x0, x1);
+        const int ne = (int)(e1 - e0);
+        const int n_int = ne * I.nq;                 // interior points of the item
+        const int n_all = n_int + (int)(x1 - x0);     // plus boundary/sensor points
+        const int n_tiles = (n_all + 15) >> 4;
+        auto point_xy = [&](int idx) -> float2 {
+            if (idx < n_int) return I.pts[e0 * I.nq + idx];
+            return I.pts[I.n_pts + x0 + (idx - n_int)];
+        };
+
+        // tiles go to wavefronts starting at a block-dependent offset, so the two
+        // blocks sharing a CU put their ragged extra tiles on different SIMDs
+        const int wrot = (wave + (int)((blockIdx.x + item) % kFWaves)) % kFWaves;
+        // 1. forward
+        for (int t = wrot; t < n_tiles; t += kFWaves) {
+            const int idx = 16 * t + (lane & 15);
+            const bool valid = idx < n_all;
+            const float2 p = valid ? point_xy(idx) : make_float2(0.f, 0.f);
+            Vec a, tx, ty;
+            Acts<L> unused;
+            tile_forward<L, false>(S, lane, p.x, p.y, a, tx, ty, unused);
+            float u, ux, uy;
+            tile_outputs<L>(S, lane, a, tx, ty, u, ux, uy);
+            if (valid && lane < 16) uxy[idx] = idx < n_int ? make_float2(ux, uy) : make_float2(u, 0.f);
+        }
+        __syncthreads();
+
+        if (I.fast) {
+            // 2+3. chunks of whole elements, thread (element, q); G of all tests in registers
+            float *cbuf = rbar + ne * I.ntest;  // [kKB][kCbs] per-point terms
+            const int epc = kFThreads / I.nq;
+            for (int c0 = 0; c0 < ne; c0 += epc) {
+                const int ce = min(epc, ne - c0);
+                const int el = c0 + tid / I.nq, q = tid - (tid / I.nq) * I.nq;
+                const bool act = tid < ce * I.nq;
+                const int64_t gbase = ((e0 + el) * I.ntest) * (int64_t)I.nq + q;
+                float gx[kKB], gy[kKB];
+#pragma unroll
+                for (int k = 0; k < kKB; ++k) {
+                    const bool ok = act && k < I.ntest;
+                    gx[k] = ok ? I.Gx[gbase + (int64_t)k * I.nq] : 0.f;
+                    gy[k] = ok ? I.Gy[gbase + (int64_t)k * I.nq] : 0.f;
+                }
+                const float2 d = act ? uxy[el * I.nq + q] : make_float2(0.f, 0.f);
+#pragma unroll
+                for (int k = 0; k < kKB; ++k)
+                    if (k < I.ntest) cbuf[k * kCbs + tid] = fmaf(d.x, gx[k], d.y * gy[k]);
+                __syncthreads();
+                // row sums, 8 lanes per (element, test) row
+                for (int r8 = tid; r8 < 8 * ce * I.ntest; r8 += kFThreads) {
+                    const int r = r8 >> 3, part = r8 & 7;
+                    const int e2 = r / I.ntest, k = r - e2 * I.ntest;
+                    const float *row = cbuf + k * kCbs + e2 * I.nq;
+                    float a = 0.f;
+                    for (int qq = part; qq < I.nq; qq += 8) a += row[qq];
+                    a += __shfl_xor(a, 4, 8);
+                    a += __shfl_xor(a, 2, 8);
+                    a += __shfl_xor(a, 1, 8);
+                    if (part == 0) {
+                        const float R = eps * a - I.F[(e0 + c0 + e2) * I.ntest + k];
+                        rbar[(c0 + e2) * I.ntest + k] = I.two_cv * R;
+                        lrr += (double)R * (double)R;
+                        lra += (double)R * (double)a;
+                    }
+                }
+                __syncthreads();
+                if (A.want_grad && act) {
+                    // reload G (cache hits) rather than keep 2 kKB registers live across the barrier
+                    const float *rb = rbar + el * I.ntest;
+#pragma unroll
+                    for (int k = 0; k < kKB; ++k) {
+                        const bool ok = k < I.ntest;
+                        gx[k] = ok ? I.Gx[gbase + (int64_t)k * I.nq] : 0.f;
+                        gy[k] = ok ? I.Gy[gbase + (int64_t)k * I.nq] : 0.f;
+                    }
+                    float bx = 0.f, by = 0.f;
+#pragma unroll
+                    for (int k = 0; k < kKB; ++k)
+                        if (k < I.ntest) {
+                            bx = fmaf(rb[k], gx[k], bx);
+                            by = fmaf(rb[k], gy[k], by);
+                        }
+                    uxy[el * I.nq + q] = make_float2(eps * bx, eps * by);
+                }
+            }
+        } else {
+        // 2. contraction: rows (element, test function), 16 lanes per row, two rows per
+            //    batch, every load of a batch in flight before the first use
+            {
+                constexpr int kRG = kFThreads / 16;
+                const int rg = tid >> 4, rl = tid & 15;
+                const int n_rows = ne * I.ntest;
+                for (int r0 = 0; r0 < n_rows; r0 += 2 * kRG) {
+                    float acc[2] = {0.f, 0.f}, fv[2];
+                    int row[2];
+                    int64_t base[2];
+                    int el[2];
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        row[i] = r0 + rg + i * kRG;
+                        el[i] = row[i] / I.ntest;
+                        const int k = row[i] - el[i] * I.ntest;
+                        base[i] = ((e0 + el[i]) * I.ntest + k) * (int64_t)I.nq;
+                        fv[i] = row[i] < n_rows ? I.F[(e0 + el[i]) * I.ntest + k] : 0.f;
+                    }
+                    for (int qc = 0; qc < I.nq; qc += 128) {
+                        float gx[2][8], gy[2][8];
+#pragma unroll
+                        for (int i = 0; i < 2; ++i)
+#pragma unroll
+                            for (int t = 0; t < 8; ++t) {
+                                const int q = qc + rl + 16 * t;
+                                const bool ok = row[i] < n_rows && q < I.nq;
+                                gx[i][t] = ok ? I.Gx[base[i] + q] : 0.f;
+                                gy[i][t] = ok ? I.Gy[base[i] + q] : 0.f;
+                            }
+#pragma unroll
+                        for (int i = 0; i < 2; ++i)
+#pragma unroll
+                            for (int t = 0; t < 8; ++t) {
+                                const int q = qc + rl + 16 * t;
+                                if (row[i] < n_rows && q < I.nq) {
+                                    const float2 d = uxy[el[i] * I.nq + q];
+                                    acc[i] = fmaf(d.x, gx[i][t], fmaf(d.y, gy[i][t], acc[i]));
+                                }
+                            }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        float a = acc[i];
+                        a += __shfl_xor(a, 8, 16);
+                        a += __shfl_xor(a, 4, 16);
+                        a += __shfl_xor(a, 2, 16);
+                        a += __shfl_xor(a, 1, 16);
+                        if (rl == 0 && row[i] < n_rows) {
+                            const float R = eps * a - fv[i];
+                            rbar[row[i]] = I.two_cv * R;
+                            lrr += (double)R * (double)R;
+                            lra += (double)R * (double)a;
+                        }
+                    }
+                }
+            }
+        }
+        for (int idx = n_int + tid; idx < n_all; idx += kFThreads) {
+            const int64_t xi = x0 + (idx - n_int);
+            const float d = uxy[idx].x - I.tgt[xi];
+            const bool bnd = xi < I.n_bnd;
+            if (bnd) lbb += (double)d * (double)d;
+            else lss += (double)d * (double)d;
+            uxy[idx] = make_float2((bnd ? I.wb2 : I.ws2) * d, 0.f);
+        }
+        __syncthreads();
+        if (!A.want_grad) {
+            __syncthreads();
+            continue;
+        }
+
+        // 3. adjoint of the contraction (generic path), thread per point, 16 tests per batch
+        for (int idx = tid; idx < (I.fast ? 0 : n_int); idx += kFThreads) {
+            const int el = idx / I.nq, q = idx - el * I.nq;
+            const int64_t e = e0 + el;
+            const float *rb = rbar + el * I.ntest;
+            float bx = 0.f, by = 0.f;
+            for (int k0 = 0; k0 < I.ntest; k0 += 16) {
+                float gx[16], gy[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const int k = k0 + t;
+                    const int64_t o = (e * I.ntest + k) * (int64_t)I.nq + q;
+                    gx[t] = k < I.ntest ? I.Gx[o] : 0.f;
+                    gy[t] = k < I.ntest ? I.Gy[o] : 0.f;
+                }
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const float r = (k0 + t < I.ntest) ? rb[k0 + t] : 0.f;
+                    bx = fmaf(r, gx[t], bx);
+                    by = fmaf(r, gy[t], by);
+                }
+            }
+            uxy[idx] = make_float2(eps * bx, eps * by);
+        }
+        __syncthreads();
+
+        // 4. backward with recompute
+        for (int t = wrot; t < n_tiles; t += kFWaves) {
+            const int idx = 16 * t + (lane & 15);
+            const bool valid = idx < n_all;
+            const float2 p = valid ? point_xy(idx) : make_float2(0.f, 0.f);
+            float ub = 0.f, uxb = 0.f, uyb = 0.f;
+            if (valid) {
+                const float2 d = uxy[idx];
+                if (idx < n_int) {
+                    uxb = d.x;
+                    uyb = d.y;
+                } else {
+                    ub = d.x;
+                }
+            }
+            Acts<L> K;
+            Vec a, tx, ty;
+            tile_forward<L, true>(S, lane, p.x, p.y, a, tx, ty, K);
+            tile_backward<L>(S, T0, T1, lane, p.x, p.y, ub, uxb, uyb, K, G);
+        }
+        __syncthreads();
+    }
+    if (cur >= 0)
+        flush<L>(S, dyn, A, I.row0 + (int64_t)(blockIdx.x - I.blk0), G, lrr, lra, lbb, lss, tid, wave, lane);
 }
 
 // ---------------------------------------------------------------------------
-// fixed-order reduction of the block partials into the outputs
+// fixed-order reduction of the block partials into the outputs, one instance
+// per blockIdx.y; optionally followed by Adam (Kingma and Ba, Algorithm 1) on
+// that instance's parameters with the step count read from device memory
 // ---------------------------------------------------------------------------
 // block = 32 columns x 32 row slices; slice t sums rows t, t+32, ... in order,
 // then the 32 slice sums of a column are added in slice order (fixed order
-// for any launch).  Loss partials are summed by block 0 the same way.
+// for any launch).  Loss partials are summed by the x = 0 block the same way.
 constexpr int kFinCols = 32, kFinSlices = 32;
+struct AdamArgs {
+    float *params, *m, *v;
+    const int64_t *step;
+    float lr, b1, b2, eps;
+};
+
 template <int L>
 __global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
-    const float *__restrict__ gpart, const double *__restrict__ lpart, int rows, int H, int64_t npf, double cv,
-    int64_t n_bnd, int64_t n_sen, float tau, float gamma, float *__restrict__ loss_out, float *__restrict__ grad_out,
-    float *__restrict__ grad_eps_out) {
+    const InstDesc *__restrict__ inst, const float *__restrict__ gpart, const double *__restrict__ lpart, int H,
+    int64_t npf, float *__restrict__ loss_out, float *__restrict__ grad_out, float *__restrict__ grad_eps_out,
+    AdamArgs ad) {
     __shared__ float part[kFinSlices][kFinCols + 1];
     __shared__ double lred[kFinSlices][4];
+    const int ii = blockIdx.y;
+    const InstDesc &I = inst[ii];
+    const int rows = I.n_rows;
+    const float *gp = gpart + (int64_t)I.row0 * kMaxPadded;
+    const double *lp = lpart + (int64_t)I.row0 * 4;
     const int c = threadIdx.x % kFinCols, t = threadIdx.x / kFinCols;
     const int64_t j = (int64_t)blockIdx.x * kFinCols + c;
+    const bool want = (grad_out || ad.params) && j < npf;
     int pj = -1;  // padded index of flat parameter j
-    if (grad_out && j < npf) {
+    if (want) {
         if (j < 2 * H) pj = (int)j;
         else if (j < 3 * H) pj = kOffB1 + (int)(j - 2 * H);
         else {
@@ -731,7 +791,7 @@ __global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int b = b0 + i * kFinSlices;
-                v[i] = b < rows ? gpart[(int64_t)b * kMaxPadded + pj] : 0.f;
+                v[i] = b < rows ? gp[(int64_t)b * kMaxPadded + pj] : 0.f;
             }
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc += v[i];
@@ -745,7 +805,7 @@ __global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int b = b0 + i * kFinSlices;
-                v[i] = b < rows ? lpart[b * 4 + c] : 0.0;
+                v[i] = b < rows ? lp[b * 4 + c] : 0.0;
             }
 #pragma unroll
             for (int i = 0; i < 16; ++i) l4 += v[i];
@@ -754,35 +814,41 @@ __global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
     }
     __syncthreads();
     if (t == 0 && pj >= 0) {
-        float s = 0.f;
-        for (int q = 0; q < kFinSlices; ++q) s += part[q][c];
-        grad_out[j] = s;
+        float g = 0.f;
+        for (int q = 0; q < kFinSlices; ++q) g += part[q][c];
+        if (grad_out) grad_out[(int64_t)ii * npf + j] = g;
+        if (ad.params) {
+            const int64_t k = (int64_t)ii * npf + j;
+            const float st = (float)*ad.step;
+            const float c1 = 1.0f - powf(ad.b1, st), c2 = 1.0f - powf(ad.b2, st);
+            const float mi = fmaf(ad.b1, ad.m[k], (1.0f - ad.b1) * g);
+            const float vi = fmaf(ad.b2, ad.v[k], (1.0f - ad.b2) * g * g);
+            ad.m[k] = mi;
+            ad.v[k] = vi;
+            ad.params[k] -= ad.lr * (mi / c1) / (sqrtf(vi / c2) + ad.eps);
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         double tt[4] = {0, 0, 0, 0};
         for (int q = 0; q < kFinSlices; ++q)
             for (int i = 0; i < 4; ++i) tt[i] += lred[q][i];
-        const double Lv = cv * tt[0];
-        const double Lb = n_bnd ? tt[2] / (double)n_bnd : 0.0;
-        const double Ls = n_sen ? tt[3] / (double)n_sen : 0.0;
+        const double Lv = I.cv * tt[0];
+        const double Lb = I.n_bnd ? tt[2] / (double)I.n_bnd : 0.0;
+        const double Ls = I.n_sen ? tt[3] / (double)I.n_sen : 0.0;
         if (loss_out) {
-            loss_out[0] = (float)(Lv + (double)tau * Lb + (double)gamma * Ls);
-            loss_out[1] = (float)Lv;
-            loss_out[2] = (float)Lb;
-            loss_out[3] = (float)Ls;
+            float *lo = loss_out + 4 * (int64_t)ii;
+            lo[0] = (float)(Lv + (double)I.tau * Lb + (double)I.gamma * Ls);
+            lo[1] = (float)Lv;
+            lo[2] = (float)Lb;
+            lo[3] = (float)Ls;
         }
-        if (grad_eps_out) *grad_eps_out = (float)(2.0 * cv * tt[1]);
+        if (grad_eps_out) grad_eps_out[ii] = (float)(2.0 * I.cv * tt[1]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// host side
+// host side: work plans
 // ---------------------------------------------------------------------------
-struct FusedWorkspace {
-    DevBuf gpart, lpart;
-    int blocks = 0;
-};
-
 static int cu_count(int dev) {
     static int cached[64] = {0};
     if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
@@ -803,19 +869,6 @@ static size_t dyn_budget(int dev) {
     return lim > stat ? lim - stat : 0;
 }
 
-template <int L>
-static hipError_t launch_fused(int blocks, size_t dyn_bytes, const FusedArgs &a, hipStream_t s) {
-    static size_t attr_bytes = 0;
-    if (dyn_bytes > 48 * 1024 && attr_bytes < dyn_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_fused<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)dyn_bytes);
-        if (e != hipSuccess) return e;
-        attr_bytes = dyn_bytes;
-    }
-    k_fused<L><<<blocks, kFThreads, dyn_bytes, s>>>(a);
-    return hipGetLastError();
-}
-
 static size_t dyn_budget_for(int L, int dev) {
     switch (L) {
     case 1: return dyn_budget<1>(dev);
@@ -825,92 +878,317 @@ static size_t dyn_budget_for(int L, int dev) {
     }
 }
 
-vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
-                             const float *d_eps, float *d_loss, float *d_grad, float *d_grad_eps, hipStream_t s) {
-    const int L = cfg->n_hidden, H = cfg->width;
-    const int64_t nx = p->n_bnd + p->n_sen;
-    const int64_t total = p->n_pts + nx;
-    const int cus = cu_count(p->device);
-    // items: a multiple of the block count, each about total / n_items points (at most ~2048)
-    int blocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus * kFBlocksPerCU, kMaxBlocks), p->n_elem);
-    const int64_t per_block_pts = (total + blocks - 1) / blocks;
-    const int64_t rounds = (per_block_pts + 2047) / 2048;
-    int64_t n_items = std::min<int64_t>((int64_t)blocks * rounds, p->n_elem);
-    if (n_items < blocks) blocks = (int)n_items;
-    const int64_t max_e = (p->n_elem + n_items - 1) / n_items;
-    const int64_t max_x = (nx + n_items - 1) / n_items;
-    const int64_t cap_pts = max_e * p->nq + max_x;
-    const bool fast = p->nq <= kFThreads && p->ntest <= kKB;
-    size_t dyn = sizeof(float) * (2 * cap_pts + max_e * p->ntest + (fast ? (size_t)p->ntest * kCbs : 0));
-    dyn = std::max(dyn, sizeof(float) * (size_t)kMaxPadded);
-    if (dyn > dyn_budget_for(L, p->device))
-        return fail(VPINN_E_UNSUPPORTED, "fused path: an element's quadrature and test data exceed the LDS budget");
+template <int L>
+static hipError_t set_dyn_attr(size_t dyn_bytes) {
+    return hipFuncSetAttribute((const void *)k_fused<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+}
 
-    auto *ws = reinterpret_cast<FusedWorkspace *>(p->fused_ws);
-    if (!ws) {
-        ws = new FusedWorkspace();
-        p->fused_ws = ws;
-        p->fused_ws_free = [](void *w) { delete reinterpret_cast<FusedWorkspace *>(w); };
+// A plan fixes, for a set of instances with one network shape and loss
+// weighting: the items of every instance, the contiguous item range of every
+// block (balanced by point count), and which partial rows each block writes.
+struct FusedPlan {
+    DevBuf inst, item_inst, blk_items, gpart, lpart;
+    std::vector<InstDesc> host_inst;
+    int blocks = 0, n_inst = 0, rows = 0, L = 0, H = 0;
+    int64_t items = 0, npf = 0;
+    size_t dyn = 0;
+    int item_cap_pts = 0;
+};
+
+static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_loss_cfg *cfg, int dev,
+                               FusedPlan &P) {
+    const int L = cfg->n_hidden, H = cfg->width;
+    const int cus = cu_count(dev);
+    int64_t total_all = 0, elems_all = 0;
+    for (int i = 0; i < n; ++i) {
+        total_all += probs[i]->n_pts + probs[i]->n_bnd + probs[i]->n_sen;
+        elems_all += probs[i]->n_elem;
     }
-    if (ws->blocks < blocks) {
-        VP_HIP(ws->gpart.reserve(sizeof(float) * kMaxPadded * blocks));
-        VP_HIP(ws->lpart.reserve(sizeof(double) * 4 * blocks));
-        ws->blocks = blocks;
+    const int max_blocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus * kFBlocksPerCU, kMaxBlocks),
+                                                  elems_all);
+    // item size: one instance gets a multiple of the block count of items (each
+    // at most ~2048 points); in a batch, items of about half a block's share
+    // of the points let the contiguous block ranges balance
+    const int64_t target = std::max<int64_t>(1, std::min<int64_t>(2048, total_all / (2 * (int64_t)max_blocks)));
+    const int64_t single_items =
+        std::min<int64_t>(elems_all, (int64_t)max_blocks * ((total_all + (int64_t)max_blocks * 2048 - 1) /
+                                                           ((int64_t)max_blocks * 2048)));
+    std::vector<InstDesc> D(n);
+    std::vector<int64_t> item_pts;  // points per global item
+    std::vector<int> item_inst;
+    size_t dyn = sizeof(float) * (size_t)kMaxPadded;
+    int cap_max = 0;
+    for (int i = 0; i < n; ++i) {
+        const vpinn_problem *p = probs[i];
+        const int64_t nx = p->n_bnd + p->n_sen, tot = p->n_pts + nx;
+        const int64_t ni = n == 1 ? single_items
+                                  : std::max<int64_t>(1, std::min<int64_t>(p->n_elem, (tot + target / 2) / target));
+        InstDesc &d = D[i];
+        d = InstDesc{};
+        d.Gx = p->Gx.as<float>();
+        d.Gy = p->Gy.as<float>();
+        d.F = p->F.as<float>();
+        d.pts = p->pts.as<float2>();
+        d.tgt = p->tgt.as<float>();
+        d.n_elem = p->n_elem;
+        d.n_pts = p->n_pts;
+        d.n_bnd = p->n_bnd;
+        d.n_sen = p->n_sen;
+        d.n_items = ni;
+        d.item0 = (int64_t)item_inst.size();
+        d.nq = p->nq;
+        d.ntest = p->ntest;
+        d.fast = (p->nq <= kFThreads && p->ntest <= kKB) ? 1 : 0;
+        d.cv = cfg->loss_norm == VPINN_NORM_ELEM ? 1.0 / (double)p->n_elem : 1.0 / (double)p->ntest;
+        d.two_cv = (float)(2.0 * d.cv);
+        d.wb2 = p->n_bnd ? (float)(2.0 * cfg->tau / (double)p->n_bnd) : 0.f;
+        d.ws2 = p->n_sen ? (float)(2.0 * cfg->gamma / (double)p->n_sen) : 0.f;
+        d.tau = cfg->tau;
+        d.gamma = cfg->gamma;
+        for (int64_t it = 0; it < ni; ++it) {
+            const int64_t e0 = it * p->n_elem / ni, e1 = (it + 1) * p->n_elem / ni;
+            const int64_t x0 = it * nx / ni, x1 = (it + 1) * nx / ni;
+            item_pts.push_back((e1 - e0) * p->nq + (x1 - x0));
+            item_inst.push_back(i);
+        }
+        const int64_t max_e = (p->n_elem + ni - 1) / ni, max_x = (nx + ni - 1) / ni;
+        const int64_t cap = max_e * p->nq + max_x;
+        cap_max = (int)std::max<int64_t>(cap_max, cap);
     }
-    const double cv = cfg->loss_norm == VPINN_NORM_ELEM ? 1.0 / (double)p->n_elem : 1.0 / (double)p->ntest;
-    FusedArgs a{};
-    a.params = d_params;
-    a.H = H;
-    a.Gx = p->Gx.as<float>();
-    a.Gy = p->Gy.as<float>();
-    a.F = p->F.as<float>();
-    a.pts = p->pts.as<float2>();
-    a.tgt = p->tgt.as<float>();
-    a.eps_ptr = d_eps;
-    a.n_elem = p->n_elem;
-    a.n_pts = p->n_pts;
-    a.n_bnd = p->n_bnd;
-    a.n_sen = p->n_sen;
-    a.nq = p->nq;
-    a.ntest = p->ntest;
-    a.n_items = n_items;
-    a.cv = cv;
-    a.two_cv = (float)(2.0 * cv);
-    a.wb2 = p->n_bnd ? (float)(2.0 * cfg->tau / (double)p->n_bnd) : 0.f;
-    a.ws2 = p->n_sen ? (float)(2.0 * cfg->gamma / (double)p->n_sen) : 0.f;
-    a.tau = cfg->tau;
-    a.gamma = cfg->gamma;
-    a.want_grad = d_grad != nullptr;
-    a.n_params_flat = vpinn_n_params(H, L);
-    a.item_cap_pts = (int)cap_pts;
-    a.gpart = ws->gpart.as<float>();
-    a.lpart = ws->lpart.as<double>();
-    a.fast_contract = fast ? 1 : 0;
+    // the shared dynamic-LDS layout: item points (float2), then 2 c_v R, then the contraction buffer
+    for (int i = 0; i < n; ++i) {
+        const InstDesc &d = D[i];
+        const int64_t max_e = (d.n_elem + d.n_items - 1) / d.n_items;
+        const size_t need = sizeof(float) * (2 * (size_t)cap_max + max_e * d.ntest + (d.fast ? (size_t)d.ntest * kCbs : 0));
+        dyn = std::max(dyn, need);
+    }
+    if (dyn > dyn_budget_for(L, dev))
+        return fail(VPINN_E_UNSUPPORTED, "fused path: an element's quadrature and test data exceed the LDS budget");
+    const int64_t items = (int64_t)item_inst.size();
+    const int blocks = (int)std::min<int64_t>(max_blocks, items);
+    // contiguous item ranges with about equal point counts
+    std::vector<int64_t> blk(blocks + 1, items);
+    blk[0] = 0;
+    {
+        int64_t acc = 0, it = 0;
+        for (int b = 1; b < blocks; ++b) {
+            const double goal = (double)total_all * b / blocks;
+            while (it < items && (double)(acc + item_pts[it]) <= goal) acc += item_pts[it++];
+            // every block keeps at least one item
+            const int64_t lo = blk[b - 1] + 1, hi = items - (blocks - b);
+            blk[b] = std::min<int64_t>(std::max<int64_t>(it, lo), hi);
+            while (it < blk[b]) acc += item_pts[it++];
+            while (it > blk[b]) acc -= item_pts[--it];
+        }
+    }
+    // partial rows: instance i gets one row per block whose range meets its items
+    int rows = 0;
+    {
+        int b = 0;
+        for (int i = 0; i < n; ++i) {
+            InstDesc &d = D[i];
+            const int64_t f = d.item0, l = d.item0 + d.n_items - 1;
+            while (blk[b + 1] <= f) ++b;
+            int bl = b;
+            while (blk[bl + 1] <= l) ++bl;
+            d.blk0 = b;
+            d.n_rows = bl - b + 1;
+            d.row0 = rows;
+            rows += d.n_rows;
+        }
+    }
+    VP_HIP(P.inst.reserve(sizeof(InstDesc) * n));
+    VP_HIP(P.item_inst.reserve(sizeof(int) * items));
+    VP_HIP(P.blk_items.reserve(sizeof(int64_t) * (blocks + 1)));
+    VP_HIP(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)rows));
+    VP_HIP(P.lpart.reserve(sizeof(double) * 4 * (size_t)rows));
+    VP_HIP(hipMemcpy(P.inst.ptr, D.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(P.item_inst.ptr, item_inst.data(), sizeof(int) * items, hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(P.blk_items.ptr, blk.data(), sizeof(int64_t) * (blocks + 1), hipMemcpyHostToDevice));
     hipError_t e;
     switch (L) {
-    case 1: e = launch_fused<1>(blocks, dyn, a, s); break;
-    case 2: e = launch_fused<2>(blocks, dyn, a, s); break;
-    case 3: e = launch_fused<3>(blocks, dyn, a, s); break;
-    case 4: e = launch_fused<4>(blocks, dyn, a, s); break;
-    default: return fail(VPINN_E_UNSUPPORTED, "n_hidden out of range");
+    case 1: e = set_dyn_attr<1>(dyn); break;
+    case 2: e = set_dyn_attr<2>(dyn); break;
+    case 3: e = set_dyn_attr<3>(dyn); break;
+    default: e = set_dyn_attr<4>(dyn); break;
     }
-    if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("fused launch: ") + hipGetErrorString(e));
-    const int64_t npf = vpinn_n_params(H, L);
-    const unsigned fb = (unsigned)std::max<int64_t>(1, (npf + kFinCols - 1) / kFinCols);
-    const float *gp = ws->gpart.as<float>();
-    const double *lp = ws->lpart.as<double>();
+    if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    P.host_inst = D;
+    P.blocks = blocks;
+    P.n_inst = n;
+    P.rows = rows;
+    P.items = items;
+    P.L = L;
+    P.H = H;
+    P.npf = vpinn_n_params(H, L);
+    P.dyn = dyn;
+    P.item_cap_pts = cap_max;
+    return VPINN_OK;
+}
+
+// launch the fused kernel and the per-instance reduction (with optional Adam)
+static vpinn_status run_plan(const FusedPlan &P, const float *params, const float *eps, bool want_grad,
+                             float *loss, float *grad, float *grad_eps, const AdamArgs &ad, int64_t *step,
+                             hipStream_t s) {
+    FusedArgs a{};
+    a.inst = P.inst.as<InstDesc>();
+    a.item_inst = P.item_inst.as<int>();
+    a.blk_items = P.blk_items.as<int64_t>();
+    a.params = params;
+    a.param_stride = P.npf;
+    a.eps = eps;
+    a.H = P.H;
+    a.want_grad = want_grad ? 1 : 0;
+    a.item_cap_pts = P.item_cap_pts;
+    a.gpart = P.gpart.as<float>();
+    a.lpart = P.lpart.as<double>();
+    a.step = step;
+    const dim3 fg((unsigned)std::max<int64_t>(1, (P.npf + kFinCols - 1) / kFinCols), (unsigned)P.n_inst);
     const int ft = kFinCols * kFinSlices;
-    switch (L) {
-    case 1: k_fused_final<1><<<fb, ft, 0, s>>>(gp, lp, blocks, H, npf, cv, p->n_bnd, p->n_sen, cfg->tau, cfg->gamma,
-                                               d_loss, d_grad, d_grad_eps); break;
-    case 2: k_fused_final<2><<<fb, ft, 0, s>>>(gp, lp, blocks, H, npf, cv, p->n_bnd, p->n_sen, cfg->tau, cfg->gamma,
-                                               d_loss, d_grad, d_grad_eps); break;
-    case 3: k_fused_final<3><<<fb, ft, 0, s>>>(gp, lp, blocks, H, npf, cv, p->n_bnd, p->n_sen, cfg->tau, cfg->gamma,
-                                               d_loss, d_grad, d_grad_eps); break;
-    default: k_fused_final<4><<<fb, ft, 0, s>>>(gp, lp, blocks, H, npf, cv, p->n_bnd, p->n_sen, cfg->tau, cfg->gamma,
-                                                d_loss, d_grad, d_grad_eps); break;
+    const InstDesc *di = P.inst.as<InstDesc>();
+    const float *gp = P.gpart.as<float>();
+    const double *lp = P.lpart.as<double>();
+    switch (P.L) {
+    case 1:
+        k_fused<1><<<P.blocks, kFThreads, P.dyn, s>>>(a);
+        k_fused_final<1><<<fg, ft, 0, s>>>(di, gp, lp, P.H, P.npf, loss, grad, grad_eps, ad);
+        break;
+    case 2:
+        k_fused<2><<<P.blocks, kFThreads, P.dyn, s>>>(a);
+        k_fused_final<2><<<fg, ft, 0, s>>>(di, gp, lp, P.H, P.npf, loss, grad, grad_eps, ad);
+        break;
+    case 3:
+        k_fused<3><<<P.blocks, kFThreads, P.dyn, s>>>(a);
+        k_fused_final<3><<<fg, ft, 0, s>>>(di, gp, lp, P.H, P.npf, loss, grad, grad_eps, ad);
+        break;
+    default:
+        k_fused<4><<<P.blocks, kFThreads, P.dyn, s>>>(a);
+        k_fused_final<4><<<fg, ft, 0, s>>>(di, gp, lp, P.H, P.npf, loss, grad, grad_eps, ad);
+        break;
     }
     VP_HIP(hipGetLastError());
+    return VPINN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single problem: a cached plan, rebuilt when the point sets or the loss
+// weighting change
+// ---------------------------------------------------------------------------
+struct SingleCache {
+    FusedPlan plan;
+    bool valid = false;
+    int64_t n_bnd = -1, n_sen = -1;
+    const void *pts = nullptr;
+    int L = 0, H = 0, norm = -1;
+    float tau = -1.f, gamma = -1.f;
+};
+
+vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
+                             const float *d_eps, float *d_loss, float *d_grad, float *d_grad_eps, hipStream_t s) {
+    auto *c = reinterpret_cast<SingleCache *>(p->fused_ws);
+    if (!c) {
+        c = new SingleCache();
+        p->fused_ws = c;
+        p->fused_ws_free = [](void *w) { delete reinterpret_cast<SingleCache *>(w); };
+    }
+    if (!c->valid || c->n_bnd != p->n_bnd || c->n_sen != p->n_sen || c->pts != p->pts.ptr || c->L != cfg->n_hidden ||
+        c->H != cfg->width || c->norm != cfg->loss_norm || c->tau != cfg->tau || c->gamma != cfg->gamma) {
+        c->valid = false;
+        vpinn_problem *one[1] = {p};
+        vpinn_status st = build_plan(one, 1, cfg, p->device, c->plan);
+        if (st) return st;
+        c->valid = true;
+        c->n_bnd = p->n_bnd;
+        c->n_sen = p->n_sen;
+        c->pts = p->pts.ptr;
+        c->L = cfg->n_hidden;
+        c->H = cfg->width;
+        c->norm = cfg->loss_norm;
+        c->tau = cfg->tau;
+        c->gamma = cfg->gamma;
+    }
+    AdamArgs none{};
+    return run_plan(c->plan, d_params, d_eps, d_grad != nullptr, d_loss, d_grad, d_grad_eps, none, nullptr, s);
+}
+
+}  // namespace vp
+
+// ---------------------------------------------------------------------------
+// batches of independent problems
+// ---------------------------------------------------------------------------
+struct vpinn_batch {
+    int device = 0;
+    vpinn_loss_cfg cfg{};
+    vp::FusedPlan plan;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~vpinn_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+namespace vp {
+
+vpinn_status batch_create(int32_t n, vpinn_problem *const *problems, const vpinn_loss_cfg *cfg, vpinn_batch **out) {
+    vpinn_batch *b = new (std::nothrow) vpinn_batch();
+    if (!b) return fail(VPINN_E_NOMEM, "host allocation failed");
+    b->device = problems[0]->device;
+    b->cfg = *cfg;
+    vpinn_status st = build_plan(problems, n, cfg, b->device, b->plan);
+    if (st) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return VPINN_OK;
+}
+
+vpinn_status batch_loss_and_grad(vpinn_batch *b, const float *d_params, const float *d_eps, float *d_losses,
+                                 float *d_grads, float *d_grad_eps, hipStream_t s) {
+    AdamArgs none{};
+    return run_plan(b->plan, d_params, d_eps, d_grads != nullptr || d_grad_eps != nullptr, d_losses, d_grads,
+                    d_grad_eps, none, nullptr, s);
+}
+
+vpinn_status batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr, float b1,
+                        float b2, float eps, float *d_losses, hipStream_t s) {
+    AdamArgs ad{d_params, d_m, d_v, d_step, lr, b1, b2, eps};
+    return run_plan(b->plan, d_params, nullptr, true, d_losses, nullptr, nullptr, ad, d_step, s);
+}
+
+vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
+                           float b1, float b2, float eps, float *d_losses, hipStream_t s) {
+    if (!s) return fail(VPINN_E_INVALID, "capture needs a non-null stream");
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    VP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    vpinn_status st = batch_step(b, d_params, d_m, d_v, d_step, lr, b1, b2, eps, d_losses, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    b->graph = g;
+    VP_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return VPINN_OK;
+}
+
+int batch_device(const vpinn_batch *b) { return b->device; }
+
+void batch_destroy(vpinn_batch *b) { delete b; }
+
+vpinn_status batch_replay(vpinn_batch *b, hipStream_t s) {
+    if (!b->exec) return fail(VPINN_E_INVALID, "no captured step: call vpinn_batch_capture first");
+    VP_HIP(hipGraphLaunch(b->exec, s));
     return VPINN_OK;
 }
 

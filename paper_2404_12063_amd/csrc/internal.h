@@ -108,5 +108,15 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
                              hipStream_t s);
 vpinn_status adam_step(int64_t n, float *p, const float *g, float *m, float *v, int64_t step, float lr,
                        float b1, float b2, float eps, hipStream_t s);
+vpinn_status batch_create(int32_t n, vpinn_problem *const *problems, const vpinn_loss_cfg *cfg, vpinn_batch **out);
+vpinn_status batch_loss_and_grad(vpinn_batch *b, const float *d_params, const float *d_eps, float *d_losses,
+                                 float *d_grads, float *d_grad_eps, hipStream_t s);
+vpinn_status batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr, float b1,
+                        float b2, float eps, float *d_losses, hipStream_t s);
+vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
+                           float b1, float b2, float eps, float *d_losses, hipStream_t s);
+vpinn_status batch_replay(vpinn_batch *b, hipStream_t s);
+int batch_device(const vpinn_batch *b);
+void batch_destroy(vpinn_batch *b);
 
 }  // namespace vp

@@ -82,6 +82,16 @@ _SIGNATURES = {
                                        C.c_void_p, C.c_void_p, C.c_void_p]),
     "vpinn_adam_step": (C.c_int32, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]),
+    "vpinn_batch_create": (C.c_int32, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vpinn_loss_cfg),
+                                       C.POINTER(C.c_void_p)]),
+    "vpinn_batch_loss_and_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_void_p]),
+    "vpinn_batch_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
+                                     C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
+    "vpinn_batch_capture": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
+                                        C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
+    "vpinn_batch_replay": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "vpinn_batch_free": (None, [C.c_void_p]),
     "vpinn_problem_free": (None, [C.c_void_p]),
     "vpinn_last_error": (C.c_char_p, []),
 }
@@ -222,3 +232,45 @@ def vpinn_adam_step(params, grad, m, v, step: int, lr: float = 1e-3, beta1: floa
                     eps: float = 1e-8, stream=None):
     _check(lib().vpinn_adam_step(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1,
                                  beta2, eps, _stream(stream)))
+
+
+class Batch:
+    """Owner of a vpinn_batch handle; keeps its problems alive."""
+
+    def __init__(self, handle: int, problems):
+        self.handle = handle
+        self.problems = list(problems)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.vpinn_batch_free(self.handle)
+            self.handle = None
+
+
+def vpinn_batch_create(problems, cfg: vpinn_loss_cfg) -> Batch:
+    arr = (C.c_void_p * len(problems))(*[p.handle for p in problems])
+    out = C.c_void_p()
+    _check(lib().vpinn_batch_create(len(problems), arr, C.byref(cfg), C.byref(out)))
+    return Batch(out.value, problems)
+
+
+def vpinn_batch_loss_and_grad(b: Batch, params, eps=None, losses=None, grads=None, grad_eps=None, stream=None):
+    _check(lib().vpinn_batch_loss_and_grad(b.handle, _ptr(params), _ptr(eps), _ptr(losses), _ptr(grads),
+                                           _ptr(grad_eps), _stream(stream)))
+
+
+def vpinn_batch_step(b: Batch, params, m, v, step, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                     eps: float = 1e-8, losses=None, stream=None):
+    """step: device int64 tensor of one element (incremented by the call)."""
+    _check(lib().vpinn_batch_step(b.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(step), lr, beta1, beta2, eps,
+                                  _ptr(losses), _stream(stream)))
+
+
+def vpinn_batch_capture(b: Batch, params, m, v, step, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                        eps: float = 1e-8, losses=None, stream=None):
+    _check(lib().vpinn_batch_capture(b.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(step), lr, beta1, beta2, eps,
+                                     _ptr(losses), _stream(stream)))
+
+
+def vpinn_batch_replay(b: Batch, stream=None):
+    _check(lib().vpinn_batch_replay(b.handle, _stream(stream)))
