@@ -27,6 +27,16 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 (vector and matrix) peak
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 
+def flops_split(prob):
+    """Algorithmic FLOPs of (forward + contraction + its adjoint, reverse sweep through the network)."""
+    H, L = prob.width, prob.n_hidden
+    nt = prob.test_order ** 2
+    n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
+    fwd = prob.n_points * (2 * H + 3 * (L - 1) * H * H + 2 * H + 4 * nt) + n_extra * (3 * H + (L - 1) * H * H)
+    bwd = prob.n_points * (2 * H + 6 * (L - 1) * H * H + 4 * H) + n_extra * (3 * H + 2 * (L - 1) * H * H)
+    return 2.0 * fwd, 2.0 * bwd
+
+
 def flops_per_epoch(prob) -> float:
     """Algorithmic FLOPs of one forward+adjoint epoch: 2 x the multiply-adds of the dense products.
 
@@ -71,7 +81,55 @@ def traffic_from_profile(kernel: str):
     return entry.get("hbm_bytes_per_launch")
 
 
+COPY_PROBE_BYTES = 256 << 20
+
+
+def _pmc_rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def write_traffic(fetch_csv: str, write_csv: str):
+    """Scale the per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the fused kernel by what the same
+    counters read for the 256 MiB copy (known: 256 MiB read, 256 MiB written)."""
+    def per_kernel(path, counter):
+        vals = {}
+        for r in _pmc_rows(path):
+            if r.get("Counter_Name") != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    def copy_kib(vals):
+        # the copy dispatches are the ones near 256 MiB; take their median
+        cand = sorted(v for k, vs in vals.items() for v in vs if 0.5 * (COPY_PROBE_BYTES >> 10) < v < 2.0 * (COPY_PROBE_BYTES >> 10))
+        return cand[len(cand) // 2]
+    f_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(fetch)
+    w_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(write)
+    out = {}
+    for name, key in [("k_bwd", "k_bwd<3>"), ("k_fwd_contract", "k_fwd_contract<3>")]:
+        fk = [v for k, vs in fetch.items() if key in k for v in vs]
+        wk = [v for k, vs in write.items() if key in k for v in vs]
+        if not fk or not wk:
+            continue
+        fk.sort()
+        wk.sort()
+        fb = fk[len(fk) // 2] * 1024.0 * f_scale
+        wb = wk[len(wk) // 2] * 1024.0 * w_scale
+        out[name] = {"source_digest": source_digest(), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                     "hbm_bytes_per_launch": fb + wb, "fetch_scale": f_scale, "write_scale": w_scale,
+                     "dispatches": len(fk)}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
+    """Eager steps: vpinn_loss_and_grad then vpinn_adam_step.  On the fused path the library records
+    events between its kernels, which gives the per-kernel durations of every timed step."""
     dev = torch.device("cuda:0")
     n = V.vpinn_n_params(prob.width, prob.n_hidden)
     th = torch.tensor(theta, dtype=torch.float32, device=dev)
@@ -81,30 +139,71 @@ def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
     loss = torch.zeros(4, dtype=torch.float32, device=dev)
     cfg = V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma, V.VPINN_NORM_TEST, path)
     stream = torch.cuda.current_stream()
+    fused = path == V.VPINN_PATH_FUSED
     t = 0
     for _ in range(warmup):
         t += 1
         V.vpinn_loss_and_grad(p, cfg, th, loss=loss, grad=g, stream=stream)
         V.vpinn_adam_step(th, g, m, v, t, lr=1e-3, stream=stream)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    for e in ev:
+        for x in e:
+            x.record(stream)  # creates the underlying events before their handles are handed over
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     for i in range(steps):
         t += 1
-        ev[i][0].record(stream)
+        if fused:
+            V.vpinn_set_profile_events(p, ev[i][:4])
+        else:
+            ev[i][0].record(stream)
         V.vpinn_loss_and_grad(p, cfg, th, loss=loss, grad=g, stream=stream)
-        ev[i][1].record(stream)
+        if not fused:
+            ev[i][3].record(stream)
         V.vpinn_adam_step(th, g, m, v, t, lr=1e-3, stream=stream)
-        ev[i][2].record(stream)
+        ev[i][4].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    lg = sorted(a.elapsed_time(b) for a, b, _ in ev)
-    st = sorted(a.elapsed_time(c) for a, _, c in ev)
+    if fused:
+        V.vpinn_set_profile_events(p, None)
+    mean = lambda xs: sum(xs) / len(xs)  # noqa: E731
+    out = {"wall_s": wall, "lg_ms_mean": mean([e[0].elapsed_time(e[3]) for e in ev]),
+           "step_ms_mean": mean([e[0].elapsed_time(e[4]) for e in ev])}
+    if fused:
+        out["k_fwd_contract_ms"] = mean([e[0].elapsed_time(e[1]) for e in ev])
+        out["k_bwd_ms"] = mean([e[1].elapsed_time(e[2]) for e in ev])
+        out["k_final_ms"] = mean([e[2].elapsed_time(e[3]) for e in ev])
+    return out
+
+
+def time_graph(V, torch, p, prob, theta, steps: int, warmup: int):
+    """The headline step: one problem as a batch of one, forward + adjoint + Adam (Adam inside the
+    reduction kernel, step counter in device memory) captured once in a HIP graph and replayed."""
+    dev = torch.device("cuda:0")
+    b = V.vpinn_batch_create([p], V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma))
+    th = torch.tensor(theta, dtype=torch.float32, device=dev).reshape(1, -1).contiguous()
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    step = torch.zeros(1, dtype=torch.int64, device=dev)
+    losses = torch.zeros((1, 4), dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        V.vpinn_batch_capture(b, th, m, v, step, lr=1e-3, losses=losses, stream=s)
+        for _ in range(warmup):
+            V.vpinn_batch_replay(b, stream=s)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i in range(steps):
+            ev[i][0].record(s)
+            V.vpinn_batch_replay(b, stream=s)
+            ev[i][1].record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+    st = sorted(a.elapsed_time(c) for a, c in ev)
     q = lambda xs, f: xs[min(len(xs) - 1, int(f * len(xs)))]  # noqa: E731
-    return {"wall_s": wall, "lg_ms_mean": sum(lg) / len(lg), "lg_ms_p50": q(lg, 0.5),
-            "step_ms_p10": q(st, 0.1), "step_ms_p50": q(st, 0.5), "step_ms_p90": q(st, 0.9),
-            "final_loss": float(loss[0].item()), "theta0": theta}
+    return {"wall_s": wall, "step_ms_p10": q(st, 0.1), "step_ms_p50": q(st, 0.5), "step_ms_p90": q(st, 0.9),
+            "steps_done": int(step.item()), "final_loss": float(losses[0, 0].item())}
 
 
 def cpu_baseline(prob, theta, seconds: float):
@@ -229,7 +328,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
     ap.add_argument("--workload", choices=["c2", "c5"], default="c2")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy a 256 MiB device buffer 3 times: a kernel of known traffic that calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then "
+                         "WRITE_SIZE, taken with --copy-probe) into profiles/traffic.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
@@ -240,6 +348,13 @@ def main():
     import vpinn_inputs as gen
 
     assert torch.cuda.is_available(), "needs a HIP device"
+    if args.copy_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "c5":
         bench_batched(args, V, torch, gen)
         return
@@ -252,12 +367,20 @@ def main():
           f"{len(prob.bnd_xy)} boundary points", file=sys.stderr, flush=True)
 
     main_path = V.VPINN_PATH_FUSED if args.path == "fused" else V.VPINN_PATH_PLAIN
-    res = time_path(V, torch, p, prob, theta, main_path, args.steps, args.warmup)
-    print(f"[bench] {args.path}: {res['wall_s'] / args.steps * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
+    fused = main_path == V.VPINN_PATH_FUSED
+    eager_steps = min(args.steps, 300)
+    eager = time_path(V, torch, p, prob, theta, main_path, eager_steps, args.warmup)
+    print(f"[bench] {args.path} eager: {eager['wall_s'] / eager_steps * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
+    if fused:
+        res = time_graph(V, torch, p, prob, theta, args.steps, args.warmup)
+        assert res["steps_done"] == args.warmup + args.steps
+        print(f"[bench] fused graph: {res['wall_s'] / args.steps * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
+    else:
+        res = {"wall_s": eager["wall_s"] * args.steps / eager_steps}
     plain = None
-    if not args.no_plain and main_path != V.VPINN_PATH_PLAIN:
+    if not args.no_plain and fused:
         plain = time_path(V, torch, p, prob, theta, V.VPINN_PATH_PLAIN, min(args.steps, 300), 20)
-        print(f"[bench] plain: {plain['wall_s'] / min(args.steps, 300) * 1e3:.4f} ms/step", file=sys.stderr,
+        print(f"[bench] plain eager: {plain['wall_s'] / min(args.steps, 300) * 1e3:.4f} ms/step", file=sys.stderr,
               flush=True)
 
     # loss parity at the initial parameters (one extra evaluation outside the timed region)
@@ -271,10 +394,13 @@ def main():
     ms = res["wall_s"] / args.steps * 1e3
     eps_s = 1e3 / ms
     flops = flops_per_epoch(prob)
-    kernel = "vpinn_fused" if main_path == V.VPINN_PATH_FUSED else "vpinn_plain_sequence"
-    lg_s = res["lg_ms_mean"] * 1e-3
-    achieved_tf = flops / lg_s / 1e12
-    traffic = traffic_from_profile(kernel)
+    f_fwd, f_bwd = flops_split(prob)
+    if fused:
+        kernel, k_ms, k_flops = "k_bwd (reverse sweep, MFMA)", eager["k_bwd_ms"], f_bwd
+    else:
+        kernel, k_ms, k_flops = "plain loss_and_grad sequence", eager["lg_ms_mean"], flops
+    achieved_tf = k_flops / (k_ms * 1e-3) / 1e12
+    traffic = traffic_from_profile("k_bwd") if fused else None
     out = {
         "metric": "epochs/s and Mquadpts/s fwd+adjoint, fused batched vs plain HIP, loss err<=1e-5",
         "value": round(eps_s, 3),
@@ -291,21 +417,29 @@ def main():
         "config": {"workload": "c2: Poisson -Lap u = f on [0,1]^2, 32x32 quad mesh with interior nodes "
                                "jittered +-20% h, 10x10 GLL points, 5x5 test functions, u*=sin(8pi x)sin(8pi y), "
                                "1600 boundary points, MLP 2-30-30-30-1 tanh, Adam lr 1e-3",
-                   "path": args.path, "n_elem": prob.n_elem, "quad_points": prob.n_points,
+                   "path": args.path + (" (HIP graph replay of the batch-of-one step)" if fused else " (eager)"),
+                   "n_elem": prob.n_elem, "quad_points": prob.n_points,
                    "boundary_points": len(prob.bnd_xy), "parallelism": "single GPU"},
         "mquadpts_per_s": round(prob.n_points * eps_s / 1e6, 2),
-        "step_ms_p10_p50_p90": [round(res["step_ms_p10"], 5), round(res["step_ms_p50"], 5),
-                                round(res["step_ms_p90"], 5)],
-        "roofline": {"bound": "mfma" if main_path == V.VPINN_PATH_FUSED else "alu",
+        "roofline": {"bound": "mfma" if fused else "alu",
                      "kernel": kernel,
                      "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4),
                      "traffic": traffic,
-                     "algorithmic_flop_per_launch": flops,
-                     "algorithmic_bytes_per_launch": bytes_per_epoch(prob),
-                     "launch_ms_mean": round(res["lg_ms_mean"], 5),
-                     "achieved_hbm_gbs": round(bytes_per_epoch(prob) / lg_s / 1e9, 1)},
+                     "algorithmic_flop_per_launch": k_flops,
+                     "launch_ms_mean": round(k_ms, 5)},
+        "whole_step": {"algorithmic_flop": flops, "algorithmic_bytes": bytes_per_epoch(prob),
+                       "achieved_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                       "frac_of_fp32_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+                       "effective_gbs": round(bytes_per_epoch(prob) / (ms * 1e-3) / 1e9, 1)},
     }
+    if fused:
+        out["step_ms_p10_p50_p90"] = [round(res["step_ms_p10"], 5), round(res["step_ms_p50"], 5),
+                                      round(res["step_ms_p90"], 5)]
+        out["eager"] = {"ms_per_step": round(eager["wall_s"] / eager_steps * 1e3, 5),
+                        "k_fwd_contract_ms": round(eager["k_fwd_contract_ms"], 5),
+                        "k_bwd_ms": round(eager["k_bwd_ms"], 5), "k_final_ms": round(eager["k_final_ms"], 5),
+                        "k_fwd_contract_tflops": round(f_fwd / (eager["k_fwd_contract_ms"] * 1e-3) / 1e12, 3)}
     if plain is not None:
         pms = plain["wall_s"] / min(args.steps, 300) * 1e3
         out["plain_hip"] = {"ms_per_step": round(pms, 5), "epochs_per_s": round(1e3 / pms, 3),

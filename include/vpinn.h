@@ -244,6 +244,17 @@ vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream);
 /* Release the batch (not the problems).  NULL is a no-op. */
 void vpinn_batch_free(vpinn_batch *b);
 
+/*
+ * Profiling hooks for the fused path: `events` points to 4 hipEvent_t (created by
+ * the caller with timing enabled; any may be NULL) recorded on the call's stream
+ * before the forward/contraction kernel, between it and the backward kernel,
+ * between the backward kernel and the reduction, and after the reduction, by
+ * every later vpinn_loss_and_grad (fused path) / batch call.  NULL disables.
+ * The events stay caller-owned.  A capture (vpinn_batch_capture) records none.
+ */
+vpinn_status vpinn_set_profile_events(vpinn_problem *p, void *const *events);
+vpinn_status vpinn_batch_set_profile_events(vpinn_batch *b, void *const *events);
+
 /* Release every device buffer of the problem.  NULL is a no-op. */
 void vpinn_problem_free(vpinn_problem *p);
 

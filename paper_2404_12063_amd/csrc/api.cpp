@@ -379,6 +379,20 @@ vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream) {
     return batch_replay(b, (hipStream_t)stream);
 }
 
+vpinn_status vpinn_set_profile_events(vpinn_problem *p, void *const *events) {
+    using namespace vp;
+    if (!p) return fail(VPINN_E_INVALID, "problem is null");
+    for (int i = 0; i < 4; ++i) p->prof[i] = events ? (hipEvent_t)events[i] : nullptr;
+    return VPINN_OK;
+}
+
+vpinn_status vpinn_batch_set_profile_events(vpinn_batch *b, void *const *events) {
+    using namespace vp;
+    if (!b) return fail(VPINN_E_INVALID, "batch is null");
+    batch_set_profile_events(b, events);
+    return VPINN_OK;
+}
+
 void vpinn_batch_free(vpinn_batch *b) {
     if (!b) return;
     vp::DeviceGuard dg(vp::batch_device(b));

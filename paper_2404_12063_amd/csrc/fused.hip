@@ -1,11 +1,14 @@
-// Fused single-launch FastVPINNs loss and gradient (Algorithm 3 and its backward
-// pass) on gfx950.
+// Fused FastVPINNs loss and gradient (Algorithm 3 and its backward pass) on
+// gfx950, for one problem or a batch of independent problems.
 //
-// One launch computes, for all quadrature, boundary and sensor points: network
-// values and spatial tangents, the contraction R = eps sum_q (u_x G_x + u_y G_y)
-// - F, the loss, the adjoint of the contraction, the reverse sweep through the
-// network, and the fixed-order reduction of every partial sum into the loss
-// and gradient outputs.
+// Three launches per evaluation: k_fwd_contract computes network values and
+// spatial tangents, the contraction R = eps sum_q (u_x G_x + u_y G_y) - F, the
+// loss terms and the adjoint of the contraction (dL/du per point, written to a
+// small device buffer); k_bwd runs the reverse sweep through the network for
+// tiles of 16 points spread evenly over all wavefronts; k_fused_final sums the
+// per-block partial rows in fixed order (and optionally applies Adam).  The
+// split gives each half its own register budget: three wavefronts per SIMD
+// without spills, where one kernel holding both halves needed 256 registers.
 //
 // Work decomposition.  A work item is a contiguous range of elements plus a
 // slice of the boundary/sensor points; 256-thread blocks (4 wavefronts, two
@@ -48,7 +51,8 @@ namespace vp {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFThreads = 256;
-constexpr int kFBlocksPerCU = 2;   // two co-resident blocks: one's contraction latency hides under the other's MFMAs
+constexpr int kFwdBlocksPerCU = 2;  // forward/contraction blocks resident per CU
+constexpr int kBwdBlocksPerCU = 2;  // backward blocks resident per CU (register-limited: ~250 VGPRs)
 constexpr int kFWaves = kFThreads / 64;
 constexpr int kTs = 36;            // transpose tile row stride (floats)
 constexpr int kMaxBlocks = 1024;
@@ -69,8 +73,9 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// network weights of the current instance in LDS
 template <int L>
-struct FusedShared {
+struct WeightsShared {
     // A-operand fragments of the hidden-to-hidden products, layers 2..L:
     // [layer][dir 0 = W (forward), 1 = W^T (backward)][out tile][k step][lane]
     float wf[L > 1 ? L - 1 : 1][2][2][8][64];
@@ -78,10 +83,24 @@ struct FusedShared {
     float b[L][PW];
     float wo[PW];
     float bo;
-    // per-wavefront transpose tiles [2][16 points][kTs]
-    float tt[kFWaves][2][16][kTs];
+};
+
+template <int L>
+struct FwdShared {
+    WeightsShared<L> W;
     // per-wavefront loss partials: sum R^2, sum R A, sum d_b^2, sum d_s^2
     double lp[kFWaves][4];
+};
+
+template <int L>
+struct BwdShared {
+    WeightsShared<L> W;
+    // per-wavefront transpose tiles [2][16 points][kTs]
+    float tt[kFWaves][2][16][kTs];
+    // per-wavefront column sums of the vector-shaped gradients, one slot per lane:
+    // [0, L) biases b_l, L: W1 column 0, L+1: W1 column 1, L+2: W_out, L+3: b_out
+    float vacc[kFWaves][L + 4][64];
+    float red[n_padded(L)];
 };
 
 // static description of one problem instance (device resident)
@@ -90,16 +109,19 @@ struct InstDesc {
     const float2 *pts;        // interior points then boundary then sensors
     const float *tgt;         // boundary values then sensor observations
     int64_t n_elem, n_pts, n_bnd, n_sen;
-    int64_t n_items, item0;   // items item0 .. item0 + n_items - 1 of the global list
+    int64_t n_items, item0;   // forward items item0 .. item0 + n_items - 1 of the global item list
+    int64_t n_tiles, tile0;   // backward tiles (16 points each) tile0 .. of the global tile list
+    int64_t ubase;            // offset of this instance's points in the adjoint buffer
     int nq, ntest;
     int fast;                 // nq <= kFThreads and ntest <= kKB: G stays in registers
-    int row0, blk0, n_rows;   // partial rows row0.. (one per block blk0 .. blk0 + n_rows - 1)
+    int lrow0, lblk0, ln_rows;  // loss partial rows (forward blocks lblk0 ..)
+    int grow0, gblk0, gn_rows;  // gradient partial rows (backward blocks gblk0 ..)
     float two_cv, wb2, ws2;   // 2 c_v, 2 tau / N_D, 2 gamma / N_s
     float tau, gamma;
     double cv;
 };
 
-struct FusedArgs {
+struct FwdArgs {
     const InstDesc *inst;
     const int *item_inst;       // [items] instance of each global item (instance-major order)
     const int64_t *blk_items;   // [blocks + 1] global item range of each block
@@ -109,9 +131,20 @@ struct FusedArgs {
     int H;
     int want_grad;
     int item_cap_pts;           // LDS capacity for item points
-    float *gpart;               // [rows][kMaxPadded]
-    double *lpart;              // [rows][4]
+    float2 *ubuf;               // adjoints dL/du_x, dL/du_y (interior) or dL/du (boundary, sensors)
+    double *lpart;              // [loss rows][4]
     int64_t *step;              // optional step counter, incremented once per launch
+};
+
+struct BwdArgs {
+    const InstDesc *inst;
+    const int64_t *blk_tiles;   // [blocks + 1] global tile range of each block
+    const int *blk_inst0;       // instance of each block's first tile
+    const float *params;
+    int64_t param_stride;
+    int H;
+    const float2 *ubuf;
+    float *gpart;               // [gradient rows][kMaxPadded]
 };
 
 // element and extra-point ranges of item i of an instance (even split, no work list needed)
@@ -137,7 +170,7 @@ struct Acts {
 };
 
 template <int L, bool KEEP>
-__device__ __forceinline__ void tile_forward(const FusedShared<L> &S, int lane, float x, float y, Vec &A_, Vec &TX,
+__device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane, float x, float y, Vec &A_, Vec &TX,
                                              Vec &TY, Acts<L> &keep) {
     const int g = lane >> 4;
 #pragma unroll
@@ -198,7 +231,7 @@ __device__ __forceinline__ float group_sum(float v) {
 }
 
 template <int L>
-__device__ __forceinline__ void tile_outputs(const FusedShared<L> &S, int lane, const Vec &A_, const Vec &TX,
+__device__ __forceinline__ void tile_outputs(const WeightsShared<L> &S, int lane, const Vec &A_, const Vec &TX,
                                              const Vec &TY, float &u, float &ux, float &uy) {
     const int g = lane >> 4;
     float su = 0.f, sx = 0.f, sy = 0.f;
@@ -261,20 +294,59 @@ __device__ __forceinline__ float colsum_vec(float (*T0)[kTs], int lane, const Ve
     return s;
 }
 
-// gradient accumulators of one wavefront
+// gradient accumulators of one wavefront: the hidden-to-hidden weight tiles of
+// layers 2..L in registers (MFMA accumulators); the vector-shaped gradients are
+// column sums kept in LDS (FusedShared::vacc) to spare registers
 template <int L>
 struct GradAcc {
-    f4 w[L > 1 ? L - 1 : 1][4];  // hidden-to-hidden weight tiles, layers 2..L
-    float b[L];                   // bias columns (lane % 32), per half-wave
-    float w1c0, w1c1;             // W1 columns
-    float wo;                     // W_out column
-    float bo;                     // b_out (lanes with g == 0)
+    f4 w[L > 1 ? L - 1 : 1][4];
 };
 
+// write the tangent s * p of a stored layer (s = 1 - a^2) transposed into T
+__device__ __forceinline__ void put_t_tangent(float (*T)[kTs], int lane, const Vec &a, const Vec &p) {
+    const int j = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        f4 t;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t[r] = (1.0f - a.v[m][r] * a.v[m][r]) * p.v[m][r];
+        *reinterpret_cast<f4 *>(&T[j][16 * m + 4 * g]) = t;
+    }
+}
+
+// layer-1 tangent s_1 * W1[:, col] transposed into T
 template <int L>
-__device__ __forceinline__ void tile_backward(const FusedShared<L> &S, float (*T0)[kTs], float (*T1)[kTs], int lane,
+__device__ __forceinline__ void put_t_tangent1(float (*T)[kTs], int lane, const Vec &a, const WeightsShared<L> &S,
+                                               int col) {
+    const int j = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        f4 t;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t[r] = (1.0f - a.v[m][r] * a.v[m][r]) * S.w1[16 * m + 4 * g + r][col];
+        *reinterpret_cast<f4 *>(&T[j][16 * m + 4 * g]) = t;
+    }
+}
+
+// T0 holds the out-side vector, T1 the in-side one: dW += sum over points (MFMA, K = points)
+__device__ __forceinline__ void wgrad_from_tiles(float (*T0)[kTs], float (*T1)[kTs], int lane, f4 acc[4]) {
+    wave_sync();
+    const int c = lane & 15, k = lane >> 4;
+#pragma unroll
+    for (int kp = 0; kp < 4; ++kp) {
+        const float a0 = T0[4 * kp + k][c], a1 = T0[4 * kp + k][16 + c];
+        const float b0 = T1[4 * kp + k][c], b1 = T1[4 * kp + k][16 + c];
+        acc[0] = mfma(a0, b0, acc[0]);
+        acc[1] = mfma(a0, b1, acc[1]);
+        acc[2] = mfma(a1, b0, acc[2]);
+        acc[3] = mfma(a1, b1, acc[3]);
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[kTs], float (*T1)[kTs], int lane,
                                               float x, float y, float ub, float uxb, float uyb, const Acts<L> &K,
-                                              GradAcc<L> &G) {
+                                              GradAcc<L> &G, float (*VA)[64]) {
     const int g = lane >> 4;
     Vec abar, txbar, tybar;
     {
@@ -301,8 +373,8 @@ __device__ __forceinline__ void tile_backward(const FusedShared<L> &S, float (*T
                 txbar.v[m][r] = uxb * w;
                 tybar.v[m][r] = uyb * w;
             }
-        G.wo += colsum_vec(T0, lane, v);
-        if (g == 0) G.bo += ub;
+        VA[L + 2][lane] += colsum_vec(T0, lane, v);
+        if (g == 0) VA[L + 3][lane] += ub;
     }
 #pragma unroll
     for (int l = L; l >= 2; --l) {
@@ -319,28 +391,23 @@ __device__ __forceinline__ void tile_backward(const FusedShared<L> &S, float (*T
                 const float sbar = txbar.v[m][r] * K.px[l - 1].v[m][r] + tybar.v[m][r] * K.py[l - 1].v[m][r];
                 zb.v[m][r] = s * (abar.v[m][r] - 2.0f * a * sbar);
             }
-        // inputs of layer l: a_{l-1} and t_{l-1} = s_{l-1} p_{l-1} (layer 1: s_1 times W1 column)
-        Vec ai, ti_x, ti_y;
-        const Vec &ap = K.a[l - 2];
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float a = ap.v[m][r];
-                const float s = 1.0f - a * a;
-                ai.v[m][r] = a;
-                if (l - 1 == 1) {
-                    const int n = 16 * m + 4 * g + r;
-                    ti_x.v[m][r] = s * S.w1[n][0];
-                    ti_y.v[m][r] = s * S.w1[n][1];
-                } else {
-                    ti_x.v[m][r] = s * K.px[l - 2].v[m][r];
-                    ti_y.v[m][r] = s * K.py[l - 2].v[m][r];
-                }
-            }
-        wgrad(T0, T1, lane, zb, ai, G.w[l - 2], &G.b[l - 1]);
-        wgrad(T0, T1, lane, pxb, ti_x, G.w[l - 2], nullptr);
-        wgrad(T0, T1, lane, pyb, ti_y, G.w[l - 2], nullptr);
+        // weight gradient with the inputs of layer l: a_{l-1} and t_{l-1} = s_{l-1} p_{l-1}
+        // (layer 1: s_1 times a W1 column), formed while writing the transpose tile
+        put_t(T0, lane, zb);
+        put_t(T1, lane, K.a[l - 2]);
+        wgrad_from_tiles(T0, T1, lane, G.w[l - 2]);
+        VA[l - 1][lane] += col_sum(T0, lane);
+        wave_sync();
+        put_t(T0, lane, pxb);
+        if (l - 1 == 1) put_t_tangent1<L>(T1, lane, K.a[0], S, 0);
+        else put_t_tangent(T1, lane, K.a[l - 2], K.px[l - 2]);
+        wgrad_from_tiles(T0, T1, lane, G.w[l - 2]);
+        wave_sync();
+        put_t(T0, lane, pyb);
+        if (l - 1 == 1) put_t_tangent1<L>(T1, lane, K.a[0], S, 1);
+        else put_t_tangent(T1, lane, K.a[l - 2], K.py[l - 2]);
+        wgrad_from_tiles(T0, T1, lane, G.w[l - 2]);
+        wave_sync();
         // propagate: abar = W_l^T zbar, tbar = W_l^T pbar
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
@@ -376,19 +443,18 @@ __device__ __forceinline__ void tile_backward(const FusedShared<L> &S, float (*T
                 c0.v[m][r] = fmaf(z, x, pxb);
                 c1.v[m][r] = fmaf(z, y, pyb);
             }
-        G.w1c0 += colsum_vec(T0, lane, c0);
-        G.w1c1 += colsum_vec(T0, lane, c1);
-        G.b[0] += colsum_vec(T0, lane, zb);
+        VA[L][lane] += colsum_vec(T0, lane, c0);
+        VA[L + 1][lane] += colsum_vec(T0, lane, c1);
+        VA[0][lane] += colsum_vec(T0, lane, zb);
     }
 }
 
 // ---------------------------------------------------------------------------
-// the fused kernel
+// kernels
 // ---------------------------------------------------------------------------
 // weights of one instance -> LDS (padded to 32, fragment order for the MFMA A operands)
 template <int L>
-__device__ __forceinline__ void load_weights(FusedShared<L> &S, const float *__restrict__ P, int H, int tid) {
-    // weights -> LDS (padded to 32, fragment order for the MFMA A operands)
+__device__ __forceinline__ void load_weights(WeightsShared<L> &S, const float *__restrict__ P, int H, int tid) {
     for (int t = tid; t < PW * 2; t += kFThreads) {
         const int o = t >> 1, i = t & 1;
         S.w1[o][i] = o < H ? P[o * 2 + i] : 0.f;
@@ -416,101 +482,34 @@ __device__ __forceinline__ void zero_acc(GradAcc<L> &G) {
     for (int l = 0; l < (L > 1 ? L - 1 : 1); ++l)
 #pragma unroll
         for (int t = 0; t < 4; ++t) G.w[l][t] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int l = 0; l < L; ++l) G.b[l] = 0.f;
-    G.w1c0 = G.w1c1 = G.wo = G.bo = 0.f;
 }
 
-// the block's sums for one instance -> partial row `row`; accumulators reset
+// the block's loss sums for one instance -> loss row `row`
 template <int L>
-__device__ __forceinline__ void flush(FusedShared<L> &S, float *dyn, const FusedArgs &A, int64_t row, GradAcc<L> &G,
-                                      double &lrr, double &lra, double &lbb, double &lss, int tid, int wave,
-                                      int lane) {
-    // ---- block partial: loss terms (double) and the padded gradient row ----
-    {
-        double v0 = wave_sum(lrr), v1 = wave_sum(lra), v2 = wave_sum(lbb), v3 = wave_sum(lss);
-        if (lane == 0) {
-            S.lp[wave][0] = v0;
-            S.lp[wave][1] = v1;
-            S.lp[wave][2] = v2;
-            S.lp[wave][3] = v3;
-        }
-    }
-    float *red = dyn;  // n_padded(L) floats (dynamic LDS is at least this large)
-    const int g = lane >> 4, c = lane & 15;
-    // this lane's (padded index, value) pairs; waves add them in wave order
-    constexpr int NW = 16 * (L - 1), NV = NW + L + 4;
-    int pidx[NV];
-    float pval[NV];
-    {
-        int n = 0;
-#pragma unroll
-        for (int l = 2; l <= L; ++l)
-#pragma unroll
-            for (int mo = 0; mo < 2; ++mo)
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        pidx[n] = off_w(l) + (16 * mo + 4 * g + r) * PW + 16 * mi + c;
-                        pval[n++] = G.w[l - 2][mo * 2 + mi][r];
-                    }
-        const bool lo = lane < 32;
-#pragma unroll
-        for (int l = 1; l <= L; ++l) {
-            pidx[n] = lo ? off_b(l) + lane : -1;
-            pval[n++] = G.b[l - 1] + __shfl_xor(G.b[l - 1], 32, 64);
-        }
-        pidx[n] = lo ? off_w(1) + 2 * lane : -1;
-        pval[n++] = G.w1c0 + __shfl_xor(G.w1c0, 32, 64);
-        pidx[n] = lo ? off_w(1) + 2 * lane + 1 : -1;
-        pval[n++] = G.w1c1 + __shfl_xor(G.w1c1, 32, 64);
-        pidx[n] = lo ? off_wout(L) + lane : -1;
-        pval[n++] = G.wo + __shfl_xor(G.wo, 32, 64);
-        const float bo = wave_sum(G.bo);
-        pidx[n] = lane == 0 ? off_wout(L) + PW : -1;
-        pval[n++] = bo;
-    }
-    for (int w = 0; w < kFWaves; ++w) {
-        if (wave == w && A.want_grad) {
-            float cur[NV];
-#pragma unroll
-            for (int i = 0; i < NV; ++i) cur[i] = (w > 0 && pidx[i] >= 0) ? red[pidx[i]] : 0.f;
-#pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (pidx[i] >= 0) red[pidx[i]] = cur[i] + pval[i];
-        }
-        __syncthreads();
-    }
-    const int NP = n_padded(L);
-    if (A.want_grad)
-        for (int j = tid; j < NP; j += kFThreads) A.gpart[(int64_t)row * kMaxPadded + j] = red[j];
+__device__ __forceinline__ void flush_loss(FwdShared<L> &S, const FwdArgs &A, int64_t row, int tid) {
+    __syncthreads();
     if (tid < 4) {
         double s = 0.0;
         for (int w = 0; w < kFWaves; ++w) s += S.lp[w][tid];
-        A.lpart[(int64_t)row * 4 + tid] = s;
+        A.lpart[row * 4 + tid] = s;
     }
-    zero_acc<L>(G);
-    lrr = lra = lbb = lss = 0.0;
+    __syncthreads();
+    if (tid < kFWaves * 4) (&S.lp[0][0])[tid] = 0.0;
     __syncthreads();
 }
 
+// 1-3: forward values and tangents, contraction, loss terms and the adjoint of the
+// contraction, per item (a contiguous range of elements and boundary/sensor points)
 template <int L>
-__global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A) {
-    __shared__ FusedShared<L> S;
+__global__ __launch_bounds__(kFThreads, kFwdBlocksPerCU) void k_fwd_contract(FwdArgs A) {
+    __shared__ FwdShared<L> S;
     extern __shared__ float dyn[];  // item data: float2 per item point, then 2 c_v R per (element, test)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int H = A.H;
     if (A.step && blockIdx.x == 0 && tid == 0) *A.step += 1;
-
     float2 *uxy = reinterpret_cast<float2 *>(dyn);
     float *rbar = dyn + 2 * A.item_cap_pts;
-    float(*T0)[kTs] = S.tt[wave][0];
-    float(*T1)[kTs] = S.tt[wave][1];
-
-    GradAcc<L> G;
-    zero_acc<L>(G);
-    double lrr = 0.0, lra = 0.0, lbb = 0.0, lss = 0.0;  // per-thread loss partials
+    if (tid < kFWaves * 4) (&S.lp[0][0])[tid] = 0.0;
     int cur = -1;
     InstDesc I;
     float eps = 1.0f;
@@ -518,16 +517,16 @@ __global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A)
     for (int64_t git = it_begin; git < it_end; ++git) {
         const int inst = A.item_inst[git];
         if (inst != cur) {
-            if (cur >= 0) flush<L>(S, dyn, A, I.row0 + (int64_t)(blockIdx.x - I.blk0), G, lrr, lra, lbb, lss, tid,
-                                   wave, lane);
+            if (cur >= 0) flush_loss<L>(S, A, I.lrow0 + (int64_t)(blockIdx.x - I.lblk0), tid);
             cur = inst;
             I = A.inst[inst];
             eps = A.eps ? A.eps[inst] : 1.0f;
             __syncthreads();
-            load_weights<L>(S, A.params + (int64_t)inst * A.param_stride, H, tid);
+            load_weights<L>(S.W, A.params + (int64_t)inst * A.param_stride, H, tid);
             __syncthreads();
         }
         const int64_t item = git - I.item0;
+        double lrr = 0.0, lra = 0.0, lbb = 0.0, lss = 0.0;  // this item's loss partials (per thread)
         int64_t e0, e1, x0, x1;
         item_range(I, item, e0, e1, x0, x1);
         const int ne = (int)(e1 - e0);
@@ -549,9 +548,9 @@ __global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A)
             const float2 p = valid ? point_xy(idx) : make_float2(0.f, 0.f);
             Vec a, tx, ty;
             Acts<L> unused;
-            tile_forward<L, false>(S, lane, p.x, p.y, a, tx, ty, unused);
+            tile_forward<L, false>(S.W, lane, p.x, p.y, a, tx, ty, unused);
             float u, ux, uy;
-            tile_outputs<L>(S, lane, a, tx, ty, u, ux, uy);
+            tile_outputs<L>(S.W, lane, a, tx, ty, u, ux, uy);
             if (valid && lane < 16) uxy[idx] = idx < n_int ? make_float2(ux, uy) : make_float2(u, 0.f);
         }
         __syncthreads();
@@ -681,11 +680,17 @@ __global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A)
             else lss += (double)d * (double)d;
             uxy[idx] = make_float2((bnd ? I.wb2 : I.ws2) * d, 0.f);
         }
-        __syncthreads();
-        if (!A.want_grad) {
-            __syncthreads();
-            continue;
+        {
+            const double v0 = wave_sum(lrr), v1 = wave_sum(lra), v2 = wave_sum(lbb), v3 = wave_sum(lss);
+            if (lane == 0) {
+                S.lp[wave][0] += v0;
+                S.lp[wave][1] += v1;
+                S.lp[wave][2] += v2;
+                S.lp[wave][3] += v3;
+            }
         }
+        __syncthreads();
+        if (A.want_grad) {
 
         // 3. adjoint of the contraction (generic path), thread per point, 16 tests per batch
         for (int idx = tid; idx < (I.fast ? 0 : n_int); idx += kFThreads) {
@@ -711,32 +716,114 @@ __global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A)
             }
             uxy[idx] = make_float2(eps * bx, eps * by);
         }
-        __syncthreads();
-
-        // 4. backward with recompute
-        for (int t = wrot; t < n_tiles; t += kFWaves) {
-            const int idx = 16 * t + (lane & 15);
-            const bool valid = idx < n_all;
-            const float2 p = valid ? point_xy(idx) : make_float2(0.f, 0.f);
-            float ub = 0.f, uxb = 0.f, uyb = 0.f;
-            if (valid) {
-                const float2 d = uxy[idx];
-                if (idx < n_int) {
-                    uxb = d.x;
-                    uyb = d.y;
-                } else {
-                    ub = d.x;
-                }
+            __syncthreads();
+            // adjoints of the item's points -> the instance's slice of the adjoint buffer
+            for (int idx = tid; idx < n_all; idx += kFThreads) {
+                const int64_t pi = idx < n_int ? e0 * I.nq + idx : I.n_pts + x0 + (idx - n_int);
+                A.ubuf[I.ubase + pi] = uxy[idx];
             }
-            Acts<L> K;
-            Vec a, tx, ty;
-            tile_forward<L, true>(S, lane, p.x, p.y, a, tx, ty, K);
-            tile_backward<L>(S, T0, T1, lane, p.x, p.y, ub, uxb, uyb, K, G);
         }
         __syncthreads();
     }
-    if (cur >= 0)
-        flush<L>(S, dyn, A, I.row0 + (int64_t)(blockIdx.x - I.blk0), G, lrr, lra, lbb, lss, tid, wave, lane);
+    if (cur >= 0) flush_loss<L>(S, A, I.lrow0 + (int64_t)(blockIdx.x - I.lblk0), tid);
+}
+
+// the block's gradient sums for one instance -> gradient row `row`; accumulators reset
+template <int L>
+__device__ __forceinline__ void flush_grad(BwdShared<L> &S, const BwdArgs &A, int64_t row, GradAcc<L> &G, int tid,
+                                           int wave, int lane) {
+    __syncthreads();
+    float *red = S.red;
+    const int g = lane >> 4, c = lane & 15;
+    const bool lo = lane < 32;
+    const float(*VA)[64] = S.vacc[wave];
+    const int hi = lane ^ 32;
+    // waves add their sums into red in wave order; each lane streams its values in
+    // batches of four (all reads of a batch issued before its writes)
+    for (int w = 0; w < kFWaves; ++w) {
+        if (wave == w) {
+            const bool first = (w == 0);
+#pragma unroll
+            for (int l = 2; l <= L; ++l)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int mo = t >> 1, mi = t & 1;
+                    int id[4];
+                    float curv[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) id[r] = off_w(l) + (16 * mo + 4 * g + r) * PW + 16 * mi + c;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) curv[r] = first ? 0.f : red[id[r]];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) red[id[r]] = curv[r] + G.w[l - 2][t][r];
+                }
+            const float bo = wave_sum(VA[L + 3][lane]);
+            if (lo) {
+#pragma unroll
+                for (int l = 1; l <= L; ++l) {
+                    const float v = VA[l - 1][lane] + VA[l - 1][hi];
+                    red[off_b(l) + lane] = first ? v : red[off_b(l) + lane] + v;
+                }
+                const float v0 = VA[L][lane] + VA[L][hi], v1 = VA[L + 1][lane] + VA[L + 1][hi];
+                const float v2 = VA[L + 2][lane] + VA[L + 2][hi];
+                red[off_w(1) + 2 * lane] = first ? v0 : red[off_w(1) + 2 * lane] + v0;
+                red[off_w(1) + 2 * lane + 1] = first ? v1 : red[off_w(1) + 2 * lane + 1] + v1;
+                red[off_wout(L) + lane] = first ? v2 : red[off_wout(L) + lane] + v2;
+            }
+            if (lane == 0) red[off_wout(L) + PW] = first ? bo : red[off_wout(L) + PW] + bo;
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < n_padded(L); j += kFThreads) A.gpart[row * kMaxPadded + j] = red[j];
+    zero_acc<L>(G);
+    for (int t = tid; t < kFWaves * (L + 4) * 64; t += kFThreads) (&S.vacc[0][0][0])[t] = 0.f;
+    __syncthreads();
+}
+
+// 4: reverse sweep, tiles of 16 points spread evenly over all wavefronts; the
+// forward pass of each tile is recomputed (tanh included) and kept in registers
+template <int L>
+__global__ __launch_bounds__(kFThreads, kBwdBlocksPerCU) void k_bwd(BwdArgs A) {
+    __shared__ BwdShared<L> S;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    float(*T0)[kTs] = S.tt[wave][0];
+    float(*T1)[kTs] = S.tt[wave][1];
+    GradAcc<L> G;
+    zero_acc<L>(G);
+    for (int t = tid; t < kFWaves * (L + 4) * 64; t += kFThreads) (&S.vacc[0][0][0])[t] = 0.f;
+    // the extra tile of a ragged range goes to a block-dependent wavefront, so the
+    // blocks sharing a CU do not stack their extras on one SIMD
+    const int wrot = (wave + (int)(blockIdx.x % kFWaves)) % kFWaves;
+    int64_t t = A.blk_tiles[blockIdx.x];
+    const int64_t t_end = A.blk_tiles[blockIdx.x + 1];
+    int cur = A.blk_inst0[blockIdx.x];
+    while (t < t_end) {
+        // only the fields the tile loop needs (the whole descriptor would pin registers)
+        const InstDesc *Ip = A.inst + cur;
+        const int64_t tile0 = Ip->tile0, n_pts = Ip->n_pts, n_all = Ip->n_pts + Ip->n_bnd + Ip->n_sen;
+        const float2 *__restrict__ pts = Ip->pts;
+        const float2 *__restrict__ ub_i = A.ubuf + Ip->ubase;
+        const int64_t seg_end = min(t_end, tile0 + Ip->n_tiles);
+        const int64_t row = Ip->grow0 + (int64_t)(blockIdx.x - Ip->gblk0);
+        __syncthreads();
+        load_weights<L>(S.W, A.params + (int64_t)cur * A.param_stride, A.H, tid);
+        __syncthreads();
+        for (int64_t tt = t + wrot; tt < seg_end; tt += kFWaves) {
+            const int64_t idx = 16 * (tt - tile0) + (lane & 15);
+            const bool valid = idx < n_all;
+            const float2 p = valid ? pts[idx] : make_float2(0.f, 0.f);
+            const float2 d = valid ? ub_i[idx] : make_float2(0.f, 0.f);
+            const bool interior = idx < n_pts;
+            const float ub = interior ? 0.f : d.x, uxb = interior ? d.x : 0.f, uyb = interior ? d.y : 0.f;
+            Acts<L> K;
+            Vec a, tx, ty;
+            tile_forward<L, true>(S.W, lane, p.x, p.y, a, tx, ty, K);
+            tile_backward<L>(S.W, T0, T1, lane, p.x, p.y, ub, uxb, uyb, K, G, S.vacc[wave]);
+        }
+        flush_grad<L>(S, A, row, G, tid, wave, lane);
+        t = seg_end;
+        ++cur;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -744,10 +831,10 @@ __global__ __launch_bounds__(kFThreads, kFBlocksPerCU) void k_fused(FusedArgs A)
 // per blockIdx.y; optionally followed by Adam (Kingma and Ba, Algorithm 1) on
 // that instance's parameters with the step count read from device memory
 // ---------------------------------------------------------------------------
-// block = 32 columns x 32 row slices; slice t sums rows t, t+32, ... in order,
-// then the 32 slice sums of a column are added in slice order (fixed order
+// block = 16 columns x 64 row slices; slice t sums rows t, t+64, ... in order,
+// then the 64 slice sums of a column are added in slice order (fixed order
 // for any launch).  Loss partials are summed by the x = 0 block the same way.
-constexpr int kFinCols = 32, kFinSlices = 32;
+constexpr int kFinCols = 16, kFinSlices = 64;
 struct AdamArgs {
     float *params, *m, *v;
     const int64_t *step;
@@ -763,9 +850,9 @@ __global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
     __shared__ double lred[kFinSlices][4];
     const int ii = blockIdx.y;
     const InstDesc &I = inst[ii];
-    const int rows = I.n_rows;
-    const float *gp = gpart + (int64_t)I.row0 * kMaxPadded;
-    const double *lp = lpart + (int64_t)I.row0 * 4;
+    const int rows = I.gn_rows, lrows = I.ln_rows;
+    const float *gp = gpart + (int64_t)I.grow0 * kMaxPadded;
+    const double *lp = lpart + (int64_t)I.lrow0 * 4;
     const int c = threadIdx.x % kFinCols, t = threadIdx.x / kFinCols;
     const int64_t j = (int64_t)blockIdx.x * kFinCols + c;
     const bool want = (grad_out || ad.params) && j < npf;
@@ -786,35 +873,36 @@ __global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
     }
     float acc = 0.f;
     if (pj >= 0) {
-        for (int b0 = t; b0 < rows; b0 += 16 * kFinSlices) {
-            float v[16];
+        for (int b0 = t; b0 < rows; b0 += 8 * kFinSlices) {
+            float v[8];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < 8; ++i) {
                 const int b = b0 + i * kFinSlices;
                 v[i] = b < rows ? gp[(int64_t)b * kMaxPadded + pj] : 0.f;
             }
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acc += v[i];
+            for (int i = 0; i < 8; ++i) acc += v[i];
         }
     }
     part[t][c] = acc;
     if (blockIdx.x == 0 && c < 4) {
         double l4 = 0.0;
-        for (int b0 = t; b0 < rows; b0 += 16 * kFinSlices) {
-            double v[16];
+        for (int b0 = t; b0 < lrows; b0 += 8 * kFinSlices) {
+            double v[8];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < 8; ++i) {
                 const int b = b0 + i * kFinSlices;
-                v[i] = b < rows ? lp[b * 4 + c] : 0.0;
+                v[i] = b < lrows ? lp[b * 4 + c] : 0.0;
             }
 #pragma unroll
-            for (int i = 0; i < 16; ++i) l4 += v[i];
+            for (int i = 0; i < 8; ++i) l4 += v[i];
         }
         lred[t][c] = l4;
     }
     __syncthreads();
     if (t == 0 && pj >= 0) {
         float g = 0.f;
+#pragma unroll 8
         for (int q = 0; q < kFinSlices; ++q) g += part[q][c];
         if (grad_out) grad_out[(int64_t)ii * npf + j] = g;
         if (ad.params) {
@@ -830,6 +918,7 @@ __global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         double tt[4] = {0, 0, 0, 0};
+#pragma unroll 4
         for (int q = 0; q < kFinSlices; ++q)
             for (int i = 0; i < 4; ++i) tt[i] += lred[q][i];
         const double Lv = I.cv * tt[0];
@@ -865,7 +954,7 @@ static size_t dyn_budget(int dev) {
     hipDeviceProp_t prop;
     size_t lim = 64 * 1024;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) lim = prop.sharedMemPerBlock;
-    const size_t stat = sizeof(FusedShared<L>) + 64;
+    const size_t stat = sizeof(FwdShared<L>) + 64;
     return lim > stat ? lim - stat : 0;
 }
 
@@ -880,17 +969,20 @@ static size_t dyn_budget_for(int L, int dev) {
 
 template <int L>
 static hipError_t set_dyn_attr(size_t dyn_bytes) {
-    return hipFuncSetAttribute((const void *)k_fused<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+    return hipFuncSetAttribute((const void *)k_fwd_contract<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)dyn_bytes);
 }
 
 // A plan fixes, for a set of instances with one network shape and loss
-// weighting: the items of every instance, the contiguous item range of every
-// block (balanced by point count), and which partial rows each block writes.
+// weighting: the forward items of every instance and the contiguous item range
+// of every forward block (balanced by point count), the backward tiles and the
+// tile range of every backward block (equal tile counts), and which loss and
+// gradient partial rows each block writes.
 struct FusedPlan {
-    DevBuf inst, item_inst, blk_items, gpart, lpart;
+    DevBuf inst, item_inst, blk_items, blk_tiles, blk_inst0, ubuf, gpart, lpart;
     std::vector<InstDesc> host_inst;
-    int blocks = 0, n_inst = 0, rows = 0, L = 0, H = 0;
-    int64_t items = 0, npf = 0;
+    int fblocks = 0, bblocks = 0, n_inst = 0, grows = 0, lrows = 0, L = 0, H = 0;
+    int64_t items = 0, tiles = 0, npf = 0;
     size_t dyn = 0;
     int item_cap_pts = 0;
 };
@@ -904,8 +996,9 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         total_all += probs[i]->n_pts + probs[i]->n_bnd + probs[i]->n_sen;
         elems_all += probs[i]->n_elem;
     }
-    const int max_blocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus * kFBlocksPerCU, kMaxBlocks),
-                                                  elems_all);
+    constexpr int kFwdPlanBlocksPerCU = 2;
+    const int max_blocks = (int)std::min<int64_t>(
+        std::min<int64_t>((int64_t)cus * kFwdPlanBlocksPerCU, kMaxBlocks), elems_all);
     // item size: one instance gets a multiple of the block count of items (each
     // at most ~2048 points); in a batch, items of about half a block's share
     // of the points let the contiguous block ranges balance
@@ -916,8 +1009,8 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     std::vector<InstDesc> D(n);
     std::vector<int64_t> item_pts;  // points per global item
     std::vector<int> item_inst;
-    size_t dyn = sizeof(float) * (size_t)kMaxPadded;
     int cap_max = 0;
+    int64_t tiles = 0, ubase = 0;
     for (int i = 0; i < n; ++i) {
         const vpinn_problem *p = probs[i];
         const int64_t nx = p->n_bnd + p->n_sen, tot = p->n_pts + nx;
@@ -936,6 +1029,11 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         d.n_sen = p->n_sen;
         d.n_items = ni;
         d.item0 = (int64_t)item_inst.size();
+        d.n_tiles = (tot + 15) / 16;
+        d.tile0 = tiles;
+        tiles += d.n_tiles;
+        d.ubase = ubase;
+        ubase += tot;
         d.nq = p->nq;
         d.ntest = p->ntest;
         d.fast = (p->nq <= kFThreads && p->ntest <= kKB) ? 1 : 0;
@@ -952,10 +1050,10 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
             item_inst.push_back(i);
         }
         const int64_t max_e = (p->n_elem + ni - 1) / ni, max_x = (nx + ni - 1) / ni;
-        const int64_t cap = max_e * p->nq + max_x;
-        cap_max = (int)std::max<int64_t>(cap_max, cap);
+        cap_max = (int)std::max<int64_t>(cap_max, max_e * p->nq + max_x);
     }
-    // the shared dynamic-LDS layout: item points (float2), then 2 c_v R, then the contraction buffer
+    // the forward kernel's dynamic LDS: item points (float2), then 2 c_v R, then the contraction buffer
+    size_t dyn = 16;
     for (int i = 0; i < n; ++i) {
         const InstDesc &d = D[i];
         const int64_t max_e = (d.n_elem + d.n_items - 1) / d.n_items;
@@ -964,60 +1062,89 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     }
     if (dyn > dyn_budget_for(L, dev))
         return fail(VPINN_E_UNSUPPORTED, "fused path: an element's quadrature and test data exceed the LDS budget");
+    // forward blocks: contiguous item ranges with about equal point counts
     const int64_t items = (int64_t)item_inst.size();
-    const int blocks = (int)std::min<int64_t>(max_blocks, items);
-    // contiguous item ranges with about equal point counts
-    std::vector<int64_t> blk(blocks + 1, items);
+    const int fblocks = (int)std::min<int64_t>(max_blocks, items);
+    std::vector<int64_t> blk(fblocks + 1, items);
     blk[0] = 0;
     {
         int64_t acc = 0, it = 0;
-        for (int b = 1; b < blocks; ++b) {
-            const double goal = (double)total_all * b / blocks;
+        for (int b = 1; b < fblocks; ++b) {
+            const double goal = (double)total_all * b / fblocks;
             while (it < items && (double)(acc + item_pts[it]) <= goal) acc += item_pts[it++];
             // every block keeps at least one item
-            const int64_t lo = blk[b - 1] + 1, hi = items - (blocks - b);
+            const int64_t lo = blk[b - 1] + 1, hi = items - (fblocks - b);
             blk[b] = std::min<int64_t>(std::max<int64_t>(it, lo), hi);
             while (it < blk[b]) acc += item_pts[it++];
             while (it > blk[b]) acc -= item_pts[--it];
         }
     }
-    // partial rows: instance i gets one row per block whose range meets its items
-    int rows = 0;
+    // backward blocks: equal shares of the tile list
+    const int bblocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus * kBwdBlocksPerCU, kMaxBlocks), tiles);
+    std::vector<int64_t> bt(bblocks + 1);
+    std::vector<int> binst(bblocks);
+    for (int b = 0; b <= bblocks; ++b) bt[b] = (int64_t)b * tiles / bblocks;
+    // rows: instance i gets one loss row per forward block and one gradient row per
+    // backward block whose range meets its items / tiles
+    int lrows = 0, grows = 0;
     {
-        int b = 0;
+        int fb = 0, bb = 0;
         for (int i = 0; i < n; ++i) {
             InstDesc &d = D[i];
             const int64_t f = d.item0, l = d.item0 + d.n_items - 1;
-            while (blk[b + 1] <= f) ++b;
-            int bl = b;
-            while (blk[bl + 1] <= l) ++bl;
-            d.blk0 = b;
-            d.n_rows = bl - b + 1;
-            d.row0 = rows;
-            rows += d.n_rows;
+            while (blk[fb + 1] <= f) ++fb;
+            int fl = fb;
+            while (blk[fl + 1] <= l) ++fl;
+            d.lblk0 = fb;
+            d.ln_rows = fl - fb + 1;
+            d.lrow0 = lrows;
+            lrows += d.ln_rows;
+            const int64_t tf = d.tile0, tl = d.tile0 + d.n_tiles - 1;
+            while (bt[bb + 1] <= tf) ++bb;
+            int bl = bb;
+            while (bt[bl + 1] <= tl) ++bl;
+            d.gblk0 = bb;
+            d.gn_rows = bl - bb + 1;
+            d.grow0 = grows;
+            grows += d.gn_rows;
+        }
+        int i = 0;
+        for (int b = 0; b < bblocks; ++b) {
+            while (D[i].tile0 + D[i].n_tiles <= bt[b]) ++i;
+            binst[b] = i;
         }
     }
     VP_HIP(P.inst.reserve(sizeof(InstDesc) * n));
     VP_HIP(P.item_inst.reserve(sizeof(int) * items));
-    VP_HIP(P.blk_items.reserve(sizeof(int64_t) * (blocks + 1)));
-    VP_HIP(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)rows));
-    VP_HIP(P.lpart.reserve(sizeof(double) * 4 * (size_t)rows));
+    VP_HIP(P.blk_items.reserve(sizeof(int64_t) * (fblocks + 1)));
+    VP_HIP(P.blk_tiles.reserve(sizeof(int64_t) * (bblocks + 1)));
+    VP_HIP(P.blk_inst0.reserve(sizeof(int) * bblocks));
+    VP_HIP(P.ubuf.reserve(sizeof(float2) * (size_t)ubase));
+    VP_HIP(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)grows));
+    VP_HIP(P.lpart.reserve(sizeof(double) * 4 * (size_t)lrows));
     VP_HIP(hipMemcpy(P.inst.ptr, D.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
     VP_HIP(hipMemcpy(P.item_inst.ptr, item_inst.data(), sizeof(int) * items, hipMemcpyHostToDevice));
-    VP_HIP(hipMemcpy(P.blk_items.ptr, blk.data(), sizeof(int64_t) * (blocks + 1), hipMemcpyHostToDevice));
-    hipError_t e;
-    switch (L) {
-    case 1: e = set_dyn_attr<1>(dyn); break;
-    case 2: e = set_dyn_attr<2>(dyn); break;
-    case 3: e = set_dyn_attr<3>(dyn); break;
-    default: e = set_dyn_attr<4>(dyn); break;
+    VP_HIP(hipMemcpy(P.blk_items.ptr, blk.data(), sizeof(int64_t) * (fblocks + 1), hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(P.blk_tiles.ptr, bt.data(), sizeof(int64_t) * (bblocks + 1), hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(P.blk_inst0.ptr, binst.data(), sizeof(int) * bblocks, hipMemcpyHostToDevice));
+    if (dyn > 48 * 1024) {
+        hipError_t e;
+        switch (L) {
+        case 1: e = set_dyn_attr<1>(dyn); break;
+        case 2: e = set_dyn_attr<2>(dyn); break;
+        case 3: e = set_dyn_attr<3>(dyn); break;
+        default: e = set_dyn_attr<4>(dyn); break;
+        }
+        if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     }
-    if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     P.host_inst = D;
-    P.blocks = blocks;
+    P.fblocks = fblocks;
+    P.bblocks = bblocks;
     P.n_inst = n;
-    P.rows = rows;
+    P.grows = grows;
+    P.lrows = lrows;
     P.items = items;
+    P.tiles = tiles;
     P.L = L;
     P.H = H;
     P.npf = vpinn_n_params(H, L);
@@ -1026,45 +1153,53 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     return VPINN_OK;
 }
 
-// launch the fused kernel and the per-instance reduction (with optional Adam)
+template <int L>
+static void launch_all(const FusedPlan &P, const FwdArgs &fa, const BwdArgs &ba, bool want_grad, dim3 fg, int ft,
+                       float *loss, float *grad, float *grad_eps, const AdamArgs &ad, hipEvent_t const *ev,
+                       hipStream_t s) {
+    if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
+    k_fwd_contract<L><<<P.fblocks, kFThreads, P.dyn, s>>>(fa);
+    if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
+    if (want_grad) k_bwd<L><<<P.bblocks, kFThreads, 0, s>>>(ba);
+    if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
+    k_fused_final<L><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf,
+                                        loss, grad, grad_eps, ad);
+    if (ev && ev[3]) (void)hipEventRecord(ev[3], s);
+}
+
+// launch forward/contraction, backward, and the per-instance reduction (with optional Adam)
 static vpinn_status run_plan(const FusedPlan &P, const float *params, const float *eps, bool want_grad,
                              float *loss, float *grad, float *grad_eps, const AdamArgs &ad, int64_t *step,
-                             hipStream_t s) {
-    FusedArgs a{};
-    a.inst = P.inst.as<InstDesc>();
-    a.item_inst = P.item_inst.as<int>();
-    a.blk_items = P.blk_items.as<int64_t>();
-    a.params = params;
-    a.param_stride = P.npf;
-    a.eps = eps;
-    a.H = P.H;
-    a.want_grad = want_grad ? 1 : 0;
-    a.item_cap_pts = P.item_cap_pts;
-    a.gpart = P.gpart.as<float>();
-    a.lpart = P.lpart.as<double>();
-    a.step = step;
+                             hipEvent_t const *ev, hipStream_t s) {
+    FwdArgs fa{};
+    fa.inst = P.inst.as<InstDesc>();
+    fa.item_inst = P.item_inst.as<int>();
+    fa.blk_items = P.blk_items.as<int64_t>();
+    fa.params = params;
+    fa.param_stride = P.npf;
+    fa.eps = eps;
+    fa.H = P.H;
+    fa.want_grad = want_grad ? 1 : 0;
+    fa.item_cap_pts = P.item_cap_pts;
+    fa.ubuf = P.ubuf.as<float2>();
+    fa.lpart = P.lpart.as<double>();
+    fa.step = step;
+    BwdArgs ba{};
+    ba.inst = P.inst.as<InstDesc>();
+    ba.blk_tiles = P.blk_tiles.as<int64_t>();
+    ba.blk_inst0 = P.blk_inst0.as<int>();
+    ba.params = params;
+    ba.param_stride = P.npf;
+    ba.H = P.H;
+    ba.ubuf = P.ubuf.as<float2>();
+    ba.gpart = P.gpart.as<float>();
     const dim3 fg((unsigned)std::max<int64_t>(1, (P.npf + kFinCols - 1) / kFinCols), (unsigned)P.n_inst);
     const int ft = kFinCols * kFinSlices;
-    const InstDesc *di = P.inst.as<InstDesc>();
-    const float *gp = P.gpart.as<float>();
-    const double *lp = P.lpart.as<double>();
     switch (P.L) {
-    case 1:
-        k_fused<1><<<P.blocks, kFThreads, P.dyn, s>>>(a);
-        k_fused_final<1><<<fg, ft, 0, s>>>(di, gp, lp, P.H, P.npf, loss, grad, grad_eps, ad);
-        break;
-    case 2:
-        k_fused<2><<<P.blocks, kFThreads, P.dyn, s>>>(a);
-        k_fused_final<2><<<fg, ft, 0, s>>>(di, gp, lp, P.H, P.npf, loss, grad, grad_eps, ad);
-        break;
-    case 3:
-        k_fused<3><<<P.blocks, kFThreads, P.dyn, s>>>(a);
-        k_fused_final<3><<<fg, ft, 0, s>>>(di, gp, lp, P.H, P.npf, loss, grad, grad_eps, ad);
-        break;
-    default:
-        k_fused<4><<<P.blocks, kFThreads, P.dyn, s>>>(a);
-        k_fused_final<4><<<fg, ft, 0, s>>>(di, gp, lp, P.H, P.npf, loss, grad, grad_eps, ad);
-        break;
+    case 1: launch_all<1>(P, fa, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 2: launch_all<2>(P, fa, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 3: launch_all<3>(P, fa, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    default: launch_all<4>(P, fa, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
     }
     VP_HIP(hipGetLastError());
     return VPINN_OK;
@@ -1108,7 +1243,8 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
         c->gamma = cfg->gamma;
     }
     AdamArgs none{};
-    return run_plan(c->plan, d_params, d_eps, d_grad != nullptr, d_loss, d_grad, d_grad_eps, none, nullptr, s);
+    return run_plan(c->plan, d_params, d_eps, d_grad != nullptr || d_grad_eps != nullptr, d_loss, d_grad, d_grad_eps,
+                    none, nullptr, p->prof, s);
 }
 
 }  // namespace vp
@@ -1122,6 +1258,7 @@ struct vpinn_batch {
     vp::FusedPlan plan;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t prof[4] = {nullptr, nullptr, nullptr, nullptr};
     ~vpinn_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1148,13 +1285,13 @@ vpinn_status batch_loss_and_grad(vpinn_batch *b, const float *d_params, const fl
                                  float *d_grads, float *d_grad_eps, hipStream_t s) {
     AdamArgs none{};
     return run_plan(b->plan, d_params, d_eps, d_grads != nullptr || d_grad_eps != nullptr, d_losses, d_grads,
-                    d_grad_eps, none, nullptr, s);
+                    d_grad_eps, none, nullptr, b->prof, s);
 }
 
 vpinn_status batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr, float b1,
                         float b2, float eps, float *d_losses, hipStream_t s) {
     AdamArgs ad{d_params, d_m, d_v, d_step, lr, b1, b2, eps};
-    return run_plan(b->plan, d_params, nullptr, true, d_losses, nullptr, nullptr, ad, d_step, s);
+    return run_plan(b->plan, d_params, nullptr, true, d_losses, nullptr, nullptr, ad, d_step, b->prof, s);
 }
 
 vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
@@ -1168,8 +1305,14 @@ vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d
         (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
+    hipEvent_t saved[4];
+    for (int i = 0; i < 4; ++i) {
+        saved[i] = b->prof[i];
+        b->prof[i] = nullptr;
+    }
     VP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     vpinn_status st = batch_step(b, d_params, d_m, d_v, d_step, lr, b1, b2, eps, d_losses, s);
+    for (int i = 0; i < 4; ++i) b->prof[i] = saved[i];
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st) {
@@ -1183,6 +1326,10 @@ vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d
 }
 
 int batch_device(const vpinn_batch *b) { return b->device; }
+
+void batch_set_profile_events(vpinn_batch *b, void *const *events) {
+    for (int i = 0; i < 4; ++i) b->prof[i] = events ? (hipEvent_t)events[i] : nullptr;
+}
 
 void batch_destroy(vpinn_batch *b) { delete b; }
 

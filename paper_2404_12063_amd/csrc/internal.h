@@ -84,6 +84,7 @@ struct vpinn_problem {
     vp::DevBuf loss_e;       // double [n_elem]: per-element sum_k R^2 (or per-block partials)
     vp::DevBuf gpart;        // float [blocks][kMaxPadded]: per-block gradient partials
     vp::DevBuf eps_part;     // double [blocks]
+    hipEvent_t prof[4] = {nullptr, nullptr, nullptr, nullptr};  // optional timing events (caller-owned)
     void *fused_ws = nullptr;              // fused-path workspace (owned)
     void (*fused_ws_free)(void *) = nullptr;
     int64_t all_pts() const { return n_pts + n_bnd + n_sen; }
@@ -116,6 +117,7 @@ vpinn_status batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v,
 vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
                            float b1, float b2, float eps, float *d_losses, hipStream_t s);
 vpinn_status batch_replay(vpinn_batch *b, hipStream_t s);
+void batch_set_profile_events(vpinn_batch *b, void *const *events);
 int batch_device(const vpinn_batch *b);
 void batch_destroy(vpinn_batch *b);
 

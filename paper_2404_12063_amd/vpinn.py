@@ -92,6 +92,8 @@ _SIGNATURES = {
                                         C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
     "vpinn_batch_replay": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "vpinn_batch_free": (None, [C.c_void_p]),
+    "vpinn_set_profile_events": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "vpinn_batch_set_profile_events": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "vpinn_problem_free": (None, [C.c_void_p]),
     "vpinn_last_error": (C.c_char_p, []),
 }
@@ -274,3 +276,29 @@ def vpinn_batch_capture(b: Batch, params, m, v, step, lr: float = 1e-3, beta1: f
 
 def vpinn_batch_replay(b: Batch, stream=None):
     _check(lib().vpinn_batch_replay(b.handle, _stream(stream)))
+
+
+def _event_array(events):
+    if events is None:
+        return None
+    handles = []
+    for e in events:
+        if e is None:
+            handles.append(None)
+        else:
+            h = e.cuda_event
+            if not h:
+                raise ValueError("torch events must be recorded once before their handles are passed")
+            handles.append(h)
+    return (C.c_void_p * 4)(*handles)
+
+
+def vpinn_set_profile_events(p: Problem, events=None):
+    """events: 4 torch.cuda.Event(enable_timing=True) already recorded once (or None to disable)."""
+    arr = _event_array(events)
+    _check(lib().vpinn_set_profile_events(p.handle, arr))
+
+
+def vpinn_batch_set_profile_events(b: Batch, events=None):
+    arr = _event_array(events)
+    _check(lib().vpinn_batch_set_profile_events(b.handle, arr))
