@@ -88,6 +88,7 @@ struct WeightsShared {
 template <int L>
 struct FwdShared {
     WeightsShared<L> W;
+    float stage[n_padded(L)];  // flat parameters, staged for load_weights
     // per-wavefront loss partials: sum R^2, sum R A, sum d_b^2, sum d_s^2
     double lp[kFWaves][4];
 };
@@ -452,27 +453,44 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-// weights of one instance -> LDS (padded to 32, fragment order for the MFMA A operands)
+// weights of one instance -> LDS (padded to 32, fragment order for the MFMA A operands).
+// The flat parameters are first copied into `stage` with every thread's loads in
+// flight at once (npf <= n_padded(L)), then rearranged LDS to LDS.
 template <int L>
-__device__ __forceinline__ void load_weights(WeightsShared<L> &S, const float *__restrict__ P, int H, int tid) {
+__device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, const float *__restrict__ P, int H,
+                                             int tid) {
+    const int npf = 3 * H + (L - 1) * (H * H + H) + H + 1;
+    constexpr int kLoads = (n_padded(L) + kFThreads - 1) / kFThreads;
+    float v[kLoads];
+#pragma unroll
+    for (int i = 0; i < kLoads; ++i) {
+        const int j = tid + i * kFThreads;
+        v[i] = j < npf ? P[j] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < kLoads; ++i) {
+        const int j = tid + i * kFThreads;
+        if (j < npf) stage[j] = v[i];
+    }
+    __syncthreads();
     for (int t = tid; t < PW * 2; t += kFThreads) {
         const int o = t >> 1, i = t & 1;
-        S.w1[o][i] = o < H ? P[o * 2 + i] : 0.f;
+        S.w1[o][i] = o < H ? stage[o * 2 + i] : 0.f;
     }
     for (int t = tid; t < L * PW; t += kFThreads) {
         const int l = t / PW + 1, o = t % PW;
-        const int64_t off = (l == 1) ? 2 * H : hoff_w(H, l) + (int64_t)H * H;
-        S.b[l - 1][o] = o < H ? P[off + o] : 0.f;
+        const int off = (l == 1) ? 2 * H : (int)hoff_w(H, l) + H * H;
+        S.b[l - 1][o] = o < H ? stage[off + o] : 0.f;
     }
-    for (int t = tid; t < PW; t += kFThreads) S.wo[t] = t < H ? P[hoff_w(H, L + 1) + t] : 0.f;
-    if (tid == 0) S.bo = P[hoff_w(H, L + 1) + H];
+    for (int t = tid; t < PW; t += kFThreads) S.wo[t] = t < H ? stage[hoff_w(H, L + 1) + t] : 0.f;
+    if (tid == 0) S.bo = stage[hoff_w(H, L + 1) + H];
     for (int t = tid; t < (L - 1) * 2 * 2 * 8 * 64; t += kFThreads) {
         const int ln = t & 63, s = (t >> 6) & 7, mt = (t >> 9) & 1, dir = (t >> 10) & 1, l = 2 + (t >> 11);
         const int m = s >> 2, r = s & 3;
         // forward: W[16 mt + ln % 16][16 m + 4 (ln / 16) + r]; backward: W[16 m + 4 (ln / 16) + r][16 mt + ln % 16]
         const int o = dir == 0 ? 16 * mt + (ln & 15) : 16 * m + 4 * (ln >> 4) + r;
         const int i = dir == 0 ? 16 * m + 4 * (ln >> 4) + r : 16 * mt + (ln & 15);
-        S.wf[l - 2][dir][mt][s][ln] = (o < H && i < H) ? P[hoff_w(H, l) + (int64_t)o * H + i] : 0.f;
+        S.wf[l - 2][dir][mt][s][ln] = (o < H && i < H) ? stage[hoff_w(H, l) + o * H + i] : 0.f;
     }
 }
 
@@ -522,7 +540,7 @@ __global__ __launch_bounds__(kFThreads, kFwdBlocksPerCU) void k_fwd_contract(Fwd
             I = A.inst[inst];
             eps = A.eps ? A.eps[inst] : 1.0f;
             __syncthreads();
-            load_weights<L>(S.W, A.params + (int64_t)inst * A.param_stride, H, tid);
+            load_weights<L>(S.W, S.stage, A.params + (int64_t)inst * A.param_stride, H, tid);
             __syncthreads();
         }
         const int64_t item = git - I.item0;
@@ -691,31 +709,30 @@ __global__ __launch_bounds__(kFThreads, kFwdBlocksPerCU) void k_fwd_contract(Fwd
         }
         __syncthreads();
         if (A.want_grad) {
-
-        // 3. adjoint of the contraction (generic path), thread per point, 16 tests per batch
-        for (int idx = tid; idx < (I.fast ? 0 : n_int); idx += kFThreads) {
-            const int el = idx / I.nq, q = idx - el * I.nq;
-            const int64_t e = e0 + el;
-            const float *rb = rbar + el * I.ntest;
-            float bx = 0.f, by = 0.f;
-            for (int k0 = 0; k0 < I.ntest; k0 += 16) {
-                float gx[16], gy[16];
+            // 3. adjoint of the contraction (generic path), thread per point, 16 tests per batch
+            for (int idx = tid; idx < (I.fast ? 0 : n_int); idx += kFThreads) {
+                const int el = idx / I.nq, q = idx - el * I.nq;
+                const int64_t e = e0 + el;
+                const float *rb = rbar + el * I.ntest;
+                float bx = 0.f, by = 0.f;
+                for (int k0 = 0; k0 < I.ntest; k0 += 16) {
+                    float gx[16], gy[16];
 #pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    const int k = k0 + t;
-                    const int64_t o = (e * I.ntest + k) * (int64_t)I.nq + q;
-                    gx[t] = k < I.ntest ? I.Gx[o] : 0.f;
-                    gy[t] = k < I.ntest ? I.Gy[o] : 0.f;
-                }
+                    for (int t = 0; t < 16; ++t) {
+                        const int k = k0 + t;
+                        const int64_t o = (e * I.ntest + k) * (int64_t)I.nq + q;
+                        gx[t] = k < I.ntest ? I.Gx[o] : 0.f;
+                        gy[t] = k < I.ntest ? I.Gy[o] : 0.f;
+                    }
 #pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    const float r = (k0 + t < I.ntest) ? rb[k0 + t] : 0.f;
-                    bx = fmaf(r, gx[t], bx);
-                    by = fmaf(r, gy[t], by);
+                    for (int t = 0; t < 16; ++t) {
+                        const float r = (k0 + t < I.ntest) ? rb[k0 + t] : 0.f;
+                        bx = fmaf(r, gx[t], bx);
+                        by = fmaf(r, gy[t], by);
+                    }
                 }
+                uxy[idx] = make_float2(eps * bx, eps * by);
             }
-            uxy[idx] = make_float2(eps * bx, eps * by);
-        }
             __syncthreads();
             // adjoints of the item's points -> the instance's slice of the adjoint buffer
             for (int idx = tid; idx < n_all; idx += kFThreads) {
@@ -738,39 +755,53 @@ __device__ __forceinline__ void flush_grad(BwdShared<L> &S, const BwdArgs &A, in
     const bool lo = lane < 32;
     const float(*VA)[64] = S.vacc[wave];
     const int hi = lane ^ 32;
-    // waves add their sums into red in wave order; each lane streams its values in
-    // batches of four (all reads of a batch issued before its writes)
+    // waves add their sums into red in wave order; a wave issues all of its reads
+    // before its writes, so each turn costs one LDS round trip
+    constexpr int NW = 16 * (L > 1 ? L - 1 : 0);
     for (int w = 0; w < kFWaves; ++w) {
         if (wave == w) {
             const bool first = (w == 0);
+            float cw[NW > 0 ? NW : 1], cv[L + 3], cb = 0.f;
+            if (!first) {
+#pragma unroll
+                for (int l = 2; l <= L; ++l)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            cw[16 * (l - 2) + 4 * t + r] =
+                                red[off_w(l) + (16 * (t >> 1) + 4 * g + r) * PW + 16 * (t & 1) + c];
+                if (lo) {
+#pragma unroll
+                    for (int l = 1; l <= L; ++l) cv[l - 1] = red[off_b(l) + lane];
+                    cv[L] = red[off_w(1) + 2 * lane];
+                    cv[L + 1] = red[off_w(1) + 2 * lane + 1];
+                    cv[L + 2] = red[off_wout(L) + lane];
+                }
+                if (lane == 0) cb = red[off_wout(L) + PW];
+            } else {
+#pragma unroll
+                for (int i = 0; i < (NW > 0 ? NW : 1); ++i) cw[i] = 0.f;
+#pragma unroll
+                for (int i = 0; i < L + 3; ++i) cv[i] = 0.f;
+            }
+            const float bo = wave_sum(VA[L + 3][lane]);
 #pragma unroll
             for (int l = 2; l <= L; ++l)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int mo = t >> 1, mi = t & 1;
-                    int id[4];
-                    float curv[4];
+                for (int t = 0; t < 4; ++t)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) id[r] = off_w(l) + (16 * mo + 4 * g + r) * PW + 16 * mi + c;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) curv[r] = first ? 0.f : red[id[r]];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) red[id[r]] = curv[r] + G.w[l - 2][t][r];
-                }
-            const float bo = wave_sum(VA[L + 3][lane]);
+                    for (int r = 0; r < 4; ++r)
+                        red[off_w(l) + (16 * (t >> 1) + 4 * g + r) * PW + 16 * (t & 1) + c] =
+                            cw[16 * (l - 2) + 4 * t + r] + G.w[l - 2][t][r];
             if (lo) {
 #pragma unroll
-                for (int l = 1; l <= L; ++l) {
-                    const float v = VA[l - 1][lane] + VA[l - 1][hi];
-                    red[off_b(l) + lane] = first ? v : red[off_b(l) + lane] + v;
-                }
-                const float v0 = VA[L][lane] + VA[L][hi], v1 = VA[L + 1][lane] + VA[L + 1][hi];
-                const float v2 = VA[L + 2][lane] + VA[L + 2][hi];
-                red[off_w(1) + 2 * lane] = first ? v0 : red[off_w(1) + 2 * lane] + v0;
-                red[off_w(1) + 2 * lane + 1] = first ? v1 : red[off_w(1) + 2 * lane + 1] + v1;
-                red[off_wout(L) + lane] = first ? v2 : red[off_wout(L) + lane] + v2;
+                for (int l = 1; l <= L; ++l) red[off_b(l) + lane] = cv[l - 1] + (VA[l - 1][lane] + VA[l - 1][hi]);
+                red[off_w(1) + 2 * lane] = cv[L] + (VA[L][lane] + VA[L][hi]);
+                red[off_w(1) + 2 * lane + 1] = cv[L + 1] + (VA[L + 1][lane] + VA[L + 1][hi]);
+                red[off_wout(L) + lane] = cv[L + 2] + (VA[L + 2][lane] + VA[L + 2][hi]);
             }
-            if (lane == 0) red[off_wout(L) + PW] = first ? bo : red[off_wout(L) + PW] + bo;
+            if (lane == 0) red[off_wout(L) + PW] = cb + bo;
         }
         __syncthreads();
     }
@@ -806,7 +837,7 @@ __global__ __launch_bounds__(kFThreads, kBwdBlocksPerCU) void k_bwd(BwdArgs A) {
         const int64_t seg_end = min(t_end, tile0 + Ip->n_tiles);
         const int64_t row = Ip->grow0 + (int64_t)(blockIdx.x - Ip->gblk0);
         __syncthreads();
-        load_weights<L>(S.W, A.params + (int64_t)cur * A.param_stride, A.H, tid);
+        load_weights<L>(S.W, S.red, A.params + (int64_t)cur * A.param_stride, A.H, tid);
         __syncthreads();
         for (int64_t tt = t + wrot; tt < seg_end; tt += kFWaves) {
             const int64_t idx = 16 * (tt - tile0) + (lane & 15);
