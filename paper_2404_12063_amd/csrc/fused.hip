@@ -484,13 +484,24 @@ __device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, 
     }
     for (int t = tid; t < PW; t += kFThreads) S.wo[t] = t < H ? stage[hoff_w(H, L + 1) + t] : 0.f;
     if (tid == 0) S.bo = stage[hoff_w(H, L + 1) + H];
-    for (int t = tid; t < (L - 1) * 2 * 2 * 8 * 64; t += kFThreads) {
-        const int ln = t & 63, s = (t >> 6) & 7, mt = (t >> 9) & 1, dir = (t >> 10) & 1, l = 2 + (t >> 11);
-        const int m = s >> 2, r = s & 3;
-        // forward: W[16 mt + ln % 16][16 m + 4 (ln / 16) + r]; backward: W[16 m + 4 (ln / 16) + r][16 mt + ln % 16]
-        const int o = dir == 0 ? 16 * mt + (ln & 15) : 16 * m + 4 * (ln >> 4) + r;
-        const int i = dir == 0 ? 16 * m + 4 * (ln >> 4) + r : 16 * mt + (ln & 15);
-        S.wf[l - 2][dir][mt][s][ln] = (o < H && i < H) ? stage[hoff_w(H, l) + o * H + i] : 0.f;
+    // fragments: thread tid fills lane ln = tid % 64, slot s = tid / 64 + 4 m of every
+    // (l, dir, mt, m); all reads are issued before the writes
+    static_assert(kFThreads == 256, "fragment fill assumes four wavefronts");
+    constexpr int kFr = (L - 1) * 8;
+    const int ln = tid & 63, r = tid >> 6, c = ln & 15, q = 4 * (ln >> 4) + r;
+    float f[kFr > 0 ? kFr : 1];
+#pragma unroll
+    for (int k = 0; k < kFr; ++k) {
+        const int m = k & 1, mt = (k >> 1) & 1, dir = (k >> 2) & 1, l = 2 + (k >> 3);
+        // forward: W[16 mt + c][16 m + q]; backward: W[16 m + q][16 mt + c]
+        const int o = dir == 0 ? 16 * mt + c : 16 * m + q;
+        const int i = dir == 0 ? 16 * m + q : 16 * mt + c;
+        f[k] = (o < H && i < H) ? stage[hoff_w(H, l) + o * H + i] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < kFr; ++k) {
+        const int m = k & 1, mt = (k >> 1) & 1, dir = (k >> 2) & 1, l = 2 + (k >> 3);
+        S.wf[l - 2][dir][mt][r + 4 * m][ln] = f[k];
     }
 }
 
@@ -560,10 +571,14 @@ __global__ __launch_bounds__(kFThreads, kFwdBlocksPerCU) void k_fwd_contract(Fwd
         // blocks sharing a CU put their ragged extra tiles on different SIMDs
         const int wrot = (wave + (int)((blockIdx.x + item) % kFWaves)) % kFWaves;
         // 1. forward
+        float2 pn = (16 * wrot + (lane & 15) < n_all) ? point_xy(16 * wrot + (lane & 15)) : make_float2(0.f, 0.f);
         for (int t = wrot; t < n_tiles; t += kFWaves) {
             const int idx = 16 * t + (lane & 15);
             const bool valid = idx < n_all;
-            const float2 p = valid ? point_xy(idx) : make_float2(0.f, 0.f);
+            const float2 p = pn;
+            // the next tile's point is loaded while this tile computes
+            const int nidx = idx + 16 * kFWaves;
+            pn = nidx < n_all ? point_xy(nidx) : make_float2(0.f, 0.f);
             Vec a, tx, ty;
             Acts<L> unused;
             tile_forward<L, false>(S.W, lane, p.x, p.y, a, tx, ty, unused);
@@ -745,67 +760,76 @@ __global__ __launch_bounds__(kFThreads, kFwdBlocksPerCU) void k_fwd_contract(Fwd
     if (cur >= 0) flush_loss<L>(S, A, I.lrow0 + (int64_t)(blockIdx.x - I.lblk0), tid);
 }
 
-// the block's gradient sums for one instance -> gradient row `row`; accumulators reset
+// one wavefront's gradient sums in padded order -> P (op: store, or add to what P holds)
+template <int L, bool ADD>
+__device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const float (*VA)[64], int lane) {
+    const int g = lane >> 4, c = lane & 15, hi = lane ^ 32;
+    const bool lo = lane < 32;
+    constexpr int NW = 16 * (L > 1 ? L - 1 : 0);
+    float cw[NW > 0 ? NW : 1], cv[L + 3], cb = 0.f;
+#pragma unroll
+    for (int i = 0; i < (NW > 0 ? NW : 1); ++i) cw[i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < L + 3; ++i) cv[i] = 0.f;
+    if (ADD) {
+#pragma unroll
+        for (int l = 2; l <= L; ++l)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    cw[16 * (l - 2) + 4 * t + r] = P[off_w(l) + (16 * (t >> 1) + 4 * g + r) * PW + 16 * (t & 1) + c];
+        if (lo) {
+#pragma unroll
+            for (int l = 1; l <= L; ++l) cv[l - 1] = P[off_b(l) + lane];
+            cv[L] = P[off_w(1) + 2 * lane];
+            cv[L + 1] = P[off_w(1) + 2 * lane + 1];
+            cv[L + 2] = P[off_wout(L) + lane];
+        }
+        if (lane == 0) cb = P[off_wout(L) + PW];
+    }
+    const float bo = wave_sum(VA[L + 3][lane]);
+    // the partner's sum comes first, so the pair adds as (lower wave) + (upper wave)
+#pragma unroll
+    for (int l = 2; l <= L; ++l)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                P[off_w(l) + (16 * (t >> 1) + 4 * g + r) * PW + 16 * (t & 1) + c] =
+                    ADD ? G.w[l - 2][t][r] + cw[16 * (l - 2) + 4 * t + r] : G.w[l - 2][t][r];
+    if (lo) {
+#pragma unroll
+        for (int l = 1; l <= L; ++l) {
+            const float v = VA[l - 1][lane] + VA[l - 1][hi];
+            P[off_b(l) + lane] = ADD ? v + cv[l - 1] : v;
+        }
+        const float v0 = VA[L][lane] + VA[L][hi], v1 = VA[L + 1][lane] + VA[L + 1][hi];
+        const float vo = VA[L + 2][lane] + VA[L + 2][hi];
+        P[off_w(1) + 2 * lane] = ADD ? v0 + cv[L] : v0;
+        P[off_w(1) + 2 * lane + 1] = ADD ? v1 + cv[L + 1] : v1;
+        P[off_wout(L) + lane] = ADD ? vo + cv[L + 2] : vo;
+    }
+    if (lane == 0) P[off_wout(L) + PW] = ADD ? bo + cb : bo;
+}
+
+// the block's gradient sums for one instance -> gradient row `row`; accumulators reset.
+// Fixed pairwise order (w0 + w1) + (w2 + w3): waves 1 and 3 store into two LDS
+// regions (red, and the transpose tiles, idle here), waves 0 and 2 add theirs, and
+// the two regions are added on the way out.
 template <int L>
 __device__ __forceinline__ void flush_grad(BwdShared<L> &S, const BwdArgs &A, int64_t row, GradAcc<L> &G, int tid,
                                            int wave, int lane) {
+    static_assert(kFWaves == 4, "pairwise flush assumes four wavefronts");
+    static_assert(n_padded(L) <= kFWaves * 2 * 16 * kTs, "second region must fit the transpose tiles");
+    float *R0 = S.red, *R1 = &S.tt[0][0][0][0];
+    float *mine = (wave >> 1) ? R1 : R0;
     __syncthreads();
-    float *red = S.red;
-    const int g = lane >> 4, c = lane & 15;
-    const bool lo = lane < 32;
-    const float(*VA)[64] = S.vacc[wave];
-    const int hi = lane ^ 32;
-    // waves add their sums into red in wave order; a wave issues all of its reads
-    // before its writes, so each turn costs one LDS round trip
-    constexpr int NW = 16 * (L > 1 ? L - 1 : 0);
-    for (int w = 0; w < kFWaves; ++w) {
-        if (wave == w) {
-            const bool first = (w == 0);
-            float cw[NW > 0 ? NW : 1], cv[L + 3], cb = 0.f;
-            if (!first) {
-#pragma unroll
-                for (int l = 2; l <= L; ++l)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            cw[16 * (l - 2) + 4 * t + r] =
-                                red[off_w(l) + (16 * (t >> 1) + 4 * g + r) * PW + 16 * (t & 1) + c];
-                if (lo) {
-#pragma unroll
-                    for (int l = 1; l <= L; ++l) cv[l - 1] = red[off_b(l) + lane];
-                    cv[L] = red[off_w(1) + 2 * lane];
-                    cv[L + 1] = red[off_w(1) + 2 * lane + 1];
-                    cv[L + 2] = red[off_wout(L) + lane];
-                }
-                if (lane == 0) cb = red[off_wout(L) + PW];
-            } else {
-#pragma unroll
-                for (int i = 0; i < (NW > 0 ? NW : 1); ++i) cw[i] = 0.f;
-#pragma unroll
-                for (int i = 0; i < L + 3; ++i) cv[i] = 0.f;
-            }
-            const float bo = wave_sum(VA[L + 3][lane]);
-#pragma unroll
-            for (int l = 2; l <= L; ++l)
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        red[off_w(l) + (16 * (t >> 1) + 4 * g + r) * PW + 16 * (t & 1) + c] =
-                            cw[16 * (l - 2) + 4 * t + r] + G.w[l - 2][t][r];
-            if (lo) {
-#pragma unroll
-                for (int l = 1; l <= L; ++l) red[off_b(l) + lane] = cv[l - 1] + (VA[l - 1][lane] + VA[l - 1][hi]);
-                red[off_w(1) + 2 * lane] = cv[L] + (VA[L][lane] + VA[L][hi]);
-                red[off_w(1) + 2 * lane + 1] = cv[L + 1] + (VA[L + 1][lane] + VA[L + 1][hi]);
-                red[off_wout(L) + lane] = cv[L + 2] + (VA[L + 2][lane] + VA[L + 2][hi]);
-            }
-            if (lane == 0) red[off_wout(L) + PW] = cb + bo;
-        }
-        __syncthreads();
-    }
-    for (int j = tid; j < n_padded(L); j += kFThreads) A.gpart[row * kMaxPadded + j] = red[j];
+    if (wave & 1) put_partial<L, false>(mine, G, S.vacc[wave], lane);
+    __syncthreads();
+    if (!(wave & 1)) put_partial<L, true>(mine, G, S.vacc[wave], lane);
+    __syncthreads();
+    for (int j = tid; j < n_padded(L); j += kFThreads) A.gpart[row * kMaxPadded + j] = R0[j] + R1[j];
     zero_acc<L>(G);
     for (int t = tid; t < kFWaves * (L + 4) * 64; t += kFThreads) (&S.vacc[0][0][0])[t] = 0.f;
     __syncthreads();
@@ -839,11 +863,19 @@ __global__ __launch_bounds__(kFThreads, kBwdBlocksPerCU) void k_bwd(BwdArgs A) {
         __syncthreads();
         load_weights<L>(S.W, S.red, A.params + (int64_t)cur * A.param_stride, A.H, tid);
         __syncthreads();
+        // the next tile's point and adjoint are loaded while this tile computes
+        auto fetch = [&](int64_t tt, float2 &p, float2 &d) {
+            const int64_t idx = 16 * (tt - tile0) + (lane & 15);
+            const bool ok = tt < seg_end && idx < n_all;
+            p = ok ? pts[idx] : make_float2(0.f, 0.f);
+            d = ok ? ub_i[idx] : make_float2(0.f, 0.f);
+        };
+        float2 pn, dn;
+        fetch(t + wrot, pn, dn);
         for (int64_t tt = t + wrot; tt < seg_end; tt += kFWaves) {
             const int64_t idx = 16 * (tt - tile0) + (lane & 15);
-            const bool valid = idx < n_all;
-            const float2 p = valid ? pts[idx] : make_float2(0.f, 0.f);
-            const float2 d = valid ? ub_i[idx] : make_float2(0.f, 0.f);
+            const float2 p = pn, d = dn;
+            fetch(tt + kFWaves, pn, dn);
             const bool interior = idx < n_pts;
             const float ub = interior ? 0.f : d.x, uxb = interior ? d.x : 0.f, uyb = interior ? d.y : 0.f;
             Acts<L> K;
