@@ -52,8 +52,12 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFThreads = 256;
 constexpr int kFwdBlocksPerCU = 2;  // forward/contraction blocks resident per CU
-constexpr int kBwdBlocksPerCU = 2;  // backward blocks resident per CU (register-limited: ~250 VGPRs)
 constexpr int kFWaves = kFThreads / 64;
+// backward: one block of eight wavefronts per CU (two per SIMD, register-limited at ~250
+// VGPRs); tiles are dealt round-robin over the eight, which bounds every SIMD's share
+// within one tile of the mean, and the weights are held once per CU
+constexpr int kBThreads = 512;
+constexpr int kBWaves = kBThreads / 64;
 constexpr int kTs = 36;            // transpose tile row stride (floats)
 constexpr int kMaxBlocks = 1024;
 constexpr int kKB = 32;            // test functions held in registers by the fast contraction
@@ -96,11 +100,15 @@ struct FwdShared {
 template <int L>
 struct BwdShared {
     WeightsShared<L> W;
-    // per-wavefront transpose tiles [2][16 points][kTs]
-    float tt[kFWaves][2][16][kTs];
+    union {
+        // per-wavefront transpose tiles [2][16 points][kTs]
+        float tt[kBWaves][2][16][kTs];
+        // during the flush: three of the four pair-sum regions (the fourth is red)
+        float part[3][n_padded(L)];
+    };
     // per-wavefront column sums of the vector-shaped gradients, one slot per lane:
     // [0, L) biases b_l, L: W1 column 0, L+1: W1 column 1, L+2: W_out, L+3: b_out
-    float vacc[kFWaves][L + 4][64];
+    float vacc[kBWaves][L + 4][64];
     float red[n_padded(L)];
 };
 
@@ -456,53 +464,51 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
 // weights of one instance -> LDS (padded to 32, fragment order for the MFMA A operands).
 // The flat parameters are first copied into `stage` with every thread's loads in
 // flight at once (npf <= n_padded(L)), then rearranged LDS to LDS.
-template <int L>
+template <int L, int NT>
 __device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, const float *__restrict__ P, int H,
                                              int tid) {
     const int npf = 3 * H + (L - 1) * (H * H + H) + H + 1;
-    constexpr int kLoads = (n_padded(L) + kFThreads - 1) / kFThreads;
+    constexpr int kLoads = (n_padded(L) + NT - 1) / NT;
     float v[kLoads];
 #pragma unroll
     for (int i = 0; i < kLoads; ++i) {
-        const int j = tid + i * kFThreads;
+        const int j = tid + i * NT;
         v[i] = j < npf ? P[j] : 0.f;
     }
 #pragma unroll
     for (int i = 0; i < kLoads; ++i) {
-        const int j = tid + i * kFThreads;
+        const int j = tid + i * NT;
         if (j < npf) stage[j] = v[i];
     }
     __syncthreads();
-    for (int t = tid; t < PW * 2; t += kFThreads) {
+    for (int t = tid; t < PW * 2; t += NT) {
         const int o = t >> 1, i = t & 1;
         S.w1[o][i] = o < H ? stage[o * 2 + i] : 0.f;
     }
-    for (int t = tid; t < L * PW; t += kFThreads) {
+    for (int t = tid; t < L * PW; t += NT) {
         const int l = t / PW + 1, o = t % PW;
         const int off = (l == 1) ? 2 * H : (int)hoff_w(H, l) + H * H;
         S.b[l - 1][o] = o < H ? stage[off + o] : 0.f;
     }
-    for (int t = tid; t < PW; t += kFThreads) S.wo[t] = t < H ? stage[hoff_w(H, L + 1) + t] : 0.f;
+    for (int t = tid; t < PW; t += NT) S.wo[t] = t < H ? stage[hoff_w(H, L + 1) + t] : 0.f;
     if (tid == 0) S.bo = stage[hoff_w(H, L + 1) + H];
-    // fragments: thread tid fills lane ln = tid % 64, slot s = tid / 64 + 4 m of every
-    // (l, dir, mt, m); all reads are issued before the writes
-    static_assert(kFThreads == 256, "fragment fill assumes four wavefronts");
-    constexpr int kFr = (L - 1) * 8;
-    const int ln = tid & 63, r = tid >> 6, c = ln & 15, q = 4 * (ln >> 4) + r;
+    // fragments [l][dir][mt][slot][lane] in flat order, NT consecutive entries per
+    // pass; all reads are issued before the writes
+    static_assert(NT % 64 == 0 && (2 * 2 * 8 * 64) % NT == 0, "fragment fill: whole passes per layer");
+    constexpr int kFr = (L - 1) * 2 * 2 * 8 * 64 / NT;
     float f[kFr > 0 ? kFr : 1];
 #pragma unroll
     for (int k = 0; k < kFr; ++k) {
-        const int m = k & 1, mt = (k >> 1) & 1, dir = (k >> 2) & 1, l = 2 + (k >> 3);
+        const int t = tid + NT * k;
+        const int ln = t & 63, sl = (t >> 6) & 7, mt = (t >> 9) & 1, dir = (t >> 10) & 1, l = 2 + (t >> 11);
+        const int c = ln & 15, q = 4 * (ln >> 4) + (sl & 3), m = sl >> 2;
         // forward: W[16 mt + c][16 m + q]; backward: W[16 m + q][16 mt + c]
         const int o = dir == 0 ? 16 * mt + c : 16 * m + q;
         const int i = dir == 0 ? 16 * m + q : 16 * mt + c;
         f[k] = (o < H && i < H) ? stage[hoff_w(H, l) + o * H + i] : 0.f;
     }
 #pragma unroll
-    for (int k = 0; k < kFr; ++k) {
-        const int m = k & 1, mt = (k >> 1) & 1, dir = (k >> 2) & 1, l = 2 + (k >> 3);
-        S.wf[l - 2][dir][mt][r + 4 * m][ln] = f[k];
-    }
+    for (int k = 0; k < kFr; ++k) (&S.wf[0][0][0][0][0])[tid + NT * k] = f[k];
 }
 
 template <int L>
@@ -551,7 +557,7 @@ __global__ __launch_bounds__(kFThreads, kFwdBlocksPerCU) void k_fwd_contract(Fwd
             I = A.inst[inst];
             eps = A.eps ? A.eps[inst] : 1.0f;
             __syncthreads();
-            load_weights<L>(S.W, S.stage, A.params + (int64_t)inst * A.param_stride, H, tid);
+            load_weights<L, kFThreads>(S.W, S.stage, A.params + (int64_t)inst * A.param_stride, H, tid);
             __syncthreads();
         }
         const int64_t item = git - I.item0;
@@ -814,42 +820,39 @@ __device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const
 }
 
 // the block's gradient sums for one instance -> gradient row `row`; accumulators reset.
-// Fixed pairwise order (w0 + w1) + (w2 + w3): waves 1 and 3 store into two LDS
-// regions (red, and the transpose tiles, idle here), waves 0 and 2 add theirs, and
-// the two regions are added on the way out.
+// Fixed order ((w0 + w1) + (w2 + w3)) + ((w4 + w5) + (w6 + w7)): odd wavefronts store
+// into four LDS regions (red, and three over the transpose tiles, idle here), even ones
+// add theirs, and the four regions are added on the way out.
 template <int L>
 __device__ __forceinline__ void flush_grad(BwdShared<L> &S, const BwdArgs &A, int64_t row, GradAcc<L> &G, int tid,
                                            int wave, int lane) {
-    static_assert(kFWaves == 4, "pairwise flush assumes four wavefronts");
-    static_assert(n_padded(L) <= kFWaves * 2 * 16 * kTs, "second region must fit the transpose tiles");
-    float *R0 = S.red, *R1 = &S.tt[0][0][0][0];
-    float *mine = (wave >> 1) ? R1 : R0;
+    static_assert(kBWaves == 8, "pairwise flush assumes eight wavefronts");
+    float *mine = (wave >> 1) == 0 ? S.red : S.part[(wave >> 1) - 1];
     __syncthreads();
     if (wave & 1) put_partial<L, false>(mine, G, S.vacc[wave], lane);
     __syncthreads();
     if (!(wave & 1)) put_partial<L, true>(mine, G, S.vacc[wave], lane);
     __syncthreads();
-    for (int j = tid; j < n_padded(L); j += kFThreads) A.gpart[row * kMaxPadded + j] = R0[j] + R1[j];
+    for (int j = tid; j < n_padded(L); j += kBThreads)
+        A.gpart[row * kMaxPadded + j] = (S.red[j] + S.part[0][j]) + (S.part[1][j] + S.part[2][j]);
     zero_acc<L>(G);
-    for (int t = tid; t < kFWaves * (L + 4) * 64; t += kFThreads) (&S.vacc[0][0][0])[t] = 0.f;
+    for (int t = tid; t < kBWaves * (L + 4) * 64; t += kBThreads) (&S.vacc[0][0][0])[t] = 0.f;
     __syncthreads();
 }
 
 // 4: reverse sweep, tiles of 16 points spread evenly over all wavefronts; the
 // forward pass of each tile is recomputed (tanh included) and kept in registers
 template <int L>
-__global__ __launch_bounds__(kFThreads, kBwdBlocksPerCU) void k_bwd(BwdArgs A) {
+__global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
     __shared__ BwdShared<L> S;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     float(*T0)[kTs] = S.tt[wave][0];
     float(*T1)[kTs] = S.tt[wave][1];
     GradAcc<L> G;
     zero_acc<L>(G);
-    for (int t = tid; t < kFWaves * (L + 4) * 64; t += kFThreads) (&S.vacc[0][0][0])[t] = 0.f;
-    // the extra tile of a ragged range goes to a block-dependent wavefront, so the
-    // blocks sharing a CU do not stack their extras on one SIMD
-    const int wrot = (wave + (int)(blockIdx.x % kFWaves)) % kFWaves;
+    for (int t = tid; t < kBWaves * (L + 4) * 64; t += kBThreads) (&S.vacc[0][0][0])[t] = 0.f;
     int64_t t = A.blk_tiles[blockIdx.x];
+    const int64_t t_blk = t;
     const int64_t t_end = A.blk_tiles[blockIdx.x + 1];
     int cur = A.blk_inst0[blockIdx.x];
     while (t < t_end) {
@@ -861,7 +864,7 @@ __global__ __launch_bounds__(kFThreads, kBwdBlocksPerCU) void k_bwd(BwdArgs A) {
         const int64_t seg_end = min(t_end, tile0 + Ip->n_tiles);
         const int64_t row = Ip->grow0 + (int64_t)(blockIdx.x - Ip->gblk0);
         __syncthreads();
-        load_weights<L>(S.W, S.red, A.params + (int64_t)cur * A.param_stride, A.H, tid);
+        load_weights<L, kBThreads>(S.W, S.red, A.params + (int64_t)cur * A.param_stride, A.H, tid);
         __syncthreads();
         // the next tile's point and adjoint are loaded while this tile computes
         auto fetch = [&](int64_t tt, float2 &p, float2 &d) {
@@ -871,11 +874,13 @@ __global__ __launch_bounds__(kFThreads, kBwdBlocksPerCU) void k_bwd(BwdArgs A) {
             d = ok ? ub_i[idx] : make_float2(0.f, 0.f);
         };
         float2 pn, dn;
-        fetch(t + wrot, pn, dn);
-        for (int64_t tt = t + wrot; tt < seg_end; tt += kFWaves) {
+        // the block's tiles go round-robin over its wavefronts, continuing across instances
+        const int64_t first = t + (int64_t)((wave - (int)((t - t_blk) % kBWaves) + kBWaves) % kBWaves);
+        fetch(first, pn, dn);
+        for (int64_t tt = first; tt < seg_end; tt += kBWaves) {
             const int64_t idx = 16 * (tt - tile0) + (lane & 15);
             const float2 p = pn, d = dn;
-            fetch(tt + kFWaves, pn, dn);
+            fetch(tt + kBWaves, pn, dn);
             const bool interior = idx < n_pts;
             const float ub = interior ? 0.f : d.x, uxb = interior ? d.x : 0.f, uyb = interior ? d.y : 0.f;
             Acts<L> K;
@@ -1143,7 +1148,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         }
     }
     // backward blocks: equal shares of the tile list
-    const int bblocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus * kBwdBlocksPerCU, kMaxBlocks), tiles);
+    const int bblocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus, kMaxBlocks), tiles);
     std::vector<int64_t> bt(bblocks + 1);
     std::vector<int> binst(bblocks);
     for (int b = 0; b <= bblocks; ++b) bt[b] = (int64_t)b * tiles / bblocks;
@@ -1223,7 +1228,7 @@ static void launch_all(const FusedPlan &P, const FwdArgs &fa, const BwdArgs &ba,
     if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
     k_fwd_contract<L><<<P.fblocks, kFThreads, P.dyn, s>>>(fa);
     if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
-    if (want_grad) k_bwd<L><<<P.bblocks, kFThreads, 0, s>>>(ba);
+    if (want_grad) k_bwd<L><<<P.bblocks, kBThreads, 0, s>>>(ba);
     if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
     k_fused_final<L><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf,
                                         loss, grad, grad_eps, ad);

@@ -1,11 +1,11 @@
 // The unfused ("plain") HIP path: one kernel per stage of Algorithm 3 and its
 // backward pass, with every intermediate materialised in device memory, as a
 // tensor framework would run it:
-//   k_fwd          network values and the two spatial tangents at every point,
+//   k_plain_fwd          network values and the two spatial tangents at every point,
 //                  storing the activations (Sec. 2.2; forward-mode derivatives)
-//   k_contract     A[e,k] = sum_q (u_x G_x + u_y G_y), R = eps A - F, sum_k R^2
-//   k_adj_contract dL/du_x[e,q] = eps sum_k 2 c_v R[e,k] G_x[e,k,q] (and y)
-//   k_bwd          reverse sweep through value and tangent graphs, per-block
+//   k_plain_contract     A[e,k] = sum_q (u_x G_x + u_y G_y), R = eps A - F, sum_k R^2
+//   k_plain_adj_contract dL/du_x[e,q] = eps sum_k 2 c_v R[e,k] G_x[e,k,q] (and y)
+//   k_plain_bwd          reverse sweep through value and tangent graphs, per-block
 //                  weight-gradient partials
 //   k_final_*      fixed-order reductions of the loss and gradient partials
 // One lane owns one point; weights are wavefront-uniform (scalar loads).
@@ -17,7 +17,7 @@ namespace vp {
 // ---------------------------------------------------------------------------
 // parameter layout conversion
 // ---------------------------------------------------------------------------
-__global__ void k_pack(const float *__restrict__ src, int H, int L, float *__restrict__ dst) {
+__global__ void k_plain_pack(const float *__restrict__ src, int H, int L, float *__restrict__ dst) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_padded(L)) return;
     float v = 0.0f;
@@ -66,7 +66,7 @@ __device__ inline int padded_index(int H, int L, int64_t j) {
 }
 
 // grad[j] = sum over partial rows of the padded entry of j, in row order
-__global__ void k_final_grad(const float *__restrict__ gpart, int rows, int H, int L, int64_t np_flat,
+__global__ void k_plain_final_grad(const float *__restrict__ gpart, int rows, int H, int L, int64_t np_flat,
                              float *__restrict__ grad) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= np_flat) return;
@@ -90,7 +90,7 @@ __device__ inline double block_sum(double v, double *red) {
     return r;
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_final_loss(
+__global__ __launch_bounds__(kFinThreads) void k_plain_final_loss(
     const double *__restrict__ lv_part, int64_t n_lv, double cv, const double *__restrict__ ep_part, int64_t n_ep,
     const float *__restrict__ u, const float *__restrict__ tgt, int64_t n_int, int64_t n_bnd, int64_t n_sen,
     float tau, float gamma, float *__restrict__ loss_out, float *__restrict__ grad_eps) {
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kFinThreads) void k_final_loss(
 __host__ __device__ constexpr int act_slots(int L) { return 32 + 96 * (L - 1); }
 
 template <int L>
-__global__ __launch_bounds__(256) void k_fwd(const float *__restrict__ w, const float2 *__restrict__ pts,
+__global__ __launch_bounds__(256) void k_plain_fwd(const float *__restrict__ w, const float2 *__restrict__ pts,
                                              int64_t np, float *__restrict__ u, float *__restrict__ ux,
                                              float *__restrict__ uy, float *__restrict__ act) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_fwd(const float *__restrict__ w, const 
 // ---------------------------------------------------------------------------
 // contraction (Alg. 3): wavefront per element, lanes over quadrature points
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_contract(const float *__restrict__ Gx, const float *__restrict__ Gy,
+__global__ __launch_bounds__(256) void k_plain_contract(const float *__restrict__ Gx, const float *__restrict__ Gy,
                                                   const float *__restrict__ F, const float *__restrict__ ux,
                                                   const float *__restrict__ uy, const float *__restrict__ eps_ptr,
                                                   int64_t n_elem, int nq, int ntest, float *__restrict__ A,
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_contract(const float *__restrict__ Gx, 
 }
 
 // adjoint of the contraction, thread per interior point
-__global__ __launch_bounds__(256) void k_adj_contract(const float *__restrict__ Gx, const float *__restrict__ Gy,
+__global__ __launch_bounds__(256) void k_plain_adj_contract(const float *__restrict__ Gx, const float *__restrict__ Gy,
                                                       const float *__restrict__ R, const float *__restrict__ eps_ptr,
                                                       float two_cv, int64_t n_elem, int nq, int ntest,
                                                       float *__restrict__ uxb, float *__restrict__ uyb) {
@@ -332,7 +332,7 @@ __device__ inline void column_sum(float (*Zs)[kLs], int lane, const float v[PW],
 }
 
 template <int L>
-__global__ __launch_bounds__(kBwdThreads) void k_bwd(const float *__restrict__ w, const float2 *__restrict__ pts,
+__global__ __launch_bounds__(kBwdThreads) void k_plain_bwd(const float *__restrict__ w, const float2 *__restrict__ pts,
                                                      int64_t n_int, int64_t np, const float *__restrict__ act,
                                                      const float *__restrict__ uxb_in,
                                                      const float *__restrict__ uyb_in, const float *__restrict__ u,
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd(const float *__restrict__ w
 // launchers
 // ---------------------------------------------------------------------------
 vpinn_status pack_params(const float *d_params, int H, int L, float *d_wpad, hipStream_t s) {
-    k_pack<<<(n_padded(L) + 255) / 256, 256, 0, s>>>(d_params, H, L, d_wpad);
+    k_plain_pack<<<(n_padded(L) + 255) / 256, 256, 0, s>>>(d_params, H, L, d_wpad);
     VP_HIP(hipGetLastError());
     return VPINN_OK;
 }
@@ -478,7 +478,7 @@ vpinn_status pack_params(const float *d_params, int H, int L, float *d_wpad, hip
 template <int L>
 static void launch_fwd(const float *w, const float2 *pts, int64_t np, float *u, float *ux, float *uy, float *act,
                        hipStream_t s) {
-    k_fwd<L><<<dim3((unsigned)((np + 255) / 256)), 256, 0, s>>>(w, pts, np, u, ux, uy, act);
+    k_plain_fwd<L><<<dim3((unsigned)((np + 255) / 256)), 256, 0, s>>>(w, pts, np, u, ux, uy, act);
 }
 
 static vpinn_status fwd_dispatch(int L, const float *w, const float2 *pts, int64_t np, float *u, float *ux, float *uy,
@@ -506,7 +506,7 @@ template <int L>
 static void launch_bwd(int blocks, const float *w, const float2 *pts, int64_t n_int, int64_t np, const float *act,
                        const float *uxb, const float *uyb, const float *u, const float *tgt, int64_t n_bnd,
                        float wb2, float ws2, float *gpart, hipStream_t s) {
-    k_bwd<L><<<blocks, kBwdThreads, 0, s>>>(w, pts, n_int, np, act, uxb, uyb, u, tgt, n_bnd, wb2, ws2, gpart);
+    k_plain_bwd<L><<<blocks, kBwdThreads, 0, s>>>(w, pts, n_int, np, act, uxb, uyb, u, tgt, n_bnd, wb2, ws2, gpart);
 }
 
 vpinn_status plain_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
@@ -538,14 +538,14 @@ vpinn_status plain_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
                       want_grad ? p->act.as<float>() : nullptr, s);
     if (st) return st;
     float *R = d_R_out ? d_R_out : p->R.as<float>();
-    k_contract<<<dim3((unsigned)((p->n_elem + 3) / 4)), 256, 0, s>>>(
+    k_plain_contract<<<dim3((unsigned)((p->n_elem + 3) / 4)), 256, 0, s>>>(
         p->Gx.as<float>(), p->Gy.as<float>(), p->F.as<float>(), p->ux.as<float>(), p->uy.as<float>(), d_eps,
         p->n_elem, p->nq, p->ntest, p->A.as<float>(), R, p->loss_e.as<double>(), p->eps_part.as<double>());
     VP_HIP(hipGetLastError());
     if (d_R_out && !d_loss) return VPINN_OK;
     const double cv = cfg->loss_norm == VPINN_NORM_ELEM ? 1.0 / (double)p->n_elem : 1.0 / (double)p->ntest;
     if (want_grad) {
-        k_adj_contract<<<dim3((unsigned)((n_int + 255) / 256)), 256, 0, s>>>(
+        k_plain_adj_contract<<<dim3((unsigned)((n_int + 255) / 256)), 256, 0, s>>>(
             p->Gx.as<float>(), p->Gy.as<float>(), R, d_eps, (float)(2.0 * cv), p->n_elem, p->nq, p->ntest,
             p->uxb.as<float>(), p->uyb.as<float>());
         VP_HIP(hipGetLastError());
@@ -568,12 +568,12 @@ vpinn_status plain_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
         }
         VP_HIP(hipGetLastError());
         const int64_t npf = vpinn_n_params(H, L);
-        k_final_grad<<<dim3((unsigned)((npf + 255) / 256)), 256, 0, s>>>(p->gpart.as<float>(), bwd_blocks, H, L, npf,
+        k_plain_final_grad<<<dim3((unsigned)((npf + 255) / 256)), 256, 0, s>>>(p->gpart.as<float>(), bwd_blocks, H, L, npf,
                                                                       d_grad);
         VP_HIP(hipGetLastError());
     }
     if (d_loss || d_grad_eps) {
-        k_final_loss<<<1, kFinThreads, 0, s>>>(p->loss_e.as<double>(), p->n_elem, cv, p->eps_part.as<double>(),
+        k_plain_final_loss<<<1, kFinThreads, 0, s>>>(p->loss_e.as<double>(), p->n_elem, cv, p->eps_part.as<double>(),
                                                p->n_elem, p->u.as<float>(), p->tgt.as<float>(), n_int, p->n_bnd,
                                                p->n_sen, cfg->tau, cfg->gamma, d_loss, d_grad_eps);
         VP_HIP(hipGetLastError());
