@@ -203,13 +203,23 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
             f4 z, px = {0.f, 0.f, 0.f, 0.f}, py = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int r = 0; r < 4; ++r) z[r] = S.b[l - 1][16 * mo + 4 * g + r];
+            // the layer's weight fragments are read before the products (the scheduling
+            // barrier keeps the compiler from sinking the reads to their uses), and the MFMA
+            // cluster runs at raised wave priority, so the two wavefronts sharing a SIMD
+            // alternate between matrix and vector work instead of contending in step
+            float wv[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) wv[s] = S.wf[l - 2][0][mo][s][lane];
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                const float w = S.wf[l - 2][0][mo][s][lane];
+                const float w = wv[s];
                 z = mfma(w, A_.v[s >> 2][s & 3], z);
                 px = mfma(w, TX.v[s >> 2][s & 3], px);
                 py = mfma(w, TY.v[s >> 2][s & 3], py);
             }
+            __builtin_amdgcn_s_setprio(0);
             Z.v[mo] = z;
             PX.v[mo] = px;
             PY.v[mo] = py;
@@ -341,15 +351,25 @@ __device__ __forceinline__ void put_t_tangent1(float (*T)[kTs], int lane, const 
 __device__ __forceinline__ void wgrad_from_tiles(float (*T0)[kTs], float (*T1)[kTs], int lane, f4 acc[4]) {
     wave_sync();
     const int c = lane & 15, k = lane >> 4;
+    // every operand read is issued before the first product
+    float a0[4], a1[4], b0[4], b1[4];
 #pragma unroll
     for (int kp = 0; kp < 4; ++kp) {
-        const float a0 = T0[4 * kp + k][c], a1 = T0[4 * kp + k][16 + c];
-        const float b0 = T1[4 * kp + k][c], b1 = T1[4 * kp + k][16 + c];
-        acc[0] = mfma(a0, b0, acc[0]);
-        acc[1] = mfma(a0, b1, acc[1]);
-        acc[2] = mfma(a1, b0, acc[2]);
-        acc[3] = mfma(a1, b1, acc[3]);
+        a0[kp] = T0[4 * kp + k][c];
+        a1[kp] = T0[4 * kp + k][16 + c];
+        b0[kp] = T1[4 * kp + k][c];
+        b1[kp] = T1[4 * kp + k][16 + c];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int kp = 0; kp < 4; ++kp) {
+        acc[0] = mfma(a0[kp], b0[kp], acc[0]);
+        acc[1] = mfma(a0[kp], b1[kp], acc[1]);
+        acc[2] = mfma(a1[kp], b0[kp], acc[2]);
+        acc[3] = mfma(a1[kp], b1[kp], acc[3]);
+    }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 template <int L>
@@ -421,13 +441,19 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
             f4 sa = {0.f, 0.f, 0.f, 0.f}, sx = {0.f, 0.f, 0.f, 0.f}, sy = {0.f, 0.f, 0.f, 0.f};
+            float wv[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) wv[s] = S.wf[l - 2][1][mi][s][lane];
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                const float w = S.wf[l - 2][1][mi][s][lane];
+                const float w = wv[s];
                 sa = mfma(w, zb.v[s >> 2][s & 3], sa);
                 sx = mfma(w, pxb.v[s >> 2][s & 3], sx);
                 sy = mfma(w, pyb.v[s >> 2][s & 3], sy);
             }
+            __builtin_amdgcn_s_setprio(0);
             abar.v[mi] = sa;
             txbar.v[mi] = sx;
             tybar.v[mi] = sy;
