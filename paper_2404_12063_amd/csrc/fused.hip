@@ -1,33 +1,24 @@
 // Fused FastVPINNs loss and gradient (Algorithm 3 and its backward pass) on
 // gfx950, for one problem or a batch of independent problems.
 //
-// Three launches per evaluation: k_fwd_contract computes network values and
-// spatial tangents, the contraction R = eps sum_q (u_x G_x + u_y G_y) - F, the
-// loss terms and the adjoint of the contraction (dL/du per point, written to a
-// small device buffer); k_bwd runs the reverse sweep through the network for
-// tiles of 16 points spread evenly over all wavefronts; k_fused_final sums the
-// per-block partial rows in fixed order (and optionally applies Adam).  The
-// split gives each half its own register budget: three wavefronts per SIMD
-// without spills, where one kernel holding both halves needed 256 registers.
-//
-// Work decomposition.  A work item is a contiguous range of elements plus a
-// slice of the boundary/sensor points; 256-thread blocks (4 wavefronts, two
-// blocks per CU) take items round-robin.  Per item:
-//   1. forward (values + tangents) for all points of the item, tiles of 16
-//      points spread over the wavefronts; u_x, u_y (or u) go to LDS;
-//   2. contraction, thread per point over chunks of whole elements: every G
-//      load of the chunk is in flight before the first use; the per-point
-//      terms go through LDS to per-(element, test) row sums; 2 c_v R kept in
-//      LDS; loss partials;
-//   3. dL/du_x[q] = eps sum_k 2 c_v R[e,k] G_x[e,k,q] (and y) from the G values
-//      still in registers (a generic path reloads them for large elements);
-//   4. backward per tile: the forward pass is recomputed (tanh included) and
-//      the activations kept in registers for the reverse sweep.
-// The block's gradient accumulators live in registers across items.  At the
-// end every block writes one partial row; a second small kernel sums the rows
-// in block order and writes the outputs (no float atomics: bitwise
-// reproducible; the kernel boundary orders the partial writes before the
-// reads, which costs far less than a device-scope fence per block).
+// Four launches per evaluation, each shaped for its own bound:
+//   k_fwd      network values and spatial tangents at every point (MFMA), tiles
+//              of 16 points dealt round-robin over the wavefronts of one block
+//              per CU; interior points store (u_x, u_y), boundary and sensor
+//              points their mismatch loss partials and adjoint dL/du directly;
+//   k_contract the contraction R = eps sum_q (u_x G_x + u_y G_y) - F, the loss
+//              partials and the adjoint dL/du_x[q] = eps sum_k 2 c_v R_k G_x[k,q]
+//              (and y), one block per chunk of whole elements: each thread keeps
+//              its point's G values in registers between the two uses, so G is
+//              streamed from HBM once, by many small blocks (latency hidden by
+//              occupancy rather than by a register-heavy fused kernel);
+//   k_bwd      the reverse sweep through the network, same tiling as k_fwd; the
+//              forward pass of each tile is recomputed (tanh included) and the
+//              activations kept in registers;
+//   k_fused_final  fixed-order sum of the per-block partial rows into the
+//              outputs (and optionally Adam).
+// No float atomics anywhere: results are bitwise reproducible, and the kernel
+// boundaries order partial writes before their reads at no fence cost.
 //
 // Register layout of a 32-neuron vector over a 16-point tile ("chained"):
 // lane l holds point j = l % 16 and neurons 16 m + 4 g + r (g = l / 16,
@@ -50,9 +41,13 @@ namespace vp {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kFThreads = 256;
-constexpr int kFwdBlocksPerCU = 2;  // forward/contraction blocks resident per CU
-constexpr int kFWaves = kFThreads / 64;
+// forward: one block per CU; the forward alone needs few registers (~126), so
+// three wavefronts per SIMD hide each other's LDS and MFMA latencies
+constexpr int kFwThreads = 768;
+constexpr int kFwWaves = kFwThreads / 64;
+// contraction: many small blocks, one chunk of whole elements each
+constexpr int kCThreads = 256;
+constexpr int kCWaves = kCThreads / 64;
 // backward: one block of eight wavefronts per CU (two per SIMD, register-limited at ~250
 // VGPRs); tiles are dealt round-robin over the eight, which bounds every SIMD's share
 // within one tile of the mean, and the weights are held once per CU
@@ -60,8 +55,8 @@ constexpr int kBThreads = 512;
 constexpr int kBWaves = kBThreads / 64;
 constexpr int kTs = 36;            // transpose tile row stride (floats)
 constexpr int kMaxBlocks = 1024;
-constexpr int kKB = 32;            // test functions held in registers by the fast contraction
-constexpr int kCbs = kFThreads + 1;  // row stride of the per-point term buffer
+constexpr int kKB = 32;              // test functions held in registers by the fast contraction
+constexpr int kCbs = kCThreads + 1;  // row stride of the per-point term buffer
 
 struct Vec {
     f4 v[2];
@@ -93,8 +88,7 @@ template <int L>
 struct FwdShared {
     WeightsShared<L> W;
     float stage[n_padded(L)];  // flat parameters, staged for load_weights
-    // per-wavefront loss partials: sum R^2, sum R A, sum d_b^2, sum d_s^2
-    double lp[kFWaves][4];
+    double lp[kFwWaves][2];    // per-wavefront loss partials: sum d_b^2, sum d_s^2
 };
 
 template <int L>
@@ -118,13 +112,15 @@ struct InstDesc {
     const float2 *pts;        // interior points then boundary then sensors
     const float *tgt;         // boundary values then sensor observations
     int64_t n_elem, n_pts, n_bnd, n_sen;
-    int64_t n_items, item0;   // forward items item0 .. item0 + n_items - 1 of the global item list
-    int64_t n_tiles, tile0;   // backward tiles (16 points each) tile0 .. of the global tile list
-    int64_t ubase;            // offset of this instance's points in the adjoint buffer
-    int nq, ntest;
-    int fast;                 // nq <= kFThreads and ntest <= kKB: G stays in registers
-    int lrow0, lblk0, ln_rows;  // loss partial rows (forward blocks lblk0 ..)
-    int grow0, gblk0, gn_rows;  // gradient partial rows (backward blocks gblk0 ..)
+    int64_t n_tiles, tile0;   // tiles (16 points each) tile0 .. of the global tile list
+    int64_t ubase;            // offset of this instance's points in the point buffer
+    int64_t cblk0, n_chunks;  // contraction blocks cblk0 .. (epc elements each)
+    int nq, ntest, epc;
+    int fast;                 // nq <= kCThreads and ntest <= kKB: G stays in registers
+    // loss partial rows lrow0 .. lrow0 + ln_rows - 1: first one per tile block
+    // (gblk0 ..), then one per contraction block
+    int lrow0, ln_rows;
+    int grow0, gblk0, gn_rows;  // gradient partial rows (tile blocks gblk0 ..)
     float two_cv, wb2, ws2;   // 2 c_v, 2 tau / N_D, 2 gamma / N_s
     float tau, gamma;
     double cv;
@@ -132,17 +128,23 @@ struct InstDesc {
 
 struct FwdArgs {
     const InstDesc *inst;
-    const int *item_inst;       // [items] instance of each global item (instance-major order)
-    const int64_t *blk_items;   // [blocks + 1] global item range of each block
+    const int64_t *blk_tiles;   // [blocks + 1] global tile range of each block (shared with k_bwd)
+    const int *blk_inst0;       // instance of each block's first tile
     const float *params;        // [n_inst][param_stride] flat layout, width H
     int64_t param_stride;
-    const float *eps;           // [n_inst] or null (eps = 1)
     int H;
-    int want_grad;
-    int item_cap_pts;           // LDS capacity for item points
-    float2 *ubuf;               // adjoints dL/du_x, dL/du_y (interior) or dL/du (boundary, sensors)
+    float2 *ubuf;               // per point: (u_x, u_y) at interior points, (dL/du, 0) elsewhere
     double *lpart;              // [loss rows][4]
     int64_t *step;              // optional step counter, incremented once per launch
+};
+
+struct ContractArgs {
+    const InstDesc *inst;
+    const int *cblk_inst;       // [contraction blocks] instance of each block
+    const float *eps;           // [n_inst] or null (eps = 1)
+    int want_grad;
+    float2 *ubuf;               // in: (u_x, u_y); out: (dL/du_x, dL/du_y) at interior points
+    double *lpart;
 };
 
 struct BwdArgs {
@@ -155,16 +157,6 @@ struct BwdArgs {
     const float2 *ubuf;
     float *gpart;               // [gradient rows][kMaxPadded]
 };
-
-// element and extra-point ranges of item i of an instance (even split, no work list needed)
-__device__ __forceinline__ void item_range(const InstDesc &I, int64_t i, int64_t &e0, int64_t &e1, int64_t &x0,
-                                           int64_t &x1) {
-    const int64_t nx = I.n_bnd + I.n_sen;
-    e0 = i * I.n_elem / I.n_items;
-    e1 = (i + 1) * I.n_elem / I.n_items;
-    x0 = i * nx / I.n_items;
-    x1 = (i + 1) * nx / I.n_items;
-}
 
 // ---------------------------------------------------------------------------
 // forward through the network for one tile.  If `keep` is non-null the
@@ -282,27 +274,6 @@ __device__ __forceinline__ float col_sum(float (*T)[kTs], int lane) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) s += T[j0 + j][n];
     return s;
-}
-
-// weight gradient dW[o][i] += sum_points Zo[o] * Ai[i] via the transpose tiles;
-// acc[mo * 2 + mi] holds the 16x16 tile (rows 16 mo + 4 g + r, column 16 mi + lane % 16)
-__device__ __forceinline__ void wgrad(float (*T0)[kTs], float (*T1)[kTs], int lane, const Vec &Zo, const Vec &Ai,
-                                      f4 acc[4], float *bias_acc) {
-    put_t(T0, lane, Zo);
-    put_t(T1, lane, Ai);
-    wave_sync();
-    const int c = lane & 15, k = lane >> 4;
-#pragma unroll
-    for (int kp = 0; kp < 4; ++kp) {
-        const float a0 = T0[4 * kp + k][c], a1 = T0[4 * kp + k][16 + c];
-        const float b0 = T1[4 * kp + k][c], b1 = T1[4 * kp + k][16 + c];
-        acc[0] = mfma(a0, b0, acc[0]);
-        acc[1] = mfma(a0, b1, acc[1]);
-        acc[2] = mfma(a1, b0, acc[2]);
-        acc[3] = mfma(a1, b1, acc[3]);
-    }
-    if (bias_acc) *bias_acc += col_sum(T0, lane);
-    wave_sync();
 }
 
 __device__ __forceinline__ float colsum_vec(float (*T0)[kTs], int lane, const Vec &V) {
@@ -520,8 +491,9 @@ __device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, 
     if (tid == 0) S.bo = stage[hoff_w(H, L + 1) + H];
     // fragments [l][dir][mt][slot][lane] in flat order, NT consecutive entries per
     // pass; all reads are issued before the writes
-    static_assert(NT % 64 == 0 && (2 * 2 * 8 * 64) % NT == 0, "fragment fill: whole passes per layer");
-    constexpr int kFr = (L - 1) * 2 * 2 * 8 * 64 / NT;
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    constexpr int kTot = (L - 1) * 2 * 2 * 8 * 64;
+    constexpr int kFr = (kTot + NT - 1) / NT;
     float f[kFr > 0 ? kFr : 1];
 #pragma unroll
     for (int k = 0; k < kFr; ++k) {
@@ -531,10 +503,11 @@ __device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, 
         // forward: W[16 mt + c][16 m + q]; backward: W[16 m + q][16 mt + c]
         const int o = dir == 0 ? 16 * mt + c : 16 * m + q;
         const int i = dir == 0 ? 16 * m + q : 16 * mt + c;
-        f[k] = (o < H && i < H) ? stage[hoff_w(H, l) + o * H + i] : 0.f;
+        f[k] = (t < kTot && o < H && i < H) ? stage[hoff_w(H, l) + o * H + i] : 0.f;
     }
 #pragma unroll
-    for (int k = 0; k < kFr; ++k) (&S.wf[0][0][0][0][0])[tid + NT * k] = f[k];
+    for (int k = 0; k < kFr; ++k)
+        if (tid + NT * k < kTot) (&S.wf[0][0][0][0][0])[tid + NT * k] = f[k];
 }
 
 template <int L>
@@ -545,251 +518,203 @@ __device__ __forceinline__ void zero_acc(GradAcc<L> &G) {
         for (int t = 0; t < 4; ++t) G.w[l][t] = f4{0.f, 0.f, 0.f, 0.f};
 }
 
-// the block's loss sums for one instance -> loss row `row`
+// 1: forward values and tangents at every point.  Blocks own contiguous tile ranges
+// (the same ranges as k_bwd), possibly spanning instances; the tiles of a range go
+// round-robin over the block's wavefronts.
 template <int L>
-__device__ __forceinline__ void flush_loss(FwdShared<L> &S, const FwdArgs &A, int64_t row, int tid) {
-    __syncthreads();
-    if (tid < 4) {
-        double s = 0.0;
-        for (int w = 0; w < kFWaves; ++w) s += S.lp[w][tid];
-        A.lpart[row * 4 + tid] = s;
-    }
-    __syncthreads();
-    if (tid < kFWaves * 4) (&S.lp[0][0])[tid] = 0.0;
-    __syncthreads();
-}
-
-// 1-3: forward values and tangents, contraction, loss terms and the adjoint of the
-// contraction, per item (a contiguous range of elements and boundary/sensor points)
-template <int L>
-__global__ __launch_bounds__(kFThreads, kFwdBlocksPerCU) void k_fwd_contract(FwdArgs A) {
+__global__ __launch_bounds__(kFwThreads, 1) void k_fwd(FwdArgs A) {
     __shared__ FwdShared<L> S;
-    extern __shared__ float dyn[];  // item data: float2 per item point, then 2 c_v R per (element, test)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int H = A.H;
     if (A.step && blockIdx.x == 0 && tid == 0) *A.step += 1;
-    float2 *uxy = reinterpret_cast<float2 *>(dyn);
-    float *rbar = dyn + 2 * A.item_cap_pts;
-    if (tid < kFWaves * 4) (&S.lp[0][0])[tid] = 0.0;
-    int cur = -1;
-    InstDesc I;
-    float eps = 1.0f;
-    const int64_t it_begin = A.blk_items[blockIdx.x], it_end = A.blk_items[blockIdx.x + 1];
-    for (int64_t git = it_begin; git < it_end; ++git) {
-        const int inst = A.item_inst[git];
-        if (inst != cur) {
-            if (cur >= 0) flush_loss<L>(S, A, I.lrow0 + (int64_t)(blockIdx.x - I.lblk0), tid);
-            cur = inst;
-            I = A.inst[inst];
-            eps = A.eps ? A.eps[inst] : 1.0f;
-            __syncthreads();
-            load_weights<L, kFThreads>(S.W, S.stage, A.params + (int64_t)inst * A.param_stride, H, tid);
-            __syncthreads();
-        }
-        const int64_t item = git - I.item0;
-        double lrr = 0.0, lra = 0.0, lbb = 0.0, lss = 0.0;  // this item's loss partials (per thread)
-        int64_t e0, e1, x0, x1;
-        item_range(I, item, e0, e1, x0, x1);
-        const int ne = (int)(e1 - e0);
-        const int n_int = ne * I.nq;                 // interior points of the item
-        const int n_all = n_int + (int)(x1 - x0);     // plus boundary/sensor points
-        const int n_tiles = (n_all + 15) >> 4;
-        auto point_xy = [&](int idx) -> float2 {
-            if (idx < n_int) return I.pts[e0 * I.nq + idx];
-            return I.pts[I.n_pts + x0 + (idx - n_int)];
+    int64_t t = A.blk_tiles[blockIdx.x];
+    const int64_t t_end = A.blk_tiles[blockIdx.x + 1], t_blk = t;
+    int cur = A.blk_inst0[blockIdx.x];
+    while (t < t_end) {
+        const InstDesc *Ip = A.inst + cur;
+        const int64_t tile0 = Ip->tile0, n_pts = Ip->n_pts, n_bnd = Ip->n_bnd;
+        const int64_t n_all = n_pts + n_bnd + Ip->n_sen;
+        const float2 *__restrict__ pts = Ip->pts;
+        const float *__restrict__ tgt = Ip->tgt;
+        float2 *__restrict__ ub_i = A.ubuf + Ip->ubase;
+        const float wb2 = Ip->wb2, ws2 = Ip->ws2;
+        const int64_t seg_end = min(t_end, tile0 + Ip->n_tiles);
+        const int64_t row = Ip->lrow0 + (int64_t)(blockIdx.x - Ip->gblk0);
+        __syncthreads();
+        load_weights<L, kFwThreads>(S.W, S.stage, A.params + (int64_t)cur * A.param_stride, A.H, tid);
+        __syncthreads();
+        double lbb = 0.0, lss = 0.0;
+        // the next tile's point is loaded while this tile computes
+        auto fetch = [&](int64_t tt) -> float2 {
+            const int64_t idx = 16 * (tt - tile0) + (lane & 15);
+            return (tt < seg_end && idx < n_all) ? pts[idx] : make_float2(0.f, 0.f);
         };
-
-        // tiles go to wavefronts starting at a block-dependent offset, so the two
-        // blocks sharing a CU put their ragged extra tiles on different SIMDs
-        const int wrot = (wave + (int)((blockIdx.x + item) % kFWaves)) % kFWaves;
-        // 1. forward
-        float2 pn = (16 * wrot + (lane & 15) < n_all) ? point_xy(16 * wrot + (lane & 15)) : make_float2(0.f, 0.f);
-        for (int t = wrot; t < n_tiles; t += kFWaves) {
-            const int idx = 16 * t + (lane & 15);
-            const bool valid = idx < n_all;
+        const int64_t first = t + (int64_t)((wave - (int)((t - t_blk) % kFwWaves) + kFwWaves) % kFwWaves);
+        float2 pn = fetch(first);
+        for (int64_t tt = first; tt < seg_end; tt += kFwWaves) {
+            const int64_t idx = 16 * (tt - tile0) + (lane & 15);
             const float2 p = pn;
-            // the next tile's point is loaded while this tile computes
-            const int nidx = idx + 16 * kFWaves;
-            pn = nidx < n_all ? point_xy(nidx) : make_float2(0.f, 0.f);
+            pn = fetch(tt + kFwWaves);
             Vec a, tx, ty;
             Acts<L> unused;
             tile_forward<L, false>(S.W, lane, p.x, p.y, a, tx, ty, unused);
             float u, ux, uy;
             tile_outputs<L>(S.W, lane, a, tx, ty, u, ux, uy);
-            if (valid && lane < 16) uxy[idx] = idx < n_int ? make_float2(ux, uy) : make_float2(u, 0.f);
+            if (lane < 16 && idx < n_all) {
+                if (idx < n_pts) {
+                    ub_i[idx] = make_float2(ux, uy);
+                } else {
+                    // boundary (Sec. 2.3) or sensor (Sec. 4.7) mismatch: loss term and its adjoint
+                    const int64_t xi = idx - n_pts;
+                    const float d = u - tgt[xi];
+                    const bool bnd = xi < n_bnd;
+                    if (bnd) lbb += (double)d * (double)d;
+                    else lss += (double)d * (double)d;
+                    ub_i[idx] = make_float2((bnd ? wb2 : ws2) * d, 0.f);
+                }
+            }
+        }
+        // loss partials of the block for this instance, wavefronts added in order
+        const double vb = wave_sum(lbb), vs = wave_sum(lss);
+        if (lane == 0) {
+            S.lp[wave][0] = vb;
+            S.lp[wave][1] = vs;
         }
         __syncthreads();
+        if (tid < 4) {
+            double v = 0.0;
+            if (tid >= 2)
+                for (int w = 0; w < kFwWaves; ++w) v += S.lp[w][tid - 2];
+            A.lpart[row * 4 + tid] = v;
+        }
+        t = seg_end;
+        ++cur;
+    }
+}
 
-        if (I.fast) {
-            // 2+3. chunks of whole elements, thread (element, q); G of all tests in registers
-            float *cbuf = rbar + ne * I.ntest;  // [kKB][kCbs] per-point terms
-            const int epc = kFThreads / I.nq;
-            for (int c0 = 0; c0 < ne; c0 += epc) {
-                const int ce = min(epc, ne - c0);
-                const int el = c0 + tid / I.nq, q = tid - (tid / I.nq) * I.nq;
-                const bool act = tid < ce * I.nq;
-                const int64_t gbase = ((e0 + el) * I.ntest) * (int64_t)I.nq + q;
-                float gx[kKB], gy[kKB];
+// 2-3: contraction, variational loss terms and the adjoint of the contraction
+// (Algorithm 3 and its reverse), one block per chunk of epc whole elements.
+//   fast path (nq <= kCThreads, ntest <= kKB): thread (element, q) holds
+//     G_x[e,k,q], G_y[e,k,q] for all k in registers; the per-point terms
+//     u_x G_x + u_y G_y go through LDS to per-(element, test) row sums (eight
+//     lanes a row); then dL/du at q from the same registers;
+//   generic path (one element per block): rows by 16-lane groups, then the
+//     adjoint thread per q with G read again (cache-resident by then).
+__global__ __launch_bounds__(kCThreads) void k_contract(ContractArgs A) {
+    extern __shared__ float dyn[];
+    __shared__ double lp[kCWaves][2];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int inst = A.cblk_inst[blockIdx.x];
+    const InstDesc *Ip = A.inst + inst;
+    const int nq = Ip->nq, ntest = Ip->ntest;
+    const int64_t chunk = (int64_t)blockIdx.x - Ip->cblk0;
+    const int64_t e0 = chunk * Ip->epc;
+    const int ne = (int)min((int64_t)Ip->epc, Ip->n_elem - e0);
+    const float *__restrict__ Gx = Ip->Gx;
+    const float *__restrict__ Gy = Ip->Gy;
+    const float *__restrict__ F = Ip->F;
+    const float two_cv = Ip->two_cv;
+    const float eps = A.eps ? A.eps[inst] : 1.0f;
+    float2 *__restrict__ ub = A.ubuf + Ip->ubase;
+    double lrr = 0.0, lra = 0.0;
+    if (Ip->fast) {
+        float *cbuf = dyn;                  // [ntest][kCbs] per-point terms
+        float *rbar = dyn + ntest * kCbs;   // [ne][ntest] 2 c_v R
+        const int el = tid / nq, q = tid - el * nq;
+        const bool act = el < ne;
+        const int64_t gbase = ((e0 + el) * ntest) * (int64_t)nq + q;
+        float gx[kKB], gy[kKB];
 #pragma unroll
-                for (int k = 0; k < kKB; ++k) {
-                    const bool ok = act && k < I.ntest;
-                    gx[k] = ok ? I.Gx[gbase + (int64_t)k * I.nq] : 0.f;
-                    gy[k] = ok ? I.Gy[gbase + (int64_t)k * I.nq] : 0.f;
-                }
-                const float2 d = act ? uxy[el * I.nq + q] : make_float2(0.f, 0.f);
+        for (int k = 0; k < kKB; ++k) {
+            const bool ok = act && k < ntest;
+            gx[k] = ok ? Gx[gbase + (int64_t)k * nq] : 0.f;
+            gy[k] = ok ? Gy[gbase + (int64_t)k * nq] : 0.f;
+        }
+        const float2 d = act ? ub[(e0 + el) * nq + q] : make_float2(0.f, 0.f);
 #pragma unroll
-                for (int k = 0; k < kKB; ++k)
-                    if (k < I.ntest) cbuf[k * kCbs + tid] = fmaf(d.x, gx[k], d.y * gy[k]);
-                __syncthreads();
-                // row sums, 8 lanes per (element, test) row
-                for (int r8 = tid; r8 < 8 * ce * I.ntest; r8 += kFThreads) {
-                    const int r = r8 >> 3, part = r8 & 7;
-                    const int e2 = r / I.ntest, k = r - e2 * I.ntest;
-                    const float *row = cbuf + k * kCbs + e2 * I.nq;
-                    float a = 0.f;
-                    for (int qq = part; qq < I.nq; qq += 8) a += row[qq];
-                    a += __shfl_xor(a, 4, 8);
-                    a += __shfl_xor(a, 2, 8);
-                    a += __shfl_xor(a, 1, 8);
-                    if (part == 0) {
-                        const float R = eps * a - I.F[(e0 + c0 + e2) * I.ntest + k];
-                        rbar[(c0 + e2) * I.ntest + k] = I.two_cv * R;
-                        lrr += (double)R * (double)R;
-                        lra += (double)R * (double)a;
-                    }
-                }
-                __syncthreads();
-                if (A.want_grad && act) {
-                    // reload G (cache hits) rather than keep 2 kKB registers live across the barrier
-                    const float *rb = rbar + el * I.ntest;
-#pragma unroll
-                    for (int k = 0; k < kKB; ++k) {
-                        const bool ok = k < I.ntest;
-                        gx[k] = ok ? I.Gx[gbase + (int64_t)k * I.nq] : 0.f;
-                        gy[k] = ok ? I.Gy[gbase + (int64_t)k * I.nq] : 0.f;
-                    }
-                    float bx = 0.f, by = 0.f;
-#pragma unroll
-                    for (int k = 0; k < kKB; ++k)
-                        if (k < I.ntest) {
-                            bx = fmaf(rb[k], gx[k], bx);
-                            by = fmaf(rb[k], gy[k], by);
-                        }
-                    uxy[el * I.nq + q] = make_float2(eps * bx, eps * by);
-                }
-            }
-        } else {
-        // 2. contraction: rows (element, test function), 16 lanes per row, two rows per
-            //    batch, every load of a batch in flight before the first use
-            {
-                constexpr int kRG = kFThreads / 16;
-                const int rg = tid >> 4, rl = tid & 15;
-                const int n_rows = ne * I.ntest;
-                for (int r0 = 0; r0 < n_rows; r0 += 2 * kRG) {
-                    float acc[2] = {0.f, 0.f}, fv[2];
-                    int row[2];
-                    int64_t base[2];
-                    int el[2];
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        row[i] = r0 + rg + i * kRG;
-                        el[i] = row[i] / I.ntest;
-                        const int k = row[i] - el[i] * I.ntest;
-                        base[i] = ((e0 + el[i]) * I.ntest + k) * (int64_t)I.nq;
-                        fv[i] = row[i] < n_rows ? I.F[(e0 + el[i]) * I.ntest + k] : 0.f;
-                    }
-                    for (int qc = 0; qc < I.nq; qc += 128) {
-                        float gx[2][8], gy[2][8];
-#pragma unroll
-                        for (int i = 0; i < 2; ++i)
-#pragma unroll
-                            for (int t = 0; t < 8; ++t) {
-                                const int q = qc + rl + 16 * t;
-                                const bool ok = row[i] < n_rows && q < I.nq;
-                                gx[i][t] = ok ? I.Gx[base[i] + q] : 0.f;
-                                gy[i][t] = ok ? I.Gy[base[i] + q] : 0.f;
-                            }
-#pragma unroll
-                        for (int i = 0; i < 2; ++i)
-#pragma unroll
-                            for (int t = 0; t < 8; ++t) {
-                                const int q = qc + rl + 16 * t;
-                                if (row[i] < n_rows && q < I.nq) {
-                                    const float2 d = uxy[el[i] * I.nq + q];
-                                    acc[i] = fmaf(d.x, gx[i][t], fmaf(d.y, gy[i][t], acc[i]));
-                                }
-                            }
-                    }
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        float a = acc[i];
-                        a += __shfl_xor(a, 8, 16);
-                        a += __shfl_xor(a, 4, 16);
-                        a += __shfl_xor(a, 2, 16);
-                        a += __shfl_xor(a, 1, 16);
-                        if (rl == 0 && row[i] < n_rows) {
-                            const float R = eps * a - fv[i];
-                            rbar[row[i]] = I.two_cv * R;
-                            lrr += (double)R * (double)R;
-                            lra += (double)R * (double)a;
-                        }
-                    }
-                }
+        for (int k = 0; k < kKB; ++k)
+            if (k < ntest) cbuf[k * kCbs + tid] = fmaf(d.x, gx[k], d.y * gy[k]);
+        __syncthreads();
+        for (int r8 = tid; r8 < 8 * ne * ntest; r8 += kCThreads) {
+            const int r = r8 >> 3, part = r8 & 7;
+            const int e2 = r / ntest, k = r - e2 * ntest;
+            const float *rowp = cbuf + k * kCbs + e2 * nq;
+            float a = 0.f;
+            for (int qq = part; qq < nq; qq += 8) a += rowp[qq];
+            a += __shfl_xor(a, 4, 8);
+            a += __shfl_xor(a, 2, 8);
+            a += __shfl_xor(a, 1, 8);
+            if (part == 0) {
+                const float R = eps * a - F[(e0 + e2) * ntest + k];
+                rbar[e2 * ntest + k] = two_cv * R;
+                lrr += (double)R * (double)R;
+                lra += (double)R * (double)a;
             }
         }
-        for (int idx = n_int + tid; idx < n_all; idx += kFThreads) {
-            const int64_t xi = x0 + (idx - n_int);
-            const float d = uxy[idx].x - I.tgt[xi];
-            const bool bnd = xi < I.n_bnd;
-            if (bnd) lbb += (double)d * (double)d;
-            else lss += (double)d * (double)d;
-            uxy[idx] = make_float2((bnd ? I.wb2 : I.ws2) * d, 0.f);
+        __syncthreads();
+        if (A.want_grad && act) {
+            const float *rb = rbar + el * ntest;
+            float bx = 0.f, by = 0.f;
+#pragma unroll
+            for (int k = 0; k < kKB; ++k)
+                if (k < ntest) {
+                    bx = fmaf(rb[k], gx[k], bx);
+                    by = fmaf(rb[k], gy[k], by);
+                }
+            ub[(e0 + el) * nq + q] = make_float2(eps * bx, eps * by);
         }
-        {
-            const double v0 = wave_sum(lrr), v1 = wave_sum(lra), v2 = wave_sum(lbb), v3 = wave_sum(lss);
-            if (lane == 0) {
-                S.lp[wave][0] += v0;
-                S.lp[wave][1] += v1;
-                S.lp[wave][2] += v2;
-                S.lp[wave][3] += v3;
+    } else {
+        float *rbar = dyn;  // [ntest] 2 c_v R of the block's element
+        const int64_t ebase = e0 * ntest;
+        const float2 *__restrict__ uxy = ub + e0 * nq;
+        constexpr int kRG = kCThreads / 16;
+        const int rg = tid >> 4, rl = tid & 15;
+        for (int k0 = 0; k0 < ntest; k0 += kRG) {
+            const int k = k0 + rg;
+            float acc = 0.f;
+            if (k < ntest) {
+                const float *gxr = Gx + (ebase + k) * (int64_t)nq, *gyr = Gy + (ebase + k) * (int64_t)nq;
+                for (int q = rl; q < nq; q += 16) {
+                    const float2 d = uxy[q];
+                    acc = fmaf(d.x, gxr[q], fmaf(d.y, gyr[q], acc));
+                }
+            }
+            acc += __shfl_xor(acc, 8, 16);
+            acc += __shfl_xor(acc, 4, 16);
+            acc += __shfl_xor(acc, 2, 16);
+            acc += __shfl_xor(acc, 1, 16);
+            if (rl == 0 && k < ntest) {
+                const float R = eps * acc - F[ebase + k];
+                rbar[k] = two_cv * R;
+                lrr += (double)R * (double)R;
+                lra += (double)R * (double)acc;
             }
         }
         __syncthreads();
         if (A.want_grad) {
-            // 3. adjoint of the contraction (generic path), thread per point, 16 tests per batch
-            for (int idx = tid; idx < (I.fast ? 0 : n_int); idx += kFThreads) {
-                const int el = idx / I.nq, q = idx - el * I.nq;
-                const int64_t e = e0 + el;
-                const float *rb = rbar + el * I.ntest;
+            for (int q = tid; q < nq; q += kCThreads) {
                 float bx = 0.f, by = 0.f;
-                for (int k0 = 0; k0 < I.ntest; k0 += 16) {
-                    float gx[16], gy[16];
-#pragma unroll
-                    for (int t = 0; t < 16; ++t) {
-                        const int k = k0 + t;
-                        const int64_t o = (e * I.ntest + k) * (int64_t)I.nq + q;
-                        gx[t] = k < I.ntest ? I.Gx[o] : 0.f;
-                        gy[t] = k < I.ntest ? I.Gy[o] : 0.f;
-                    }
-#pragma unroll
-                    for (int t = 0; t < 16; ++t) {
-                        const float r = (k0 + t < I.ntest) ? rb[k0 + t] : 0.f;
-                        bx = fmaf(r, gx[t], bx);
-                        by = fmaf(r, gy[t], by);
-                    }
+                for (int k = 0; k < ntest; ++k) {
+                    const int64_t o = (ebase + k) * (int64_t)nq + q;
+                    bx = fmaf(rbar[k], Gx[o], bx);
+                    by = fmaf(rbar[k], Gy[o], by);
                 }
-                uxy[idx] = make_float2(eps * bx, eps * by);
-            }
-            __syncthreads();
-            // adjoints of the item's points -> the instance's slice of the adjoint buffer
-            for (int idx = tid; idx < n_all; idx += kFThreads) {
-                const int64_t pi = idx < n_int ? e0 * I.nq + idx : I.n_pts + x0 + (idx - n_int);
-                A.ubuf[I.ubase + pi] = uxy[idx];
+                ub[e0 * nq + q] = make_float2(eps * bx, eps * by);
             }
         }
-        __syncthreads();
     }
-    if (cur >= 0) flush_loss<L>(S, A, I.lrow0 + (int64_t)(blockIdx.x - I.lblk0), tid);
+    // loss partials of the block, wavefronts added in order
+    const double vr = wave_sum(lrr), va = wave_sum(lra);
+    if (lane == 0) {
+        lp[wave][0] = vr;
+        lp[wave][1] = va;
+    }
+    __syncthreads();
+    if (tid < 4) {
+        double v = 0.0;
+        if (tid < 2)
+            for (int w = 0; w < kCWaves; ++w) v += lp[w][tid];
+        A.lpart[(Ip->lrow0 + Ip->gn_rows + chunk) * 4 + tid] = v;
+    }
 }
 
 // one wavefront's gradient sums in padded order -> P (op: store, or add to what P holds)
@@ -925,10 +850,14 @@ __global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
 // per blockIdx.y; optionally followed by Adam (Kingma and Ba, Algorithm 1) on
 // that instance's parameters with the step count read from device memory
 // ---------------------------------------------------------------------------
-// block = 16 columns x 64 row slices; slice t sums rows t, t+64, ... in order,
-// then the 64 slice sums of a column are added in slice order (fixed order
-// for any launch).  Loss partials are summed by the x = 0 block the same way.
-constexpr int kFinCols = 16, kFinSlices = 64;
+// block = 64 columns (one per lane) x 16 wavefronts: wavefront w sums rows w,
+// w + 16, ... of its lane's column in order, then a column's 16 wavefront sums
+// are added in wavefront order.  Loss rows: the x = 0 block spreads them over
+// all its threads (thread i sums rows i, i + 1024, ...), adds each wavefront's
+// values with a fixed butterfly and the 16 wavefront sums in order.  The order
+// is fixed for a given plan, so results are bitwise reproducible.
+constexpr int kFinCols = 64, kFinWaves = 16, kFinThreads = kFinCols * kFinWaves;
+constexpr int kFinBatch = 16;  // row loads in flight per lane
 struct AdamArgs {
     float *params, *m, *v;
     const int64_t *step;
@@ -936,18 +865,18 @@ struct AdamArgs {
 };
 
 template <int L>
-__global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
+__global__ __launch_bounds__(kFinThreads) void k_fused_final(
     const InstDesc *__restrict__ inst, const float *__restrict__ gpart, const double *__restrict__ lpart, int H,
     int64_t npf, float *__restrict__ loss_out, float *__restrict__ grad_out, float *__restrict__ grad_eps_out,
     AdamArgs ad) {
-    __shared__ float part[kFinSlices][kFinCols + 1];
-    __shared__ double lred[kFinSlices][4];
+    __shared__ float part[kFinWaves][kFinCols];
+    __shared__ double lred[kFinWaves][4];
     const int ii = blockIdx.y;
     const InstDesc &I = inst[ii];
     const int rows = I.gn_rows, lrows = I.ln_rows;
     const float *gp = gpart + (int64_t)I.grow0 * kMaxPadded;
     const double *lp = lpart + (int64_t)I.lrow0 * 4;
-    const int c = threadIdx.x % kFinCols, t = threadIdx.x / kFinCols;
+    const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.x * kFinCols + c;
     const bool want = (grad_out || ad.params) && j < npf;
     int pj = -1;  // padded index of flat parameter j
@@ -967,37 +896,38 @@ __global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
     }
     float acc = 0.f;
     if (pj >= 0) {
-        for (int b0 = t; b0 < rows; b0 += 8 * kFinSlices) {
-            float v[8];
+        for (int b0 = w; b0 < rows; b0 += kFinBatch * kFinWaves) {
+            float v[kFinBatch];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int b = b0 + i * kFinSlices;
+            for (int i = 0; i < kFinBatch; ++i) {
+                const int b = b0 + i * kFinWaves;
                 v[i] = b < rows ? gp[(int64_t)b * kMaxPadded + pj] : 0.f;
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) acc += v[i];
+            for (int i = 0; i < kFinBatch; ++i) acc += v[i];
         }
     }
-    part[t][c] = acc;
-    if (blockIdx.x == 0 && c < 4) {
-        double l4 = 0.0;
-        for (int b0 = t; b0 < lrows; b0 += 8 * kFinSlices) {
-            double v[8];
+    part[w][c] = acc;
+    if (blockIdx.x == 0) {
+        double l4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = threadIdx.x; b < lrows; b += kFinThreads) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int b = b0 + i * kFinSlices;
-                v[i] = b < lrows ? lp[b * 4 + c] : 0.0;
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) l4 += v[i];
+            for (int i = 0; i < 4; ++i) l4[i] += lp[(int64_t)b * 4 + i];
         }
-        lred[t][c] = l4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double v = wave_sum(l4[i]);
+            if (c == 0) lred[w][i] = v;
+        }
     }
     __syncthreads();
-    if (t == 0 && pj >= 0) {
+    if (w == 0 && pj >= 0) {
+        float pv[kFinWaves];
+#pragma unroll
+        for (int q = 0; q < kFinWaves; ++q) pv[q] = part[q][c];
         float g = 0.f;
-#pragma unroll 8
-        for (int q = 0; q < kFinSlices; ++q) g += part[q][c];
+#pragma unroll
+        for (int q = 0; q < kFinWaves; ++q) g += pv[q];
         if (grad_out) grad_out[(int64_t)ii * npf + j] = g;
         if (ad.params) {
             const int64_t k = (int64_t)ii * npf + j;
@@ -1010,10 +940,11 @@ __global__ __launch_bounds__(kFinCols *kFinSlices) void k_fused_final(
             ad.params[k] -= ad.lr * (mi / c1) / (sqrtf(vi / c2) + ad.eps);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 64) {
         double tt[4] = {0, 0, 0, 0};
-#pragma unroll 4
-        for (int q = 0; q < kFinSlices; ++q)
+#pragma unroll
+        for (int q = 0; q < kFinWaves; ++q)
+#pragma unroll
             for (int i = 0; i < 4; ++i) tt[i] += lred[q][i];
         const double Lv = I.cv * tt[0];
         const double Lb = I.n_bnd ? tt[2] / (double)I.n_bnd : 0.0;
@@ -1042,74 +973,29 @@ static int cu_count(int dev) {
     return n;
 }
 
-// dynamic LDS available next to the static part (the device limit per workgroup minus the static size)
-template <int L>
-static size_t dyn_budget(int dev) {
-    hipDeviceProp_t prop;
-    size_t lim = 64 * 1024;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) lim = prop.sharedMemPerBlock;
-    const size_t stat = sizeof(FwdShared<L>) + 64;
-    return lim > stat ? lim - stat : 0;
-}
-
-static size_t dyn_budget_for(int L, int dev) {
-    switch (L) {
-    case 1: return dyn_budget<1>(dev);
-    case 2: return dyn_budget<2>(dev);
-    case 3: return dyn_budget<3>(dev);
-    default: return dyn_budget<4>(dev);
-    }
-}
-
-template <int L>
-static hipError_t set_dyn_attr(size_t dyn_bytes) {
-    return hipFuncSetAttribute((const void *)k_fwd_contract<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)dyn_bytes);
-}
-
 // A plan fixes, for a set of instances with one network shape and loss
-// weighting: the forward items of every instance and the contiguous item range
-// of every forward block (balanced by point count), the backward tiles and the
-// tile range of every backward block (equal tile counts), and which loss and
-// gradient partial rows each block writes.
+// weighting: the global tile list (16 points a tile, instance-major) and the
+// contiguous tile range of each of the one-per-CU blocks of k_fwd and k_bwd
+// (equal tile counts), the contraction chunks of every instance, and which loss
+// and gradient partial rows each block writes.
 struct FusedPlan {
-    DevBuf inst, item_inst, blk_items, blk_tiles, blk_inst0, ubuf, gpart, lpart;
+    DevBuf inst, blk_tiles, blk_inst0, cblk_inst, ubuf, gpart, lpart;
     std::vector<InstDesc> host_inst;
-    int fblocks = 0, bblocks = 0, n_inst = 0, grows = 0, lrows = 0, L = 0, H = 0;
-    int64_t items = 0, tiles = 0, npf = 0;
-    size_t dyn = 0;
-    int item_cap_pts = 0;
+    int tblocks = 0, n_inst = 0, grows = 0, lrows = 0, L = 0, H = 0;
+    int64_t cblocks = 0, tiles = 0, npf = 0;
+    size_t cdyn = 0;  // dynamic LDS of k_contract
 };
 
 static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_loss_cfg *cfg, int dev,
                                FusedPlan &P) {
     const int L = cfg->n_hidden, H = cfg->width;
     const int cus = cu_count(dev);
-    int64_t total_all = 0, elems_all = 0;
-    for (int i = 0; i < n; ++i) {
-        total_all += probs[i]->n_pts + probs[i]->n_bnd + probs[i]->n_sen;
-        elems_all += probs[i]->n_elem;
-    }
-    constexpr int kFwdPlanBlocksPerCU = 2;
-    const int max_blocks = (int)std::min<int64_t>(
-        std::min<int64_t>((int64_t)cus * kFwdPlanBlocksPerCU, kMaxBlocks), elems_all);
-    // item size: one instance gets a multiple of the block count of items (each
-    // at most ~2048 points); in a batch, items of about half a block's share
-    // of the points let the contiguous block ranges balance
-    const int64_t target = std::max<int64_t>(1, std::min<int64_t>(2048, total_all / (2 * (int64_t)max_blocks)));
-    const int64_t single_items =
-        std::min<int64_t>(elems_all, (int64_t)max_blocks * ((total_all + (int64_t)max_blocks * 2048 - 1) /
-                                                           ((int64_t)max_blocks * 2048)));
     std::vector<InstDesc> D(n);
-    std::vector<int64_t> item_pts;  // points per global item
-    std::vector<int> item_inst;
-    int cap_max = 0;
-    int64_t tiles = 0, ubase = 0;
+    int64_t tiles = 0, ubase = 0, cblocks = 0;
+    size_t cdyn = 16;
     for (int i = 0; i < n; ++i) {
         const vpinn_problem *p = probs[i];
-        const int64_t nx = p->n_bnd + p->n_sen, tot = p->n_pts + nx;
-        const int64_t ni = n == 1 ? single_items
-                                  : std::max<int64_t>(1, std::min<int64_t>(p->n_elem, (tot + target / 2) / target));
+        const int64_t tot = p->n_pts + p->n_bnd + p->n_sen;
         InstDesc &d = D[i];
         d = InstDesc{};
         d.Gx = p->Gx.as<float>();
@@ -1121,8 +1007,6 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         d.n_pts = p->n_pts;
         d.n_bnd = p->n_bnd;
         d.n_sen = p->n_sen;
-        d.n_items = ni;
-        d.item0 = (int64_t)item_inst.size();
         d.n_tiles = (tot + 15) / 16;
         d.tile0 = tiles;
         tiles += d.n_tiles;
@@ -1130,69 +1014,35 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         ubase += tot;
         d.nq = p->nq;
         d.ntest = p->ntest;
-        d.fast = (p->nq <= kFThreads && p->ntest <= kKB) ? 1 : 0;
+        d.fast = (p->nq <= kCThreads && p->ntest <= kKB) ? 1 : 0;
+        d.epc = d.fast ? std::max(1, kCThreads / p->nq) : 1;
+        d.n_chunks = (p->n_elem + d.epc - 1) / d.epc;
+        d.cblk0 = cblocks;
+        cblocks += d.n_chunks;
+        const size_t need = sizeof(float) * (d.fast ? (size_t)d.ntest * kCbs + (size_t)d.epc * d.ntest : (size_t)d.ntest);
+        cdyn = std::max(cdyn, need);
         d.cv = cfg->loss_norm == VPINN_NORM_ELEM ? 1.0 / (double)p->n_elem : 1.0 / (double)p->ntest;
         d.two_cv = (float)(2.0 * d.cv);
         d.wb2 = p->n_bnd ? (float)(2.0 * cfg->tau / (double)p->n_bnd) : 0.f;
         d.ws2 = p->n_sen ? (float)(2.0 * cfg->gamma / (double)p->n_sen) : 0.f;
         d.tau = cfg->tau;
         d.gamma = cfg->gamma;
-        for (int64_t it = 0; it < ni; ++it) {
-            const int64_t e0 = it * p->n_elem / ni, e1 = (it + 1) * p->n_elem / ni;
-            const int64_t x0 = it * nx / ni, x1 = (it + 1) * nx / ni;
-            item_pts.push_back((e1 - e0) * p->nq + (x1 - x0));
-            item_inst.push_back(i);
-        }
-        const int64_t max_e = (p->n_elem + ni - 1) / ni, max_x = (nx + ni - 1) / ni;
-        cap_max = (int)std::max<int64_t>(cap_max, max_e * p->nq + max_x);
     }
-    // the forward kernel's dynamic LDS: item points (float2), then 2 c_v R, then the contraction buffer
-    size_t dyn = 16;
-    for (int i = 0; i < n; ++i) {
-        const InstDesc &d = D[i];
-        const int64_t max_e = (d.n_elem + d.n_items - 1) / d.n_items;
-        const size_t need = sizeof(float) * (2 * (size_t)cap_max + max_e * d.ntest + (d.fast ? (size_t)d.ntest * kCbs : 0));
-        dyn = std::max(dyn, need);
-    }
-    if (dyn > dyn_budget_for(L, dev))
-        return fail(VPINN_E_UNSUPPORTED, "fused path: an element's quadrature and test data exceed the LDS budget");
-    // forward blocks: contiguous item ranges with about equal point counts
-    const int64_t items = (int64_t)item_inst.size();
-    const int fblocks = (int)std::min<int64_t>(max_blocks, items);
-    std::vector<int64_t> blk(fblocks + 1, items);
-    blk[0] = 0;
-    {
-        int64_t acc = 0, it = 0;
-        for (int b = 1; b < fblocks; ++b) {
-            const double goal = (double)total_all * b / fblocks;
-            while (it < items && (double)(acc + item_pts[it]) <= goal) acc += item_pts[it++];
-            // every block keeps at least one item
-            const int64_t lo = blk[b - 1] + 1, hi = items - (fblocks - b);
-            blk[b] = std::min<int64_t>(std::max<int64_t>(it, lo), hi);
-            while (it < blk[b]) acc += item_pts[it++];
-            while (it > blk[b]) acc -= item_pts[--it];
-        }
-    }
-    // backward blocks: equal shares of the tile list
-    const int bblocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus, kMaxBlocks), tiles);
-    std::vector<int64_t> bt(bblocks + 1);
-    std::vector<int> binst(bblocks);
-    for (int b = 0; b <= bblocks; ++b) bt[b] = (int64_t)b * tiles / bblocks;
-    // rows: instance i gets one loss row per forward block and one gradient row per
-    // backward block whose range meets its items / tiles
+    if (cblocks > (int64_t)INT32_MAX) return fail(VPINN_E_UNSUPPORTED, "fused path: too many elements for one launch");
+    if (cdyn > 64 * 1024) return fail(VPINN_E_UNSUPPORTED, "fused path: test-function count exceeds the LDS budget");
+    // tile blocks (k_fwd and k_bwd): one per CU, equal shares of the tile list
+    const int tblocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus, kMaxBlocks), tiles);
+    std::vector<int64_t> bt(tblocks + 1);
+    std::vector<int> binst(tblocks);
+    for (int b = 0; b <= tblocks; ++b) bt[b] = (int64_t)b * tiles / tblocks;
+    // rows: instance i gets one loss row and one gradient row per tile block whose
+    // range meets its tiles, then one loss row per contraction block
     int lrows = 0, grows = 0;
+    std::vector<int> cinst((size_t)cblocks);
     {
-        int fb = 0, bb = 0;
+        int bb = 0;
         for (int i = 0; i < n; ++i) {
             InstDesc &d = D[i];
-            const int64_t f = d.item0, l = d.item0 + d.n_items - 1;
-            while (blk[fb + 1] <= f) ++fb;
-            int fl = fb;
-            while (blk[fl + 1] <= l) ++fl;
-            d.lblk0 = fb;
-            d.ln_rows = fl - fb + 1;
-            d.lrow0 = lrows;
-            lrows += d.ln_rows;
             const int64_t tf = d.tile0, tl = d.tile0 + d.n_tiles - 1;
             while (bt[bb + 1] <= tf) ++bb;
             int bl = bb;
@@ -1201,83 +1051,83 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
             d.gn_rows = bl - bb + 1;
             d.grow0 = grows;
             grows += d.gn_rows;
+            d.lrow0 = lrows;
+            d.ln_rows = d.gn_rows + (int)d.n_chunks;
+            lrows += d.ln_rows;
+            for (int64_t c = 0; c < d.n_chunks; ++c) cinst[(size_t)(d.cblk0 + c)] = i;
         }
         int i = 0;
-        for (int b = 0; b < bblocks; ++b) {
+        for (int b = 0; b < tblocks; ++b) {
             while (D[i].tile0 + D[i].n_tiles <= bt[b]) ++i;
             binst[b] = i;
         }
     }
     VP_HIP(P.inst.reserve(sizeof(InstDesc) * n));
-    VP_HIP(P.item_inst.reserve(sizeof(int) * items));
-    VP_HIP(P.blk_items.reserve(sizeof(int64_t) * (fblocks + 1)));
-    VP_HIP(P.blk_tiles.reserve(sizeof(int64_t) * (bblocks + 1)));
-    VP_HIP(P.blk_inst0.reserve(sizeof(int) * bblocks));
+    VP_HIP(P.blk_tiles.reserve(sizeof(int64_t) * (tblocks + 1)));
+    VP_HIP(P.blk_inst0.reserve(sizeof(int) * tblocks));
+    VP_HIP(P.cblk_inst.reserve(sizeof(int) * (size_t)cblocks));
     VP_HIP(P.ubuf.reserve(sizeof(float2) * (size_t)ubase));
     VP_HIP(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)grows));
     VP_HIP(P.lpart.reserve(sizeof(double) * 4 * (size_t)lrows));
     VP_HIP(hipMemcpy(P.inst.ptr, D.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
-    VP_HIP(hipMemcpy(P.item_inst.ptr, item_inst.data(), sizeof(int) * items, hipMemcpyHostToDevice));
-    VP_HIP(hipMemcpy(P.blk_items.ptr, blk.data(), sizeof(int64_t) * (fblocks + 1), hipMemcpyHostToDevice));
-    VP_HIP(hipMemcpy(P.blk_tiles.ptr, bt.data(), sizeof(int64_t) * (bblocks + 1), hipMemcpyHostToDevice));
-    VP_HIP(hipMemcpy(P.blk_inst0.ptr, binst.data(), sizeof(int) * bblocks, hipMemcpyHostToDevice));
-    if (dyn > 48 * 1024) {
-        hipError_t e;
-        switch (L) {
-        case 1: e = set_dyn_attr<1>(dyn); break;
-        case 2: e = set_dyn_attr<2>(dyn); break;
-        case 3: e = set_dyn_attr<3>(dyn); break;
-        default: e = set_dyn_attr<4>(dyn); break;
-        }
+    VP_HIP(hipMemcpy(P.blk_tiles.ptr, bt.data(), sizeof(int64_t) * (tblocks + 1), hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(P.blk_inst0.ptr, binst.data(), sizeof(int) * tblocks, hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(P.cblk_inst.ptr, cinst.data(), sizeof(int) * (size_t)cblocks, hipMemcpyHostToDevice));
+    if (cdyn > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_contract, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)cdyn);
         if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     }
     P.host_inst = D;
-    P.fblocks = fblocks;
-    P.bblocks = bblocks;
+    P.tblocks = tblocks;
+    P.cblocks = cblocks;
     P.n_inst = n;
     P.grows = grows;
     P.lrows = lrows;
-    P.items = items;
     P.tiles = tiles;
     P.L = L;
     P.H = H;
     P.npf = vpinn_n_params(H, L);
-    P.dyn = dyn;
-    P.item_cap_pts = cap_max;
+    P.cdyn = cdyn;
     return VPINN_OK;
 }
 
 template <int L>
-static void launch_all(const FusedPlan &P, const FwdArgs &fa, const BwdArgs &ba, bool want_grad, dim3 fg, int ft,
-                       float *loss, float *grad, float *grad_eps, const AdamArgs &ad, hipEvent_t const *ev,
-                       hipStream_t s) {
+static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs &ca, const BwdArgs &ba,
+                       bool want_grad, dim3 fg, int ft, float *loss, float *grad, float *grad_eps, const AdamArgs &ad,
+                       hipEvent_t const *ev, hipStream_t s) {
     if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
-    k_fwd_contract<L><<<P.fblocks, kFThreads, P.dyn, s>>>(fa);
+    k_fwd<L><<<P.tblocks, kFwThreads, 0, s>>>(fa);
+    k_contract<<<(unsigned)P.cblocks, kCThreads, P.cdyn, s>>>(ca);
     if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
-    if (want_grad) k_bwd<L><<<P.bblocks, kBThreads, 0, s>>>(ba);
+    if (want_grad) k_bwd<L><<<P.tblocks, kBThreads, 0, s>>>(ba);
     if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
     k_fused_final<L><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf,
                                         loss, grad, grad_eps, ad);
     if (ev && ev[3]) (void)hipEventRecord(ev[3], s);
 }
 
-// launch forward/contraction, backward, and the per-instance reduction (with optional Adam)
+// launch forward, contraction, backward, and the per-instance reduction (with optional Adam)
 static vpinn_status run_plan(const FusedPlan &P, const float *params, const float *eps, bool want_grad,
                              float *loss, float *grad, float *grad_eps, const AdamArgs &ad, int64_t *step,
                              hipEvent_t const *ev, hipStream_t s) {
     FwdArgs fa{};
     fa.inst = P.inst.as<InstDesc>();
-    fa.item_inst = P.item_inst.as<int>();
-    fa.blk_items = P.blk_items.as<int64_t>();
+    fa.blk_tiles = P.blk_tiles.as<int64_t>();
+    fa.blk_inst0 = P.blk_inst0.as<int>();
     fa.params = params;
     fa.param_stride = P.npf;
-    fa.eps = eps;
     fa.H = P.H;
-    fa.want_grad = want_grad ? 1 : 0;
-    fa.item_cap_pts = P.item_cap_pts;
     fa.ubuf = P.ubuf.as<float2>();
     fa.lpart = P.lpart.as<double>();
     fa.step = step;
+    ContractArgs ca{};
+    ca.inst = P.inst.as<InstDesc>();
+    ca.cblk_inst = P.cblk_inst.as<int>();
+    ca.eps = eps;
+    ca.want_grad = want_grad ? 1 : 0;
+    ca.ubuf = P.ubuf.as<float2>();
+    ca.lpart = P.lpart.as<double>();
     BwdArgs ba{};
     ba.inst = P.inst.as<InstDesc>();
     ba.blk_tiles = P.blk_tiles.as<int64_t>();
@@ -1288,12 +1138,12 @@ static vpinn_status run_plan(const FusedPlan &P, const float *params, const floa
     ba.ubuf = P.ubuf.as<float2>();
     ba.gpart = P.gpart.as<float>();
     const dim3 fg((unsigned)std::max<int64_t>(1, (P.npf + kFinCols - 1) / kFinCols), (unsigned)P.n_inst);
-    const int ft = kFinCols * kFinSlices;
+    const int ft = kFinThreads;
     switch (P.L) {
-    case 1: launch_all<1>(P, fa, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
-    case 2: launch_all<2>(P, fa, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
-    case 3: launch_all<3>(P, fa, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
-    default: launch_all<4>(P, fa, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 1: launch_all<1>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 2: launch_all<2>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 3: launch_all<3>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    default: launch_all<4>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
     }
     VP_HIP(hipGetLastError());
     return VPINN_OK;
