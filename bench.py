@@ -27,14 +27,24 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 (vector and matrix) peak
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 
-def flops_split(prob):
-    """Algorithmic FLOPs of (forward + contraction + its adjoint, reverse sweep through the network)."""
+def kernel_work(prob):
+    """Algorithmic work of each fused-path kernel for one epoch (dense products as 2 x multiply-adds).
+
+    k_fwd: values and tangents, interior 2H + 3(L-1)H^2 + 2H MACs a point, boundary/sensor 3H + (L-1)H^2;
+    k_contract: 4 N_test MACs a point (contraction and its adjoint); bytes: G_x, G_y once (8 N_test a point),
+    F (4 N_test an element), (u_x, u_y) in and (dL/du_x, dL/du_y) out (16 a point);
+    k_bwd: reverse sweep, interior 2H + 6(L-1)H^2 + 4H MACs a point, boundary/sensor 3H + 2(L-1)H^2.
+    """
     H, L = prob.width, prob.n_hidden
     nt = prob.test_order ** 2
     n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
-    fwd = prob.n_points * (2 * H + 3 * (L - 1) * H * H + 2 * H + 4 * nt) + n_extra * (3 * H + (L - 1) * H * H)
-    bwd = prob.n_points * (2 * H + 6 * (L - 1) * H * H + 4 * H) + n_extra * (3 * H + 2 * (L - 1) * H * H)
-    return 2.0 * fwd, 2.0 * bwd
+    return {
+        "k_fwd": {"flop": 2.0 * (prob.n_points * (2 * H + 3 * (L - 1) * H * H + 2 * H) + n_extra * (3 * H + (L - 1) * H * H))},
+        "k_contract": {"flop": 2.0 * prob.n_points * 4 * nt,
+                       "bytes": 8.0 * nt * prob.n_points + 4.0 * nt * prob.n_elem + 16.0 * prob.n_points},
+        "k_bwd": {"flop": 2.0 * (prob.n_points * (2 * H + 6 * (L - 1) * H * H + 4 * H)
+                                 + n_extra * (3 * H + 2 * (L - 1) * H * H))},
+    }
 
 
 def flops_per_epoch(prob) -> float:
@@ -68,14 +78,15 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel: str):
-    """HBM bytes per launch from the committed counter summary, if it was taken on the current sources."""
+def traffic_from_profile(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary, if it was taken on
+    the current sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    entry = rec.get(kernel)
+    entry = rec.get(workload, {}).get(kernel)
     if not entry or entry.get("source_digest") != source_digest():
         return None
     return entry.get("hbm_bytes_per_launch")
@@ -90,9 +101,9 @@ def _pmc_rows(path):
         return list(csv.DictReader(f))
 
 
-def write_traffic(fetch_csv: str, write_csv: str):
-    """Scale the per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the fused kernel by what the same
-    counters read for the 256 MiB copy (known: 256 MiB read, 256 MiB written)."""
+def write_traffic(workload: str, fetch_csv: str, write_csv: str):
+    """Scale the per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of each fused-path kernel by what the same
+    counters read for the 256 MiB copy (known: 256 MiB read, 256 MiB written); store under `workload`."""
     def per_kernel(path, counter):
         vals = {}
         for r in _pmc_rows(path):
@@ -109,21 +120,26 @@ def write_traffic(fetch_csv: str, write_csv: str):
     f_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(fetch)
     w_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(write)
     out = {}
-    for name, key in [("k_bwd", "k_bwd<3>"), ("k_fwd_contract", "k_fwd_contract<3>")]:
-        fk = [v for k, vs in fetch.items() if key in k for v in vs]
-        wk = [v for k, vs in write.items() if key in k for v in vs]
+    for name, key in [("k_bwd", "k_bwd<3>"), ("k_fwd", "k_fwd<3>"), ("k_contract", "k_contract(")]:
+        fk = sorted(v for k, vs in fetch.items() if key in k for v in vs)
+        wk = sorted(v for k, vs in write.items() if key in k for v in vs)
         if not fk or not wk:
             continue
-        fk.sort()
-        wk.sort()
         fb = fk[len(fk) // 2] * 1024.0 * f_scale
         wb = wk[len(wk) // 2] * 1024.0 * w_scale
         out[name] = {"source_digest": source_digest(), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                      "hbm_bytes_per_launch": fb + wb, "fetch_scale": f_scale, "write_scale": w_scale,
                      "dispatches": len(fk)}
     path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+        if not all(isinstance(v, dict) and all(isinstance(x, dict) for x in v.values()) for v in rec.values()):
+            rec = {}
+    rec[workload] = out
     with open(path, "w") as f:
-        json.dump(out, f, indent=1)
+        json.dump(rec, f, indent=1)
     print(json.dumps(out))
 
 
@@ -145,7 +161,8 @@ def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
         t += 1
         V.vpinn_loss_and_grad(p, cfg, th, loss=loss, grad=g, stream=stream)
         V.vpinn_adam_step(th, g, m, v, t, lr=1e-3, stream=stream)
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    NE = V.PROFILE_EVENTS
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(NE + 1)] for _ in range(steps)]
     for e in ev:
         for x in e:
             x.record(stream)  # creates the underlying events before their handles are handed over
@@ -154,31 +171,32 @@ def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
     for i in range(steps):
         t += 1
         if fused:
-            V.vpinn_set_profile_events(p, ev[i][:4])
+            V.vpinn_set_profile_events(p, ev[i][:NE])
         else:
             ev[i][0].record(stream)
         V.vpinn_loss_and_grad(p, cfg, th, loss=loss, grad=g, stream=stream)
         if not fused:
-            ev[i][3].record(stream)
+            ev[i][NE - 1].record(stream)
         V.vpinn_adam_step(th, g, m, v, t, lr=1e-3, stream=stream)
-        ev[i][4].record(stream)
+        ev[i][NE].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     if fused:
         V.vpinn_set_profile_events(p, None)
     mean = lambda xs: sum(xs) / len(xs)  # noqa: E731
-    out = {"wall_s": wall, "lg_ms_mean": mean([e[0].elapsed_time(e[3]) for e in ev]),
-           "step_ms_mean": mean([e[0].elapsed_time(e[4]) for e in ev])}
+    out = {"wall_s": wall, "lg_ms_mean": mean([e[0].elapsed_time(e[NE - 1]) for e in ev]),
+           "step_ms_mean": mean([e[0].elapsed_time(e[NE]) for e in ev])}
     if fused:
-        out["k_fwd_contract_ms"] = mean([e[0].elapsed_time(e[1]) for e in ev])
-        out["k_bwd_ms"] = mean([e[1].elapsed_time(e[2]) for e in ev])
-        out["k_final_ms"] = mean([e[2].elapsed_time(e[3]) for e in ev])
+        for k, name in enumerate(["k_fwd_ms", "k_contract_ms", "k_bwd_ms", "k_final_ms"]):
+            out[name] = mean([e[k].elapsed_time(e[k + 1]) for e in ev])
     return out
 
 
 def time_graph(V, torch, p, prob, theta, steps: int, warmup: int):
     """The headline step: one problem as a batch of one, forward + adjoint + Adam (Adam inside the
-    reduction kernel, step counter in device memory) captured once in a HIP graph and replayed."""
+    reduction kernel, step counter in device memory) captured once in a HIP graph and replayed.
+    Throughput: `steps` replays back to back, bracketed by synchronisations (host wall clock) and by one
+    pair of events; the per-step distribution comes from a separate run with an event pair per step."""
     dev = torch.device("cuda:0")
     b = V.vpinn_batch_create([p], V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma))
     th = torch.tensor(theta, dtype=torch.float32, device=dev).reshape(1, -1).contiguous()
@@ -187,23 +205,31 @@ def time_graph(V, torch, p, prob, theta, steps: int, warmup: int):
     step = torch.zeros(1, dtype=torch.int64, device=dev)
     losses = torch.zeros((1, 4), dtype=torch.float32, device=dev)
     s = torch.cuda.Stream()
+    n_dist = min(steps, 200)
     with torch.cuda.stream(s):
         V.vpinn_batch_capture(b, th, m, v, step, lr=1e-3, losses=losses, stream=s)
         for _ in range(warmup):
             V.vpinn_batch_replay(b, stream=s)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        for i in range(steps):
+        e0.record(s)
+        for _ in range(steps):
+            V.vpinn_batch_replay(b, stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_dist)]
+        for i in range(n_dist):
             ev[i][0].record(s)
             V.vpinn_batch_replay(b, stream=s)
             ev[i][1].record(s)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
     st = sorted(a.elapsed_time(c) for a, c in ev)
     q = lambda xs, f: xs[min(len(xs) - 1, int(f * len(xs)))]  # noqa: E731
-    return {"wall_s": wall, "step_ms_p10": q(st, 0.1), "step_ms_p50": q(st, 0.5), "step_ms_p90": q(st, 0.9),
-            "steps_done": int(step.item()), "final_loss": float(losses[0, 0].item())}
+    return {"wall_s": wall, "event_ms_total": e0.elapsed_time(e1), "step_ms_p10": q(st, 0.1),
+            "step_ms_p50": q(st, 0.5), "step_ms_p90": q(st, 0.9), "steps_done": int(step.item()) - n_dist,
+            "final_loss": float(losses[0, 0].item())}
 
 
 def cpu_baseline(prob, theta, seconds: float):
@@ -270,6 +296,37 @@ def bench_batched(args, V, torch, gen):
         wall = time.perf_counter() - w0
     st = sorted(a.elapsed_time(c) for a, c in ev)
     ms = wall / args.steps * 1e3
+    # per-kernel durations: a few eager batched steps with the library's profiling events
+    NE = V.PROFILE_EVENTS
+    n_prof = 10
+    pev = [[torch.cuda.Event(enable_timing=True) for _ in range(NE)] for _ in range(n_prof)]
+    with torch.cuda.stream(s):
+        for e in pev:
+            for x in e:
+                x.record(s)
+        for i in range(n_prof):
+            V.vpinn_batch_set_profile_events(b, pev[i])
+            V.vpinn_batch_step(b, T, M, Vv, step, lr=1e-3, losses=losses, stream=s)
+        V.vpinn_batch_set_profile_events(b, None)
+    torch.cuda.synchronize()
+    kms = {name: sum(e[k].elapsed_time(e[k + 1]) for e in pev) / n_prof
+           for k, name in enumerate(["k_fwd", "k_contract", "k_bwd", "k_fused_final"])}
+    work = {}
+    for pr in probs:
+        for name, w in kernel_work(pr).items():
+            for key, val in w.items():
+                work.setdefault(name, {}).setdefault(key, 0.0)
+                work[name][key] += val
+    kernels = {}
+    for name in ("k_fwd", "k_contract", "k_bwd"):
+        ent = {"ms": round(kms[name], 4), "tflops": round(work[name]["flop"] / (kms[name] * 1e-3) / 1e12, 3)}
+        if "bytes" in work[name]:
+            ent["gbs"] = round(work[name]["bytes"] / (kms[name] * 1e-3) / 1e9, 1)
+            ent["frac_hbm_peak"] = round(ent["gbs"] / PEAK_HBM_GBS, 4)
+        kernels[name] = ent
+    kernels["k_fused_final"] = {"ms": round(kms["k_fused_final"], 4), "note": "reduction + Adam for 64 instances"}
+    dom = max(("k_fwd", "k_contract", "k_bwd"), key=lambda k: kms[k])
+    dom_tf = work[dom]["flop"] / (kms[dom] * 1e-3) / 1e12
     # unfused comparator: each instance's plain loss/grad and Adam, in a loop
     pcfg = V.loss_cfg(30, 3, 10.0, 0.0, path=V.VPINN_PATH_PLAIN)
     Ts = [torch.tensor(th[i], dtype=torch.float32, device=dev) for i in range(64)]
@@ -306,11 +363,13 @@ def bench_batched(args, V, torch, gen):
         "mquadpts_per_s": round(P * eps_s / 1e6, 2),
         "step_ms_p10_p50_p90": [round(st[len(st) // 10], 4), round(st[len(st) // 2], 4),
                                 round(st[(9 * len(st)) // 10], 4)],
-        "roofline": {"bound": "mfma", "kernel": "k_fused (batched step incl. reduction+Adam)",
-                     "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                     "algorithmic_flop_per_launch": flops,
-                     "algorithmic_bytes_per_launch": sum(bytes_per_epoch(pr) for pr in probs)},
+        "roofline": {"bound": "mfma", "kernel": dom + " (all 64 instances in one launch)",
+                     "achieved": round(dom_tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(dom_tf / PEAK_FP32_TFLOPS, 4), "traffic": traffic_from_profile("c5", dom),
+                     "algorithmic_flop_per_launch": work[dom]["flop"], "launch_ms_mean": round(kms[dom], 4)},
+        "whole_step": {"algorithmic_flop": flops, "algorithmic_bytes": sum(bytes_per_epoch(pr) for pr in probs),
+                       "achieved_tflops": round(achieved, 3), "frac_of_fp32_peak": round(achieved / PEAK_FP32_TFLOPS, 4)},
+        "eager_kernels": kernels,
         "plain_hip": {"ms_per_step": round(pms, 4), "epochs_per_s": round(1e3 / pms, 3),
                       "note": "64 x (unfused loss/grad + Adam) per step"},
         "speedup_vs_plain": round(pms / ms, 3),
@@ -327,16 +386,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
-    ap.add_argument("--workload", choices=["c2", "c5"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c5", "probe"], default="c2",
+                    help="c2 (default, the headline): one 1,024-element problem; c5: 64-instance batch; probe: "
+                         "20x20 test functions on 4,096 elements (G-stream bound)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times: a kernel of known traffic that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then "
-                         "WRITE_SIZE, taken with --copy-probe) into profiles/traffic.json")
+                         "WRITE_SIZE, taken with --copy-probe on --workload W) into profiles/traffic.json[W]")
     args = ap.parse_args()
     if args.traffic_from:
-        write_traffic(*args.traffic_from)
+        write_traffic(args.workload, *args.traffic_from)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -358,12 +419,26 @@ def main():
     if args.workload == "c5":
         bench_batched(args, V, torch, gen)
         return
-    prob = gen.config_c2()
+    bench_single(args, V, torch, gen)
+
+
+WORKLOAD_TEXT = {
+    "c2": "c2: Poisson -Lap u = f on [0,1]^2, 32x32 quad mesh with interior nodes jittered +-20% h, 10x10 GLL "
+          "points, 5x5 test functions, u*=sin(8pi x)sin(8pi y), 1600 boundary points, MLP 2-30-30-30-1 tanh, "
+          "Adam lr 1e-3",
+    "probe": "probe: the c4 mesh (64x64 jittered, 4096 elements) with 10x10 GLL points and 20x20 test functions "
+             "(the paper's largest p-refinement), u*=sin(2pi x)sin(2pi y), 1600 boundary points, MLP "
+             "2-30-30-30-1 tanh: the only shape whose G stream (1.3 GB) outweighs the network arithmetic",
+}
+
+
+def bench_single(args, V, torch, gen):
+    prob = gen.config_c2() if args.workload == "c2" else gen.config_probe()
     theta = prob.params()
     p = V.vpinn_assemble(prob.mesh.xy, prob.mesh.quad, prob.quad_order, prob.test_order,
                          prob.f_amp, prob.f_kx, prob.f_ky)
     V.vpinn_set_boundary(p, prob.bnd_xy, prob.bnd_g)
-    print(f"[bench] workload c2: {prob.n_elem} elements, {prob.n_points} quadrature points, "
+    print(f"[bench] workload {args.workload}: {prob.n_elem} elements, {prob.n_points} quadrature points, "
           f"{len(prob.bnd_xy)} boundary points", file=sys.stderr, flush=True)
 
     main_path = V.VPINN_PATH_FUSED if args.path == "fused" else V.VPINN_PATH_PLAIN
@@ -394,13 +469,38 @@ def main():
     ms = res["wall_s"] / args.steps * 1e3
     eps_s = 1e3 / ms
     flops = flops_per_epoch(prob)
-    f_fwd, f_bwd = flops_split(prob)
+    work = kernel_work(prob)
+    kernels = {}
     if fused:
-        kernel, k_ms, k_flops = "k_bwd (reverse sweep, MFMA)", eager["k_bwd_ms"], f_bwd
+        for name in ("k_fwd", "k_contract", "k_bwd"):
+            k_ms = eager[name + "_ms"]
+            ent = {"ms": round(k_ms, 5), "tflops": round(work[name]["flop"] / (k_ms * 1e-3) / 1e12, 3)}
+            ent["frac_fp32_peak"] = round(ent["tflops"] / PEAK_FP32_TFLOPS, 4)
+            if "bytes" in work[name]:
+                ent["gbs"] = round(work[name]["bytes"] / (k_ms * 1e-3) / 1e9, 1)
+                ent["frac_hbm_peak"] = round(ent["gbs"] / PEAK_HBM_GBS, 4)
+            kernels[name] = ent
+        kernels["k_fused_final"] = {"ms": round(eager["k_final_ms"], 5)}
+        dom = max(("k_fwd", "k_contract", "k_bwd"), key=lambda k: eager[k + "_ms"])
+        k_ms = eager[dom + "_ms"]
+        if dom == "k_contract" and work[dom]["flop"] / work[dom]["bytes"] < 1.0:
+            achieved = work[dom]["bytes"] / (k_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                    "algorithmic_bytes_per_launch": work[dom]["bytes"]}
+        else:
+            achieved = work[dom]["flop"] / (k_ms * 1e-3) / 1e12
+            roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                    "algorithmic_flop_per_launch": work[dom]["flop"]}
+        roof["traffic"] = traffic_from_profile(args.workload, dom)
+        roof["launch_ms_mean"] = round(k_ms, 5)
     else:
-        kernel, k_ms, k_flops = "plain loss_and_grad sequence", eager["lg_ms_mean"], flops
-    achieved_tf = k_flops / (k_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile("k_bwd") if fused else None
+        k_ms = eager["lg_ms_mean"]
+        achieved = flops / (k_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "plain loss_and_grad sequence", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": None, "algorithmic_flop_per_launch": flops, "launch_ms_mean": round(k_ms, 5)}
     out = {
         "metric": "epochs/s and Mquadpts/s fwd+adjoint, fused batched vs plain HIP, loss err<=1e-5",
         "value": round(eps_s, 3),
@@ -414,20 +514,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "c2: Poisson -Lap u = f on [0,1]^2, 32x32 quad mesh with interior nodes "
-                               "jittered +-20% h, 10x10 GLL points, 5x5 test functions, u*=sin(8pi x)sin(8pi y), "
-                               "1600 boundary points, MLP 2-30-30-30-1 tanh, Adam lr 1e-3",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "path": args.path + (" (HIP graph replay of the batch-of-one step)" if fused else " (eager)"),
                    "n_elem": prob.n_elem, "quad_points": prob.n_points,
                    "boundary_points": len(prob.bnd_xy), "parallelism": "single GPU"},
         "mquadpts_per_s": round(prob.n_points * eps_s / 1e6, 2),
-        "roofline": {"bound": "mfma" if fused else "alu",
-                     "kernel": kernel,
-                     "achieved": round(achieved_tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4),
-                     "traffic": traffic,
-                     "algorithmic_flop_per_launch": k_flops,
-                     "launch_ms_mean": round(k_ms, 5)},
+        "roofline": roof,
         "whole_step": {"algorithmic_flop": flops, "algorithmic_bytes": bytes_per_epoch(prob),
                        "achieved_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
                        "frac_of_fp32_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
@@ -436,10 +528,8 @@ def main():
     if fused:
         out["step_ms_p10_p50_p90"] = [round(res["step_ms_p10"], 5), round(res["step_ms_p50"], 5),
                                       round(res["step_ms_p90"], 5)]
-        out["eager"] = {"ms_per_step": round(eager["wall_s"] / eager_steps * 1e3, 5),
-                        "k_fwd_contract_ms": round(eager["k_fwd_contract_ms"], 5),
-                        "k_bwd_ms": round(eager["k_bwd_ms"], 5), "k_final_ms": round(eager["k_final_ms"], 5),
-                        "k_fwd_contract_tflops": round(f_fwd / (eager["k_fwd_contract_ms"] * 1e-3) / 1e12, 3)}
+        out["gpu_event_ms_per_step"] = round(res["event_ms_total"] / args.steps, 5)
+        out["eager"] = {"ms_per_step": round(eager["wall_s"] / eager_steps * 1e3, 5), "kernels": kernels}
     if plain is not None:
         pms = plain["wall_s"] / min(args.steps, 300) * 1e3
         out["plain_hip"] = {"ms_per_step": round(pms, 5), "epochs_per_s": round(1e3 / pms, 3),

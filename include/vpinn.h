@@ -129,7 +129,7 @@ vpinn_status vpinn_read_tensor(const vpinn_problem *p, int32_t which, float *hos
 /* ------------------------------------------------------------------------ */
 /* Loss and gradient (Algorithm 3 with its backward pass)                    */
 /* ------------------------------------------------------------------------ */
-#define VPINN_PATH_FUSED 0 /* one fused forward + contraction + adjoint launch and a reduction */
+#define VPINN_PATH_FUSED 0 /* forward, contraction + adjoint, reverse sweep and reduction kernels */
 #define VPINN_PATH_PLAIN 1 /* unfused kernel sequence that materialises every intermediate */
 #define VPINN_NORM_TEST 0  /* c_v = 1/N_test: mean over test functions, sum over elements (Alg. 3) */
 #define VPINN_NORM_ELEM 1  /* c_v = 1/N_elem: the variational-loss equation of Sec. 2.3 */
@@ -245,13 +245,15 @@ vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream);
 void vpinn_batch_free(vpinn_batch *b);
 
 /*
- * Profiling hooks for the fused path: `events` points to 4 hipEvent_t (created by
- * the caller with timing enabled; any may be NULL) recorded on the call's stream
- * before the forward/contraction kernel, between it and the backward kernel,
- * between the backward kernel and the reduction, and after the reduction, by
- * every later vpinn_loss_and_grad (fused path) / batch call.  NULL disables.
- * The events stay caller-owned.  A capture (vpinn_batch_capture) records none.
+ * Profiling hooks for the fused path: `events` points to VPINN_PROFILE_EVENTS
+ * hipEvent_t (created by the caller with timing enabled; any may be NULL)
+ * recorded on the call's stream before the forward kernel, between it and the
+ * contraction kernel, between that and the backward kernel, between the backward
+ * kernel and the reduction, and after the reduction, by every later
+ * vpinn_loss_and_grad (fused path) / batch call.  NULL disables.  The events stay
+ * caller-owned.  A capture (vpinn_batch_capture) records none.
  */
+#define VPINN_PROFILE_EVENTS 5
 vpinn_status vpinn_set_profile_events(vpinn_problem *p, void *const *events);
 vpinn_status vpinn_batch_set_profile_events(vpinn_batch *b, void *const *events);
 

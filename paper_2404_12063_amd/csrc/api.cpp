@@ -382,7 +382,7 @@ vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream) {
 vpinn_status vpinn_set_profile_events(vpinn_problem *p, void *const *events) {
     using namespace vp;
     if (!p) return fail(VPINN_E_INVALID, "problem is null");
-    for (int i = 0; i < 4; ++i) p->prof[i] = events ? (hipEvent_t)events[i] : nullptr;
+    for (int i = 0; i < VPINN_PROFILE_EVENTS; ++i) p->prof[i] = events ? (hipEvent_t)events[i] : nullptr;
     return VPINN_OK;
 }
 

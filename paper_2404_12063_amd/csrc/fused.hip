@@ -56,6 +56,12 @@ constexpr int kBWaves = kBThreads / 64;
 constexpr int kTs = 36;            // transpose tile row stride (floats)
 constexpr int kMaxBlocks = 1024;
 constexpr int kKB = 32;              // test functions held in registers by the fast contraction
+constexpr int kRowQ = 4;             // quadrature points per lane in the row-streaming contraction
+// contraction paths: thread per point with every test function in registers
+// (nq <= kCThreads, ntest <= kKB); wavefront per test-function row, G read once,
+// with Q = 1, 2 or 4 points a lane (nq <= 64 Q; one kernel per Q keeps each at
+// the occupancy its registers allow); two passes over G for larger elements
+enum { kPathFast = 0, kPathRows1 = 1, kPathRows2 = 2, kPathRows4 = 3, kPathGeneric = 4, kNumPaths = 5 };
 constexpr int kCbs = kCThreads + 1;  // row stride of the per-point term buffer
 
 struct Vec {
@@ -116,7 +122,7 @@ struct InstDesc {
     int64_t ubase;            // offset of this instance's points in the point buffer
     int64_t cblk0, n_chunks;  // contraction blocks cblk0 .. (epc elements each)
     int nq, ntest, epc;
-    int fast;                 // nq <= kCThreads and ntest <= kKB: G stays in registers
+    int path;                 // contraction path (kPathFast .. kPathGeneric)
     // loss partial rows lrow0 .. lrow0 + ln_rows - 1: first one per tile block
     // (gblk0 ..), then one per contraction block
     int lrow0, ln_rows;
@@ -141,6 +147,7 @@ struct FwdArgs {
 struct ContractArgs {
     const InstDesc *inst;
     const int *cblk_inst;       // [contraction blocks] instance of each block
+    int64_t cblk_base;          // global contraction block of this launch's block 0
     const float *eps;           // [n_inst] or null (eps = 1)
     int want_grad;
     float2 *ubuf;               // in: (u_x, u_y); out: (dL/du_x, dL/du_y) at interior points
@@ -591,118 +598,39 @@ __global__ __launch_bounds__(kFwThreads, 1) void k_fwd(FwdArgs A) {
     }
 }
 
-// 2-3: contraction, variational loss terms and the adjoint of the contraction
-// (Algorithm 3 and its reverse), one block per chunk of epc whole elements.
-//   fast path (nq <= kCThreads, ntest <= kKB): thread (element, q) holds
-//     G_x[e,k,q], G_y[e,k,q] for all k in registers; the per-point terms
-//     u_x G_x + u_y G_y go through LDS to per-(element, test) row sums (eight
-//     lanes a row); then dL/du at q from the same registers;
-//   generic path (one element per block): rows by 16-lane groups, then the
-//     adjoint thread per q with G read again (cache-resident by then).
-__global__ __launch_bounds__(kCThreads) void k_contract(ContractArgs A) {
-    extern __shared__ float dyn[];
-    __shared__ double lp[kCWaves][2];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int inst = A.cblk_inst[blockIdx.x];
-    const InstDesc *Ip = A.inst + inst;
-    const int nq = Ip->nq, ntest = Ip->ntest;
-    const int64_t chunk = (int64_t)blockIdx.x - Ip->cblk0;
-    const int64_t e0 = chunk * Ip->epc;
-    const int ne = (int)min((int64_t)Ip->epc, Ip->n_elem - e0);
-    const float *__restrict__ Gx = Ip->Gx;
-    const float *__restrict__ Gy = Ip->Gy;
-    const float *__restrict__ F = Ip->F;
-    const float two_cv = Ip->two_cv;
-    const float eps = A.eps ? A.eps[inst] : 1.0f;
-    float2 *__restrict__ ub = A.ubuf + Ip->ubase;
-    double lrr = 0.0, lra = 0.0;
-    if (Ip->fast) {
-        float *cbuf = dyn;                  // [ntest][kCbs] per-point terms
-        float *rbar = dyn + ntest * kCbs;   // [ne][ntest] 2 c_v R
-        const int el = tid / nq, q = tid - el * nq;
-        const bool act = el < ne;
-        const int64_t gbase = ((e0 + el) * ntest) * (int64_t)nq + q;
-        float gx[kKB], gy[kKB];
-#pragma unroll
-        for (int k = 0; k < kKB; ++k) {
-            const bool ok = act && k < ntest;
-            gx[k] = ok ? Gx[gbase + (int64_t)k * nq] : 0.f;
-            gy[k] = ok ? Gy[gbase + (int64_t)k * nq] : 0.f;
-        }
-        const float2 d = act ? ub[(e0 + el) * nq + q] : make_float2(0.f, 0.f);
-#pragma unroll
-        for (int k = 0; k < kKB; ++k)
-            if (k < ntest) cbuf[k * kCbs + tid] = fmaf(d.x, gx[k], d.y * gy[k]);
-        __syncthreads();
-        for (int r8 = tid; r8 < 8 * ne * ntest; r8 += kCThreads) {
-            const int r = r8 >> 3, part = r8 & 7;
-            const int e2 = r / ntest, k = r - e2 * ntest;
-            const float *rowp = cbuf + k * kCbs + e2 * nq;
-            float a = 0.f;
-            for (int qq = part; qq < nq; qq += 8) a += rowp[qq];
-            a += __shfl_xor(a, 4, 8);
-            a += __shfl_xor(a, 2, 8);
-            a += __shfl_xor(a, 1, 8);
-            if (part == 0) {
-                const float R = eps * a - F[(e0 + e2) * ntest + k];
-                rbar[e2 * ntest + k] = two_cv * R;
-                lrr += (double)R * (double)R;
-                lra += (double)R * (double)a;
-            }
-        }
-        __syncthreads();
-        if (A.want_grad && act) {
-            const float *rb = rbar + el * ntest;
-            float bx = 0.f, by = 0.f;
-#pragma unroll
-            for (int k = 0; k < kKB; ++k)
-                if (k < ntest) {
-                    bx = fmaf(rb[k], gx[k], bx);
-                    by = fmaf(rb[k], gy[k], by);
-                }
-            ub[(e0 + el) * nq + q] = make_float2(eps * bx, eps * by);
-        }
-    } else {
-        float *rbar = dyn;  // [ntest] 2 c_v R of the block's element
-        const int64_t ebase = e0 * ntest;
-        const float2 *__restrict__ uxy = ub + e0 * nq;
-        constexpr int kRG = kCThreads / 16;
-        const int rg = tid >> 4, rl = tid & 15;
-        for (int k0 = 0; k0 < ntest; k0 += kRG) {
-            const int k = k0 + rg;
-            float acc = 0.f;
-            if (k < ntest) {
-                const float *gxr = Gx + (ebase + k) * (int64_t)nq, *gyr = Gy + (ebase + k) * (int64_t)nq;
-                for (int q = rl; q < nq; q += 16) {
-                    const float2 d = uxy[q];
-                    acc = fmaf(d.x, gxr[q], fmaf(d.y, gyr[q], acc));
-                }
-            }
-            acc += __shfl_xor(acc, 8, 16);
-            acc += __shfl_xor(acc, 4, 16);
-            acc += __shfl_xor(acc, 2, 16);
-            acc += __shfl_xor(acc, 1, 16);
-            if (rl == 0 && k < ntest) {
-                const float R = eps * acc - F[ebase + k];
-                rbar[k] = two_cv * R;
-                lrr += (double)R * (double)R;
-                lra += (double)R * (double)acc;
-            }
-        }
-        __syncthreads();
-        if (A.want_grad) {
-            for (int q = tid; q < nq; q += kCThreads) {
-                float bx = 0.f, by = 0.f;
-                for (int k = 0; k < ntest; ++k) {
-                    const int64_t o = (ebase + k) * (int64_t)nq + q;
-                    bx = fmaf(rbar[k], Gx[o], bx);
-                    by = fmaf(rbar[k], Gy[o], by);
-                }
-                ub[e0 * nq + q] = make_float2(eps * bx, eps * by);
-            }
-        }
-    }
-    // loss partials of the block, wavefronts added in order
+// Contraction, variational loss terms and the adjoint of the contraction
+// (Algorithm 3 and its reverse), one block per chunk of epc whole elements, three
+// kernels for three element shapes (each instance's chunks go to one of them):
+//   fast (nq <= kCThreads, ntest <= kKB): thread (element, q) holds G_x[e,k,q],
+//     G_y[e,k,q] for all k in registers; the per-point terms u_x G_x + u_y G_y go
+//     through LDS to per-(element, test) row sums (eight lanes a row); then dL/du
+//     at q from the same registers;
+//   rows (nq <= 64 kRowQ, any ntest): one element per block, G streamed row by row,
+//     each row used twice from registers;
+//   generic (larger elements): rows by 16-lane groups, then the adjoint thread per q
+//     with G read again (cache-resident by then).
+// In every case G is read from HBM once; loss partials go to one row per block.
+
+struct ContractCtx {
+    const InstDesc *I;
+    int64_t chunk, e0;
+    float eps;
+};
+
+__device__ __forceinline__ ContractCtx contract_ctx(const ContractArgs &A) {
+    const int64_t b = A.cblk_base + blockIdx.x;
+    const int inst = A.cblk_inst[b];
+    ContractCtx c;
+    c.I = A.inst + inst;
+    c.chunk = b - c.I->cblk0;
+    c.e0 = c.chunk * c.I->epc;
+    c.eps = A.eps ? A.eps[inst] : 1.0f;
+    return c;
+}
+
+// the block's loss sums (sum R^2, sum R A), wavefronts added in order -> its loss row
+__device__ __forceinline__ void contract_flush(const ContractArgs &A, const ContractCtx &c, double lrr, double lra,
+                                               double (*lp)[2], int tid, int wave, int lane) {
     const double vr = wave_sum(lrr), va = wave_sum(lra);
     if (lane == 0) {
         lp[wave][0] = vr;
@@ -713,8 +641,240 @@ __global__ __launch_bounds__(kCThreads) void k_contract(ContractArgs A) {
         double v = 0.0;
         if (tid < 2)
             for (int w = 0; w < kCWaves; ++w) v += lp[w][tid];
-        A.lpart[(Ip->lrow0 + Ip->gn_rows + chunk) * 4 + tid] = v;
+        A.lpart[(c.I->lrow0 + c.I->gn_rows + c.chunk) * 4 + tid] = v;
     }
+}
+
+__global__ __launch_bounds__(kCThreads) void k_contract_fast(ContractArgs A) {
+    extern __shared__ float dyn[];
+    __shared__ double lp[kCWaves][2];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const ContractCtx c = contract_ctx(A);
+    const InstDesc *Ip = c.I;
+    const int nq = Ip->nq, ntest = Ip->ntest;
+    const int64_t e0 = c.e0;
+    const int ne = (int)min((int64_t)Ip->epc, Ip->n_elem - e0);
+    const float *__restrict__ Gx = Ip->Gx;
+    const float *__restrict__ Gy = Ip->Gy;
+    const float *__restrict__ F = Ip->F;
+    const float two_cv = Ip->two_cv, eps = c.eps;
+    float2 *__restrict__ ub = A.ubuf + Ip->ubase;
+    double lrr = 0.0, lra = 0.0;
+    float *cbuf = dyn;                  // [ntest][kCbs] per-point terms
+    float *rbar = dyn + ntest * kCbs;   // [ne][ntest] 2 c_v R
+    const int el = tid / nq, q = tid - el * nq;
+    const bool act = el < ne;
+    const int64_t gbase = ((e0 + el) * ntest) * (int64_t)nq + q;
+    float gx[kKB], gy[kKB];
+#pragma unroll
+    for (int k = 0; k < kKB; ++k) {
+        const bool ok = act && k < ntest;
+        gx[k] = ok ? Gx[gbase + (int64_t)k * nq] : 0.f;
+        gy[k] = ok ? Gy[gbase + (int64_t)k * nq] : 0.f;
+    }
+    const float2 d = act ? ub[(e0 + el) * nq + q] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < kKB; ++k)
+        if (k < ntest) cbuf[k * kCbs + tid] = fmaf(d.x, gx[k], d.y * gy[k]);
+    __syncthreads();
+    for (int r8 = tid; r8 < 8 * ne * ntest; r8 += kCThreads) {
+        const int r = r8 >> 3, part = r8 & 7;
+        const int e2 = r / ntest, k = r - e2 * ntest;
+        const float *rowp = cbuf + k * kCbs + e2 * nq;
+        float a = 0.f;
+        for (int qq = part; qq < nq; qq += 8) a += rowp[qq];
+        a += __shfl_xor(a, 4, 8);
+        a += __shfl_xor(a, 2, 8);
+        a += __shfl_xor(a, 1, 8);
+        if (part == 0) {
+            const float R = eps * a - F[(e0 + e2) * ntest + k];
+            rbar[e2 * ntest + k] = two_cv * R;
+            lrr += (double)R * (double)R;
+            lra += (double)R * (double)a;
+        }
+    }
+    __syncthreads();
+    if (A.want_grad && act) {
+        const float *rb = rbar + el * ntest;
+        float bx = 0.f, by = 0.f;
+#pragma unroll
+        for (int k = 0; k < kKB; ++k)
+            if (k < ntest) {
+                bx = fmaf(rb[k], gx[k], bx);
+                by = fmaf(rb[k], gy[k], by);
+            }
+        ub[(e0 + el) * nq + q] = make_float2(eps * bx, eps * by);
+    }
+    contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
+}
+
+// row-streaming contraction of one element: wavefront w takes test-function rows
+// k = w, w + kCWaves, ..., kRP rows per pass with all their loads in flight; a row's G values (lane holds q = lane + 64 i, i < Q) give A_k by
+// a wavefront sum and then, still in registers, the row's share 2 c_v R_k G[k, q] of
+// the adjoint; the wavefront partials are added in wavefront order at the end.
+constexpr int kRP = 4;
+template <int Q>
+struct RowBuf {
+    float gx[kRP][Q], gy[kRP][Q];
+};
+
+template <int Q>
+__device__ __forceinline__ void rows_load(RowBuf<Q> &B, const float *__restrict__ Gx, const float *__restrict__ Gy,
+                                          int64_t ebase, int k0, int ntest, int nq, int lane) {
+#pragma unroll
+    for (int r = 0; r < kRP; ++r) {
+        const int k = k0 + r * kCWaves;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int q = lane + 64 * i;
+            const bool ok = k < ntest && q < nq;
+            const int64_t o = (ebase + k) * (int64_t)nq + q;
+            B.gx[r][i] = ok ? Gx[o] : 0.f;
+            B.gy[r][i] = ok ? Gy[o] : 0.f;
+        }
+    }
+}
+
+template <int Q>
+__device__ __forceinline__ void rows_use(const RowBuf<Q> &B, const float *ux, const float *uy, float *bx, float *by,
+                                         const float *__restrict__ F, int64_t ebase, int k0, int ntest, float eps,
+                                         float two_cv, int lane, double &lrr, double &lra) {
+#pragma unroll
+    for (int r = 0; r < kRP; ++r) {
+        const int k = k0 + r * kCWaves;
+        float a = 0.f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) a = fmaf(ux[i], B.gx[r][i], fmaf(uy[i], B.gy[r][i], a));
+        a = wave_sum(a);
+        if (k < ntest) {
+            const float R = eps * a - F[ebase + k];
+            const float rb = two_cv * R;
+            if (lane == 0) {
+                lrr += (double)R * (double)R;
+                lra += (double)R * (double)a;
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                bx[i] = fmaf(rb, B.gx[r][i], bx[i]);
+                by[i] = fmaf(rb, B.gy[r][i], by[i]);
+            }
+        }
+    }
+}
+
+template <int Q>
+__device__ __forceinline__ void contract_rows(const ContractArgs &A, const ContractCtx &c, float *bsum, int tid,
+                                              int wave, int lane, double &lrr, double &lra) {
+    const InstDesc *Ip = c.I;
+    const int nq = Ip->nq, ntest = Ip->ntest;
+    const float *__restrict__ Gx = Ip->Gx;
+    const float *__restrict__ Gy = Ip->Gy;
+    const float *__restrict__ F = Ip->F;
+    const float two_cv = Ip->two_cv, eps = c.eps;
+    float2 *__restrict__ ub = A.ubuf + Ip->ubase;
+    const int64_t e0 = c.e0, ebase = e0 * ntest;
+    float ux[Q], uy[Q], bx[Q], by[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int q = lane + 64 * i;
+        const float2 d = q < nq ? ub[e0 * nq + q] : make_float2(0.f, 0.f);
+        ux[i] = d.x;
+        uy[i] = d.y;
+        bx[i] = 0.f;
+        by[i] = 0.f;
+    }
+    // high occupancy (few registers a wavefront) keeps many rows in flight per SIMD
+    constexpr int kStep = kRP * kCWaves;
+    for (int k0 = wave; k0 < ntest; k0 += kStep) {
+        RowBuf<Q> B;
+        rows_load<Q>(B, Gx, Gy, ebase, k0, ntest, nq, lane);
+        rows_use<Q>(B, ux, uy, bx, by, F, ebase, k0, ntest, eps, two_cv, lane, lrr, lra);
+    }
+    if (A.want_grad) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            bsum[((wave * 2 + 0) * Q + i) * 64 + lane] = bx[i];
+            bsum[((wave * 2 + 1) * Q + i) * 64 + lane] = by[i];
+        }
+        __syncthreads();
+        for (int t = tid; t < Q * 64; t += kCThreads) {
+            const int i = t >> 6, l = t & 63, q = l + 64 * i;
+            if (q < nq) {
+                float sx = 0.f, sy = 0.f;
+                for (int w = 0; w < kCWaves; ++w) {
+                    sx += bsum[((w * 2 + 0) * Q + i) * 64 + l];
+                    sy += bsum[((w * 2 + 1) * Q + i) * 64 + l];
+                }
+                ub[e0 * nq + q] = make_float2(eps * sx, eps * sy);
+            }
+        }
+    }
+}
+
+template <int Q>
+__global__ __launch_bounds__(kCThreads) void k_contract_rows(ContractArgs A) {
+    __shared__ float bsum[kCWaves * 2 * Q * 64];
+    __shared__ double lp[kCWaves][2];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const ContractCtx c = contract_ctx(A);
+    double lrr = 0.0, lra = 0.0;
+    contract_rows<Q>(A, c, bsum, tid, wave, lane, lrr, lra);
+    contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
+}
+
+__global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) {
+    extern __shared__ float dyn[];
+    __shared__ double lp[kCWaves][2];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const ContractCtx c = contract_ctx(A);
+    const InstDesc *Ip = c.I;
+    const int nq = Ip->nq, ntest = Ip->ntest;
+    const int64_t e0 = c.e0;
+    const float *__restrict__ Gx = Ip->Gx;
+    const float *__restrict__ Gy = Ip->Gy;
+    const float *__restrict__ F = Ip->F;
+    const float two_cv = Ip->two_cv, eps = c.eps;
+    float2 *__restrict__ ub = A.ubuf + Ip->ubase;
+    double lrr = 0.0, lra = 0.0;
+    float *rbar = dyn;  // [ntest] 2 c_v R of the block's element
+    const int64_t ebase = e0 * ntest;
+    const float2 *__restrict__ uxy = ub + e0 * nq;
+    constexpr int kRG = kCThreads / 16;
+    const int rg = tid >> 4, rl = tid & 15;
+    for (int k0 = 0; k0 < ntest; k0 += kRG) {
+        const int k = k0 + rg;
+        float acc = 0.f;
+        if (k < ntest) {
+            const float *gxr = Gx + (ebase + k) * (int64_t)nq, *gyr = Gy + (ebase + k) * (int64_t)nq;
+            for (int q = rl; q < nq; q += 16) {
+                const float2 d = uxy[q];
+                acc = fmaf(d.x, gxr[q], fmaf(d.y, gyr[q], acc));
+            }
+        }
+        acc += __shfl_xor(acc, 8, 16);
+        acc += __shfl_xor(acc, 4, 16);
+        acc += __shfl_xor(acc, 2, 16);
+        acc += __shfl_xor(acc, 1, 16);
+        if (rl == 0 && k < ntest) {
+            const float R = eps * acc - F[ebase + k];
+            rbar[k] = two_cv * R;
+            lrr += (double)R * (double)R;
+            lra += (double)R * (double)acc;
+        }
+    }
+    __syncthreads();
+    if (A.want_grad) {
+        for (int q = tid; q < nq; q += kCThreads) {
+            float bx = 0.f, by = 0.f;
+            for (int k = 0; k < ntest; ++k) {
+                const int64_t o = (ebase + k) * (int64_t)nq + q;
+                bx = fmaf(rbar[k], Gx[o], bx);
+                by = fmaf(rbar[k], Gy[o], by);
+            }
+            ub[e0 * nq + q] = make_float2(eps * bx, eps * by);
+        }
+    }
+    contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
 }
 
 // one wavefront's gradient sums in padded order -> P (op: store, or add to what P holds)
@@ -983,7 +1143,8 @@ struct FusedPlan {
     std::vector<InstDesc> host_inst;
     int tblocks = 0, n_inst = 0, grows = 0, lrows = 0, L = 0, H = 0;
     int64_t cblocks = 0, tiles = 0, npf = 0;
-    size_t cdyn = 0;  // dynamic LDS of k_contract
+    int64_t cpath_blocks[kNumPaths] = {};  // contraction blocks of each path, in path order
+    size_t cdyn_fast = 0, cdyn_generic = 0;  // dynamic LDS of k_contract_fast / k_contract_generic
 };
 
 static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_loss_cfg *cfg, int dev,
@@ -992,7 +1153,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     const int cus = cu_count(dev);
     std::vector<InstDesc> D(n);
     int64_t tiles = 0, ubase = 0, cblocks = 0;
-    size_t cdyn = 16;
+    size_t cdyn_fast = 16, cdyn_generic = 16;
     for (int i = 0; i < n; ++i) {
         const vpinn_problem *p = probs[i];
         const int64_t tot = p->n_pts + p->n_bnd + p->n_sen;
@@ -1014,13 +1175,16 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         ubase += tot;
         d.nq = p->nq;
         d.ntest = p->ntest;
-        d.fast = (p->nq <= kCThreads && p->ntest <= kKB) ? 1 : 0;
-        d.epc = d.fast ? std::max(1, kCThreads / p->nq) : 1;
+        d.path = (p->nq <= kCThreads && p->ntest <= kKB) ? kPathFast
+                 : (p->nq <= 64)                          ? kPathRows1
+                 : (p->nq <= 128)                         ? kPathRows2
+                 : (p->nq <= 64 * kRowQ)                  ? kPathRows4
+                                                          : kPathGeneric;
+        d.epc = d.path == kPathFast ? std::max(1, kCThreads / p->nq) : 1;
         d.n_chunks = (p->n_elem + d.epc - 1) / d.epc;
-        d.cblk0 = cblocks;
-        cblocks += d.n_chunks;
-        const size_t need = sizeof(float) * (d.fast ? (size_t)d.ntest * kCbs + (size_t)d.epc * d.ntest : (size_t)d.ntest);
-        cdyn = std::max(cdyn, need);
+        if (d.path == kPathFast)
+            cdyn_fast = std::max(cdyn_fast, sizeof(float) * ((size_t)d.ntest * kCbs + (size_t)d.epc * d.ntest));
+        if (d.path == kPathGeneric) cdyn_generic = std::max(cdyn_generic, sizeof(float) * (size_t)d.ntest);
         d.cv = cfg->loss_norm == VPINN_NORM_ELEM ? 1.0 / (double)p->n_elem : 1.0 / (double)p->ntest;
         d.two_cv = (float)(2.0 * d.cv);
         d.wb2 = p->n_bnd ? (float)(2.0 * cfg->tau / (double)p->n_bnd) : 0.f;
@@ -1028,8 +1192,18 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         d.tau = cfg->tau;
         d.gamma = cfg->gamma;
     }
+    // contraction blocks grouped by path (one launch each), instance order within a path
+    int64_t cpath_blocks[kNumPaths] = {};
+    for (int path = 0; path < kNumPaths; ++path)
+        for (int i = 0; i < n; ++i)
+            if (D[i].path == path) {
+                D[i].cblk0 = cblocks;
+                cblocks += D[i].n_chunks;
+                cpath_blocks[path] += D[i].n_chunks;
+            }
     if (cblocks > (int64_t)INT32_MAX) return fail(VPINN_E_UNSUPPORTED, "fused path: too many elements for one launch");
-    if (cdyn > 64 * 1024) return fail(VPINN_E_UNSUPPORTED, "fused path: test-function count exceeds the LDS budget");
+    if (cdyn_fast > 64 * 1024 || cdyn_generic > 64 * 1024)
+        return fail(VPINN_E_UNSUPPORTED, "fused path: test-function count exceeds the LDS budget");
     // tile blocks (k_fwd and k_bwd): one per CU, equal shares of the tile list
     const int tblocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus, kMaxBlocks), tiles);
     std::vector<int64_t> bt(tblocks + 1);
@@ -1073,9 +1247,9 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     VP_HIP(hipMemcpy(P.blk_tiles.ptr, bt.data(), sizeof(int64_t) * (tblocks + 1), hipMemcpyHostToDevice));
     VP_HIP(hipMemcpy(P.blk_inst0.ptr, binst.data(), sizeof(int) * tblocks, hipMemcpyHostToDevice));
     VP_HIP(hipMemcpy(P.cblk_inst.ptr, cinst.data(), sizeof(int) * (size_t)cblocks, hipMemcpyHostToDevice));
-    if (cdyn > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_contract, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)cdyn);
+    if (cdyn_fast > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_contract_fast, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)cdyn_fast);
         if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     }
     P.host_inst = D;
@@ -1088,7 +1262,9 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     P.L = L;
     P.H = H;
     P.npf = vpinn_n_params(H, L);
-    P.cdyn = cdyn;
+    for (int k = 0; k < kNumPaths; ++k) P.cpath_blocks[k] = cpath_blocks[k];
+    P.cdyn_fast = cdyn_fast;
+    P.cdyn_generic = cdyn_generic;
     return VPINN_OK;
 }
 
@@ -1098,13 +1274,27 @@ static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs
                        hipEvent_t const *ev, hipStream_t s) {
     if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
     k_fwd<L><<<P.tblocks, kFwThreads, 0, s>>>(fa);
-    k_contract<<<(unsigned)P.cblocks, kCThreads, P.cdyn, s>>>(ca);
     if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
-    if (want_grad) k_bwd<L><<<P.tblocks, kBThreads, 0, s>>>(ba);
+    {
+        ContractArgs c = ca;
+        c.cblk_base = 0;
+        if (P.cpath_blocks[kPathFast]) k_contract_fast<<<(unsigned)P.cpath_blocks[kPathFast], kCThreads, P.cdyn_fast, s>>>(c);
+        c.cblk_base += P.cpath_blocks[kPathFast];
+        if (P.cpath_blocks[kPathRows1]) k_contract_rows<1><<<(unsigned)P.cpath_blocks[kPathRows1], kCThreads, 0, s>>>(c);
+        c.cblk_base += P.cpath_blocks[kPathRows1];
+        if (P.cpath_blocks[kPathRows2]) k_contract_rows<2><<<(unsigned)P.cpath_blocks[kPathRows2], kCThreads, 0, s>>>(c);
+        c.cblk_base += P.cpath_blocks[kPathRows2];
+        if (P.cpath_blocks[kPathRows4]) k_contract_rows<4><<<(unsigned)P.cpath_blocks[kPathRows4], kCThreads, 0, s>>>(c);
+        c.cblk_base += P.cpath_blocks[kPathRows4];
+        if (P.cpath_blocks[kPathGeneric])
+            k_contract_generic<<<(unsigned)P.cpath_blocks[kPathGeneric], kCThreads, P.cdyn_generic, s>>>(c);
+    }
     if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
+    if (want_grad) k_bwd<L><<<P.tblocks, kBThreads, 0, s>>>(ba);
+    if (ev && ev[3]) (void)hipEventRecord(ev[3], s);
     k_fused_final<L><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf,
                                         loss, grad, grad_eps, ad);
-    if (ev && ev[3]) (void)hipEventRecord(ev[3], s);
+    if (ev && ev[4]) (void)hipEventRecord(ev[4], s);
 }
 
 // launch forward, contraction, backward, and the per-instance reduction (with optional Adam)
@@ -1202,7 +1392,7 @@ struct vpinn_batch {
     vp::FusedPlan plan;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipEvent_t prof[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t prof[VPINN_PROFILE_EVENTS] = {};
     ~vpinn_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1249,14 +1439,14 @@ vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d
         (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
-    hipEvent_t saved[4];
-    for (int i = 0; i < 4; ++i) {
+    hipEvent_t saved[VPINN_PROFILE_EVENTS];
+    for (int i = 0; i < VPINN_PROFILE_EVENTS; ++i) {
         saved[i] = b->prof[i];
         b->prof[i] = nullptr;
     }
     VP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     vpinn_status st = batch_step(b, d_params, d_m, d_v, d_step, lr, b1, b2, eps, d_losses, s);
-    for (int i = 0; i < 4; ++i) b->prof[i] = saved[i];
+    for (int i = 0; i < VPINN_PROFILE_EVENTS; ++i) b->prof[i] = saved[i];
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st) {
@@ -1272,7 +1462,7 @@ vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d
 int batch_device(const vpinn_batch *b) { return b->device; }
 
 void batch_set_profile_events(vpinn_batch *b, void *const *events) {
-    for (int i = 0; i < 4; ++i) b->prof[i] = events ? (hipEvent_t)events[i] : nullptr;
+    for (int i = 0; i < VPINN_PROFILE_EVENTS; ++i) b->prof[i] = events ? (hipEvent_t)events[i] : nullptr;
 }
 
 void batch_destroy(vpinn_batch *b) { delete b; }

@@ -84,7 +84,7 @@ struct vpinn_problem {
     vp::DevBuf loss_e;       // double [n_elem]: per-element sum_k R^2 (or per-block partials)
     vp::DevBuf gpart;        // float [blocks][kMaxPadded]: per-block gradient partials
     vp::DevBuf eps_part;     // double [blocks]
-    hipEvent_t prof[4] = {nullptr, nullptr, nullptr, nullptr};  // optional timing events (caller-owned)
+    hipEvent_t prof[VPINN_PROFILE_EVENTS] = {};  // optional timing events (caller-owned)
     void *fused_ws = nullptr;              // fused-path workspace (owned)
     void (*fused_ws_free)(void *) = nullptr;
     int64_t all_pts() const { return n_pts + n_bnd + n_sen; }

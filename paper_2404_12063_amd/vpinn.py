@@ -32,6 +32,7 @@ VPINN_PATH_PLAIN = 1
 VPINN_NORM_TEST = 0
 VPINN_NORM_ELEM = 1
 VPINN_TENSOR_GX, VPINN_TENSOR_GY, VPINN_TENSOR_F, VPINN_TENSOR_X = 0, 1, 2, 3
+PROFILE_EVENTS = 5  # VPINN_PROFILE_EVENTS: forward | contraction | backward | reduction
 
 SCALAR_FN = C.CFUNCTYPE(C.c_double, C.c_double, C.c_double, C.c_void_p)
 
@@ -281,6 +282,8 @@ def vpinn_batch_replay(b: Batch, stream=None):
 def _event_array(events):
     if events is None:
         return None
+    if len(events) != PROFILE_EVENTS:
+        raise ValueError(f"expected {PROFILE_EVENTS} events, got {len(events)}")
     handles = []
     for e in events:
         if e is None:
@@ -290,11 +293,11 @@ def _event_array(events):
             if not h:
                 raise ValueError("torch events must be recorded once before their handles are passed")
             handles.append(h)
-    return (C.c_void_p * 4)(*handles)
+    return (C.c_void_p * PROFILE_EVENTS)(*handles)
 
 
 def vpinn_set_profile_events(p: Problem, events=None):
-    """events: 4 torch.cuda.Event(enable_timing=True) already recorded once (or None to disable)."""
+    """events: PROFILE_EVENTS torch.cuda.Event(enable_timing=True) already recorded once (or None to disable)."""
     arr = _event_array(events)
     _check(lib().vpinn_set_profile_events(p.handle, arr))
 

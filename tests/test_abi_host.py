@@ -37,6 +37,17 @@ def test_header_declares_the_boundary_calls():
         assert must in names
 
 
+def test_binding_constants_match_the_header(V):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defines = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(VPINN_[A-Z_0-9]+)\s+\(?(-?\d+)\)?", text)}
+    assert "VPINN_PROFILE_EVENTS" in defines and "VPINN_E_UNSUPPORTED" in defines
+    for name, value in defines.items():
+        if name.startswith("VPINN_MAX_"):
+            continue
+        bound = V.PROFILE_EVENTS if name == "VPINN_PROFILE_EVENTS" else getattr(V, name)
+        assert bound == value, name
+
+
 def test_library_exports_every_declared_symbol(V):
     out = subprocess.run(["nm", "-D", "--defined-only", V.LIB_PATH], capture_output=True, text=True, check=True)
     exported = {line.split()[-1] for line in out.stdout.splitlines() if " T " in line}

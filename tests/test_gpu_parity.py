@@ -61,6 +61,12 @@ def _problem(name):
         return p
     if name == "p20":         # the p-refinement maximum (20x20 test functions) on a small mesh
         return gen.poisson_sinsin_square("p20", 4, 10, 20, 2, 80, 0.2, seed=6)
+    if name == "q6t7":        # 49 test functions on 36 points: row-streaming contraction, one point per lane
+        return gen.poisson_sinsin_square("q6t7", 3, 6, 7, 2, 40, 0.2, seed=8)
+    if name == "q12t6":       # 144 points, 36 test functions: row streaming with four points a lane
+        return gen.poisson_sinsin_square("q12t6", 2, 12, 6, 2, 40, 0.2, seed=9)
+    if name == "q17":         # 289 points per element: the two-pass contraction for large elements
+        return gen.poisson_sinsin_square("q17", 2, 17, 3, 2, 40, 0.2, seed=7)
     if name == "gear_small":  # a small toothed annulus: skewed elements, nonzero boundary data
         import math
         kp = 4 * math.pi
@@ -178,7 +184,8 @@ def test_network_values_and_tangents(V, torch, H, L):
 # ----------------------------------------------------------------------------- loss and gradient
 
 @pytest.mark.parametrize("path", ["plain", "fused"])
-@pytest.mark.parametrize("name", ["c1", "c2", "gear_small", "ragged", "tiny_n2", "deep32", "nobnd", "p20"])
+@pytest.mark.parametrize("name", ["c1", "c2", "gear_small", "ragged", "tiny_n2", "deep32", "nobnd", "p20", "q6t7",
+                                  "q12t6", "q17"])
 def test_loss_and_grad_match_oracle(V, torch, path, name):
     prob = _problem(name)
     theta = _params(prob)
@@ -187,11 +194,14 @@ def test_loss_and_grad_match_oracle(V, torch, path, name):
     _check(loss, grad, _oracle(prob, theta), tag=f"{name}/{path}")
 
 
+@pytest.mark.parametrize("orders", [(10, 5), (6, 7), (17, 3)])
 @pytest.mark.parametrize("path", ["plain", "fused"])
-def test_inverse_problem_eps_gradient(V, torch, path):
-    """C4-shaped inverse problem on a reduced mesh: trainable eps, sensors and boundary points."""
+def test_inverse_problem_eps_gradient(V, torch, path, orders):
+    """C4-shaped inverse problem on a reduced mesh: trainable eps, sensors and boundary points (orders chosen
+    so that each of the fused path's three contraction schemes is exercised)."""
     prob = gen.config_c4()
-    small = gen.Problem("c4small", gen.square_mesh(12, 12, 0.2, seed=1), 10, 5, prob.f_amp, prob.f_kx, prob.f_ky,
+    nq, nt = orders
+    small = gen.Problem("c4small", gen.square_mesh(12, 12, 0.2, seed=1), nq, nt, prob.f_amp, prob.f_kx, prob.f_ky,
                         prob.bnd_xy, prob.bnd_g, prob.sens_xy[:300], prob.sens_u[:300], tau=10.0, gamma=10.0)
     from oracle import oracle as O
     asm = O.assemble_problem(small)
