@@ -192,7 +192,38 @@ def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
     return out
 
 
-def time_graph(V, torch, p, prob, theta, steps: int, warmup: int):
+def profile_batch_kernels(V, torch, b, s, T, M, Vv, step, losses, n_steps: int):
+    """Mean duration of each fused-path kernel over eager batched steps of plan `b` (its profiling events)."""
+    NE = V.PROFILE_EVENTS
+    pev = [[torch.cuda.Event(enable_timing=True) for _ in range(NE)] for _ in range(n_steps)]
+    for e in pev:
+        for x in e:
+            x.record(s)
+    for i in range(n_steps):
+        V.vpinn_batch_set_profile_events(b, pev[i])
+        V.vpinn_batch_step(b, T, M, Vv, step, lr=1e-3, losses=losses, stream=s)
+    V.vpinn_batch_set_profile_events(b, None)
+    torch.cuda.synchronize()
+    out = {name: sum(e[k].elapsed_time(e[k + 1]) for e in pev) / n_steps
+           for k, name in enumerate(["k_fwd", "k_contract", "k_bwd", "k_fused_final"])}
+    out["steps"] = n_steps
+    return out
+
+
+def tune_batch(V, b, params, stream, fixed, reps):
+    """Autotune the batch's tile shapes, or apply a fixed tuning (profiling runs want one plan only)."""
+    if fixed is not None:
+        V.vpinn_batch_set_tuning(b, *fixed)
+        tuning = V.vpinn_batch_get_tuning(b)
+        print(f"[bench] fixed tile shapes (fwd_waves, chunk_shift, rows_per_pass) = {tuning}", file=sys.stderr, flush=True)
+    else:
+        tuning = V.vpinn_batch_autotune(b, params, reps=reps, stream=stream)
+        print(f"[bench] autotuned tile shapes (fwd_waves, chunk_shift, rows_per_pass) = {tuning}", file=sys.stderr,
+              flush=True)
+    return tuning
+
+
+def time_graph(V, torch, p, prob, theta, steps: int, warmup: int, fixed_tuning=None):
     """The headline step: one problem as a batch of one, forward + adjoint + Adam (Adam inside the
     reduction kernel, step counter in device memory) captured once in a HIP graph and replayed.
     Throughput: `steps` replays back to back, bracketed by synchronisations (host wall clock) and by one
@@ -207,6 +238,8 @@ def time_graph(V, torch, p, prob, theta, steps: int, warmup: int):
     s = torch.cuda.Stream()
     n_dist = min(steps, 200)
     with torch.cuda.stream(s):
+        tuning = tune_batch(V, b, th, s, fixed_tuning, reps=5)
+        kms = profile_batch_kernels(V, torch, b, s, th, m, v, step, losses, n_steps=min(steps, 100))
         V.vpinn_batch_capture(b, th, m, v, step, lr=1e-3, losses=losses, stream=s)
         for _ in range(warmup):
             V.vpinn_batch_replay(b, stream=s)
@@ -227,8 +260,9 @@ def time_graph(V, torch, p, prob, theta, steps: int, warmup: int):
         torch.cuda.synchronize()
     st = sorted(a.elapsed_time(c) for a, c in ev)
     q = lambda xs, f: xs[min(len(xs) - 1, int(f * len(xs)))]  # noqa: E731
-    return {"wall_s": wall, "event_ms_total": e0.elapsed_time(e1), "step_ms_p10": q(st, 0.1),
-            "step_ms_p50": q(st, 0.5), "step_ms_p90": q(st, 0.9), "steps_done": int(step.item()) - n_dist,
+    return {"wall_s": wall, "event_ms_total": e0.elapsed_time(e1), "tuning": list(tuning), "kernel_ms": kms,
+            "step_ms_p10": q(st, 0.1),
+            "step_ms_p50": q(st, 0.5), "step_ms_p90": q(st, 0.9), "steps_done": int(step.item()) - n_dist - kms["steps"],
             "final_loss": float(losses[0, 0].item())}
 
 
@@ -281,6 +315,7 @@ def bench_batched(args, V, torch, gen):
     losses = torch.zeros((64, 4), device=dev)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
+        tuning = tune_batch(V, b, T, s, args.tuning, reps=3)
         V.vpinn_batch_capture(b, T, M, Vv, step, lr=1e-3, losses=losses, stream=s)
         for _ in range(args.warmup):
             V.vpinn_batch_replay(b, stream=s)
@@ -296,21 +331,9 @@ def bench_batched(args, V, torch, gen):
         wall = time.perf_counter() - w0
     st = sorted(a.elapsed_time(c) for a, c in ev)
     ms = wall / args.steps * 1e3
-    # per-kernel durations: a few eager batched steps with the library's profiling events
-    NE = V.PROFILE_EVENTS
-    n_prof = 10
-    pev = [[torch.cuda.Event(enable_timing=True) for _ in range(NE)] for _ in range(n_prof)]
+    # per-kernel durations: eager batched steps of the same plan with the library's profiling events
     with torch.cuda.stream(s):
-        for e in pev:
-            for x in e:
-                x.record(s)
-        for i in range(n_prof):
-            V.vpinn_batch_set_profile_events(b, pev[i])
-            V.vpinn_batch_step(b, T, M, Vv, step, lr=1e-3, losses=losses, stream=s)
-        V.vpinn_batch_set_profile_events(b, None)
-    torch.cuda.synchronize()
-    kms = {name: sum(e[k].elapsed_time(e[k + 1]) for e in pev) / n_prof
-           for k, name in enumerate(["k_fwd", "k_contract", "k_bwd", "k_fused_final"])}
+        kms = profile_batch_kernels(V, torch, b, s, T, M, Vv, step, losses, n_steps=10)
     work = {}
     for pr in probs:
         for name, w in kernel_work(pr).items():
@@ -359,7 +382,7 @@ def bench_batched(args, V, torch, gen):
                                "counts log-uniform in [256,16384], GLL n in {4,6,10}, test N_t in {3,5}, "
                                "k in 1..16, each with its own 2-30-30-30-1 tanh MLP; one batched "
                                "forward+adjoint+Adam step per epoch replayed from a HIP graph",
-                   "instances": 64, "quad_points": P, "parallelism": "single GPU"},
+                   "instances": 64, "quad_points": P, "parallelism": "single GPU", "tuning": list(tuning)},
         "mquadpts_per_s": round(P * eps_s / 1e6, 2),
         "step_ms_p10_p50_p90": [round(st[len(st) // 10], 4), round(st[len(st) // 2], 4),
                                 round(st[(9 * len(st)) // 10], 4)],
@@ -395,6 +418,9 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then "
                          "WRITE_SIZE, taken with --copy-probe on --workload W) into profiles/traffic.json[W]")
+    ap.add_argument("--tuning", type=lambda t: tuple(int(x) for x in t.split(",")), default=None,
+                    metavar="FWD_WAVES,CHUNK_SHIFT,ROWS_PER_PASS",
+                    help="use this tile-shape tuning instead of autotuning (profiling runs)")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(args.workload, *args.traffic_from)
@@ -447,7 +473,7 @@ def bench_single(args, V, torch, gen):
     eager = time_path(V, torch, p, prob, theta, main_path, eager_steps, args.warmup)
     print(f"[bench] {args.path} eager: {eager['wall_s'] / eager_steps * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
     if fused:
-        res = time_graph(V, torch, p, prob, theta, args.steps, args.warmup)
+        res = time_graph(V, torch, p, prob, theta, args.steps, args.warmup, args.tuning)
         assert res["steps_done"] == args.warmup + args.steps
         print(f"[bench] fused graph: {res['wall_s'] / args.steps * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
     else:
@@ -472,17 +498,18 @@ def bench_single(args, V, torch, gen):
     work = kernel_work(prob)
     kernels = {}
     if fused:
+        km = res["kernel_ms"]
         for name in ("k_fwd", "k_contract", "k_bwd"):
-            k_ms = eager[name + "_ms"]
+            k_ms = km[name]
             ent = {"ms": round(k_ms, 5), "tflops": round(work[name]["flop"] / (k_ms * 1e-3) / 1e12, 3)}
             ent["frac_fp32_peak"] = round(ent["tflops"] / PEAK_FP32_TFLOPS, 4)
             if "bytes" in work[name]:
                 ent["gbs"] = round(work[name]["bytes"] / (k_ms * 1e-3) / 1e9, 1)
                 ent["frac_hbm_peak"] = round(ent["gbs"] / PEAK_HBM_GBS, 4)
             kernels[name] = ent
-        kernels["k_fused_final"] = {"ms": round(eager["k_final_ms"], 5)}
-        dom = max(("k_fwd", "k_contract", "k_bwd"), key=lambda k: eager[k + "_ms"])
-        k_ms = eager[dom + "_ms"]
+        kernels["k_fused_final"] = {"ms": round(km["k_fused_final"], 5), "note": "reduction + Adam"}
+        dom = max(("k_fwd", "k_contract", "k_bwd"), key=lambda k: km[k])
+        k_ms = km[dom]
         if dom == "k_contract" and work[dom]["flop"] / work[dom]["bytes"] < 1.0:
             achieved = work[dom]["bytes"] / (k_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
@@ -516,6 +543,7 @@ def bench_single(args, V, torch, gen):
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "path": args.path + (" (HIP graph replay of the batch-of-one step)" if fused else " (eager)"),
+                   "tuning": res.get("tuning"),
                    "n_elem": prob.n_elem, "quad_points": prob.n_points,
                    "boundary_points": len(prob.bnd_xy), "parallelism": "single GPU"},
         "mquadpts_per_s": round(prob.n_points * eps_s / 1e6, 2),
@@ -529,7 +557,10 @@ def bench_single(args, V, torch, gen):
         out["step_ms_p10_p50_p90"] = [round(res["step_ms_p10"], 5), round(res["step_ms_p50"], 5),
                                       round(res["step_ms_p90"], 5)]
         out["gpu_event_ms_per_step"] = round(res["event_ms_total"] / args.steps, 5)
-        out["eager"] = {"ms_per_step": round(eager["wall_s"] / eager_steps * 1e3, 5), "kernels": kernels}
+        out["kernels"] = kernels
+        out["kernels_note"] = ("mean durations over eager batched steps of the same tuned plan as the timed graph, "
+                               "from the library's profiling events")
+        out["single_problem_api_eager_ms_per_step"] = round(eager["wall_s"] / eager_steps * 1e3, 5)
     if plain is not None:
         pms = plain["wall_s"] / min(args.steps, 300) * 1e3
         out["plain_hip"] = {"ms_per_step": round(pms, 5), "epochs_per_s": round(1e3 / pms, 3),

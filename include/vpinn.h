@@ -198,9 +198,11 @@ typedef struct vpinn_batch vpinn_batch;
  * the network shape and loss weighting in `cfg` (cfg->path is ignored: batches
  * always use the fused kernel).  The batch borrows the problems' device data:
  * they must outlive it, and a later vpinn_set_boundary/vpinn_set_sensors on
- * any of them requires a new batch.  Work is split into items balanced by
- * point count over the device's compute units.  Allocates its workspace here;
- * later batch calls allocate nothing.
+ * any of them requires a new batch.  Work is split into tiles of 16 points
+ * (forward and reverse sweeps: equal shares, one block per compute unit) and
+ * chunks of whole elements (contraction), with the tuning {12, 0, 4} (see
+ * vpinn_tuning).  Allocates its workspace here; later loss/step/capture/replay
+ * calls allocate nothing.
  */
 vpinn_status vpinn_batch_create(int32_t n, vpinn_problem *const *problems, const vpinn_loss_cfg *cfg,
                                 vpinn_batch **out);
@@ -243,6 +245,48 @@ vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream);
 
 /* Release the batch (not the problems).  NULL is a no-op. */
 void vpinn_batch_free(vpinn_batch *b);
+
+/*
+ * Tile shapes of a batch's plan.  Every choice computes the same loss and
+ * gradient; they differ in speed and in FP32 summation order (results are
+ * bitwise reproducible for a fixed tuning).
+ *   fwd_waves      wavefronts per forward-pass block (one block per CU): 8, 12, 16
+ *   chunk_shift    small elements (N_quad <= 256, N_test <= 32): elements per
+ *                  contraction block = max(1, floor(256 / N_quad) >> chunk_shift),
+ *                  0..2
+ *   rows_per_pass  larger test spaces: test-function rows of G a wavefront
+ *                  streams per pass, 2, 4 or 8
+ * A new batch starts with {12, 0, 4}.
+ */
+typedef struct {
+    int32_t fwd_waves;
+    int32_t chunk_shift;
+    int32_t rows_per_pass;
+} vpinn_tuning;
+
+/* The batch's current tuning.  Errors: VPINN_E_INVALID (null argument). */
+vpinn_status vpinn_batch_get_tuning(const vpinn_batch *b, vpinn_tuning *out);
+
+/*
+ * Rebuild the batch's plan with tuning *t (allocates; drops a captured graph, so
+ * capture again before replaying).  Errors: VPINN_E_INVALID (null argument or a
+ * value outside the lists above), VPINN_E_NOMEM, VPINN_E_DEVICE.
+ */
+vpinn_status vpinn_batch_set_tuning(vpinn_batch *b, const vpinn_tuning *t);
+
+/*
+ * vpinn_batch_autotune -- the project's tile-shape autotuner.  Times every
+ * tuning that matters for this batch (forward block sizes always; contraction
+ * chunking only if some problem has small elements; rows per pass only if some
+ * problem streams rows) by `reps` loss-and-gradient evaluations at d_params
+ * (device [n][n_params], not modified) after one warm-up each, keeps the one
+ * with the lowest median time, and returns it in *best (may be NULL).
+ * Synchronous on `stream`; allocates scratch outputs and each candidate plan;
+ * drops a captured graph like vpinn_batch_set_tuning.  Errors: VPINN_E_INVALID
+ * (null batch or params, reps outside 1..100), VPINN_E_NOMEM, VPINN_E_DEVICE.
+ */
+vpinn_status vpinn_batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps, vpinn_tuning *best,
+                                  void *stream);
 
 /*
  * Profiling hooks for the fused path: `events` points to VPINN_PROFILE_EVENTS

@@ -379,6 +379,30 @@ vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream) {
     return batch_replay(b, (hipStream_t)stream);
 }
 
+vpinn_status vpinn_batch_get_tuning(const vpinn_batch *b, vpinn_tuning *out) {
+    using namespace vp;
+    if (!b || !out) return fail(VPINN_E_INVALID, "batch or out is null");
+    return batch_get_tuning(b, out);
+}
+
+vpinn_status vpinn_batch_set_tuning(vpinn_batch *b, const vpinn_tuning *t) {
+    using namespace vp;
+    if (!b || !t) return fail(VPINN_E_INVALID, "batch or tuning is null");
+    DeviceGuard dg(batch_device(b));
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the batch's device");
+    return batch_set_tuning(b, t);
+}
+
+vpinn_status vpinn_batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps, vpinn_tuning *best,
+                                  void *stream) {
+    using namespace vp;
+    if (!b || !d_params) return fail(VPINN_E_INVALID, "batch or params is null");
+    if (reps < 1 || reps > 100) return fail(VPINN_E_INVALID, "reps must be in 1..100");
+    DeviceGuard dg(batch_device(b));
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the batch's device");
+    return batch_autotune(b, d_params, reps, best, (hipStream_t)stream);
+}
+
 vpinn_status vpinn_set_profile_events(vpinn_problem *p, void *const *events) {
     using namespace vp;
     if (!p) return fail(VPINN_E_INVALID, "problem is null");

@@ -41,10 +41,9 @@ namespace vp {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// forward: one block per CU; the forward alone needs few registers (~126), so
-// three wavefronts per SIMD hide each other's LDS and MFMA latencies
-constexpr int kFwThreads = 768;
-constexpr int kFwWaves = kFwThreads / 64;
+// forward: one block per CU of 8, 12 or 16 wavefronts (a tuning choice); the
+// forward alone needs few registers (~126), so up to four wavefronts per SIMD
+// hide each other's LDS and MFMA latencies
 // contraction: many small blocks, one chunk of whole elements each
 constexpr int kCThreads = 256;
 constexpr int kCWaves = kCThreads / 64;
@@ -90,11 +89,11 @@ struct WeightsShared {
     float bo;
 };
 
-template <int L>
+template <int L, int NW>
 struct FwdShared {
     WeightsShared<L> W;
     float stage[n_padded(L)];  // flat parameters, staged for load_weights
-    double lp[kFwWaves][2];    // per-wavefront loss partials: sum d_b^2, sum d_s^2
+    double lp[NW][2];          // per-wavefront loss partials: sum d_b^2, sum d_s^2
 };
 
 template <int L>
@@ -528,9 +527,10 @@ __device__ __forceinline__ void zero_acc(GradAcc<L> &G) {
 // 1: forward values and tangents at every point.  Blocks own contiguous tile ranges
 // (the same ranges as k_bwd), possibly spanning instances; the tiles of a range go
 // round-robin over the block's wavefronts.
-template <int L>
-__global__ __launch_bounds__(kFwThreads, 1) void k_fwd(FwdArgs A) {
-    __shared__ FwdShared<L> S;
+template <int L, int NW>
+__global__ __launch_bounds__(NW * 64, 1) void k_fwd(FwdArgs A) {
+    constexpr int kFwThreads = NW * 64, kFwWaves = NW;
+    __shared__ FwdShared<L, NW> S;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (A.step && blockIdx.x == 0 && tid == 0) *A.step += 1;
     int64_t t = A.blk_tiles[blockIdx.x];
@@ -709,17 +709,16 @@ __global__ __launch_bounds__(kCThreads) void k_contract_fast(ContractArgs A) {
 }
 
 // row-streaming contraction of one element: wavefront w takes test-function rows
-// k = w, w + kCWaves, ..., kRP rows per pass with all their loads in flight; a row's G values (lane holds q = lane + 64 i, i < Q) give A_k by
+// k = w, w + kCWaves, ..., kRP rows per pass (a tuning choice) with all their loads in flight; a row's G values (lane holds q = lane + 64 i, i < Q) give A_k by
 // a wavefront sum and then, still in registers, the row's share 2 c_v R_k G[k, q] of
 // the adjoint; the wavefront partials are added in wavefront order at the end.
-constexpr int kRP = 4;
-template <int Q>
+template <int Q, int kRP>
 struct RowBuf {
     float gx[kRP][Q], gy[kRP][Q];
 };
 
-template <int Q>
-__device__ __forceinline__ void rows_load(RowBuf<Q> &B, const float *__restrict__ Gx, const float *__restrict__ Gy,
+template <int Q, int kRP>
+__device__ __forceinline__ void rows_load(RowBuf<Q, kRP> &B, const float *__restrict__ Gx, const float *__restrict__ Gy,
                                           int64_t ebase, int k0, int ntest, int nq, int lane) {
 #pragma unroll
     for (int r = 0; r < kRP; ++r) {
@@ -735,8 +734,8 @@ __device__ __forceinline__ void rows_load(RowBuf<Q> &B, const float *__restrict_
     }
 }
 
-template <int Q>
-__device__ __forceinline__ void rows_use(const RowBuf<Q> &B, const float *ux, const float *uy, float *bx, float *by,
+template <int Q, int kRP>
+__device__ __forceinline__ void rows_use(const RowBuf<Q, kRP> &B, const float *ux, const float *uy, float *bx, float *by,
                                          const float *__restrict__ F, int64_t ebase, int k0, int ntest, float eps,
                                          float two_cv, int lane, double &lrr, double &lra) {
 #pragma unroll
@@ -762,7 +761,7 @@ __device__ __forceinline__ void rows_use(const RowBuf<Q> &B, const float *ux, co
     }
 }
 
-template <int Q>
+template <int Q, int kRP>
 __device__ __forceinline__ void contract_rows(const ContractArgs &A, const ContractCtx &c, float *bsum, int tid,
                                               int wave, int lane, double &lrr, double &lra) {
     const InstDesc *Ip = c.I;
@@ -786,9 +785,9 @@ __device__ __forceinline__ void contract_rows(const ContractArgs &A, const Contr
     // high occupancy (few registers a wavefront) keeps many rows in flight per SIMD
     constexpr int kStep = kRP * kCWaves;
     for (int k0 = wave; k0 < ntest; k0 += kStep) {
-        RowBuf<Q> B;
-        rows_load<Q>(B, Gx, Gy, ebase, k0, ntest, nq, lane);
-        rows_use<Q>(B, ux, uy, bx, by, F, ebase, k0, ntest, eps, two_cv, lane, lrr, lra);
+        RowBuf<Q, kRP> B;
+        rows_load<Q, kRP>(B, Gx, Gy, ebase, k0, ntest, nq, lane);
+        rows_use<Q, kRP>(B, ux, uy, bx, by, F, ebase, k0, ntest, eps, two_cv, lane, lrr, lra);
     }
     if (A.want_grad) {
 #pragma unroll
@@ -811,14 +810,14 @@ __device__ __forceinline__ void contract_rows(const ContractArgs &A, const Contr
     }
 }
 
-template <int Q>
+template <int Q, int RP>
 __global__ __launch_bounds__(kCThreads) void k_contract_rows(ContractArgs A) {
     __shared__ float bsum[kCWaves * 2 * Q * 64];
     __shared__ double lp[kCWaves][2];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const ContractCtx c = contract_ctx(A);
     double lrr = 0.0, lra = 0.0;
-    contract_rows<Q>(A, c, bsum, tid, wave, lane, lrr, lra);
+    contract_rows<Q, RP>(A, c, bsum, tid, wave, lane, lrr, lra);
     contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
 }
 
@@ -1138,8 +1137,18 @@ static int cu_count(int dev) {
 // contiguous tile range of each of the one-per-CU blocks of k_fwd and k_bwd
 // (equal tile counts), the contraction chunks of every instance, and which loss
 // and gradient partial rows each block writes.
+// tile shapes a plan is built with (vpinn_tuning): forward wavefronts per block,
+// elements per small-element contraction block (shift), rows per pass of the
+// row-streaming contraction
+static const vpinn_tuning kDefaultTuning = {12, 0, 4};
+static bool tuning_valid(const vpinn_tuning &t) {
+    return (t.fwd_waves == 8 || t.fwd_waves == 12 || t.fwd_waves == 16) && t.chunk_shift >= 0 && t.chunk_shift <= 2 &&
+           (t.rows_per_pass == 2 || t.rows_per_pass == 4 || t.rows_per_pass == 8);
+}
+
 struct FusedPlan {
     DevBuf inst, blk_tiles, blk_inst0, cblk_inst, ubuf, gpart, lpart;
+    vpinn_tuning tune = kDefaultTuning;
     std::vector<InstDesc> host_inst;
     int tblocks = 0, n_inst = 0, grows = 0, lrows = 0, L = 0, H = 0;
     int64_t cblocks = 0, tiles = 0, npf = 0;
@@ -1148,7 +1157,8 @@ struct FusedPlan {
 };
 
 static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_loss_cfg *cfg, int dev,
-                               FusedPlan &P) {
+                               const vpinn_tuning &tune, FusedPlan &P) {
+    P.tune = tune;
     const int L = cfg->n_hidden, H = cfg->width;
     const int cus = cu_count(dev);
     std::vector<InstDesc> D(n);
@@ -1180,7 +1190,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
                  : (p->nq <= 128)                         ? kPathRows2
                  : (p->nq <= 64 * kRowQ)                  ? kPathRows4
                                                           : kPathGeneric;
-        d.epc = d.path == kPathFast ? std::max(1, kCThreads / p->nq) : 1;
+        d.epc = d.path == kPathFast ? std::max(1, (kCThreads / p->nq) >> tune.chunk_shift) : 1;
         d.n_chunks = (p->n_elem + d.epc - 1) / d.epc;
         if (d.path == kPathFast)
             cdyn_fast = std::max(cdyn_fast, sizeof(float) * ((size_t)d.ntest * kCbs + (size_t)d.epc * d.ntest));
@@ -1268,23 +1278,37 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     return VPINN_OK;
 }
 
+template <int Q>
+static void launch_rows(int rp, unsigned blocks, const ContractArgs &c, hipStream_t s) {
+    switch (rp) {
+    case 2: k_contract_rows<Q, 2><<<blocks, kCThreads, 0, s>>>(c); break;
+    case 8: k_contract_rows<Q, 8><<<blocks, kCThreads, 0, s>>>(c); break;
+    default: k_contract_rows<Q, 4><<<blocks, kCThreads, 0, s>>>(c); break;
+    }
+}
+
 template <int L>
 static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs &ca, const BwdArgs &ba,
                        bool want_grad, dim3 fg, int ft, float *loss, float *grad, float *grad_eps, const AdamArgs &ad,
                        hipEvent_t const *ev, hipStream_t s) {
     if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
-    k_fwd<L><<<P.tblocks, kFwThreads, 0, s>>>(fa);
+    switch (P.tune.fwd_waves) {
+    case 8: k_fwd<L, 8><<<P.tblocks, 8 * 64, 0, s>>>(fa); break;
+    case 16: k_fwd<L, 16><<<P.tblocks, 16 * 64, 0, s>>>(fa); break;
+    default: k_fwd<L, 12><<<P.tblocks, 12 * 64, 0, s>>>(fa); break;
+    }
     if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
     {
         ContractArgs c = ca;
         c.cblk_base = 0;
         if (P.cpath_blocks[kPathFast]) k_contract_fast<<<(unsigned)P.cpath_blocks[kPathFast], kCThreads, P.cdyn_fast, s>>>(c);
         c.cblk_base += P.cpath_blocks[kPathFast];
-        if (P.cpath_blocks[kPathRows1]) k_contract_rows<1><<<(unsigned)P.cpath_blocks[kPathRows1], kCThreads, 0, s>>>(c);
+        const int rp = P.tune.rows_per_pass;
+        if (P.cpath_blocks[kPathRows1]) launch_rows<1>(rp, (unsigned)P.cpath_blocks[kPathRows1], c, s);
         c.cblk_base += P.cpath_blocks[kPathRows1];
-        if (P.cpath_blocks[kPathRows2]) k_contract_rows<2><<<(unsigned)P.cpath_blocks[kPathRows2], kCThreads, 0, s>>>(c);
+        if (P.cpath_blocks[kPathRows2]) launch_rows<2>(rp, (unsigned)P.cpath_blocks[kPathRows2], c, s);
         c.cblk_base += P.cpath_blocks[kPathRows2];
-        if (P.cpath_blocks[kPathRows4]) k_contract_rows<4><<<(unsigned)P.cpath_blocks[kPathRows4], kCThreads, 0, s>>>(c);
+        if (P.cpath_blocks[kPathRows4]) launch_rows<4>(rp, (unsigned)P.cpath_blocks[kPathRows4], c, s);
         c.cblk_base += P.cpath_blocks[kPathRows4];
         if (P.cpath_blocks[kPathGeneric])
             k_contract_generic<<<(unsigned)P.cpath_blocks[kPathGeneric], kCThreads, P.cdyn_generic, s>>>(c);
@@ -1364,7 +1388,7 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
         c->H != cfg->width || c->norm != cfg->loss_norm || c->tau != cfg->tau || c->gamma != cfg->gamma) {
         c->valid = false;
         vpinn_problem *one[1] = {p};
-        vpinn_status st = build_plan(one, 1, cfg, p->device, c->plan);
+        vpinn_status st = build_plan(one, 1, cfg, p->device, kDefaultTuning, c->plan);
         if (st) return st;
         c->valid = true;
         c->n_bnd = p->n_bnd;
@@ -1389,6 +1413,7 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
 struct vpinn_batch {
     int device = 0;
     vpinn_loss_cfg cfg{};
+    std::vector<vpinn_problem *> probs;  // borrowed; kept to rebuild the plan with another tuning
     vp::FusedPlan plan;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1406,7 +1431,8 @@ vpinn_status batch_create(int32_t n, vpinn_problem *const *problems, const vpinn
     if (!b) return fail(VPINN_E_NOMEM, "host allocation failed");
     b->device = problems[0]->device;
     b->cfg = *cfg;
-    vpinn_status st = build_plan(problems, n, cfg, b->device, b->plan);
+    b->probs.assign(problems, problems + n);
+    vpinn_status st = build_plan(problems, n, cfg, b->device, kDefaultTuning, b->plan);
     if (st) {
         delete b;
         return st;
@@ -1466,6 +1492,85 @@ void batch_set_profile_events(vpinn_batch *b, void *const *events) {
 }
 
 void batch_destroy(vpinn_batch *b) { delete b; }
+
+static void drop_graph(vpinn_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+vpinn_status batch_get_tuning(const vpinn_batch *b, vpinn_tuning *out) {
+    *out = b->plan.tune;
+    return VPINN_OK;
+}
+
+vpinn_status batch_set_tuning(vpinn_batch *b, const vpinn_tuning *t) {
+    if (!tuning_valid(*t)) return fail(VPINN_E_INVALID, "tuning value outside the supported lists");
+    FusedPlan np;
+    vpinn_status st = build_plan(b->probs.data(), (int)b->probs.size(), &b->cfg, b->device, *t, np);
+    if (st) return st;
+    drop_graph(b);
+    b->plan = std::move(np);
+    return VPINN_OK;
+}
+
+// Time every tuning that can matter for this batch on its own data and keep the
+// fastest (median of `reps` loss-and-gradient evaluations after one warm-up).
+vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps, vpinn_tuning *best_out,
+                            hipStream_t s) {
+    const FusedPlan &P0 = b->plan;
+    const bool has_fast = P0.cpath_blocks[kPathFast] > 0;
+    const bool has_rows = P0.cpath_blocks[kPathRows1] + P0.cpath_blocks[kPathRows2] + P0.cpath_blocks[kPathRows4] > 0;
+    std::vector<vpinn_tuning> cand;
+    for (int fw : {8, 12, 16})
+        for (int cs = 0; cs <= (has_fast ? 2 : 0); ++cs)
+            for (int rp : {2, 4, 8})
+                if (has_rows || rp == 4) cand.push_back(vpinn_tuning{fw, cs, rp});
+    const int n = (int)b->probs.size();
+    DevBuf losses, grads;
+    VP_HIP(losses.reserve(sizeof(float) * 4 * (size_t)n));
+    VP_HIP(grads.reserve(sizeof(float) * (size_t)P0.npf * (size_t)n));
+    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    for (auto &e : ev) VP_HIP(hipEventCreate(&e));
+    auto free_events = [&]() {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    vpinn_tuning best = P0.tune;
+    float best_ms = -1.f;
+    AdamArgs none{};
+    for (const vpinn_tuning &c : cand) {
+        FusedPlan P;
+        vpinn_status st = build_plan(b->probs.data(), n, &b->cfg, b->device, c, P);
+        if (!st) st = run_plan(P, d_params, nullptr, true, losses.as<float>(), grads.as<float>(), nullptr, none,
+                               nullptr, nullptr, s);
+        for (int r = 0; r < reps && !st; ++r) {
+            if (hipEventRecord(ev[2 * r], s) != hipSuccess) st = fail(VPINN_E_DEVICE, "hipEventRecord failed");
+            if (!st) st = run_plan(P, d_params, nullptr, true, losses.as<float>(), grads.as<float>(), nullptr, none,
+                                   nullptr, nullptr, s);
+            if (!st && hipEventRecord(ev[2 * r + 1], s) != hipSuccess) st = fail(VPINN_E_DEVICE, "hipEventRecord failed");
+        }
+        if (!st && hipStreamSynchronize(s) != hipSuccess) st = fail(VPINN_E_DEVICE, "hipStreamSynchronize failed");
+        if (st) {
+            free_events();
+            return st;
+        }
+        std::vector<float> t(reps);
+        for (int r = 0; r < reps; ++r) (void)hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]);
+        std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+        const float med = t[reps / 2];
+        if (best_ms < 0.f || med < best_ms) {
+            best_ms = med;
+            best = c;
+        }
+    }
+    free_events();
+    vpinn_status st = batch_set_tuning(b, &best);
+    if (st) return st;
+    if (best_out) *best_out = best;
+    return VPINN_OK;
+}
 
 vpinn_status batch_replay(vpinn_batch *b, hipStream_t s) {
     if (!b->exec) return fail(VPINN_E_INVALID, "no captured step: call vpinn_batch_capture first");

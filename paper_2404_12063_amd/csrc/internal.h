@@ -46,6 +46,23 @@ vpinn_status fail(vpinn_status code, const std::string &msg);
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : ptr(o.ptr), bytes(o.bytes) {
+        o.ptr = nullptr;
+        o.bytes = 0;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            ptr = o.ptr;
+            bytes = o.bytes;
+            o.ptr = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
     ~DevBuf() { release(); }
     void release() {
         if (ptr) (void)hipFree(ptr);
@@ -118,6 +135,9 @@ vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d
                            float b1, float b2, float eps, float *d_losses, hipStream_t s);
 vpinn_status batch_replay(vpinn_batch *b, hipStream_t s);
 void batch_set_profile_events(vpinn_batch *b, void *const *events);
+vpinn_status batch_get_tuning(const vpinn_batch *b, vpinn_tuning *out);
+vpinn_status batch_set_tuning(vpinn_batch *b, const vpinn_tuning *t);
+vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps, vpinn_tuning *best, hipStream_t s);
 int batch_device(const vpinn_batch *b);
 void batch_destroy(vpinn_batch *b);
 

@@ -58,6 +58,13 @@ class vpinn_loss_cfg(C.Structure):
                 ("loss_norm", C.c_int32), ("path", C.c_int32)]
 
 
+class vpinn_tuning(C.Structure):
+    _fields_ = [("fwd_waves", C.c_int32), ("chunk_shift", C.c_int32), ("rows_per_pass", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.fwd_waves, self.chunk_shift, self.rows_per_pass)
+
+
 class VpinnError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"vpinn error {code}: {msg}")
@@ -93,6 +100,9 @@ _SIGNATURES = {
                                         C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
     "vpinn_batch_replay": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "vpinn_batch_free": (None, [C.c_void_p]),
+    "vpinn_batch_get_tuning": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_tuning)]),
+    "vpinn_batch_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_tuning)]),
+    "vpinn_batch_autotune": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(vpinn_tuning), C.c_void_p]),
     "vpinn_set_profile_events": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "vpinn_batch_set_profile_events": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "vpinn_problem_free": (None, [C.c_void_p]),
@@ -277,6 +287,25 @@ def vpinn_batch_capture(b: Batch, params, m, v, step, lr: float = 1e-3, beta1: f
 
 def vpinn_batch_replay(b: Batch, stream=None):
     _check(lib().vpinn_batch_replay(b.handle, _stream(stream)))
+
+
+def vpinn_batch_get_tuning(b: Batch):
+    """(fwd_waves, chunk_shift, rows_per_pass) of the batch's plan."""
+    t = vpinn_tuning()
+    _check(lib().vpinn_batch_get_tuning(b.handle, C.byref(t)))
+    return t.as_tuple()
+
+
+def vpinn_batch_set_tuning(b: Batch, fwd_waves: int, chunk_shift: int, rows_per_pass: int):
+    t = vpinn_tuning(fwd_waves, chunk_shift, rows_per_pass)
+    _check(lib().vpinn_batch_set_tuning(b.handle, C.byref(t)))
+
+
+def vpinn_batch_autotune(b: Batch, params, reps: int = 5, stream=None):
+    """Time the batch's candidate tile shapes at `params` and keep the fastest; returns it."""
+    t = vpinn_tuning()
+    _check(lib().vpinn_batch_autotune(b.handle, _ptr(params), reps, C.byref(t), _stream(stream)))
+    return t.as_tuple()
 
 
 def _event_array(events):

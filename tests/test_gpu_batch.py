@@ -191,3 +191,96 @@ def test_c5_batched_workload_sampled(V, torch):
         ref = O.problem_loss_grad(probs[i], O.assemble_problem(probs[i]), th[i])
         assert abs(L[i, 0] - ref.loss[0]) / ref.loss[0] < 1e-5
         assert np.linalg.norm(Gd[i] - ref.grad) / np.linalg.norm(ref.grad) < 1e-4
+
+
+def _all_shapes():
+    """Mixed instances plus one that streams contraction rows (N_t = 7) and one with large elements (n = 17)."""
+    out = _mixed_instances()
+    for i, (m, n, nt) in enumerate([(3, 6, 7), (2, 17, 3)]):
+        p = gen.poisson_sinsin_square(f"shape{i}", m, n, nt, 2, 40, 0.2, seed=200 + i)
+        p.gamma = 5.0
+        out.append(p)
+    return out
+
+
+def _batch_eval(V, torch, b, T, n_inst, n):
+    dev = torch.device("cuda:0")
+    losses = torch.zeros((n_inst, 4), device=dev)
+    grads = torch.zeros((n_inst, n), device=dev)
+    V.vpinn_batch_loss_and_grad(b, T, losses=losses, grads=grads)
+    torch.cuda.synchronize()
+    return losses.cpu().double().numpy(), grads.cpu().double().numpy()
+
+
+def test_tunings_agree_with_oracle(V, torch):
+    """Every tile shape computes the same loss and gradient (to FP32 rounding) as the FP64 oracle."""
+    from oracle import oracle as O
+    probs = _all_shapes()
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
+    assert V.vpinn_batch_get_tuning(b) == (12, 0, 4)
+    n = V.vpinn_n_params(30, 3)
+    th = _params(probs)
+    T = torch.tensor(th, dtype=torch.float32, device="cuda:0")
+    refs = [O.problem_loss_grad(p, O.assemble_problem(p), th[i]) for i, p in enumerate(probs)]
+    for tune in [(8, 2, 2), (16, 1, 8), (12, 0, 4)]:
+        V.vpinn_batch_set_tuning(b, *tune)
+        assert V.vpinn_batch_get_tuning(b) == tune
+        L, G = _batch_eval(V, torch, b, T, len(probs), n)
+        for i, ref in enumerate(refs):
+            assert abs(L[i, 0] - ref.loss[0]) / ref.loss[0] < 1e-5, (tune, i)
+            assert np.linalg.norm(G[i] - ref.grad) / np.linalg.norm(ref.grad) < 1e-4, (tune, i)
+        # a fixed tuning is bitwise reproducible
+        L2, G2 = _batch_eval(V, torch, b, T, len(probs), n)
+        assert np.array_equal(L, L2) and np.array_equal(G, G2)
+
+
+def test_autotune_picks_a_valid_tuning_and_keeps_parity(V, torch):
+    probs = _all_shapes()
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
+    n = V.vpinn_n_params(30, 3)
+    T = torch.tensor(_params(probs), dtype=torch.float32, device="cuda:0")
+    L0, G0 = _batch_eval(V, torch, b, T, len(probs), n)
+    best = V.vpinn_batch_autotune(b, T, reps=2)
+    assert best == V.vpinn_batch_get_tuning(b)
+    assert best[0] in (8, 12, 16) and 0 <= best[1] <= 2 and best[2] in (2, 4, 8)
+    L1, G1 = _batch_eval(V, torch, b, T, len(probs), n)
+    np.testing.assert_allclose(L1, L0, rtol=1e-5)
+    for i in range(len(probs)):
+        assert np.linalg.norm(G1[i] - G0[i]) / np.linalg.norm(G0[i]) < 1e-5
+    # the parameters are not modified by tuning
+    np.testing.assert_array_equal(T.cpu().numpy(), _params(probs).astype(np.float32))
+    with pytest.raises(V.VpinnError):
+        V.vpinn_batch_set_tuning(b, 10, 0, 4)
+    with pytest.raises(V.VpinnError):
+        V.vpinn_batch_autotune(b, T, reps=0)
+
+
+def test_capture_after_tuning_replays(V, torch):
+    """A new tuning drops the captured graph; capturing again gives a graph that matches eager steps."""
+    probs = _all_shapes()[:3]
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
+    dev = torch.device("cuda:0")
+    th = _params(probs)
+    T = torch.tensor(th, dtype=torch.float32, device=dev)
+    M, Vv = torch.zeros_like(T), torch.zeros_like(T)
+    step = torch.zeros(1, dtype=torch.int64, device=dev)
+    s = torch.cuda.Stream()
+    V.vpinn_batch_capture(b, T, M, Vv, step, stream=s)
+    V.vpinn_batch_set_tuning(b, 8, 1, 2)
+    with pytest.raises(V.VpinnError):
+        V.vpinn_batch_replay(b, stream=s)
+    V.vpinn_batch_capture(b, T, M, Vv, step, stream=s)
+    for _ in range(3):
+        V.vpinn_batch_replay(b, stream=s)
+    s.synchronize()
+    T2 = torch.tensor(th, dtype=torch.float32, device=dev)
+    M2, V2 = torch.zeros_like(T2), torch.zeros_like(T2)
+    step2 = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(3):
+        V.vpinn_batch_step(b, T2, M2, V2, step2, stream=s)
+    s.synchronize()
+    assert int(step.item()) == 3 and int(step2.item()) == 3
+    assert torch.equal(T, T2) and torch.equal(M, M2) and torch.equal(Vv, V2)
