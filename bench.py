@@ -120,7 +120,8 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str):
     f_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(fetch)
     w_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(write)
     out = {}
-    for name, key in [("k_bwd", "k_bwd<3>"), ("k_fwd", "k_fwd<3>"), ("k_contract", "k_contract(")]:
+    # kernel families (template arguments vary with the tuning); a --profile-run bench runs one plan only
+    for name, key in [("k_bwd", "k_bwd<"), ("k_fwd", "k_fwd<"), ("k_contract", "k_contract_")]:
         fk = sorted(v for k, vs in fetch.items() if key in k for v in vs)
         wk = sorted(v for k, vs in write.items() if key in k for v in vs)
         if not fk or not wk:
@@ -418,6 +419,9 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then "
                          "WRITE_SIZE, taken with --copy-probe on --workload W) into profiles/traffic.json[W]")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="counter runs: time only the tuned batch-of-one plan (no single-problem-API steps, no "
+                         "loss check), so every fused kernel in the trace belongs to that plan; implies no CPU baseline")
     ap.add_argument("--tuning", type=lambda t: tuple(int(x) for x in t.split(",")), default=None,
                     metavar="FWD_WAVES,CHUNK_SHIFT,ROWS_PER_PASS",
                     help="use this tile-shape tuning instead of autotuning (profiling runs)")
@@ -425,6 +429,8 @@ def main():
     if args.traffic_from:
         write_traffic(args.workload, *args.traffic_from)
         return
+    if args.profile_run:
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
@@ -470,8 +476,12 @@ def bench_single(args, V, torch, gen):
     main_path = V.VPINN_PATH_FUSED if args.path == "fused" else V.VPINN_PATH_PLAIN
     fused = main_path == V.VPINN_PATH_FUSED
     eager_steps = min(args.steps, 300)
-    eager = time_path(V, torch, p, prob, theta, main_path, eager_steps, args.warmup)
-    print(f"[bench] {args.path} eager: {eager['wall_s'] / eager_steps * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
+    if args.profile_run and fused:
+        eager = None
+    else:
+        eager = time_path(V, torch, p, prob, theta, main_path, eager_steps, args.warmup)
+        print(f"[bench] {args.path} eager: {eager['wall_s'] / eager_steps * 1e3:.4f} ms/step", file=sys.stderr,
+              flush=True)
     if fused:
         res = time_graph(V, torch, p, prob, theta, args.steps, args.warmup, args.tuning)
         assert res["steps_done"] == args.warmup + args.steps
@@ -487,9 +497,10 @@ def bench_single(args, V, torch, gen):
     # loss parity at the initial parameters (one extra evaluation outside the timed region)
     dev = torch.device("cuda:0")
     loss0 = torch.zeros(4, dtype=torch.float32, device=dev)
-    V.vpinn_loss_and_grad(p, V.loss_cfg(prob.width, prob.n_hidden, prob.tau, 0.0, 0, main_path),
-                          torch.tensor(theta, dtype=torch.float32, device=dev), loss=loss0)
-    torch.cuda.synchronize()
+    if not args.profile_run:
+        V.vpinn_loss_and_grad(p, V.loss_cfg(prob.width, prob.n_hidden, prob.tau, 0.0, 0, main_path),
+                              torch.tensor(theta, dtype=torch.float32, device=dev), loss=loss0)
+        torch.cuda.synchronize()
     gpu_loss0 = float(loss0[0].item())
 
     ms = res["wall_s"] / args.steps * 1e3
@@ -560,7 +571,8 @@ def bench_single(args, V, torch, gen):
         out["kernels"] = kernels
         out["kernels_note"] = ("mean durations over eager batched steps of the same tuned plan as the timed graph, "
                                "from the library's profiling events")
-        out["single_problem_api_eager_ms_per_step"] = round(eager["wall_s"] / eager_steps * 1e3, 5)
+        if eager is not None:
+            out["single_problem_api_eager_ms_per_step"] = round(eager["wall_s"] / eager_steps * 1e3, 5)
     if plain is not None:
         pms = plain["wall_s"] / min(args.steps, 300) * 1e3
         out["plain_hip"] = {"ms_per_step": round(pms, 5), "epochs_per_s": round(1e3 / pms, 3),
