@@ -60,7 +60,7 @@ def lib():
         L.orc_jacobian.argtypes = [_dp, C.c_double, C.c_double, _dp, _dp, C.POINTER(C.c_double)]
         L.orc_assemble.restype = C.c_int
         L.orc_assemble.argtypes = [C.c_int64, _dp, C.c_int64, _ip, C.c_int, C.c_int, C.c_int, _dp,
-                                   FN2, C.c_void_p, _dp, _dp, _dp, _dp, C.POINTER(C.c_int64)]
+                                   FN2, C.c_void_p, _dp, _dp, _dp, _dp, C.c_void_p, C.POINTER(C.c_int64)]
         L.orc_n_params.restype = C.c_int64
         L.orc_n_params.argtypes = [C.c_int, C.c_int]
         L.orc_mlp_eval.restype = None
@@ -68,10 +68,11 @@ def lib():
         L.orc_mlp_vjp.restype = None
         L.orc_mlp_vjp.argtypes = [C.c_int, C.c_int, _dp, C.c_int64, _dp, _dp, _dp, _dp, _dp]
         L.orc_residual.restype = None
-        L.orc_residual.argtypes = [C.c_int64, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp]
+        L.orc_residual.argtypes = [C.c_int64, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_void_p,
+                                   C.c_double, C.c_double, _dp]
         L.orc_loss_grad.restype = C.c_int
-        L.orc_loss_grad.argtypes = [C.c_int64, C.c_int, C.c_int, _dp, _dp, _dp, _dp,
-                                    C.c_int64, _dp, _dp, C.c_int64, _dp, _dp,
+        L.orc_loss_grad.argtypes = [C.c_int64, C.c_int, C.c_int, _dp, _dp, _dp, _dp, C.c_void_p, C.c_double,
+                                    C.c_double, C.c_int64, _dp, _dp, C.c_int64, _dp, _dp,
                                     C.c_int, C.c_int, _dp, C.c_double, C.c_double, C.c_double,
                                     C.c_double, _dp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_adam.restype = None
@@ -135,6 +136,7 @@ class Assembled:
     X: np.ndarray    # [n_elem, n_quad, 2]
     n: int
     nt: int
+    M: Optional[np.ndarray] = None  # [n_elem, n_test, n_quad] w_q det J v_k (convection term), if asked for
 
     @property
     def n_elem(self):
@@ -149,8 +151,9 @@ class OracleError(RuntimeError):
 
 
 def assemble(xy, quad, n: int, nt: int, f_amp: float = 0.0, f_kx: float = 0.0, f_ky: float = 0.0,
-             f_callable=None) -> Assembled:
-    """G_x, G_y, F and physical quadrature points; f either amp*sin(kx x)sin(ky y) or a callable."""
+             f_callable=None, want_M: bool = False) -> Assembled:
+    """G_x, G_y, F and physical quadrature points; f either amp*sin(kx x)sin(ky y) or a callable.
+    want_M: also the convection-term weights M = w_q det J v_k (convection-diffusion, Section 2.1)."""
     xy = _f64(xy)
     quad = np.ascontiguousarray(np.asarray(quad, dtype=np.int32))
     ne = quad.shape[0]
@@ -159,21 +162,24 @@ def assemble(xy, quad, n: int, nt: int, f_amp: float = 0.0, f_kx: float = 0.0, f
     Gy = np.zeros((ne, ntest, nq))
     F = np.zeros((ne, ntest))
     X = np.zeros((ne, nq, 2))
+    M = np.zeros((ne, ntest, nq)) if want_M else None
     bad = C.c_int64(-1)
     if f_callable is None:
         kind, par, cb = 1, np.array([f_amp, f_kx, f_ky], dtype=np.float64), FN2(lambda x, y, u: 0.0)
     else:
         kind, par, cb = 0, np.zeros(3), FN2(lambda x, y, u: float(f_callable(x, y)))
     rc = lib().orc_assemble(xy.shape[0], xy.ravel(), ne, quad.ravel(), n, nt, kind, par, cb, None,
-                            Gx, Gy, F, X, C.byref(bad))
+                            Gx, Gy, F, X, M.ctypes.data_as(C.c_void_p) if want_M else None, C.byref(bad))
     if rc != 0:
         raise OracleError(rc, bad.value)
-    return Assembled(Gx, Gy, F, X, n, nt)
+    return Assembled(Gx, Gy, F, X, n, nt, M)
 
 
 def assemble_problem(prob) -> Assembled:
+    conv = tuple(getattr(prob, "conv", (0.0, 0.0)))
     return assemble(prob.mesh.xy, prob.mesh.quad, prob.quad_order, prob.test_order,
-                    prob.f_amp, prob.f_kx, prob.f_ky)
+                    prob.f_amp, prob.f_kx, prob.f_ky, f_callable=getattr(prob, "f_fn", None),
+                    want_M=conv != (0.0, 0.0))
 
 
 # --------------------------------------------------------------------------- network
@@ -197,10 +203,20 @@ def mlp_vjp(theta, H: int, L: int, xy, ub, uxb, uyb):
     return g
 
 
-def residual(asm: Assembled, ux, uy, eps: float = 1.0):
+def _conv_args(asm: Assembled, conv):
+    if conv is None or tuple(conv) == (0.0, 0.0):
+        return None, 0.0, 0.0
+    if asm.M is None:
+        raise ValueError("a convection term needs an assembly with want_M=True")
+    return asm.M.ctypes.data_as(C.c_void_p), float(conv[0]), float(conv[1])
+
+
+def residual(asm: Assembled, ux, uy, eps: float = 1.0, conv=None):
+    """R = eps * A + sum_q (b . grad u) M - F; conv = (b_x, b_y) or None."""
     R = np.zeros_like(asm.F)
+    Mp, bx, by = _conv_args(asm, conv)
     lib().orc_residual(asm.n_elem, asm.n * asm.n, asm.nt * asm.nt, asm.Gx.ravel(), asm.Gy.ravel(),
-                       asm.F.ravel(), _f64(ux).ravel(), _f64(uy).ravel(), eps, R)
+                       asm.F.ravel(), _f64(ux).ravel(), _f64(uy).ravel(), eps, Mp, bx, by, R)
     return R
 
 
@@ -221,7 +237,7 @@ def c_v(asm: Assembled, loss_norm: int = 0) -> float:
 
 def loss_grad(asm: Assembled, theta, H: int, L: int, bnd_xy=None, bnd_g=None, sens_xy=None, sens_u=None,
               eps: float = 1.0, tau: float = 10.0, gamma: float = 0.0, loss_norm: int = 0,
-              want_grad: bool = True, want_R: bool = False) -> LossGrad:
+              want_grad: bool = True, want_R: bool = False, conv=None) -> LossGrad:
     bxy = _f64(np.zeros((0, 2)) if bnd_xy is None else bnd_xy).reshape(-1, 2)
     bg = _f64(np.zeros(0) if bnd_g is None else bnd_g)
     sxy = _f64(np.zeros((0, 2)) if sens_xy is None else sens_xy).reshape(-1, 2)
@@ -230,9 +246,10 @@ def loss_grad(asm: Assembled, theta, H: int, L: int, bnd_xy=None, bnd_g=None, se
     grad = np.zeros(n_params(H, L)) if want_grad else None
     geps = C.c_double(0.0)
     R = np.zeros_like(asm.F) if want_R else None
+    Mp, cbx, cby = _conv_args(asm, conv)
     rc = lib().orc_loss_grad(
         asm.n_elem, asm.n * asm.n, asm.nt * asm.nt, asm.Gx.ravel(), asm.Gy.ravel(), asm.F.ravel(),
-        asm.X.ravel(), bxy.shape[0], bxy.ravel(), bg, sxy.shape[0], sxy.ravel(), su,
+        asm.X.ravel(), Mp, cbx, cby, bxy.shape[0], bxy.ravel(), bg, sxy.shape[0], sxy.ravel(), su,
         H, L, _f64(theta), eps, tau, gamma, c_v(asm, loss_norm), loss,
         grad.ctypes.data_as(C.c_void_p) if want_grad else None,
         C.cast(C.pointer(geps), C.c_void_p) if want_grad else None,
@@ -244,10 +261,12 @@ def loss_grad(asm: Assembled, theta, H: int, L: int, bnd_xy=None, bnd_g=None, se
 
 def problem_loss_grad(prob, asm: Assembled, theta, eps: Optional[float] = None, loss_norm: int = 0,
                       want_grad: bool = True) -> LossGrad:
-    e = 1.0 if eps is None else eps
+    """eps: the trainable diffusion coefficient of the inverse problem; otherwise the problem's own
+    diffusion coefficient (1 for Poisson); the problem's convection velocity enters through conv."""
+    e = getattr(prob, "diff", 1.0) if eps is None else eps
     return loss_grad(asm, theta, prob.width, prob.n_hidden, prob.bnd_xy, prob.bnd_g,
                      prob.sens_xy, prob.sens_u, eps=e, tau=prob.tau, gamma=prob.gamma,
-                     loss_norm=loss_norm, want_grad=want_grad)
+                     loss_norm=loss_norm, want_grad=want_grad, conv=getattr(prob, "conv", None))
 
 
 def adam(theta, g, m, v, t: int, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):

@@ -171,9 +171,12 @@ static double forcing(int kind, const double *par, orc_fn2 fn, void *user, doubl
     return fn(x, y, user);
 }
 
+/* G_x, G_y: w_q det J (grad v_k)(x_q); F: sum_q w_q det J f v_k; X: the points;
+ * M (optional): w_q det J v_k(x_q), the weights of the convection term
+ * int_K (b . grad u) v_k dx of the convection-diffusion weak form (Sec. 2.1). */
 int orc_assemble(int64_t n_nodes, const double *xy, int64_t n_elem, const int32_t *quad,
                  int n, int nt, int f_kind, const double *f_par, orc_fn2 f_fn, void *f_user,
-                 double *Gx, double *Gy, double *F, double *X, int64_t *bad_elem)
+                 double *Gx, double *Gy, double *F, double *X, double *M, int64_t *bad_elem)
 {
     if (n < 2 || nt < 1 || n_elem < 0 || !xy || !quad) return ORC_E_ARG;
     if (f_kind == 0 && !f_fn) return ORC_E_ARG;
@@ -217,6 +220,7 @@ int orc_assemble(int64_t n_nodes, const double *xy, int64_t n_elem, const int32_
                         const int64_t o = (e * ntest + k) * nq + q;
                         Gx[o] = wq * D * vx;
                         Gy[o] = wq * D * vy;
+                        if (M) M[o] = wq * D * val;
                         F[e * ntest + k] += wq * D * f * val;
                     }
                 }
@@ -405,19 +409,24 @@ void orc_mlp_vjp(int H, int L, const double *theta, int64_t npts, const double *
 
 /* ------------------------------------------------------------------------- */
 /* residual from given solution gradients at the quadrature points            */
-/* R[e,k] = eps * sum_q (u_x G_x + u_y G_y)[e,k,q] - F[e,k]  (Algorithm 3)     */
+/* R[e,k] = eps * sum_q (u_x G_x + u_y G_y)[e,k,q]                            */
+/*        + sum_q (b_x u_x + b_y u_y) M[e,k,q] - F[e,k]                       */
+/* (Algorithm 3; the convection term of the convection-diffusion weak form,   */
+/* Sec. 2.1, when M is given)                                                 */
 /* ------------------------------------------------------------------------- */
 void orc_residual(int64_t n_elem, int nq, int ntest, const double *Gx, const double *Gy,
-                  const double *F, const double *ux, const double *uy, double eps, double *R)
+                  const double *F, const double *ux, const double *uy, double eps,
+                  const double *M, double cbx, double cby, double *R)
 {
     for (int64_t e = 0; e < n_elem; ++e) {
         for (int k = 0; k < ntest; ++k) {
-            double acc = 0.0;
+            double acc = 0.0, conv = 0.0;
             for (int q = 0; q < nq; ++q) {
                 const int64_t o = (e * ntest + k) * nq + q;
                 acc += ux[e * nq + q] * Gx[o] + uy[e * nq + q] * Gy[o];
+                if (M) conv += (cbx * ux[e * nq + q] + cby * uy[e * nq + q]) * M[o];
             }
-            R[e * ntest + k] = eps * acc - F[e * ntest + k];
+            R[e * ntest + k] = eps * acc + conv - F[e * ntest + k];
         }
     }
 }
@@ -428,7 +437,7 @@ void orc_residual(int64_t n_elem, int nq, int ntest, const double *Gx, const dou
 /* loss[0..3] = L, L_v, L_b, L_s (L_b, L_s unweighted means)                  */
 /* ------------------------------------------------------------------------- */
 int orc_loss_grad(int64_t n_elem, int nq, int ntest, const double *Gx, const double *Gy,
-                  const double *F, const double *X,
+                  const double *F, const double *X, const double *M, double cbx, double cby,
                   int64_t n_bnd, const double *bxy, const double *bg,
                   int64_t n_sen, const double *sxy, const double *su,
                   int H, int L, const double *theta, double eps, double tau, double gamma,
@@ -449,19 +458,21 @@ int orc_loss_grad(int64_t n_elem, int nq, int ntest, const double *Gx, const dou
             mlp_forward(theta, X[(e * nq + q) * 2], X[(e * nq + q) * 2 + 1], &tp[q]);
         double le = 0.0;
         for (int k = 0; k < ntest; ++k) {
-            double acc = 0.0;
+            double acc = 0.0, conv = 0.0;
             for (int q = 0; q < nq; ++q) {
                 const int64_t o = (e * ntest + k) * nq + q;
                 acc += tp[q].ux * Gx[o] + tp[q].uy * Gy[o];
+                if (M) conv += (cbx * tp[q].ux + cby * tp[q].uy) * M[o];
             }
             A[k] = acc;
-            R[k] = eps * acc - F[e * ntest + k];
+            R[k] = eps * acc + conv - F[e * ntest + k];
             if (R_out) R_out[e * ntest + k] = R[k];
             le += R[k] * R[k];
         }
         Lv += cv * le;
         if (!grad && !grad_eps) continue;
-        /* dL/dR = 2 c_v R ; dL/deps = sum_k dL/dR A ; dL/du_x[q] = eps sum_k dL/dR G_x */
+        /* dL/dR = 2 c_v R ; dL/deps = sum_k dL/dR A ;                         */
+        /* dL/du_x[q] = sum_k dL/dR (eps G_x + b_x M)  (and y likewise)       */
         for (int k = 0; k < ntest; ++k) geps += 2.0 * cv * R[k] * A[k];
         if (grad) {
             for (int q = 0; q < nq; ++q) {
@@ -470,6 +481,10 @@ int orc_loss_grad(int64_t n_elem, int nq, int ntest, const double *Gx, const dou
                     const int64_t o = (e * ntest + k) * nq + q;
                     bx += 2.0 * cv * R[k] * eps * Gx[o];
                     by += 2.0 * cv * R[k] * eps * Gy[o];
+                    if (M) {
+                        bx += 2.0 * cv * R[k] * cbx * M[o];
+                        by += 2.0 * cv * R[k] * cby * M[o];
+                    }
                 }
                 mlp_backward(theta, &tp[q], 0.0, bx, by, grad, work);
             }

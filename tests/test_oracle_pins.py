@@ -459,3 +459,73 @@ def test_adam_constant_gradient_keeps_step(oracle):
         before = th.copy()
         oracle.adam(th, g, m, v, t, lr=1e-2, eps=0.0)
         np.testing.assert_allclose(th - before, -1e-2 * np.sign(g), rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------- convection-diffusion
+
+@pytest.mark.parametrize("n,exact", [(10, True), (12, True), (4, False)])
+def test_cd_manufactured_cubic_residual_vanishes(oracle, n, exact):
+    """-eps Lap u + b . grad u = f with u = x^3 + x y^2 + 2y (grad u = (3x^2 + y^2, 2xy + 2), Lap u = 8x):
+    the weak residual eps int grad u . grad v + int (b . grad u) v - int f v is exactly zero, and GLL
+    integrates every term exactly once 2n-3 covers the integrand's degree on a bilinear element."""
+    eps, bx, by = 0.7, 0.9, -0.4
+    f = lambda x, y: -eps * 8.0 * x + bx * (3 * x * x + y * y) + by * (2 * x * y + 2.0)  # noqa: E731
+    mesh = _skewed_mesh(3, seed=12)
+    asm = oracle.assemble(mesh.xy, mesh.quad, n, 4, f_callable=f, want_M=True)
+    X = asm.X
+    ux = 3 * X[..., 0] ** 2 + X[..., 1] ** 2
+    uy = 2 * X[..., 0] * X[..., 1] + 2.0
+    R = oracle.residual(asm, ux, uy, eps=eps, conv=(bx, by))
+    scale = np.abs(asm.F).max() + np.abs(asm.Gx).max() + np.abs(asm.M).max()
+    if exact:
+        assert np.abs(R).max() < 1e-12 * scale
+    else:
+        assert np.abs(R).max() > 1e-8 * scale
+    # the convection term is what closes the balance: without it the residual is far from zero
+    R0 = oracle.residual(asm, ux, uy, eps=eps)
+    assert np.abs(R0).max() > 1e-3 * scale
+
+
+def test_cd_linear_field_closed_form(oracle):
+    """u = a x + c y, f = 0 on axis-aligned rectangles: the diffusion part vanishes (patch test) and
+    int_K (b . grad u) v_(r,s) = (b . (a, c)) * det J * (int phi_r)(int phi_s), with int phi_1 = -2 and
+    int phi_r = 0 for r >= 2, so R[e, (1,1)] = (b . (a, c)) * area_e and every other R[e, k] = 0."""
+    a, c, bx, by, eps = 1.7, -0.6, 0.3, 2.1, 1.3
+    mesh = gen.square_mesh(3, 2, 0.0)
+    asm = oracle.assemble(mesh.xy, mesh.quad, 6, 3, 0.0, 0.0, 0.0, want_M=True)
+    X = asm.X
+    R = oracle.residual(asm, np.full(X.shape[:2], a), np.full(X.shape[:2], c), eps=eps, conv=(bx, by))
+    area = (1.0 / 3.0) * (1.0 / 2.0)
+    expect = np.zeros_like(R)
+    expect[:, 0] = (bx * a + by * c) * area
+    np.testing.assert_allclose(R, expect, atol=1e-13)
+    # M sums to the integral of the test function: area for (1,1), zero otherwise
+    np.testing.assert_allclose(asm.M.sum(axis=2)[:, 0], area, rtol=1e-13)
+
+
+def test_cd_gradient_matches_finite_differences(oracle):
+    """With a convection term, dL/dtheta still equals central differences of the oracle's loss."""
+    H, L = 4, 2
+    mesh = gen.square_mesh(2, 2, 0.2, seed=6)
+    asm = oracle.assemble(mesh.xy, mesh.quad, 4, 3, f_callable=gen.gear_forcing, want_M=True)
+    theta = gen.glorot_params(H, L, seed=10, bias_scale=0.4)
+    bxy = gen.square_boundary_points(8)
+    kw = dict(bnd_xy=bxy, bnd_g=np.zeros(8), tau=2.0, eps=0.8, conv=(1.1, -0.5))
+    r = oracle.loss_grad(asm, theta, H, L, **kw)
+
+    def f(th):
+        return oracle.loss_grad(asm, th, H, L, want_grad=False, **kw).loss[0]
+
+    h = 1e-6
+    fd = np.array([(f(theta + h * e) - f(theta - h * e)) / (2 * h) for e in np.eye(theta.size)])
+    assert np.linalg.norm(r.grad - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_cd_zero_velocity_is_poisson(oracle):
+    mesh = _skewed_mesh(2, seed=3)
+    asm = oracle.assemble(mesh.xy, mesh.quad, 5, 3, 4.0, 2.0, 1.0, want_M=True)
+    theta = gen.glorot_params(5, 2, seed=1, bias_scale=0.2)
+    a = oracle.loss_grad(asm, theta, 5, 2, eps=0.9, conv=(0.0, 0.0))
+    b = oracle.loss_grad(asm, theta, 5, 2, eps=0.9)
+    np.testing.assert_array_equal(a.loss, b.loss)
+    np.testing.assert_array_equal(a.grad, b.grad)

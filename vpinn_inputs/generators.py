@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import Callable, List, Optional, Tuple
 
 import numpy as np
 
@@ -259,6 +259,10 @@ class Problem:
     eps_init: Optional[float] = None   # trainable diffusion coefficient (inverse problem)
     eps_true: Optional[float] = None
     seed: int = 0
+    # convection-diffusion -diff Lap u + conv . grad u = f (forward problem: constants, not trained)
+    diff: float = 1.0
+    conv: Tuple[float, float] = (0.0, 0.0)
+    f_fn: Optional[Callable[[float, float], float]] = None  # forcing as a function of (x, y), else sin-sin
 
     @property
     def n_elem(self) -> int:
@@ -317,6 +321,21 @@ def config_c4(seed: int = 0) -> Problem:
                    tau=10.0, gamma=10.0, eps_init=2.0, eps_true=eps_true, seed=seed)
 
 
+def gear_forcing(x: float, y: float) -> float:
+    """Forcing of the convection-diffusion gear problem: 50 sin x + cos x."""
+    return 50.0 * math.sin(x) + math.cos(x)
+
+
+def config_gear_cd(seed: int = 0) -> Problem:
+    """Convection-diffusion -Lap u + (0.1, 0) . grad u = 50 sin x + cos x with u = 0 on the boundary (the
+    paper's gear experiment) on the toothed-annulus stand-in for its gear mesh (400x35 = 14,000 quads), 5x5 GLL,
+    4x4 test functions, 6,096 boundary points."""
+    mesh = annulus_gear_mesh(seed=seed)
+    bxy = annulus_boundary_points(6096)
+    return Problem(name="gear_cd", mesh=mesh, quad_order=5, test_order=4, f_amp=0.0, f_kx=0.0, f_ky=0.0,
+                   bnd_xy=bxy, bnd_g=np.zeros(len(bxy)), seed=seed, diff=1.0, conv=(0.1, 0.0), f_fn=gear_forcing)
+
+
 def config_probe(seed: int = 0) -> Problem:
     """The C4 mesh with 20x20 test functions (the paper's largest p-refinement): G-stream dominated."""
     p = poisson_sinsin_square("probe", 64, 10, 20, 2, 1600, 0.2, seed)
@@ -348,4 +367,5 @@ def batched_instances(n_inst: int = 64, seed: int = 0, lo: int = 256, hi: int = 
     return out
 
 
-CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4, "probe": config_probe}
+CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4, "probe": config_probe,
+           "gear_cd": config_gear_cd}
