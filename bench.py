@@ -410,9 +410,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
-    ap.add_argument("--workload", choices=["c2", "c5", "probe"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c5", "probe", "gear_cd"], default="c2",
                     help="c2 (default, the headline): one 1,024-element problem; c5: 64-instance batch; probe: "
-                         "20x20 test functions on 4,096 elements (G-stream bound)")
+                         "20x20 test functions on 4,096 elements (G-stream bound); gear_cd: the convection-diffusion "
+                         "gear problem on 14,000 elements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times: a kernel of known traffic that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -458,6 +459,10 @@ WORKLOAD_TEXT = {
     "c2": "c2: Poisson -Lap u = f on [0,1]^2, 32x32 quad mesh with interior nodes jittered +-20% h, 10x10 GLL "
           "points, 5x5 test functions, u*=sin(8pi x)sin(8pi y), 1600 boundary points, MLP 2-30-30-30-1 tanh, "
           "Adam lr 1e-3",
+    "gear_cd": "gear_cd: convection-diffusion -Lap u + (0.1, 0) . grad u = 50 sin x + cos x, u = 0 on the boundary "
+               "(the paper's gear experiment) on a toothed-annulus O-grid of 400x35 = 14,000 skewed quads (24 teeth, "
+               "amplitude 0.05), 5x5 GLL points, 4x4 test functions, 6096 boundary points, MLP 2-30-30-30-1 tanh; "
+               "eps and b folded into G at assembly",
     "probe": "probe: the c4 mesh (64x64 jittered, 4096 elements) with 10x10 GLL points and 20x20 test functions "
              "(the paper's largest p-refinement), u*=sin(2pi x)sin(2pi y), 1600 boundary points, MLP "
              "2-30-30-30-1 tanh: the only shape whose G stream (1.3 GB) outweighs the network arithmetic",
@@ -465,11 +470,9 @@ WORKLOAD_TEXT = {
 
 
 def bench_single(args, V, torch, gen):
-    prob = gen.config_c2() if args.workload == "c2" else gen.config_probe()
+    prob = gen.CONFIGS[args.workload]()
     theta = prob.params()
-    p = V.vpinn_assemble(prob.mesh.xy, prob.mesh.quad, prob.quad_order, prob.test_order,
-                         prob.f_amp, prob.f_kx, prob.f_ky)
-    V.vpinn_set_boundary(p, prob.bnd_xy, prob.bnd_g)
+    p = V.assemble_problem(prob)
     print(f"[bench] workload {args.workload}: {prob.n_elem} elements, {prob.n_points} quadrature points, "
           f"{len(prob.bnd_xy)} boundary points", file=sys.stderr, flush=True)
 

@@ -100,6 +100,23 @@ vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t 
                             const vpinn_forcing *forcing, void *stream, vpinn_problem **out);
 
 /*
+ * vpinn_assemble_cd2d -- the convection-diffusion operator -eps Lap u + b . grad u
+ * = f (Sec. 2.1; the gear problem of Sec. 4.6.4) with constant eps > 0 and
+ * b = (bx, by).  Its cell residual adds sum_q w_q det J (b . grad u)(x_q) v_k(x_q)
+ * to eps times the diffusion term; both are linear in (u_x, u_y), so they are
+ * folded into the premultiplied tensors at assembly:
+ *   G_x = w_q det J (eps dv_k/dx + bx v_k),  G_y = w_q det J (eps dv_k/dy + by v_k)
+ * and every later call (loss, gradient, batches, graphs) runs unchanged, at no
+ * extra cost per step.  vpinn_assemble is the case eps = 1, b = 0.  Because eps
+ * is folded, loss calls on such a problem take no d_eps / d_grad_eps
+ * (VPINN_E_INVALID).  Errors: as vpinn_assemble, plus VPINN_E_INVALID for a
+ * non-finite or non-positive eps or a non-finite b.
+ */
+vpinn_status vpinn_assemble_cd2d(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double eps,
+                                 double bx, double by, const vpinn_forcing *forcing, void *stream,
+                                 vpinn_problem **out);
+
+/*
  * Dirichlet points x_b and values g_b of the boundary term (Sec. 2.2), and
  * sensor points x_s with observations d_s of the data term of the inverse
  * problem (Sec. 4.7).  Host arrays xy [n][2] and values [n] are copied to the
@@ -114,6 +131,7 @@ typedef struct vpinn_problem_info {
     int64_t n_points;                /* N_elem * N_quad interior quadrature points */
     int64_t n_boundary, n_sensors;
     int32_t quad_order, test_order;
+    double diffusion, velocity_x, velocity_y; /* folded operator coefficients (1, 0, 0: Poisson) */
 } vpinn_problem_info;
 
 vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info);
@@ -149,7 +167,8 @@ int64_t vpinn_n_params(int32_t width, int32_t n_hidden);
  * vpinn_loss_and_grad -- one forward + adjoint evaluation.
  *   d_params   device, vpinn_n_params(width, n_hidden) floats
  *   d_eps      device, 1 float: the diffusion coefficient eps of -eps Lap u = f
- *              (Sec. 4.7.1); NULL means eps = 1
+ *              (Sec. 4.7.1); NULL means eps = 1; must be NULL for a problem from
+ *              vpinn_assemble_cd2d (its coefficients are folded into G)
  *   d_loss     device, 4 floats written: L, L_v, L_b, L_s (L_b and L_s are the
  *              unweighted means; L = L_v + tau L_b + gamma L_s)
  *   d_grad     device, vpinn_n_params floats written: dL/dtheta; NULL skips the

@@ -126,11 +126,14 @@ int64_t vpinn_n_params(int32_t width, int32_t n_hidden) {
 
 const char *vpinn_last_error(void) { return vp::g_err.c_str(); }
 
-vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order,
-                            const vpinn_forcing *forcing, void *stream, vpinn_problem **out) {
+static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double diff,
+                                      double conv_x, double conv_y, const vpinn_forcing *forcing, void *stream,
+                                      vpinn_problem **out) {
     using namespace vp;
     if (!out) return fail(VPINN_E_INVALID, "out is null");
     *out = nullptr;
+    if (!std::isfinite(diff) || !(diff > 0.0) || !std::isfinite(conv_x) || !std::isfinite(conv_y))
+        return fail(VPINN_E_INVALID, "the diffusion coefficient must be finite and > 0, the velocity finite");
     if (quad_order < 2 || quad_order > VPINN_MAX_QUAD_ORDER)
         return fail(VPINN_E_INVALID, "quad_order must be in 2.." + std::to_string(VPINN_MAX_QUAD_ORDER));
     if (test_order < 1 || test_order > VPINN_MAX_TEST_ORDER)
@@ -163,6 +166,9 @@ vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t 
     p->nq = (int)nq;
     p->ntest = (int)ntest;
     p->n_pts = n_elem * nq;
+    p->diff = diff;
+    p->conv_x = conv_x;
+    p->conv_y = conv_y;
     hipStream_t s = (hipStream_t)stream;
     const size_t gbytes = sizeof(float) * (size_t)(n_elem * ntest * nq);
     if (p->Gx.reserve(gbytes) != hipSuccess || p->Gy.reserve(gbytes) != hipSuccess ||
@@ -180,6 +186,17 @@ vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t 
     if (st) return bail(st);
     *out = p;
     return VPINN_OK;
+}
+
+vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order,
+                            const vpinn_forcing *forcing, void *stream, vpinn_problem **out) {
+    return assemble_operator(mesh, quad_order, test_order, 1.0, 0.0, 0.0, forcing, stream, out);
+}
+
+vpinn_status vpinn_assemble_cd2d(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double eps,
+                                 double bx, double by, const vpinn_forcing *forcing, void *stream,
+                                 vpinn_problem **out) {
+    return assemble_operator(mesh, quad_order, test_order, eps, bx, by, forcing, stream, out);
 }
 
 vpinn_status vpinn_set_boundary(vpinn_problem *pp, int64_t n, const double *xy, const double *g) {
@@ -225,6 +242,9 @@ vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info) {
     info->n_sensors = p->n_sen;
     info->quad_order = p->n;
     info->test_order = p->nt;
+    info->diffusion = p->diff;
+    info->velocity_x = p->conv_x;
+    info->velocity_y = p->conv_y;
     return VPINN_OK;
 }
 
@@ -267,6 +287,8 @@ vpinn_status vpinn_loss_and_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, co
     using namespace vp;
     if (!p || !d_params) return fail(VPINN_E_INVALID, "problem or params is null");
     if (!d_loss && !d_grad && !d_grad_eps) return fail(VPINN_E_INVALID, "nothing to compute");
+    if ((d_eps || d_grad_eps) && p->folded())
+        return fail(VPINN_E_INVALID, "a problem assembled with fixed convection-diffusion coefficients takes no eps");
     vpinn_status st = check_cfg(cfg);
     if (st) return st;
     DeviceGuard dg(p->device);
@@ -281,6 +303,8 @@ vpinn_status vpinn_residual(vpinn_problem *p, const vpinn_loss_cfg *cfg, const f
                             float *d_R, void *stream) {
     using namespace vp;
     if (!p || !d_params || !d_R) return fail(VPINN_E_INVALID, "null argument");
+    if (d_eps && p->folded())
+        return fail(VPINN_E_INVALID, "a problem assembled with fixed convection-diffusion coefficients takes no eps");
     vpinn_status st = check_cfg(cfg);
     if (st) return st;
     DeviceGuard dg(p->device);

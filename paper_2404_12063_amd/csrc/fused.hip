@@ -1443,6 +1443,11 @@ vpinn_status batch_create(int32_t n, vpinn_problem *const *problems, const vpinn
 
 vpinn_status batch_loss_and_grad(vpinn_batch *b, const float *d_params, const float *d_eps, float *d_losses,
                                  float *d_grads, float *d_grad_eps, hipStream_t s) {
+    if (d_eps || d_grad_eps)
+        for (const vpinn_problem *p : b->probs)
+            if (p->folded())
+                return fail(VPINN_E_INVALID,
+                            "a problem assembled with fixed convection-diffusion coefficients takes no eps");
     AdamArgs none{};
     return run_plan(b->plan, d_params, d_eps, d_grads != nullptr || d_grad_eps != nullptr, d_losses, d_grads,
                     d_grad_eps, none, nullptr, b->prof, s);

@@ -89,6 +89,9 @@ struct vpinn_problem {
     int n = 0, nt = 0, nq = 0, ntest = 0;
     int64_t n_pts = 0;       // interior points n_elem * nq
     int64_t n_bnd = 0, n_sen = 0;
+    // convection-diffusion coefficients folded into G at assembly (1, 0, 0: Poisson)
+    double diff = 1.0, conv_x = 0.0, conv_y = 0.0;
+    bool folded() const { return diff != 1.0 || conv_x != 0.0 || conv_y != 0.0; }
     vp::DevBuf Gx, Gy, F;    // float
     vp::DevBuf pts;          // float2 [n_pts + n_bnd + n_sen]: interior, boundary, sensors
     vp::DevBuf tgt;          // float [n_bnd + n_sen]: g_b then d_s
@@ -113,6 +116,7 @@ struct vpinn_problem {
 namespace vp {
 
 // kernel launchers (defined in the .hip files) --------------------------------
+// builds G (with p->diff, p->conv_x, p->conv_y folded in), F and the points
 vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_nodes, const int32_t *d_quad,
                              const vpinn_forcing *f, hipStream_t s);
 vpinn_status pack_params(const float *d_params, int H, int L, float *d_wpad, hipStream_t s);

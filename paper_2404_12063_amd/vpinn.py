@@ -50,7 +50,8 @@ class vpinn_forcing(C.Structure):
 class vpinn_problem_info(C.Structure):
     _fields_ = [("n_elem", C.c_int64), ("n_quad", C.c_int64), ("n_test", C.c_int64),
                 ("n_points", C.c_int64), ("n_boundary", C.c_int64), ("n_sensors", C.c_int64),
-                ("quad_order", C.c_int32), ("test_order", C.c_int32)]
+                ("quad_order", C.c_int32), ("test_order", C.c_int32),
+                ("diffusion", C.c_double), ("velocity_x", C.c_double), ("velocity_y", C.c_double)]
 
 
 class vpinn_loss_cfg(C.Structure):
@@ -75,6 +76,8 @@ _lib = None
 
 # every symbol of include/vpinn.h with its (restype, argtypes)
 _SIGNATURES = {
+    "vpinn_assemble_cd2d": (C.c_int32, [C.POINTER(vpinn_mesh), C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                        C.c_double, C.POINTER(vpinn_forcing), C.c_void_p, C.POINTER(C.c_void_p)]),
     "vpinn_assemble": (C.c_int32, [C.POINTER(vpinn_mesh), C.c_int32, C.c_int32, C.POINTER(vpinn_forcing),
                                    C.c_void_p, C.POINTER(C.c_void_p)]),
     "vpinn_set_boundary": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
@@ -173,9 +176,10 @@ class Problem:
 
 
 def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0, kx: float = 0.0,
-                   ky: float = 0.0, fn=None, stream=None) -> Problem:
+                   ky: float = 0.0, fn=None, stream=None, cd=None) -> Problem:
     """xy: host [n_nodes, 2] float64; quad: host [n_elem, 4] int32.  Forcing is amp*sin(kx x)sin(ky y),
-    or the Python callable fn(x, y) evaluated on the host (kind VPINN_FORCING_CALLBACK)."""
+    or the Python callable fn(x, y) evaluated on the host (kind VPINN_FORCING_CALLBACK).
+    cd = (eps, bx, by): the convection-diffusion operator -eps Lap u + b . grad u (vpinn_assemble_cd2d)."""
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     quad = np.ascontiguousarray(quad, dtype=np.int32)
     mesh = vpinn_mesh(xy.shape[0], xy.ctypes.data_as(C.POINTER(C.c_double)), quad.shape[0],
@@ -187,8 +191,27 @@ def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0,
         cb = SCALAR_FN(lambda x, y, u: float(fn(x, y)))
         f = vpinn_forcing(VPINN_FORCING_CALLBACK, 0.0, 0.0, 0.0, cb, None)
     out = C.c_void_p()
-    _check(lib().vpinn_assemble(C.byref(mesh), quad_order, test_order, C.byref(f), _stream(stream), C.byref(out)))
+    if cd is None:
+        _check(lib().vpinn_assemble(C.byref(mesh), quad_order, test_order, C.byref(f), _stream(stream),
+                                    C.byref(out)))
+    else:
+        eps, bx, by = (float(v) for v in cd)
+        _check(lib().vpinn_assemble_cd2d(C.byref(mesh), quad_order, test_order, eps, bx, by, C.byref(f),
+                                         _stream(stream), C.byref(out)))
     return Problem(out.value)
+
+
+def assemble_problem(prob, stream=None) -> Problem:
+    """Assemble a vpinn_inputs Problem (Poisson, or convection-diffusion when it sets diff/conv) and upload its
+    boundary and sensor sets."""
+    diff, conv = getattr(prob, "diff", 1.0), tuple(getattr(prob, "conv", (0.0, 0.0)))
+    cd = None if (diff, conv) == (1.0, (0.0, 0.0)) else (diff, conv[0], conv[1])
+    p = vpinn_assemble(prob.mesh.xy, prob.mesh.quad, prob.quad_order, prob.test_order, prob.f_amp, prob.f_kx,
+                       prob.f_ky, fn=getattr(prob, "f_fn", None), stream=stream, cd=cd)
+    vpinn_set_boundary(p, prob.bnd_xy, prob.bnd_g)
+    if len(prob.sens_xy):
+        vpinn_set_sensors(p, prob.sens_xy, prob.sens_u)
+    return p
 
 
 def vpinn_set_boundary(p: Problem, xy, g):

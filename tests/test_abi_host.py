@@ -27,7 +27,7 @@ def V():
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(vpinn_[a-z_]+)\s*\(", text)) - {"vpinn_scalar_fn"})
+    return sorted(set(re.findall(r"\b(vpinn_[a-z0-9_]+)\s*\(", text)) - {"vpinn_scalar_fn"})
 
 
 def test_header_declares_the_boundary_calls():
@@ -137,3 +137,18 @@ def test_null_arguments(V):
     assert L.vpinn_eval_network(33, 3, 1, 0, None, None, None, None, None) == V.VPINN_E_UNSUPPORTED
     L.vpinn_problem_free(None)
     del cfg
+
+
+@pytest.mark.parametrize("eps,bx,by", [(0.0, 0.1, 0.0), (-1.0, 0.0, 0.0), (float("nan"), 0.0, 0.0),
+                                       (1.0, float("inf"), 0.0), (1.0, 0.0, float("nan"))])
+def test_cd2d_rejects_bad_coefficients(V, eps, bx, by):
+    """Checked before any device work: no GPU needed."""
+    m = gen.square_mesh(2, 2)
+    xy = np.ascontiguousarray(m.xy, dtype=np.float64)
+    quad = np.ascontiguousarray(m.quad, dtype=np.int32)
+    mesh = V.vpinn_mesh(xy.shape[0], xy.ctypes.data_as(C.POINTER(C.c_double)), quad.shape[0],
+                        quad.ctypes.data_as(C.POINTER(C.c_int32)))
+    f = V.vpinn_forcing(1, 1.0, 1.0, 1.0, V.SCALAR_FN(0), None)
+    out = C.c_void_p()
+    rc = V.lib().vpinn_assemble_cd2d(C.byref(mesh), 4, 3, eps, bx, by, C.byref(f), None, C.byref(out))
+    assert rc == V.VPINN_E_INVALID and not out.value
