@@ -94,6 +94,10 @@ typedef struct vpinn_problem vpinn_problem;
  * test_order outside 1..30, n_elem < 1), VPINN_E_MESH (vertex id out of range or
  * det J <= 0 at a corner, with the element id in the message), VPINN_E_NONFINITE,
  * VPINN_E_NOMEM, VPINN_E_DEVICE.  Synchronous: returns after the tensors are built.
+ * When every element is a translate of element 0 with its vertices in the same
+ * order (a uniform mesh), G_x and G_y are identical for all elements and are
+ * stored once (the single reference premultiplier of Algorithm 2, [N_test][N_quad]);
+ * vpinn_read_tensor still returns them per element.
  * On success *out owns all device memory; free it with vpinn_problem_free.
  */
 vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order,
@@ -132,6 +136,8 @@ typedef struct vpinn_problem_info {
     int64_t n_boundary, n_sensors;
     int32_t quad_order, test_order;
     double diffusion, velocity_x, velocity_y; /* folded operator coefficients (1, 0, 0: Poisson) */
+    int32_t shared_premultiplier;    /* 1: all elements are translates of one shape, and G_x, G_y are
+                                        stored once (Algorithm 2's reference premultiplier) */
 } vpinn_problem_info;
 
 vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info);

@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/vpinn.h: argument and mesh
 // validation, ownership of device buffers, and dispatch to the kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -62,6 +63,35 @@ static vpinn_status validate_mesh(const vpinn_mesh *m) {
         }
     }
     return VPINN_OK;
+}
+
+// True if every element is a translate of element 0 with its vertices in the same
+// order: the bilinear map's non-constant coefficients agree (to 1e-12 relative), so
+// the Jacobian field, and with it G, is the same for every element.
+static bool congruent_elements(const vpinn_mesh *m) {
+    auto coeffs = [&](int64_t e, double c[6]) {
+        double x[4], y[4];
+        for (int k = 0; k < 4; ++k) {
+            const int64_t id = m->quad[4 * e + k];
+            x[k] = m->xy[2 * id];
+            y[k] = m->xy[2 * id + 1];
+        }
+        c[0] = 0.25 * (-x[0] + x[1] + x[2] - x[3]);
+        c[1] = 0.25 * (-x[0] - x[1] + x[2] + x[3]);
+        c[2] = 0.25 * (x[0] - x[1] + x[2] - x[3]);
+        c[3] = 0.25 * (-y[0] + y[1] + y[2] - y[3]);
+        c[4] = 0.25 * (-y[0] - y[1] + y[2] + y[3]);
+        c[5] = 0.25 * (y[0] - y[1] + y[2] - y[3]);
+    };
+    double c0[6], c[6], scale = 0.0;
+    coeffs(0, c0);
+    for (double v : c0) scale = std::max(scale, std::fabs(v));
+    for (int64_t e = 1; e < m->n_elem; ++e) {
+        coeffs(e, c);
+        for (int i = 0; i < 6; ++i)
+            if (std::fabs(c[i] - c0[i]) > 1e-12 * scale) return false;
+    }
+    return true;
 }
 
 static vpinn_status rebuild_points(vpinn_problem *p, const std::vector<float> &bxy, const std::vector<float> &bg,
@@ -169,8 +199,9 @@ static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order
     p->diff = diff;
     p->conv_x = conv_x;
     p->conv_y = conv_y;
+    p->shared_g = congruent_elements(mesh);
     hipStream_t s = (hipStream_t)stream;
-    const size_t gbytes = sizeof(float) * (size_t)(n_elem * ntest * nq);
+    const size_t gbytes = sizeof(float) * (size_t)((p->shared_g ? 1 : n_elem) * ntest * nq);
     if (p->Gx.reserve(gbytes) != hipSuccess || p->Gy.reserve(gbytes) != hipSuccess ||
         p->F.reserve(sizeof(float) * n_elem * ntest) != hipSuccess ||
         p->pts.reserve(sizeof(float2) * p->n_pts) != hipSuccess)
@@ -245,6 +276,7 @@ vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info) {
     info->diffusion = p->diff;
     info->velocity_x = p->conv_x;
     info->velocity_y = p->conv_y;
+    info->shared_premultiplier = p->shared_g ? 1 : 0;
     return VPINN_OK;
 }
 
@@ -263,6 +295,13 @@ vpinn_status vpinn_read_tensor(const vpinn_problem *p, int32_t which, float *hos
     if (count != want) return fail(VPINN_E_INVALID, "count must be " + std::to_string(want));
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
+    if (p->shared_g && (which == VPINN_TENSOR_GX || which == VPINN_TENSOR_GY)) {
+        // one stored premultiplier, replicated for every element on the host
+        const int64_t per = (int64_t)p->ntest * p->nq;
+        VP_HIP(hipMemcpy(host_dst, src, sizeof(float) * per, hipMemcpyDeviceToHost));
+        for (int64_t e = 1; e < p->n_elem; ++e) std::copy(host_dst, host_dst + per, host_dst + e * per);
+        return VPINN_OK;
+    }
     VP_HIP(hipMemcpy(host_dst, src, sizeof(float) * count, hipMemcpyDeviceToHost));
     return VPINN_OK;
 }

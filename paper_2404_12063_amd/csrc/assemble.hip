@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(
     const double *__restrict__ nodes, const int32_t *__restrict__ quad, int n, int nt,
     const double *__restrict__ xg, const double *__restrict__ wg, const double *__restrict__ phi,
     const double *__restrict__ dphi, int f_kind, double f_amp, double f_kx, double f_ky,
-    const double *__restrict__ f_vals, double diff, double cx, double cy, float *__restrict__ Gx,
+    const double *__restrict__ f_vals, double diff, double cx, double cy, int shared_g, float *__restrict__ Gx,
     float *__restrict__ Gy, float *__restrict__ F) {
     __shared__ double wdf[kAsmThreads];
     const int64_t e = blockIdx.x;
@@ -156,12 +156,13 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(
                 f = f_vals[e * nq + q];
             }
             wdf[threadIdx.x] = w * D * f;
-            for (int s = 0; s < nt; ++s) {
+            // a shared premultiplier is written once, from element 0
+            for (int s = 0; s < ((shared_g && e > 0) ? 0 : nt); ++s) {
                 const double ps = phi[s * n + j], dps = dphi[s * n + j];
                 for (int r = 0; r < nt; ++r) {
                     const double pr = phi[r * n + i], dpr = dphi[r * n + i];
                     const double vxi = dpr * ps, veta = pr * dps, dv = D * pr * ps;
-                    const int64_t o = (e * ntest + s * nt + r) * (int64_t)nq + q;
+                    const int64_t o = ((shared_g ? 0 : e * ntest) + s * nt + r) * (int64_t)nq + q;
                     // det J * physical gradient = (d v_xi - b v_eta, -c v_xi + a v_eta)
                     Gx[o] = (float)(w * (diff * (d * vxi - b * veta) + cx * dv));
                     Gy[o] = (float)(w * (diff * (-c * vxi + a * veta) + cy * dv));
@@ -233,7 +234,7 @@ vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_
     k_assemble<<<dim3((unsigned)p->n_elem), kAsmThreads, 0, s>>>(
         d_nodes, d_quad, n, nt, d_xg.as<double>(), d_wg.as<double>(), d_phi.as<double>(), d_dphi.as<double>(),
         f->kind, f->amp, f->kx, f->ky, callback ? d_f.as<double>() : nullptr, p->diff, p->conv_x, p->conv_y,
-        p->Gx.as<float>(), p->Gy.as<float>(), p->F.as<float>());
+        p->shared_g ? 1 : 0, p->Gx.as<float>(), p->Gy.as<float>(), p->F.as<float>());
     VP_HIP(hipGetLastError());
     VP_HIP(hipStreamSynchronize(s));
     return VPINN_OK;

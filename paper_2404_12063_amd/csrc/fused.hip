@@ -120,6 +120,7 @@ struct InstDesc {
     int64_t n_tiles, tile0;   // tiles (16 points each) tile0 .. of the global tile list
     int64_t ubase;            // offset of this instance's points in the point buffer
     int64_t cblk0, n_chunks;  // contraction blocks cblk0 .. (epc elements each)
+    int64_t gstride;          // floats between elements in G_x, G_y (0: one shared premultiplier)
     int nq, ntest, epc;
     int path;                 // contraction path (kPathFast .. kPathGeneric)
     // loss partial rows lrow0 .. lrow0 + ln_rows - 1: first one per tile block
@@ -664,7 +665,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract_fast(ContractArgs A) {
     float *rbar = dyn + ntest * kCbs;   // [ne][ntest] 2 c_v R
     const int el = tid / nq, q = tid - el * nq;
     const bool act = el < ne;
-    const int64_t gbase = ((e0 + el) * ntest) * (int64_t)nq + q;
+    const int64_t gbase = (e0 + el) * Ip->gstride + q;
     float gx[kKB], gy[kKB];
 #pragma unroll
     for (int k = 0; k < kKB; ++k) {
@@ -719,7 +720,7 @@ struct RowBuf {
 
 template <int Q, int kRP>
 __device__ __forceinline__ void rows_load(RowBuf<Q, kRP> &B, const float *__restrict__ Gx, const float *__restrict__ Gy,
-                                          int64_t ebase, int k0, int ntest, int nq, int lane) {
+                                          int64_t gbase, int k0, int ntest, int nq, int lane) {
 #pragma unroll
     for (int r = 0; r < kRP; ++r) {
         const int k = k0 + r * kCWaves;
@@ -727,7 +728,7 @@ __device__ __forceinline__ void rows_load(RowBuf<Q, kRP> &B, const float *__rest
         for (int i = 0; i < Q; ++i) {
             const int q = lane + 64 * i;
             const bool ok = k < ntest && q < nq;
-            const int64_t o = (ebase + k) * (int64_t)nq + q;
+            const int64_t o = gbase + (int64_t)k * nq + q;
             B.gx[r][i] = ok ? Gx[o] : 0.f;
             B.gy[r][i] = ok ? Gy[o] : 0.f;
         }
@@ -771,7 +772,7 @@ __device__ __forceinline__ void contract_rows(const ContractArgs &A, const Contr
     const float *__restrict__ F = Ip->F;
     const float two_cv = Ip->two_cv, eps = c.eps;
     float2 *__restrict__ ub = A.ubuf + Ip->ubase;
-    const int64_t e0 = c.e0, ebase = e0 * ntest;
+    const int64_t e0 = c.e0, ebase = e0 * ntest, gbase = e0 * Ip->gstride;
     float ux[Q], uy[Q], bx[Q], by[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -786,7 +787,7 @@ __device__ __forceinline__ void contract_rows(const ContractArgs &A, const Contr
     constexpr int kStep = kRP * kCWaves;
     for (int k0 = wave; k0 < ntest; k0 += kStep) {
         RowBuf<Q, kRP> B;
-        rows_load<Q, kRP>(B, Gx, Gy, ebase, k0, ntest, nq, lane);
+        rows_load<Q, kRP>(B, Gx, Gy, gbase, k0, ntest, nq, lane);
         rows_use<Q, kRP>(B, ux, uy, bx, by, F, ebase, k0, ntest, eps, two_cv, lane, lrr, lra);
     }
     if (A.want_grad) {
@@ -836,7 +837,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
     float2 *__restrict__ ub = A.ubuf + Ip->ubase;
     double lrr = 0.0, lra = 0.0;
     float *rbar = dyn;  // [ntest] 2 c_v R of the block's element
-    const int64_t ebase = e0 * ntest;
+    const int64_t ebase = e0 * ntest, gbase = e0 * Ip->gstride;
     const float2 *__restrict__ uxy = ub + e0 * nq;
     constexpr int kRG = kCThreads / 16;
     const int rg = tid >> 4, rl = tid & 15;
@@ -844,7 +845,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
         const int k = k0 + rg;
         float acc = 0.f;
         if (k < ntest) {
-            const float *gxr = Gx + (ebase + k) * (int64_t)nq, *gyr = Gy + (ebase + k) * (int64_t)nq;
+            const float *gxr = Gx + gbase + (int64_t)k * nq, *gyr = Gy + gbase + (int64_t)k * nq;
             for (int q = rl; q < nq; q += 16) {
                 const float2 d = uxy[q];
                 acc = fmaf(d.x, gxr[q], fmaf(d.y, gyr[q], acc));
@@ -866,7 +867,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
         for (int q = tid; q < nq; q += kCThreads) {
             float bx = 0.f, by = 0.f;
             for (int k = 0; k < ntest; ++k) {
-                const int64_t o = (ebase + k) * (int64_t)nq + q;
+                const int64_t o = gbase + (int64_t)k * nq + q;
                 bx = fmaf(rbar[k], Gx[o], bx);
                 by = fmaf(rbar[k], Gy[o], by);
             }
@@ -1185,6 +1186,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         ubase += tot;
         d.nq = p->nq;
         d.ntest = p->ntest;
+        d.gstride = p->gstride();
         d.path = (p->nq <= kCThreads && p->ntest <= kKB) ? kPathFast
                  : (p->nq <= 64)                          ? kPathRows1
                  : (p->nq <= 128)                         ? kPathRows2

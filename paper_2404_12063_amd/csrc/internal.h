@@ -92,6 +92,10 @@ struct vpinn_problem {
     // convection-diffusion coefficients folded into G at assembly (1, 0, 0: Poisson)
     double diff = 1.0, conv_x = 0.0, conv_y = 0.0;
     bool folded() const { return diff != 1.0 || conv_x != 0.0 || conv_y != 0.0; }
+    // every element a translate of one shape: G is the same for all of them and is
+    // stored once (Algorithm 2's single reference premultiplier), element stride 0
+    bool shared_g = false;
+    int64_t gstride() const { return shared_g ? 0 : (int64_t)ntest * nq; }
     vp::DevBuf Gx, Gy, F;    // float
     vp::DevBuf pts;          // float2 [n_pts + n_bnd + n_sen]: interior, boundary, sensors
     vp::DevBuf tgt;          // float [n_bnd + n_sen]: g_b then d_s

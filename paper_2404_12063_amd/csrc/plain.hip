@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void k_plain_fwd(const float *__restrict__ w, 
 __global__ __launch_bounds__(256) void k_plain_contract(const float *__restrict__ Gx, const float *__restrict__ Gy,
                                                   const float *__restrict__ F, const float *__restrict__ ux,
                                                   const float *__restrict__ uy, const float *__restrict__ eps_ptr,
-                                                  int64_t n_elem, int nq, int ntest, float *__restrict__ A,
+                                                  int64_t n_elem, int nq, int ntest, int64_t gstride,
+                                                  float *__restrict__ A,
                                                   float *__restrict__ R, double *__restrict__ lv_e,
                                                   double *__restrict__ ep_e) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void k_plain_contract(const float *__restrict_
     const float eps = eps_ptr ? *eps_ptr : 1.0f;
     double le = 0.0, lp = 0.0;
     for (int k = 0; k < ntest; ++k) {
-        const int64_t base = (e * ntest + k) * nq;
+        const int64_t base = e * gstride + (int64_t)k * nq;
         float acc = 0.0f;
         for (int q = lane; q < nq; q += 64)
             acc = fmaf(ux[e * nq + q], Gx[base + q], fmaf(uy[e * nq + q], Gy[base + q], acc));
@@ -232,7 +233,8 @@ __global__ __launch_bounds__(256) void k_plain_contract(const float *__restrict_
 __global__ __launch_bounds__(256) void k_plain_adj_contract(const float *__restrict__ Gx, const float *__restrict__ Gy,
                                                       const float *__restrict__ R, const float *__restrict__ eps_ptr,
                                                       float two_cv, int64_t n_elem, int nq, int ntest,
-                                                      float *__restrict__ uxb, float *__restrict__ uyb) {
+                                                      int64_t gstride, float *__restrict__ uxb,
+                                                      float *__restrict__ uyb) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= n_elem * nq) return;
     const int64_t e = t / nq;
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(256) void k_plain_adj_contract(const float *__restr
     float bx = 0.0f, by = 0.0f;
     for (int k = 0; k < ntest; ++k) {
         const float rb = R[e * ntest + k];
-        const int64_t o = (e * ntest + k) * nq + q;
+        const int64_t o = e * gstride + (int64_t)k * nq + q;
         bx = fmaf(rb, Gx[o], bx);
         by = fmaf(rb, Gy[o], by);
     }
@@ -540,14 +542,15 @@ vpinn_status plain_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
     float *R = d_R_out ? d_R_out : p->R.as<float>();
     k_plain_contract<<<dim3((unsigned)((p->n_elem + 3) / 4)), 256, 0, s>>>(
         p->Gx.as<float>(), p->Gy.as<float>(), p->F.as<float>(), p->ux.as<float>(), p->uy.as<float>(), d_eps,
-        p->n_elem, p->nq, p->ntest, p->A.as<float>(), R, p->loss_e.as<double>(), p->eps_part.as<double>());
+        p->n_elem, p->nq, p->ntest, p->gstride(), p->A.as<float>(), R, p->loss_e.as<double>(),
+        p->eps_part.as<double>());
     VP_HIP(hipGetLastError());
     if (d_R_out && !d_loss) return VPINN_OK;
     const double cv = cfg->loss_norm == VPINN_NORM_ELEM ? 1.0 / (double)p->n_elem : 1.0 / (double)p->ntest;
     if (want_grad) {
         k_plain_adj_contract<<<dim3((unsigned)((n_int + 255) / 256)), 256, 0, s>>>(
             p->Gx.as<float>(), p->Gy.as<float>(), R, d_eps, (float)(2.0 * cv), p->n_elem, p->nq, p->ntest,
-            p->uxb.as<float>(), p->uyb.as<float>());
+            p->gstride(), p->uxb.as<float>(), p->uyb.as<float>());
         VP_HIP(hipGetLastError());
         const float wb2 = p->n_bnd ? (float)(2.0 * cfg->tau / (double)p->n_bnd) : 0.0f;
         const float ws2 = p->n_sen ? (float)(2.0 * cfg->gamma / (double)p->n_sen) : 0.0f;

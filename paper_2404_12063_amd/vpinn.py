@@ -51,7 +51,8 @@ class vpinn_problem_info(C.Structure):
     _fields_ = [("n_elem", C.c_int64), ("n_quad", C.c_int64), ("n_test", C.c_int64),
                 ("n_points", C.c_int64), ("n_boundary", C.c_int64), ("n_sensors", C.c_int64),
                 ("quad_order", C.c_int32), ("test_order", C.c_int32),
-                ("diffusion", C.c_double), ("velocity_x", C.c_double), ("velocity_y", C.c_double)]
+                ("diffusion", C.c_double), ("velocity_x", C.c_double), ("velocity_y", C.c_double),
+                ("shared_premultiplier", C.c_int32)]
 
 
 class vpinn_loss_cfg(C.Structure):

@@ -194,10 +194,11 @@ def test_c5_batched_workload_sampled(V, torch):
 
 
 def _all_shapes():
-    """Mixed instances plus one that streams contraction rows (N_t = 7) and one with large elements (n = 17)."""
+    """Mixed instances plus one that streams contraction rows (N_t = 7), one with large elements (n = 17) and
+    one uniform mesh with a single shared premultiplier."""
     out = _mixed_instances()
-    for i, (m, n, nt) in enumerate([(3, 6, 7), (2, 17, 3)]):
-        p = gen.poisson_sinsin_square(f"shape{i}", m, n, nt, 2, 40, 0.2, seed=200 + i)
+    for i, (m, n, nt, jitter) in enumerate([(3, 6, 7, 0.2), (2, 17, 3, 0.2), (5, 6, 4, 0.0)]):
+        p = gen.poisson_sinsin_square(f"shape{i}", m, n, nt, 2, 40, jitter, seed=200 + i)
         p.gamma = 5.0
         out.append(p)
     return out

@@ -65,6 +65,8 @@ def _problem(name):
         return gen.poisson_sinsin_square("q6t7", 3, 6, 7, 2, 40, 0.2, seed=8)
     if name == "q12t6":       # 144 points, 36 test functions: row streaming with four points a lane
         return gen.poisson_sinsin_square("q12t6", 2, 12, 6, 2, 40, 0.2, seed=9)
+    if name == "uniform16":   # uniform 16x16 mesh: one shared premultiplier for every element (Algorithm 2)
+        return gen.poisson_sinsin_square("uniform16", 16, 8, 5, 4, 200, 0.0, seed=1)
     if name == "q17":         # 289 points per element: the two-pass contraction for large elements
         return gen.poisson_sinsin_square("q17", 2, 17, 3, 2, 40, 0.2, seed=7)
     if name == "gear_small":  # a small toothed annulus: skewed elements, nonzero boundary data
@@ -134,7 +136,7 @@ def _path_or_skip(V, name):
 
 # ----------------------------------------------------------------------------- assembly
 
-@pytest.mark.parametrize("name", ["c1", "c2", "gear_small", "ragged", "p20", "tiny_n2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "gear_small", "ragged", "p20", "tiny_n2", "uniform16"])
 def test_assembly_matches_oracle(V, name):
     prob = _problem(name)
     ref = _oracle_asm(name)
@@ -185,7 +187,7 @@ def test_network_values_and_tangents(V, torch, H, L):
 
 @pytest.mark.parametrize("path", ["plain", "fused"])
 @pytest.mark.parametrize("name", ["c1", "c2", "gear_small", "ragged", "tiny_n2", "deep32", "nobnd", "p20", "q6t7",
-                                  "q12t6", "q17"])
+                                  "q12t6", "q17", "uniform16"])
 def test_loss_and_grad_match_oracle(V, torch, path, name):
     prob = _problem(name)
     theta = _params(prob)
@@ -311,3 +313,10 @@ def test_c1_adam_trajectory(V, torch, path):
     l_gpu = O.problem_loss_grad(prob, asm, T.cpu().double().numpy(), want_grad=False).loss[0]
     l_cpu = O.problem_loss_grad(prob, asm, rt, want_grad=False).loss[0]
     assert abs(l_gpu - l_cpu) / l_cpu < 1e-3, (l_gpu, l_cpu)
+
+
+@pytest.mark.parametrize("name,shared", [("c1", 1), ("uniform16", 1), ("c2", 0), ("tiny_n2", 0), ("gear_small", 0)])
+def test_shared_premultiplier_detection(V, name, shared):
+    """Uniform meshes store G once (Algorithm 2); jittered and curved ones per element."""
+    p = _gpu_problem(V, _problem(name))
+    assert V.vpinn_get_info(p).shared_premultiplier == shared
