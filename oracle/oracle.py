@@ -63,17 +63,19 @@ def lib():
                                    FN2, C.c_void_p, _dp, _dp, _dp, _dp, C.c_void_p, C.POINTER(C.c_int64)]
         L.orc_n_params.restype = C.c_int64
         L.orc_n_params.argtypes = [C.c_int, C.c_int]
+        L.orc_n_params_heads.restype = C.c_int64
+        L.orc_n_params_heads.argtypes = [C.c_int, C.c_int, C.c_int]
         L.orc_mlp_eval.restype = None
-        L.orc_mlp_eval.argtypes = [C.c_int, C.c_int, _dp, C.c_int64, _dp, _dp, _dp, _dp]
+        L.orc_mlp_eval.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_int64, _dp, _dp, _dp, _dp, C.c_void_p]
         L.orc_mlp_vjp.restype = None
-        L.orc_mlp_vjp.argtypes = [C.c_int, C.c_int, _dp, C.c_int64, _dp, _dp, _dp, _dp, _dp]
+        L.orc_mlp_vjp.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_int64, _dp, _dp, _dp, _dp, C.c_void_p, _dp]
         L.orc_residual.restype = None
         L.orc_residual.argtypes = [C.c_int64, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_void_p,
-                                   C.c_double, C.c_double, _dp]
+                                   C.c_double, C.c_double, C.c_void_p, _dp]
         L.orc_loss_grad.restype = C.c_int
         L.orc_loss_grad.argtypes = [C.c_int64, C.c_int, C.c_int, _dp, _dp, _dp, _dp, C.c_void_p, C.c_double,
                                     C.c_double, C.c_int64, _dp, _dp, C.c_int64, _dp, _dp,
-                                    C.c_int, C.c_int, _dp, C.c_double, C.c_double, C.c_double,
+                                    C.c_int, C.c_int, C.c_int, _dp, C.c_double, C.c_double, C.c_double,
                                     C.c_double, _dp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_adam.restype = None
         L.orc_adam.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_double,
@@ -184,22 +186,25 @@ def assemble_problem(prob) -> Assembled:
 
 # --------------------------------------------------------------------------- network
 
-def n_params(H: int, L: int) -> int:
-    return int(lib().orc_n_params(H, L))
+def n_params(H: int, L: int, heads: int = 1) -> int:
+    return int(lib().orc_n_params_heads(H, L, heads))
 
 
-def mlp_eval(theta, H: int, L: int, xy):
+def mlp_eval(theta, H: int, L: int, xy, heads: int = 1):
+    """u, u_x, u_y at the points; with heads = 2 also the second output e."""
     xy = _f64(xy).reshape(-1, 2)
     n = xy.shape[0]
-    u, ux, uy = np.zeros(n), np.zeros(n), np.zeros(n)
-    lib().orc_mlp_eval(H, L, _f64(theta), n, xy.ravel(), u, ux, uy)
-    return u, ux, uy
+    u, ux, uy, e = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_mlp_eval(H, L, heads, _f64(theta), n, xy.ravel(), u, ux, uy, e.ctypes.data_as(C.c_void_p))
+    return (u, ux, uy) if heads == 1 else (u, ux, uy, e)
 
 
-def mlp_vjp(theta, H: int, L: int, xy, ub, uxb, uyb):
+def mlp_vjp(theta, H: int, L: int, xy, ub, uxb, uyb, eb=None, heads: int = 1):
     xy = _f64(xy).reshape(-1, 2)
-    g = np.zeros(n_params(H, L))
-    lib().orc_mlp_vjp(H, L, _f64(theta), xy.shape[0], xy.ravel(), _f64(ub), _f64(uxb), _f64(uyb), g)
+    g = np.zeros(n_params(H, L, heads))
+    ebp = None if eb is None else _f64(eb)
+    lib().orc_mlp_vjp(H, L, heads, _f64(theta), xy.shape[0], xy.ravel(), _f64(ub), _f64(uxb), _f64(uyb),
+                      None if ebp is None else ebp.ctypes.data_as(C.c_void_p), g)
     return g
 
 
@@ -211,12 +216,15 @@ def _conv_args(asm: Assembled, conv):
     return asm.M.ctypes.data_as(C.c_void_p), float(conv[0]), float(conv[1])
 
 
-def residual(asm: Assembled, ux, uy, eps: float = 1.0, conv=None):
-    """R = eps * A + sum_q (b . grad u) M - F; conv = (b_x, b_y) or None."""
+def residual(asm: Assembled, ux, uy, eps: float = 1.0, conv=None, epsq=None):
+    """R = eps * A + sum_q (b . grad u) M - F; conv = (b_x, b_y) or None; epsq: a per-point diffusion
+    coefficient (space-dependent, Sec. 4.7.2) replacing eps."""
     R = np.zeros_like(asm.F)
     Mp, bx, by = _conv_args(asm, conv)
+    ep = None if epsq is None else _f64(epsq).ravel()
     lib().orc_residual(asm.n_elem, asm.n * asm.n, asm.nt * asm.nt, asm.Gx.ravel(), asm.Gy.ravel(),
-                       asm.F.ravel(), _f64(ux).ravel(), _f64(uy).ravel(), eps, Mp, bx, by, R)
+                       asm.F.ravel(), _f64(ux).ravel(), _f64(uy).ravel(), eps, Mp, bx, by,
+                       None if ep is None else ep.ctypes.data_as(C.c_void_p), R)
     return R
 
 
@@ -237,20 +245,21 @@ def c_v(asm: Assembled, loss_norm: int = 0) -> float:
 
 def loss_grad(asm: Assembled, theta, H: int, L: int, bnd_xy=None, bnd_g=None, sens_xy=None, sens_u=None,
               eps: float = 1.0, tau: float = 10.0, gamma: float = 0.0, loss_norm: int = 0,
-              want_grad: bool = True, want_R: bool = False, conv=None) -> LossGrad:
+              want_grad: bool = True, want_R: bool = False, conv=None, heads: int = 1) -> LossGrad:
+    """heads = 2: the network's second output is the space-dependent diffusion coefficient (eps unused)."""
     bxy = _f64(np.zeros((0, 2)) if bnd_xy is None else bnd_xy).reshape(-1, 2)
     bg = _f64(np.zeros(0) if bnd_g is None else bnd_g)
     sxy = _f64(np.zeros((0, 2)) if sens_xy is None else sens_xy).reshape(-1, 2)
     su = _f64(np.zeros(0) if sens_u is None else sens_u)
     loss = np.zeros(4)
-    grad = np.zeros(n_params(H, L)) if want_grad else None
+    grad = np.zeros(n_params(H, L, heads)) if want_grad else None
     geps = C.c_double(0.0)
     R = np.zeros_like(asm.F) if want_R else None
     Mp, cbx, cby = _conv_args(asm, conv)
     rc = lib().orc_loss_grad(
         asm.n_elem, asm.n * asm.n, asm.nt * asm.nt, asm.Gx.ravel(), asm.Gy.ravel(), asm.F.ravel(),
         asm.X.ravel(), Mp, cbx, cby, bxy.shape[0], bxy.ravel(), bg, sxy.shape[0], sxy.ravel(), su,
-        H, L, _f64(theta), eps, tau, gamma, c_v(asm, loss_norm), loss,
+        H, L, heads, _f64(theta), eps, tau, gamma, c_v(asm, loss_norm), loss,
         grad.ctypes.data_as(C.c_void_p) if want_grad else None,
         C.cast(C.pointer(geps), C.c_void_p) if want_grad else None,
         R.ctypes.data_as(C.c_void_p) if want_R else None)
@@ -266,7 +275,8 @@ def problem_loss_grad(prob, asm: Assembled, theta, eps: Optional[float] = None, 
     e = getattr(prob, "diff", 1.0) if eps is None else eps
     return loss_grad(asm, theta, prob.width, prob.n_hidden, prob.bnd_xy, prob.bnd_g,
                      prob.sens_xy, prob.sens_u, eps=e, tau=prob.tau, gamma=prob.gamma,
-                     loss_norm=loss_norm, want_grad=want_grad, conv=getattr(prob, "conv", None))
+                     loss_norm=loss_norm, want_grad=want_grad, conv=getattr(prob, "conv", None),
+                     heads=getattr(prob, "heads", 1))
 
 
 def adam(theta, g, m, v, t: int, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):

@@ -235,12 +235,18 @@ int orc_assemble(int64_t n_nodes, const double *xy, int64_t n_elem, const int32_
 /* ------------------------------------------------------------------------- */
 /* the network of Section 2.2: u = l(T^L(...T^1(x))), T^l(a) = tanh(W_l a+b_l) */
 /* flat layout: W1[H][2], b1[H], (W_l[H][H], b_l[H]) for l = 2..L,            */
-/* W_out[H], b_out.                                                           */
+/* W_out[heads][H], b_out[heads]; heads = 2 adds a second linear output, the   */
+/* space-dependent diffusion coefficient eps(x, y) of Sec. 4.7.2.             */
 /* Layer l is written uniformly with input width d_{l-1} (d_0 = 2, else H).   */
 /* ------------------------------------------------------------------------- */
 int64_t orc_n_params(int H, int L)
 {
     return (int64_t)H * 2 + H + (int64_t)(L - 1) * (H * H + H) + H + 1;
+}
+
+int64_t orc_n_params_heads(int H, int L, int heads)
+{
+    return orc_n_params(H, L) + (int64_t)(heads - 1) * (H + 1);
 }
 
 static int64_t w_off(int H, int l) /* offset of W_l, l = 1..L+1 (L+1 is the output layer) */
@@ -251,15 +257,17 @@ static int64_t w_off(int H, int l) /* offset of W_l, l = 1..L+1 (L+1 is the outp
 
 /* per-point forward values and tangents; arrays are [L+1][H] with row 0 the input */
 typedef struct {
-    int H, L;
+    int H, L, heads;
     double *a, *tx, *ty, *px, *py;
     double u, ux, uy;
+    double e; /* second output (heads = 2) */
 } tape;
 
-static void tape_init(tape *t, int H, int L)
+static void tape_init(tape *t, int H, int L, int heads)
 {
     t->H = H;
     t->L = L;
+    t->heads = heads;
     size_t sz = sizeof(double) * (size_t)(L + 1) * (H > 2 ? H : 2);
     t->a = calloc(1, sz); t->tx = calloc(1, sz); t->ty = calloc(1, sz);
     t->px = calloc(1, sz); t->py = calloc(1, sz);
@@ -305,19 +313,26 @@ static void mlp_forward(const double *theta, double x, double y, tape *t)
         }
     }
     const double *Wo = theta + w_off(H, L + 1);
-    const double bo = Wo[H];
+    const double *bo = Wo + (size_t)t->heads * H;
     const double *aL = ROW(t->a, L), *txL = ROW(t->tx, L), *tyL = ROW(t->ty, L);
-    double u = bo, ux = 0.0, uy = 0.0;
+    double u = bo[0], ux = 0.0, uy = 0.0;
     for (int i = 0; i < H; ++i) {
         u += Wo[i] * aL[i];
         ux += Wo[i] * txL[i];
         uy += Wo[i] * tyL[i];
     }
     t->u = u; t->ux = ux; t->uy = uy;
+    t->e = 0.0;
+    if (t->heads == 2) {
+        double e = bo[1];
+        for (int i = 0; i < H; ++i) e += Wo[H + i] * aL[i];
+        t->e = e;
+    }
 }
 
-/* reverse sweep: given dL/du, dL/du_x, dL/du_y at the point, add dL/dtheta */
-static void mlp_backward(const double *theta, const tape *t, double ub, double uxb, double uyb,
+/* reverse sweep: given dL/du, dL/du_x, dL/du_y (and dL/de of the second output)
+ * at the point, add dL/dtheta */
+static void mlp_backward(const double *theta, const tape *t, double ub, double uxb, double uyb, double eb,
                          double *grad, double *work)
 {
     const int H = t->H, L = t->L;
@@ -335,7 +350,14 @@ static void mlp_backward(const double *theta, const tape *t, double ub, double u
         txbar[i] = uxb * Wo[i];
         tybar[i] = uyb * Wo[i];
     }
-    gWo[H] += ub;
+    gWo[(size_t)t->heads * H] += ub;
+    if (t->heads == 2) {
+        for (int i = 0; i < H; ++i) {
+            gWo[H + i] += eb * aL[i];
+            abar[i] += eb * Wo[H + i];
+        }
+        gWo[2 * (size_t)H + 1] += eb;
+    }
 
     for (int l = L; l >= 1; --l) {
         const int din = (l == 1) ? 2 : H;
@@ -376,32 +398,34 @@ static void mlp_backward(const double *theta, const tape *t, double ub, double u
     }
 }
 
-/* u, u_x, u_y of the network at n points (for the finite-difference pins) */
-void orc_mlp_eval(int H, int L, const double *theta, int64_t npts, const double *xy,
-                  double *u, double *ux, double *uy)
+/* u, u_x, u_y (and the second output e) of the network at n points (for the pins) */
+void orc_mlp_eval(int H, int L, int heads, const double *theta, int64_t npts, const double *xy,
+                  double *u, double *ux, double *uy, double *e)
 {
     tape t;
-    tape_init(&t, H, L);
+    tape_init(&t, H, L, heads);
     for (int64_t p = 0; p < npts; ++p) {
         mlp_forward(theta, xy[2 * p], xy[2 * p + 1], &t);
         if (u) u[p] = t.u;
         if (ux) ux[p] = t.ux;
         if (uy) uy[p] = t.uy;
+        if (e) e[p] = t.e;
     }
     tape_free(&t);
 }
 
-/* dL/dtheta of L = sum_p (ub[p] u + uxb[p] u_x + uyb[p] u_y) (for adjoint pins) */
-void orc_mlp_vjp(int H, int L, const double *theta, int64_t npts, const double *xy,
-                 const double *ub, const double *uxb, const double *uyb, double *grad)
+/* dL/dtheta of L = sum_p (ub[p] u + uxb[p] u_x + uyb[p] u_y + eb[p] e) (for adjoint pins) */
+void orc_mlp_vjp(int H, int L, int heads, const double *theta, int64_t npts, const double *xy,
+                 const double *ub, const double *uxb, const double *uyb, const double *eb, double *grad)
 {
     tape t;
-    tape_init(&t, H, L);
+    tape_init(&t, H, L, heads);
     double *work = malloc(sizeof(double) * 9 * (size_t)H);
-    memset(grad, 0, sizeof(double) * (size_t)orc_n_params(H, L));
+    memset(grad, 0, sizeof(double) * (size_t)orc_n_params_heads(H, L, heads));
     for (int64_t p = 0; p < npts; ++p) {
         mlp_forward(theta, xy[2 * p], xy[2 * p + 1], &t);
-        mlp_backward(theta, &t, ub ? ub[p] : 0.0, uxb ? uxb[p] : 0.0, uyb ? uyb[p] : 0.0, grad, work);
+        mlp_backward(theta, &t, ub ? ub[p] : 0.0, uxb ? uxb[p] : 0.0, uyb ? uyb[p] : 0.0, eb ? eb[p] : 0.0, grad,
+                     work);
     }
     free(work);
     tape_free(&t);
@@ -412,21 +436,24 @@ void orc_mlp_vjp(int H, int L, const double *theta, int64_t npts, const double *
 /* R[e,k] = eps * sum_q (u_x G_x + u_y G_y)[e,k,q]                            */
 /*        + sum_q (b_x u_x + b_y u_y) M[e,k,q] - F[e,k]                       */
 /* (Algorithm 3; the convection term of the convection-diffusion weak form,   */
-/* Sec. 2.1, when M is given)                                                 */
+/* Sec. 2.1, when M is given).  With epsq (per point) the diffusion          */
+/* coefficient varies in space (Sec. 4.7.2): eps * (...) becomes             */
+/* sum_q epsq[q] (u_x G_x + u_y G_y)[q].                                      */
 /* ------------------------------------------------------------------------- */
 void orc_residual(int64_t n_elem, int nq, int ntest, const double *Gx, const double *Gy,
                   const double *F, const double *ux, const double *uy, double eps,
-                  const double *M, double cbx, double cby, double *R)
+                  const double *M, double cbx, double cby, const double *epsq, double *R)
 {
     for (int64_t e = 0; e < n_elem; ++e) {
         for (int k = 0; k < ntest; ++k) {
             double acc = 0.0, conv = 0.0;
             for (int q = 0; q < nq; ++q) {
                 const int64_t o = (e * ntest + k) * nq + q;
-                acc += ux[e * nq + q] * Gx[o] + uy[e * nq + q] * Gy[o];
+                const double w = epsq ? epsq[e * nq + q] : 1.0;
+                acc += w * (ux[e * nq + q] * Gx[o] + uy[e * nq + q] * Gy[o]);
                 if (M) conv += (cbx * ux[e * nq + q] + cby * uy[e * nq + q]) * M[o];
             }
-            R[e * ntest + k] = eps * acc + conv - F[e * ntest + k];
+            R[e * ntest + k] = (epsq ? 1.0 : eps) * acc + conv - F[e * ntest + k];
         }
     }
 }
@@ -440,14 +467,17 @@ int orc_loss_grad(int64_t n_elem, int nq, int ntest, const double *Gx, const dou
                   const double *F, const double *X, const double *M, double cbx, double cby,
                   int64_t n_bnd, const double *bxy, const double *bg,
                   int64_t n_sen, const double *sxy, const double *su,
-                  int H, int L, const double *theta, double eps, double tau, double gamma,
+                  int H, int L, int heads, const double *theta, double eps, double tau, double gamma,
                   double cv, double *loss, double *grad, double *grad_eps, double *R_out)
 {
-    if (H < 1 || L < 1 || nq < 1 || ntest < 1) return ORC_E_ARG;
-    const int64_t np_ = orc_n_params(H, L);
+    /* heads = 2: the network's second output is the space-dependent diffusion
+     * coefficient e(x, y) (Sec. 4.7.2); the diffusion term becomes
+     * sum_q e(x_q) (u_x G_x + u_y G_y), and eps is not used */
+    if (H < 1 || L < 1 || nq < 1 || ntest < 1 || heads < 1 || heads > 2) return ORC_E_ARG;
+    const int64_t np_ = orc_n_params_heads(H, L, heads);
     if (grad) memset(grad, 0, sizeof(double) * (size_t)np_);
     tape *tp = malloc(sizeof(tape) * (size_t)nq);
-    for (int q = 0; q < nq; ++q) tape_init(&tp[q], H, L);
+    for (int q = 0; q < nq; ++q) tape_init(&tp[q], H, L, heads);
     double *work = malloc(sizeof(double) * 9 * (size_t)H);
     double *A = malloc(sizeof(double) * ntest), *R = malloc(sizeof(double) * ntest);
     double Lv = 0.0, geps = 0.0;
@@ -461,32 +491,38 @@ int orc_loss_grad(int64_t n_elem, int nq, int ntest, const double *Gx, const dou
             double acc = 0.0, conv = 0.0;
             for (int q = 0; q < nq; ++q) {
                 const int64_t o = (e * ntest + k) * nq + q;
-                acc += tp[q].ux * Gx[o] + tp[q].uy * Gy[o];
+                const double w = heads == 2 ? tp[q].e : 1.0;
+                acc += w * (tp[q].ux * Gx[o] + tp[q].uy * Gy[o]);
                 if (M) conv += (cbx * tp[q].ux + cby * tp[q].uy) * M[o];
             }
             A[k] = acc;
-            R[k] = eps * acc + conv - F[e * ntest + k];
+            R[k] = (heads == 2 ? 1.0 : eps) * acc + conv - F[e * ntest + k];
             if (R_out) R_out[e * ntest + k] = R[k];
             le += R[k] * R[k];
         }
         Lv += cv * le;
         if (!grad && !grad_eps) continue;
         /* dL/dR = 2 c_v R ; dL/deps = sum_k dL/dR A ;                         */
-        /* dL/du_x[q] = sum_k dL/dR (eps G_x + b_x M)  (and y likewise)       */
-        for (int k = 0; k < ntest; ++k) geps += 2.0 * cv * R[k] * A[k];
+        /* dL/du_x[q] = sum_k dL/dR (eps G_x + b_x M)  (and y likewise), with  */
+        /* eps -> e(x_q) for two outputs, and then                             */
+        /* dL/de[q] = sum_k dL/dR (u_x G_x + u_y G_y)[q]                        */
+        if (heads == 1)
+            for (int k = 0; k < ntest; ++k) geps += 2.0 * cv * R[k] * A[k];
         if (grad) {
             for (int q = 0; q < nq; ++q) {
-                double bx = 0.0, by = 0.0;
+                const double w = heads == 2 ? tp[q].e : eps;
+                double bx = 0.0, by = 0.0, be = 0.0;
                 for (int k = 0; k < ntest; ++k) {
                     const int64_t o = (e * ntest + k) * nq + q;
-                    bx += 2.0 * cv * R[k] * eps * Gx[o];
-                    by += 2.0 * cv * R[k] * eps * Gy[o];
+                    bx += 2.0 * cv * R[k] * w * Gx[o];
+                    by += 2.0 * cv * R[k] * w * Gy[o];
                     if (M) {
                         bx += 2.0 * cv * R[k] * cbx * M[o];
                         by += 2.0 * cv * R[k] * cby * M[o];
                     }
+                    be += 2.0 * cv * R[k] * (tp[q].ux * Gx[o] + tp[q].uy * Gy[o]);
                 }
-                mlp_backward(theta, &tp[q], 0.0, bx, by, grad, work);
+                mlp_backward(theta, &tp[q], 0.0, bx, by, heads == 2 ? be : 0.0, grad, work);
             }
         }
     }
@@ -497,14 +533,14 @@ int orc_loss_grad(int64_t n_elem, int nq, int ntest, const double *Gx, const dou
         mlp_forward(theta, bxy[2 * b], bxy[2 * b + 1], &tp[0]);
         const double d = tp[0].u - bg[b];
         Lb += d * d / (double)n_bnd;
-        if (grad) mlp_backward(theta, &tp[0], tau * 2.0 * d / (double)n_bnd, 0.0, 0.0, grad, work);
+        if (grad) mlp_backward(theta, &tp[0], tau * 2.0 * d / (double)n_bnd, 0.0, 0.0, 0.0, grad, work);
     }
     /* sensor data term (Section 4.7) */
     for (int64_t s = 0; s < n_sen; ++s) {
         mlp_forward(theta, sxy[2 * s], sxy[2 * s + 1], &tp[0]);
         const double d = tp[0].u - su[s];
         Ls += d * d / (double)n_sen;
-        if (grad) mlp_backward(theta, &tp[0], gamma * 2.0 * d / (double)n_sen, 0.0, 0.0, grad, work);
+        if (grad) mlp_backward(theta, &tp[0], gamma * 2.0 * d / (double)n_sen, 0.0, 0.0, 0.0, grad, work);
     }
     loss[0] = Lv + tau * Lb + gamma * Ls;
     loss[1] = Lv;

@@ -529,3 +529,96 @@ def test_cd_zero_velocity_is_poisson(oracle):
     b = oracle.loss_grad(asm, theta, 5, 2, eps=0.9)
     np.testing.assert_array_equal(a.loss, b.loss)
     np.testing.assert_array_equal(a.grad, b.grad)
+
+
+# ----------------------------------------------------------------------------- space-dependent diffusion
+
+@pytest.mark.parametrize("n,exact", [(10, True), (4, False)])
+def test_vardiff_manufactured_residual_vanishes(oracle, n, exact):
+    """-div(eps grad u) + b . grad u = f with u = x^3 + x y^2 + 2y and eps = 1 + 0.3x - 0.2y:
+    f = -(eps Lap u + eps_x u_x + eps_y u_y) + b . grad u; with the exact u, eps at the quadrature points
+    the weak residual sum_q eps_q grad u . G + (b . grad u) M - F vanishes under exact quadrature."""
+    bx, by = 0.6, 0.4
+    ex_, ey_ = 0.3, -0.2
+
+    def f(x, y):
+        e = 1.0 + ex_ * x + ey_ * y
+        ux, uy = 3 * x * x + y * y, 2 * x * y + 2.0
+        return -(e * 8.0 * x + ex_ * ux + ey_ * uy) + bx * ux + by * uy
+
+    mesh = _skewed_mesh(3, seed=13)
+    asm = oracle.assemble(mesh.xy, mesh.quad, n, 4, f_callable=f, want_M=True)
+    X = asm.X
+    ux = 3 * X[..., 0] ** 2 + X[..., 1] ** 2
+    uy = 2 * X[..., 0] * X[..., 1] + 2.0
+    epsq = 1.0 + ex_ * X[..., 0] + ey_ * X[..., 1]
+    R = oracle.residual(asm, ux, uy, conv=(bx, by), epsq=epsq)
+    scale = np.abs(asm.F).max() + np.abs(asm.Gx).max()
+    if exact:
+        assert np.abs(R).max() < 1e-12 * scale
+    else:
+        assert np.abs(R).max() > 1e-8 * scale
+    # a constant coefficient in place of the field leaves a clear residual
+    assert np.abs(oracle.residual(asm, ux, uy, eps=1.0, conv=(bx, by))).max() > 1e-3 * scale
+
+
+def test_second_head_equal_weights_reproduces_u(oracle):
+    """With W_out[1] = W_out[0] and b_out[1] = b_out[0] the second output equals u."""
+    H, L = 7, 2
+    theta = gen.glorot_params(H, L, seed=4, bias_scale=0.3, heads=2)
+    o = gen.n_params(H, L) - (H + 1)  # start of the output block
+    theta[o + H:o + 2 * H] = theta[o:o + H]
+    theta[o + 2 * H + 1] = theta[o + 2 * H]
+    xy = gen.uniform(2, "pts", 40, -1, 1).reshape(-1, 2)
+    u, ux, uy, e = oracle.mlp_eval(theta, H, L, xy, heads=2)
+    np.testing.assert_array_equal(u, e)
+
+
+def test_constant_second_head_is_constant_coefficient_cd(oracle):
+    """A second head with zero weights and bias c gives eps(x) = c everywhere: the loss and the gradient of
+    the first-head parameters equal the constant-coefficient convection-diffusion loss with eps = c."""
+    H, L, c = 6, 2, 0.7
+    mesh = _skewed_mesh(2, seed=14)
+    asm = oracle.assemble(mesh.xy, mesh.quad, 5, 3, f_callable=gen.gear_forcing, want_M=True)
+    t2 = gen.glorot_params(H, L, seed=6, bias_scale=0.3, heads=2)
+    o = gen.n_params(H, L) - (H + 1)
+    t2[o + H:o + 2 * H] = 0.0
+    t2[o + 2 * H + 1] = c
+    t1 = np.concatenate([t2[:o + H], t2[o + 2 * H:o + 2 * H + 1]])
+    bxy = gen.square_boundary_points(8)
+    kw = dict(bnd_xy=bxy, bnd_g=np.zeros(8), tau=2.0, conv=(0.9, -0.3))
+    r2 = oracle.loss_grad(asm, t2, H, L, heads=2, **kw)
+    r1 = oracle.loss_grad(asm, t1, H, L, eps=c, **kw)
+    np.testing.assert_allclose(r2.loss, r1.loss, rtol=1e-12)
+    np.testing.assert_allclose(r2.grad[:o + H], r1.grad[:o + H], rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(r2.grad[o + 2 * H], r1.grad[o + H], rtol=1e-10)
+
+
+def test_vardiff_gradient_matches_finite_differences(oracle):
+    H, L = 4, 2
+    mesh = gen.disk_mesh(3)
+    asm = oracle.assemble(mesh.xy, mesh.quad, 4, 3, f_callable=lambda x, y: 10.0, want_M=True)
+    theta = gen.glorot_params(H, L, seed=12, bias_scale=0.4, heads=2)
+    bxy = gen.circle_points(8)
+    sxy = gen.disk_sensor_points(5, 1)
+    kw = dict(bnd_xy=bxy, bnd_g=np.zeros(8), sens_xy=sxy, sens_u=gen.uniform(1, "s", 5, -1, 1), tau=2.0,
+              gamma=3.0, conv=(1.0, 0.0), heads=2)
+    r = oracle.loss_grad(asm, theta, H, L, **kw)
+
+    def f(th):
+        return oracle.loss_grad(asm, th, H, L, want_grad=False, **kw).loss[0]
+
+    h = 1e-6
+    fd = np.array([(f(theta + h * e) - f(theta - h * e)) / (2 * h) for e in np.eye(theta.size)])
+    assert np.linalg.norm(r.grad - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_disk_mesh_is_valid_and_has_disk_area(oracle):
+    """Every element of the disk mesh is convex and counter-clockwise (the oracle's assembly rejects det J <= 0),
+    and the elements' areas add up to just under pi r^2 (the mesh is inscribed in the circle)."""
+    mesh = gen.disk_mesh(32)
+    oracle.assemble(mesh.xy, mesh.quad, 3, 1, 1.0, 1.0, 1.0)
+    x, y = mesh.xy[mesh.quad][..., 0], mesh.xy[mesh.quad][..., 1]
+    shoelace = 0.5 * np.sum(x * np.roll(y, -1, 1) - y * np.roll(x, -1, 1), axis=1)
+    assert (shoelace > 0).all()
+    assert 0.0 < math.pi * 0.25 - shoelace.sum() < 2e-3

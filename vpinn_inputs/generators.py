@@ -201,6 +201,30 @@ def annulus_boundary_points(n_d: int, r_in=0.5, teeth=24, amp=0.05) -> np.ndarra
     return np.concatenate([inner, outer], 0)
 
 
+def disk_mesh(m: int, cx: float = 0.5, cy: float = 0.5, radius: float = 0.5) -> Mesh:
+    """m-by-m quads of a disk: the structured grid of [-1,1]^2 pushed onto the unit disk by the smooth map
+    (u, v) -> (u sqrt(1 - v^2/2), v sqrt(1 - u^2/2)), then scaled and shifted.  The map preserves orientation
+    and keeps every element convex and counter-clockwise for the sizes used here."""
+    sq = square_mesh(m, m, 0.0, 0, -1.0, 1.0, -1.0, 1.0)
+    u, v = sq.xy[:, 0], sq.xy[:, 1]
+    x = u * np.sqrt(1.0 - 0.5 * v * v)
+    y = v * np.sqrt(1.0 - 0.5 * u * u)
+    xy = np.stack([cx + radius * x, cy + radius * y], 1)
+    return Mesh(xy=xy, quad=sq.quad, name=f"disk{m}")
+
+
+def circle_points(n: int, cx: float = 0.5, cy: float = 0.5, radius: float = 0.5) -> np.ndarray:
+    t = 2.0 * math.pi * (np.arange(n) + 0.5) / n
+    return np.stack([cx + radius * np.cos(t), cy + radius * np.sin(t)], 1)
+
+
+def disk_sensor_points(n_s: int, seed: int, cx: float = 0.5, cy: float = 0.5, radius: float = 0.5) -> np.ndarray:
+    """Uniform in the disk: radius sqrt(U) r, angle 2 pi U (two named substreams)."""
+    r = radius * np.sqrt(uniform(seed, "dsensors/r", n_s, 0.0, 1.0))
+    t = uniform(seed, "dsensors/t", n_s, 0.0, 2.0 * math.pi)
+    return np.stack([cx + r * np.cos(t), cy + r * np.sin(t)], 1)
+
+
 def sensor_points(n_s: int, seed: int, x0=0.0, x1=1.0, y0=0.0, y1=1.0) -> np.ndarray:
     return np.stack([uniform(seed, "sensors/x", n_s, x0, x1),
                      uniform(seed, "sensors/y", n_s, y0, y1)], 1)
@@ -212,15 +236,16 @@ def sensor_points(n_s: int, seed: int, x0=0.0, x1=1.0, y0=0.0, y1=1.0) -> np.nda
 # oracle and the FP32 kernels see bit-identical parameters.
 # ----------------------------------------------------------------------------
 
-def n_params(width: int, n_hidden: int) -> int:
-    return width * 2 + width + (n_hidden - 1) * (width * width + width) + width + 1
+def n_params(width: int, n_hidden: int, heads: int = 1) -> int:
+    """heads = 2: the output layer is W_out[2][H], b_out[2] (the second output is a diffusion field)."""
+    return width * 2 + width + (n_hidden - 1) * (width * width + width) + heads * (width + 1)
 
 
 def glorot_params(width: int, n_hidden: int, seed: int, bias_scale: float = 0.0,
-                  name: str = "params") -> np.ndarray:
+                  name: str = "params", heads: int = 1) -> np.ndarray:
     """Glorot-uniform weights U(+-sqrt(6/(fan_in+fan_out))); biases U(+-bias_scale) (zero by default)."""
     parts = []
-    shapes = [(width, 2)] + [(width, width)] * (n_hidden - 1) + [(1, width)]
+    shapes = [(width, 2)] + [(width, width)] * (n_hidden - 1) + [(heads, width)]
     for li, (fo, fi) in enumerate(shapes):
         bound = math.sqrt(6.0 / (fi + fo))
         w = uniform(seed, f"{name}/W{li}", fo * fi, -bound, bound)
@@ -231,7 +256,7 @@ def glorot_params(width: int, n_hidden: int, seed: int, bias_scale: float = 0.0,
         else:
             parts.append(np.zeros(nb))
     theta = np.concatenate(parts)
-    assert theta.size == n_params(width, n_hidden)
+    assert theta.size == n_params(width, n_hidden, heads)
     return theta.astype(np.float32).astype(np.float64)
 
 
@@ -263,6 +288,8 @@ class Problem:
     diff: float = 1.0
     conv: Tuple[float, float] = (0.0, 0.0)
     f_fn: Optional[Callable[[float, float], float]] = None  # forcing as a function of (x, y), else sin-sin
+    # heads = 2: the network also outputs the diffusion coefficient eps(x, y) (space-dependent inverse problem)
+    heads: int = 1
 
     @property
     def n_elem(self) -> int:
@@ -274,7 +301,7 @@ class Problem:
 
     def params(self, seed: Optional[int] = None, bias_scale: float = 0.0) -> np.ndarray:
         s = self.seed if seed is None else seed
-        return glorot_params(self.width, self.n_hidden, s, bias_scale, name=f"params/{self.name}")
+        return glorot_params(self.width, self.n_hidden, s, bias_scale, name=f"params/{self.name}", heads=self.heads)
 
 
 def poisson_sinsin_square(name: str, m: int, n: int, nt: int, k: int, n_d: int,
@@ -336,6 +363,41 @@ def config_gear_cd(seed: int = 0) -> Problem:
                    bnd_xy=bxy, bnd_g=np.zeros(len(bxy)), seed=seed, diff=1.0, conv=(0.1, 0.0), f_fn=gear_forcing)
 
 
+class VarDiffManufactured:
+    """Manufactured data of -div(eps grad u) + b . grad u = f with eps(x, y) = 0.5 (sin x + cos y) (the
+    coefficient field of the paper's space-dependent inverse problem), b = (1, 0) and
+    u = sin(k x) sin(k y): f = -(eps Lap u + eps_x u_x + eps_y u_y) + b . grad u."""
+
+    def __init__(self, k: float = 2.0 * math.pi, b=(1.0, 0.0)):
+        self.k, self.b = k, b
+
+    def u(self, x, y):
+        return np.sin(self.k * x) * np.sin(self.k * y)
+
+    def eps(self, x, y):
+        return 0.5 * (np.sin(x) + np.cos(y))
+
+    def f(self, x: float, y: float) -> float:
+        k = self.k
+        u = math.sin(k * x) * math.sin(k * y)
+        ux, uy = k * math.cos(k * x) * math.sin(k * y), k * math.sin(k * x) * math.cos(k * y)
+        e, ex, ey = 0.5 * (math.sin(x) + math.cos(y)), 0.5 * math.cos(x), -0.5 * math.sin(y)
+        return -(e * (-2.0 * k * k * u) + ex * ux + ey * uy) + self.b[0] * ux + self.b[1] * uy
+
+
+def config_disk_vareps(seed: int = 0, m: int = 32) -> Problem:
+    """Space-dependent diffusion inverse problem on a disk (centre (0.5, 0.5), radius 0.5) of m x m = 1,024
+    quads: the network outputs u and eps(x, y); 10x10 GLL, 5x5 tests, b = (1, 0), manufactured u and eps,
+    1,600 boundary points and 1,000 sensors of u, tau = gamma = 10."""
+    man = VarDiffManufactured()
+    mesh = disk_mesh(m)
+    bxy = circle_points(1600)
+    sxy = disk_sensor_points(1000, seed)
+    return Problem(name="disk_vareps", mesh=mesh, quad_order=10, test_order=5, f_amp=0.0, f_kx=0.0, f_ky=0.0,
+                   bnd_xy=bxy, bnd_g=man.u(bxy[:, 0], bxy[:, 1]), sens_xy=sxy, sens_u=man.u(sxy[:, 0], sxy[:, 1]),
+                   tau=10.0, gamma=10.0, seed=seed, conv=(1.0, 0.0), f_fn=man.f, heads=2)
+
+
 def config_probe(seed: int = 0) -> Problem:
     """The C4 mesh with 20x20 test functions (the paper's largest p-refinement): G-stream dominated."""
     p = poisson_sinsin_square("probe", 64, 10, 20, 2, 1600, 0.2, seed)
@@ -368,4 +430,4 @@ def batched_instances(n_inst: int = 64, seed: int = 0, lo: int = 256, hi: int = 
 
 
 CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4, "probe": config_probe,
-           "gear_cd": config_gear_cd}
+           "gear_cd": config_gear_cd, "disk_vareps": config_disk_vareps}
