@@ -27,6 +27,10 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 (vector and matrix) peak
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 
+def n_outputs(prob) -> int:
+    return getattr(prob, "heads", 1)
+
+
 def kernel_work(prob):
     """Algorithmic work of each fused-path kernel for one epoch (dense products as 2 x multiply-adds).
 
@@ -34,15 +38,21 @@ def kernel_work(prob):
     k_contract: 4 N_test MACs a point (contraction and its adjoint); bytes: G_x, G_y once (8 N_test a point),
     F (4 N_test an element), (u_x, u_y) in and (dL/du_x, dL/du_y) out (16 a point);
     k_bwd: reverse sweep, interior 2H + 6(L-1)H^2 + 4H MACs a point, boundary/sensor 3H + 2(L-1)H^2.
+    A second network output (space-dependent diffusion e): k_fwd + H MACs an interior point; k_contract
+    7 N_test MACs a point (terms e (u_x G_x + u_y G_y) + (b . grad u) M, adjoint sums of G_x, G_y, M) and
+    M read once (12 N_test bytes a point) plus e in and dL/de out (8 a point); k_bwd + 2H MACs.
     """
     H, L = prob.width, prob.n_hidden
     nt = prob.test_order ** 2
     n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
+    two = n_outputs(prob) == 2
     return {
-        "k_fwd": {"flop": 2.0 * (prob.n_points * (2 * H + 3 * (L - 1) * H * H + 2 * H) + n_extra * (3 * H + (L - 1) * H * H))},
-        "k_contract": {"flop": 2.0 * prob.n_points * 4 * nt,
-                       "bytes": 8.0 * nt * prob.n_points + 4.0 * nt * prob.n_elem + 16.0 * prob.n_points},
-        "k_bwd": {"flop": 2.0 * (prob.n_points * (2 * H + 6 * (L - 1) * H * H + 4 * H)
+        "k_fwd": {"flop": 2.0 * (prob.n_points * (2 * H + 3 * (L - 1) * H * H + 2 * H + (H if two else 0))
+                                 + n_extra * (3 * H + (L - 1) * H * H))},
+        "k_contract": {"flop": 2.0 * prob.n_points * (7 if two else 4) * nt,
+                       "bytes": (12.0 if two else 8.0) * nt * prob.n_points + 4.0 * nt * prob.n_elem
+                       + (24.0 if two else 16.0) * prob.n_points},
+        "k_bwd": {"flop": 2.0 * (prob.n_points * (2 * H + 6 * (L - 1) * H * H + 4 * H + (2 * H if two else 0))
                                  + n_extra * (3 * H + 2 * (L - 1) * H * H))},
     }
 
@@ -56,6 +66,8 @@ def flops_per_epoch(prob) -> float:
     H, L = prob.width, prob.n_hidden
     nt = prob.test_order ** 2
     mac_int = (2 * H + 3 * (L - 1) * H * H + 2 * H) + (2 * H + 6 * (L - 1) * H * H + 4 * H) + 4 * nt
+    if n_outputs(prob) == 2:
+        mac_int += 3 * H + 3 * nt  # the second output, its adjoint, and the larger contraction
     mac_bnd = (3 * H + (L - 1) * H * H) + (3 * H + 2 * (L - 1) * H * H)
     n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
     return 2.0 * (prob.n_points * mac_int + n_extra * mac_bnd)
@@ -65,7 +77,8 @@ def bytes_per_epoch(prob) -> float:
     """Algorithmic HBM bytes: G_x and G_y once, F, quadrature and boundary points, parameters."""
     nt = prob.test_order ** 2
     n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
-    return (8.0 * nt * prob.n_points + 4.0 * nt * prob.n_elem + 8.0 * prob.n_points + 12.0 * n_extra)
+    g = 12.0 if n_outputs(prob) == 2 else 8.0  # G_x, G_y (and M)
+    return (g * nt * prob.n_points + 4.0 * nt * prob.n_elem + 8.0 * prob.n_points + 12.0 * n_extra)
 
 
 def source_digest() -> str:
@@ -148,13 +161,14 @@ def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
     """Eager steps: vpinn_loss_and_grad then vpinn_adam_step.  On the fused path the library records
     events between its kernels, which gives the per-kernel durations of every timed step."""
     dev = torch.device("cuda:0")
-    n = V.vpinn_n_params(prob.width, prob.n_hidden)
+    n = V.vpinn_n_params_out(prob.width, prob.n_hidden, n_outputs(prob))
     th = torch.tensor(theta, dtype=torch.float32, device=dev)
     m = torch.zeros(n, dtype=torch.float32, device=dev)
     v = torch.zeros(n, dtype=torch.float32, device=dev)
     g = torch.zeros(n, dtype=torch.float32, device=dev)
     loss = torch.zeros(4, dtype=torch.float32, device=dev)
-    cfg = V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma, V.VPINN_NORM_TEST, path)
+    cfg = V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma, V.VPINN_NORM_TEST, path,
+                     n_outputs=n_outputs(prob))
     stream = torch.cuda.current_stream()
     fused = path == V.VPINN_PATH_FUSED
     t = 0
@@ -230,7 +244,8 @@ def time_graph(V, torch, p, prob, theta, steps: int, warmup: int, fixed_tuning=N
     Throughput: `steps` replays back to back, bracketed by synchronisations (host wall clock) and by one
     pair of events; the per-step distribution comes from a separate run with an event pair per step."""
     dev = torch.device("cuda:0")
-    b = V.vpinn_batch_create([p], V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma))
+    b = V.vpinn_batch_create([p], V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma,
+                                             n_outputs=n_outputs(prob)))
     th = torch.tensor(theta, dtype=torch.float32, device=dev).reshape(1, -1).contiguous()
     m = torch.zeros_like(th)
     v = torch.zeros_like(th)
@@ -410,10 +425,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
-    ap.add_argument("--workload", choices=["c2", "c5", "probe", "gear_cd"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c5", "probe", "gear_cd", "disk_vareps"], default="c2",
                     help="c2 (default, the headline): one 1,024-element problem; c5: 64-instance batch; probe: "
                          "20x20 test functions on 4,096 elements (G-stream bound); gear_cd: the convection-diffusion "
-                         "gear problem on 14,000 elements")
+                         "gear problem on 14,000 elements; disk_vareps: space-dependent diffusion inverse problem, "
+                         "a two-output network on a 1,024-element disk")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times: a kernel of known traffic that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -463,6 +479,10 @@ WORKLOAD_TEXT = {
                "(the paper's gear experiment) on a toothed-annulus O-grid of 400x35 = 14,000 skewed quads (24 teeth, "
                "amplitude 0.05), 5x5 GLL points, 4x4 test functions, 6096 boundary points, MLP 2-30-30-30-1 tanh; "
                "eps and b folded into G at assembly",
+    "disk_vareps": "disk_vareps: inverse problem -div(eps(x,y) grad u) + (1, 0) . grad u = f on the disk of centre "
+                   "(0.5, 0.5) and radius 0.5 (32x32 quads of a squircle-mapped grid), eps = 0.5 (sin x + cos y) and "
+                   "u = sin(2pi x) sin(2pi y) manufactured, 10x10 GLL points, 5x5 test functions, 1600 boundary "
+                   "points, 1000 sensors of u, tau = gamma = 10, MLP 2-30-30-30-2 tanh whose second output is eps",
     "probe": "probe: the c4 mesh (64x64 jittered, 4096 elements) with 10x10 GLL points and 20x20 test functions "
              "(the paper's largest p-refinement), u*=sin(2pi x)sin(2pi y), 1600 boundary points, MLP "
              "2-30-30-30-1 tanh: the only shape whose G stream (1.3 GB) outweighs the network arithmetic",
@@ -492,7 +512,7 @@ def bench_single(args, V, torch, gen):
     else:
         res = {"wall_s": eager["wall_s"] * args.steps / eager_steps}
     plain = None
-    if not args.no_plain and fused:
+    if not args.no_plain and fused and n_outputs(prob) == 1:
         plain = time_path(V, torch, p, prob, theta, V.VPINN_PATH_PLAIN, min(args.steps, 300), 20)
         print(f"[bench] plain eager: {plain['wall_s'] / min(args.steps, 300) * 1e3:.4f} ms/step", file=sys.stderr,
               flush=True)
@@ -501,7 +521,8 @@ def bench_single(args, V, torch, gen):
     dev = torch.device("cuda:0")
     loss0 = torch.zeros(4, dtype=torch.float32, device=dev)
     if not args.profile_run:
-        V.vpinn_loss_and_grad(p, V.loss_cfg(prob.width, prob.n_hidden, prob.tau, 0.0, 0, main_path),
+        V.vpinn_loss_and_grad(p, V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma, 0, main_path,
+                                            n_outputs=n_outputs(prob)),
                               torch.tensor(theta, dtype=torch.float32, device=dev), loss=loss0)
         torch.cuda.synchronize()
     gpu_loss0 = float(loss0[0].item())

@@ -25,6 +25,9 @@
  *  - Network parameters use one flat float32 layout (width H, L hidden layers):
  *      W1[H][2], b1[H], then for l = 2..L: W_l[H][H], b_l[H], then
  *      W_out[H], b_out                       (vpinn_n_params(H, L) floats)
+ *    or, for a network with a second output (the space-dependent diffusion
+ *    coefficient of Sec. 4.7.2), W_out[2][H], b_out[2] at the end
+ *    (vpinn_n_params_out(H, L, 2) floats).
  *    all matrices row-major with the output neuron as the row index.
  *  - Distinct problem objects may be used from different threads; one object
  *    must not be used by two calls at once.
@@ -121,6 +124,23 @@ vpinn_status vpinn_assemble_cd2d(const vpinn_mesh *mesh, int32_t quad_order, int
                                  vpinn_problem **out);
 
 /*
+ * vpinn_assemble_vardiff -- the space-dependent diffusion operator
+ * -div(eps(x, y) grad u) + b . grad u = f of the inverse problem of Sec. 4.7.2,
+ * where eps(x, y) is the network's second output.  The cell residual is
+ *   R[e,k] = sum_q eps(x_q) (u_x G_x + u_y G_y)[e,k,q]
+ *          + sum_q (bx u_x + by u_y)(x_q) M[e,k,q] - F[e,k],
+ * with G_x, G_y the plain diffusion weights (as vpinn_assemble) and
+ * M[e,k,q] = w_q det J v_k(x_q) stored as a third tensor (eps varies per point,
+ * so nothing can be folded).  Loss calls on such a problem need
+ * cfg->n_outputs = 2, the fused path, N_quad <= 256 and N_test <= 32, and take no
+ * d_eps / d_grad_eps; everything else returns VPINN_E_UNSUPPORTED or
+ * VPINN_E_INVALID.  Errors: as vpinn_assemble, plus VPINN_E_INVALID for a
+ * non-finite b.
+ */
+vpinn_status vpinn_assemble_vardiff(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double bx,
+                                    double by, const vpinn_forcing *forcing, void *stream, vpinn_problem **out);
+
+/*
  * Dirichlet points x_b and values g_b of the boundary term (Sec. 2.2), and
  * sensor points x_s with observations d_s of the data term of the inverse
  * problem (Sec. 4.7).  Host arrays xy [n][2] and values [n] are copied to the
@@ -138,6 +158,8 @@ typedef struct vpinn_problem_info {
     double diffusion, velocity_x, velocity_y; /* folded operator coefficients (1, 0, 0: Poisson) */
     int32_t shared_premultiplier;    /* 1: all elements are translates of one shape, and G_x, G_y are
                                         stored once (Algorithm 2's reference premultiplier) */
+    int32_t variable_diffusion;      /* 1: from vpinn_assemble_vardiff (diffusion = 0: it is the
+                                        network's second output) */
 } vpinn_problem_info;
 
 vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info);
@@ -148,6 +170,7 @@ vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info);
 #define VPINN_TENSOR_GY 1
 #define VPINN_TENSOR_F 2
 #define VPINN_TENSOR_X 3
+#define VPINN_TENSOR_M 4 /* w_q det J v_k, problems from vpinn_assemble_vardiff only */
 vpinn_status vpinn_read_tensor(const vpinn_problem *p, int32_t which, float *host_dst, int64_t count);
 
 /* ------------------------------------------------------------------------ */
@@ -165,9 +188,13 @@ typedef struct vpinn_loss_cfg {
     float gamma;       /* sensor weight */
     int32_t loss_norm; /* VPINN_NORM_TEST or VPINN_NORM_ELEM */
     int32_t path;      /* VPINN_PATH_FUSED or VPINN_PATH_PLAIN */
+    int32_t n_outputs; /* 0 or 1: u only; 2: u and eps(x, y), for problems from vpinn_assemble_vardiff
+                          (fused path only) */
 } vpinn_loss_cfg;
 
 int64_t vpinn_n_params(int32_t width, int32_t n_hidden);
+/* parameters of a network with n_outputs (1 or 2) linear outputs; -1 if out of range */
+int64_t vpinn_n_params_out(int32_t width, int32_t n_hidden, int32_t n_outputs);
 
 /*
  * vpinn_loss_and_grad -- one forward + adjoint evaluation.
@@ -201,6 +228,18 @@ vpinn_status vpinn_residual(vpinn_problem *p, const vpinn_loss_cfg *cfg, const f
  */
 vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_params, int64_t n,
                                 const float *d_xy, float *d_u, float *d_ux, float *d_uy, void *stream);
+
+/*
+ * vpinn_eval_network_heads -- as vpinn_eval_network for a network with n_outputs
+ * (1 or 2) linear outputs on shared hidden layers (parameters laid out as
+ * vpinn_n_params_out); with two, d_e [n] receives the second output, the
+ * predicted diffusion coefficient eps(x, y) of the inverse problem of Sec. 4.7.2.
+ * Any output pointer may be NULL.  Errors: VPINN_E_INVALID (n_outputs not 1 or 2,
+ * d_e with one output, null params, n < 0), VPINN_E_UNSUPPORTED (shape).
+ */
+vpinn_status vpinn_eval_network_heads(int32_t width, int32_t n_hidden, int32_t n_outputs, const float *d_params,
+                                      int64_t n, const float *d_xy, float *d_u, float *d_ux, float *d_uy,
+                                      float *d_e, void *stream);
 
 /*
  * vpinn_adam_step -- Kingma-Ba Adam (Algorithm 1 of that paper, the optimiser of

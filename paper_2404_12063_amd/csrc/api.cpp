@@ -154,11 +154,17 @@ int64_t vpinn_n_params(int32_t width, int32_t n_hidden) {
     return (int64_t)width * 2 + width + (int64_t)(n_hidden - 1) * ((int64_t)width * width + width) + width + 1;
 }
 
+int64_t vpinn_n_params_out(int32_t width, int32_t n_hidden, int32_t n_outputs) {
+    if (n_outputs < 1 || n_outputs > 2) return -1;
+    const int64_t n1 = vpinn_n_params(width, n_hidden);
+    return n1 < 0 ? -1 : n1 + (int64_t)(n_outputs - 1) * (width + 1);
+}
+
 const char *vpinn_last_error(void) { return vp::g_err.c_str(); }
 
 static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double diff,
-                                      double conv_x, double conv_y, const vpinn_forcing *forcing, void *stream,
-                                      vpinn_problem **out) {
+                                      double conv_x, double conv_y, bool vardiff, const vpinn_forcing *forcing,
+                                      void *stream, vpinn_problem **out) {
     using namespace vp;
     if (!out) return fail(VPINN_E_INVALID, "out is null");
     *out = nullptr;
@@ -196,15 +202,23 @@ static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order
     p->nq = (int)nq;
     p->ntest = (int)ntest;
     p->n_pts = n_elem * nq;
-    p->diff = diff;
-    p->conv_x = conv_x;
-    p->conv_y = conv_y;
-    p->shared_g = congruent_elements(mesh);
+    if (vardiff) {
+        // nothing folded: G stays the diffusion weights and M is kept for the convection term
+        p->vardiff = true;
+        p->vd_bx = conv_x;
+        p->vd_by = conv_y;
+    } else {
+        p->diff = diff;
+        p->conv_x = conv_x;
+        p->conv_y = conv_y;
+    }
+    p->shared_g = !vardiff && congruent_elements(mesh);
     hipStream_t s = (hipStream_t)stream;
     const size_t gbytes = sizeof(float) * (size_t)((p->shared_g ? 1 : n_elem) * ntest * nq);
     if (p->Gx.reserve(gbytes) != hipSuccess || p->Gy.reserve(gbytes) != hipSuccess ||
         p->F.reserve(sizeof(float) * n_elem * ntest) != hipSuccess ||
-        p->pts.reserve(sizeof(float2) * p->n_pts) != hipSuccess)
+        p->pts.reserve(sizeof(float2) * p->n_pts) != hipSuccess ||
+        (vardiff && p->M.reserve(sizeof(float) * (size_t)(n_elem * ntest * nq)) != hipSuccess))
         return bail(fail(VPINN_E_NOMEM, "device allocation of the assembled tensors failed"));
     DevBuf d_nodes, d_quad;
     if (d_nodes.reserve(sizeof(double) * 2 * mesh->n_nodes) != hipSuccess ||
@@ -221,13 +235,18 @@ static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order
 
 vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order,
                             const vpinn_forcing *forcing, void *stream, vpinn_problem **out) {
-    return assemble_operator(mesh, quad_order, test_order, 1.0, 0.0, 0.0, forcing, stream, out);
+    return assemble_operator(mesh, quad_order, test_order, 1.0, 0.0, 0.0, false, forcing, stream, out);
+}
+
+vpinn_status vpinn_assemble_vardiff(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double bx,
+                                    double by, const vpinn_forcing *forcing, void *stream, vpinn_problem **out) {
+    return assemble_operator(mesh, quad_order, test_order, 1.0, bx, by, true, forcing, stream, out);
 }
 
 vpinn_status vpinn_assemble_cd2d(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double eps,
                                  double bx, double by, const vpinn_forcing *forcing, void *stream,
                                  vpinn_problem **out) {
-    return assemble_operator(mesh, quad_order, test_order, eps, bx, by, forcing, stream, out);
+    return assemble_operator(mesh, quad_order, test_order, eps, bx, by, false, forcing, stream, out);
 }
 
 vpinn_status vpinn_set_boundary(vpinn_problem *pp, int64_t n, const double *xy, const double *g) {
@@ -273,10 +292,11 @@ vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info) {
     info->n_sensors = p->n_sen;
     info->quad_order = p->n;
     info->test_order = p->nt;
-    info->diffusion = p->diff;
-    info->velocity_x = p->conv_x;
-    info->velocity_y = p->conv_y;
+    info->diffusion = p->vardiff ? 0.0 : p->diff;
+    info->velocity_x = p->vardiff ? p->vd_bx : p->conv_x;
+    info->velocity_y = p->vardiff ? p->vd_by : p->conv_y;
     info->shared_premultiplier = p->shared_g ? 1 : 0;
+    info->variable_diffusion = p->vardiff ? 1 : 0;
     return VPINN_OK;
 }
 
@@ -290,6 +310,11 @@ vpinn_status vpinn_read_tensor(const vpinn_problem *p, int32_t which, float *hos
     case VPINN_TENSOR_GY: src = p->Gy.ptr; want = p->n_elem * p->ntest * p->nq; break;
     case VPINN_TENSOR_F: src = p->F.ptr; want = p->n_elem * p->ntest; break;
     case VPINN_TENSOR_X: src = p->pts.ptr; want = 2 * p->n_pts; break;
+    case VPINN_TENSOR_M:
+        if (!p->vardiff) return fail(VPINN_E_INVALID, "M is kept only for problems from vpinn_assemble_vardiff");
+        src = p->M.ptr;
+        want = p->n_elem * p->ntest * p->nq;
+        break;
     default: return fail(VPINN_E_INVALID, "unknown tensor id");
     }
     if (count != want) return fail(VPINN_E_INVALID, "count must be " + std::to_string(want));
@@ -318,6 +343,22 @@ static vpinn_status check_cfg(const vpinn_loss_cfg *cfg) {
     if (cfg->path != VPINN_PATH_FUSED && cfg->path != VPINN_PATH_PLAIN) return fail(VPINN_E_INVALID, "unknown path");
     if (!std::isfinite(cfg->tau) || !std::isfinite(cfg->gamma) || cfg->tau < 0 || cfg->gamma < 0)
         return fail(VPINN_E_INVALID, "tau and gamma must be finite and >= 0");
+    if (cfg->n_outputs < 0 || cfg->n_outputs > 2) return fail(VPINN_E_INVALID, "n_outputs must be 0, 1 or 2");
+    return VPINN_OK;
+}
+
+// the network's outputs must match the operator: two (u, eps) for space-dependent
+// diffusion, on the fused path, with a trainable scalar eps excluded
+static vpinn_status check_outputs(const vpinn_problem *p, const vpinn_loss_cfg *cfg, bool scalar_eps) {
+    using namespace vp;
+    const bool two = cfg->n_outputs == 2;
+    if (two != p->vardiff)
+        return fail(VPINN_E_INVALID, p->vardiff ? "a space-dependent diffusion problem needs cfg->n_outputs = 2"
+                                                : "cfg->n_outputs = 2 needs a problem from vpinn_assemble_vardiff");
+    if (two && cfg->path != VPINN_PATH_FUSED)
+        return fail(VPINN_E_UNSUPPORTED, "space-dependent diffusion runs on the fused path only");
+    if (two && scalar_eps)
+        return fail(VPINN_E_INVALID, "a space-dependent diffusion problem takes no scalar eps");
     return VPINN_OK;
 }
 
@@ -329,6 +370,8 @@ vpinn_status vpinn_loss_and_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, co
     if ((d_eps || d_grad_eps) && p->folded())
         return fail(VPINN_E_INVALID, "a problem assembled with fixed convection-diffusion coefficients takes no eps");
     vpinn_status st = check_cfg(cfg);
+    if (st) return st;
+    st = check_outputs(p, cfg, d_eps || d_grad_eps);
     if (st) return st;
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
@@ -346,17 +389,24 @@ vpinn_status vpinn_residual(vpinn_problem *p, const vpinn_loss_cfg *cfg, const f
         return fail(VPINN_E_INVALID, "a problem assembled with fixed convection-diffusion coefficients takes no eps");
     vpinn_status st = check_cfg(cfg);
     if (st) return st;
+    if (p->vardiff || cfg->n_outputs == 2)
+        return fail(VPINN_E_UNSUPPORTED, "vpinn_residual (plain path) has no space-dependent diffusion");
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
     return plain_loss_grad(p, cfg, d_params, d_eps, nullptr, nullptr, nullptr, d_R, (hipStream_t)stream);
 }
 
-vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_params, int64_t n, const float *d_xy,
-                                float *d_u, float *d_ux, float *d_uy, void *stream) {
+vpinn_status vpinn_eval_network_heads(int32_t width, int32_t n_hidden, int32_t n_outputs, const float *d_params,
+                                      int64_t n, const float *d_xy, float *d_u, float *d_ux, float *d_uy, float *d_e,
+                                      void *stream) {
     using namespace vp;
     if (width < 1 || width > VPINN_MAX_WIDTH || n_hidden < 1 || n_hidden > VPINN_MAX_HIDDEN)
         return fail(VPINN_E_UNSUPPORTED, "width or n_hidden out of range");
+    if (n_outputs < 1 || n_outputs > 2) return fail(VPINN_E_INVALID, "n_outputs must be 1 or 2");
+    if (d_e && n_outputs != 2) return fail(VPINN_E_INVALID, "d_e needs a network with two outputs");
     if (!d_params || (n > 0 && !d_xy) || n < 0) return fail(VPINN_E_INVALID, "null argument or negative n");
+    // one padded copy per output: the second output is evaluated as a one-output
+    // network that shares the hidden layers
     static thread_local DevBuf wpad;
     static thread_local int wpad_dev = -1;
     int dev = 0;
@@ -365,11 +415,25 @@ vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_
         wpad.release();
         wpad_dev = dev;
     }
-    VP_HIP(wpad.reserve(sizeof(float) * kMaxPadded));
+    VP_HIP(wpad.reserve(sizeof(float) * 2 * kMaxPadded));
     hipStream_t s = (hipStream_t)stream;
-    vpinn_status st = pack_params(d_params, width, n_hidden, wpad.as<float>(), s);
-    if (st) return st;
-    return eval_network(n_hidden, wpad.as<float>(), n, reinterpret_cast<const float2 *>(d_xy), d_u, d_ux, d_uy, s);
+    const float2 *xy = reinterpret_cast<const float2 *>(d_xy);
+    vpinn_status st = VPINN_OK;
+    if (d_u || d_ux || d_uy) {
+        st = pack_params(d_params, width, n_hidden, n_outputs, 0, wpad.as<float>(), s);
+        if (!st) st = eval_network(n_hidden, wpad.as<float>(), n, xy, d_u, d_ux, d_uy, s);
+    }
+    if (!st && d_e) {
+        float *w2 = wpad.as<float>() + kMaxPadded;
+        st = pack_params(d_params, width, n_hidden, n_outputs, 1, w2, s);
+        if (!st) st = eval_network(n_hidden, w2, n, xy, d_e, nullptr, nullptr, s);
+    }
+    return st;
+}
+
+vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_params, int64_t n, const float *d_xy,
+                                float *d_u, float *d_ux, float *d_uy, void *stream) {
+    return vpinn_eval_network_heads(width, n_hidden, 1, d_params, n, d_xy, d_u, d_ux, d_uy, nullptr, stream);
 }
 
 vpinn_status vpinn_adam_step(int64_t n, float *d_params, const float *d_grad, float *d_m, float *d_v, int64_t step,
@@ -393,6 +457,10 @@ vpinn_status vpinn_batch_create(int32_t n, vpinn_problem *const *problems, const
     }
     vpinn_status st = check_cfg(cfg);
     if (st) return st;
+    for (int i = 0; i < n; ++i) {
+        st = check_outputs(problems[i], cfg, false);
+        if (st) return fail(st, "problem " + std::to_string(i) + ": " + vpinn_last_error());
+    }
     DeviceGuard dg(problems[0]->device);
     if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problems' device");
     return batch_create(n, problems, cfg, out);

@@ -122,14 +122,16 @@ __global__ void k_points(const double *__restrict__ nodes, const int32_t *__rest
 // F[e,k] is reduced over q in fixed order through shared memory.  With a
 // convection-diffusion operator -diff Lap u + (cx, cy) . grad u the convection
 // term's weights w_q det J v_k are folded in: G_x = w_q det J (diff v_x + cx v),
-// G_y = w_q det J (diff v_y + cy v) (Poisson: diff = 1, cx = cy = 0).
+// G_y = w_q det J (diff v_y + cy v) (Poisson: diff = 1, cx = cy = 0).  With M
+// non-null (space-dependent diffusion, nothing folded) the convection weights
+// w_q det J v_k are stored there instead.
 constexpr int kAsmThreads = 256;
 __global__ __launch_bounds__(kAsmThreads) void k_assemble(
     const double *__restrict__ nodes, const int32_t *__restrict__ quad, int n, int nt,
     const double *__restrict__ xg, const double *__restrict__ wg, const double *__restrict__ phi,
     const double *__restrict__ dphi, int f_kind, double f_amp, double f_kx, double f_ky,
     const double *__restrict__ f_vals, double diff, double cx, double cy, int shared_g, float *__restrict__ Gx,
-    float *__restrict__ Gy, float *__restrict__ F) {
+    float *__restrict__ Gy, float *__restrict__ F, float *__restrict__ M) {
     __shared__ double wdf[kAsmThreads];
     const int64_t e = blockIdx.x;
     const int nq = n * n, ntest = nt * nt;
@@ -166,6 +168,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(
                     // det J * physical gradient = (d v_xi - b v_eta, -c v_xi + a v_eta)
                     Gx[o] = (float)(w * (diff * (d * vxi - b * veta) + cx * dv));
                     Gy[o] = (float)(w * (diff * (-c * vxi + a * veta) + cy * dv));
+                    if (M) M[o] = (float)(w * dv);
                 }
             }
         }
@@ -234,7 +237,8 @@ vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_
     k_assemble<<<dim3((unsigned)p->n_elem), kAsmThreads, 0, s>>>(
         d_nodes, d_quad, n, nt, d_xg.as<double>(), d_wg.as<double>(), d_phi.as<double>(), d_dphi.as<double>(),
         f->kind, f->amp, f->kx, f->ky, callback ? d_f.as<double>() : nullptr, p->diff, p->conv_x, p->conv_y,
-        p->shared_g ? 1 : 0, p->Gx.as<float>(), p->Gy.as<float>(), p->F.as<float>());
+        p->shared_g ? 1 : 0, p->Gx.as<float>(), p->Gy.as<float>(), p->F.as<float>(),
+        p->vardiff ? p->M.as<float>() : nullptr);
     VP_HIP(hipGetLastError());
     VP_HIP(hipStreamSynchronize(s));
     return VPINN_OK;

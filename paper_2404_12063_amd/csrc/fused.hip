@@ -63,6 +63,12 @@ constexpr int kRowQ = 4;             // quadrature points per lane in the row-st
 enum { kPathFast = 0, kPathRows1 = 1, kPathRows2 = 2, kPathRows4 = 3, kPathGeneric = 4, kNumPaths = 5 };
 constexpr int kCbs = kCThreads + 1;  // row stride of the per-point term buffer
 
+// NH = 2: the network has a second linear output, the space-dependent diffusion
+// coefficient e(x, y) (Sec. 4.7.2); its weights follow the first output's in the
+// padded layout, and its gradient takes two more column-sum slots
+__host__ __device__ constexpr int n_pad_h(int L, int NH) { return NH == 2 ? n_padded2(L) : n_padded(L); }
+__host__ __device__ constexpr int n_vslots(int L, int NH) { return L + 4 + 2 * (NH - 1); }
+
 struct Vec {
     f4 v[2];
 };
@@ -87,28 +93,31 @@ struct WeightsShared {
     float b[L][PW];
     float wo[PW];
     float bo;
+    float wo2[PW];  // second output (NH = 2 only)
+    float bo2;
 };
 
 template <int L, int NW>
 struct FwdShared {
     WeightsShared<L> W;
-    float stage[n_padded(L)];  // flat parameters, staged for load_weights
+    float stage[n_padded2(L)];  // flat parameters, staged for load_weights
     double lp[NW][2];          // per-wavefront loss partials: sum d_b^2, sum d_s^2
 };
 
-template <int L>
+template <int L, int NH>
 struct BwdShared {
     WeightsShared<L> W;
     union {
         // per-wavefront transpose tiles [2][16 points][kTs]
         float tt[kBWaves][2][16][kTs];
         // during the flush: three of the four pair-sum regions (the fourth is red)
-        float part[3][n_padded(L)];
+        float part[3][n_pad_h(L, NH)];
     };
     // per-wavefront column sums of the vector-shaped gradients, one slot per lane:
-    // [0, L) biases b_l, L: W1 column 0, L+1: W1 column 1, L+2: W_out, L+3: b_out
-    float vacc[kBWaves][L + 4][64];
-    float red[n_padded(L)];
+    // [0, L) biases b_l, L: W1 column 0, L+1: W1 column 1, L+2: W_out, L+3: b_out,
+    // and with a second output L+4: its weights, L+5: its bias
+    float vacc[kBWaves][n_vslots(L, NH)][64];
+    float red[n_pad_h(L, NH)];
 };
 
 // static description of one problem instance (device resident)
@@ -121,6 +130,8 @@ struct InstDesc {
     int64_t ubase;            // offset of this instance's points in the point buffer
     int64_t cblk0, n_chunks;  // contraction blocks cblk0 .. (epc elements each)
     int64_t gstride;          // floats between elements in G_x, G_y (0: one shared premultiplier)
+    const float *M;           // space-dependent diffusion: convection weights w_q det J v_k (else null)
+    float cbx, cby;           // and the velocity
     int nq, ntest, epc;
     int path;                 // contraction path (kPathFast .. kPathGeneric)
     // loss partial rows lrow0 .. lrow0 + ln_rows - 1: first one per tile block
@@ -142,6 +153,7 @@ struct FwdArgs {
     float2 *ubuf;               // per point: (u_x, u_y) at interior points, (dL/du, 0) elsewhere
     double *lpart;              // [loss rows][4]
     int64_t *step;              // optional step counter, incremented once per launch
+    float *ebuf;                // two outputs: second output e at interior points (point buffer order)
 };
 
 struct ContractArgs {
@@ -152,6 +164,7 @@ struct ContractArgs {
     int want_grad;
     float2 *ubuf;               // in: (u_x, u_y); out: (dL/du_x, dL/du_y) at interior points
     double *lpart;
+    float *ebuf;                // two outputs: in e, out dL/de at interior points
 };
 
 struct BwdArgs {
@@ -163,6 +176,7 @@ struct BwdArgs {
     int H;
     const float2 *ubuf;
     float *gpart;               // [gradient rows][kMaxPadded]
+    const float *ebuf;          // two outputs: dL/de at interior points
 };
 
 // ---------------------------------------------------------------------------
@@ -267,6 +281,18 @@ __device__ __forceinline__ void tile_outputs(const WeightsShared<L> &S, int lane
     uy = group_sum(sy);
 }
 
+// the second output e = W_out2 . a_L + b_out2 (no tangents needed)
+template <int L>
+__device__ __forceinline__ float tile_second(const WeightsShared<L> &S, int lane, const Vec &A_) {
+    const int g = lane >> 4;
+    float se = 0.f;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) se = fmaf(S.wo2[16 * m + 4 * g + r], A_.v[m][r], se);
+    return group_sum(se) + S.bo2;
+}
+
 // write a chained vector transposed into tile T[j][n]
 __device__ __forceinline__ void put_t(float (*T)[kTs], int lane, const Vec &V) {
     const int j = lane & 15, g = lane >> 4;
@@ -350,10 +376,10 @@ __device__ __forceinline__ void wgrad_from_tiles(float (*T0)[kTs], float (*T1)[k
     __builtin_amdgcn_s_setprio(0);
 }
 
-template <int L>
+template <int L, int NH>
 __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[kTs], float (*T1)[kTs], int lane,
-                                              float x, float y, float ub, float uxb, float uyb, const Acts<L> &K,
-                                              GradAcc<L> &G, float (*VA)[64]) {
+                                              float x, float y, float ub, float uxb, float uyb, float eb,
+                                              const Acts<L> &K, GradAcc<L> &G, float (*VA)[64]) {
     const int g = lane >> 4;
     Vec abar, txbar, tybar;
     {
@@ -376,12 +402,22 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
                 }
                 v.v[m][r] = ub * aL.v[m][r] + uxb * tx + uyb * ty;
                 const float w = S.wo[n];
-                abar.v[m][r] = ub * w;
+                abar.v[m][r] = NH == 2 ? fmaf(eb, S.wo2[n], ub * w) : ub * w;
                 txbar.v[m][r] = uxb * w;
                 tybar.v[m][r] = uyb * w;
             }
         VA[L + 2][lane] += colsum_vec(T0, lane, v);
         if (g == 0) VA[L + 3][lane] += ub;
+        if (NH == 2) {
+            // second output: dW_out2 = sum_p eb a_L, db_out2 = sum_p eb
+            Vec ve;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ve.v[m][r] = eb * aL.v[m][r];
+            VA[L + 4][lane] += colsum_vec(T0, lane, ve);
+            if (g == 0) VA[L + 5][lane] += eb;
+        }
     }
 #pragma unroll
     for (int l = L; l >= 2; --l) {
@@ -468,11 +504,12 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
 // weights of one instance -> LDS (padded to 32, fragment order for the MFMA A operands).
 // The flat parameters are first copied into `stage` with every thread's loads in
 // flight at once (npf <= n_padded(L)), then rearranged LDS to LDS.
-template <int L, int NT>
+template <int L, int NT, int NH>
 __device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, const float *__restrict__ P, int H,
                                              int tid) {
-    const int npf = 3 * H + (L - 1) * (H * H + H) + H + 1;
-    constexpr int kLoads = (n_padded(L) + NT - 1) / NT;
+    // flat tail: W_out[NH][H], b_out[NH]
+    const int npf = 3 * H + (L - 1) * (H * H + H) + NH * (H + 1);
+    constexpr int kLoads = (n_pad_h(L, NH) + NT - 1) / NT;
     float v[kLoads];
 #pragma unroll
     for (int i = 0; i < kLoads; ++i) {
@@ -494,8 +531,13 @@ __device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, 
         const int off = (l == 1) ? 2 * H : (int)hoff_w(H, l) + H * H;
         S.b[l - 1][o] = o < H ? stage[off + o] : 0.f;
     }
-    for (int t = tid; t < PW; t += NT) S.wo[t] = t < H ? stage[hoff_w(H, L + 1) + t] : 0.f;
-    if (tid == 0) S.bo = stage[hoff_w(H, L + 1) + H];
+    const int ho = (int)hoff_w(H, L + 1);
+    for (int t = tid; t < PW; t += NT) S.wo[t] = t < H ? stage[ho + t] : 0.f;
+    if (tid == 0) S.bo = stage[ho + NH * H];
+    if (NH == 2) {
+        for (int t = tid; t < PW; t += NT) S.wo2[t] = t < H ? stage[ho + H + t] : 0.f;
+        if (tid == 0) S.bo2 = stage[ho + 2 * H + 1];
+    }
     // fragments [l][dir][mt][slot][lane] in flat order, NT consecutive entries per
     // pass; all reads are issued before the writes
     static_assert(NT % 64 == 0, "whole wavefronts");
@@ -528,7 +570,7 @@ __device__ __forceinline__ void zero_acc(GradAcc<L> &G) {
 // 1: forward values and tangents at every point.  Blocks own contiguous tile ranges
 // (the same ranges as k_bwd), possibly spanning instances; the tiles of a range go
 // round-robin over the block's wavefronts.
-template <int L, int NW>
+template <int L, int NW, int NH>
 __global__ __launch_bounds__(NW * 64, 1) void k_fwd(FwdArgs A) {
     constexpr int kFwThreads = NW * 64, kFwWaves = NW;
     __shared__ FwdShared<L, NW> S;
@@ -544,11 +586,12 @@ __global__ __launch_bounds__(NW * 64, 1) void k_fwd(FwdArgs A) {
         const float2 *__restrict__ pts = Ip->pts;
         const float *__restrict__ tgt = Ip->tgt;
         float2 *__restrict__ ub_i = A.ubuf + Ip->ubase;
+        float *__restrict__ e_i = NH == 2 ? A.ebuf + Ip->ubase : nullptr;
         const float wb2 = Ip->wb2, ws2 = Ip->ws2;
         const int64_t seg_end = min(t_end, tile0 + Ip->n_tiles);
         const int64_t row = Ip->lrow0 + (int64_t)(blockIdx.x - Ip->gblk0);
         __syncthreads();
-        load_weights<L, kFwThreads>(S.W, S.stage, A.params + (int64_t)cur * A.param_stride, A.H, tid);
+        load_weights<L, kFwThreads, NH>(S.W, S.stage, A.params + (int64_t)cur * A.param_stride, A.H, tid);
         __syncthreads();
         double lbb = 0.0, lss = 0.0;
         // the next tile's point is loaded while this tile computes
@@ -567,9 +610,11 @@ __global__ __launch_bounds__(NW * 64, 1) void k_fwd(FwdArgs A) {
             tile_forward<L, false>(S.W, lane, p.x, p.y, a, tx, ty, unused);
             float u, ux, uy;
             tile_outputs<L>(S.W, lane, a, tx, ty, u, ux, uy);
+            const float e = NH == 2 ? tile_second<L>(S.W, lane, a) : 0.f;
             if (lane < 16 && idx < n_all) {
                 if (idx < n_pts) {
                     ub_i[idx] = make_float2(ux, uy);
+                    if (NH == 2) e_i[idx] = e;
                 } else {
                     // boundary (Sec. 2.3) or sensor (Sec. 4.7) mismatch: loss term and its adjoint
                     const int64_t xi = idx - n_pts;
@@ -605,7 +650,10 @@ __global__ __launch_bounds__(NW * 64, 1) void k_fwd(FwdArgs A) {
 //   fast (nq <= kCThreads, ntest <= kKB): thread (element, q) holds G_x[e,k,q],
 //     G_y[e,k,q] for all k in registers; the per-point terms u_x G_x + u_y G_y go
 //     through LDS to per-(element, test) row sums (eight lanes a row); then dL/du
-//     at q from the same registers;
+//     at q from the same registers.  With a space-dependent diffusion e(x, y) (the
+//     network's second output) and velocity b the term is
+//     e_q (u_x G_x + u_y G_y) + (b . grad u)_q M, M = w_q det J v_k also held in
+//     registers, and the adjoint adds dL/de_q = sum_k 2 c_v R_k (u_x G_x + u_y G_y);
 //   rows (nq <= 64 kRowQ, any ntest): one element per block, G streamed row by row,
 //     each row used twice from registers;
 //   generic (larger elements): rows by 16-lane groups, then the adjoint thread per q
@@ -646,6 +694,7 @@ __device__ __forceinline__ void contract_flush(const ContractArgs &A, const Cont
     }
 }
 
+template <bool VAR>
 __global__ __launch_bounds__(kCThreads) void k_contract_fast(ContractArgs A) {
     extern __shared__ float dyn[];
     __shared__ double lp[kCWaves][2];
@@ -666,17 +715,27 @@ __global__ __launch_bounds__(kCThreads) void k_contract_fast(ContractArgs A) {
     const int el = tid / nq, q = tid - el * nq;
     const bool act = el < ne;
     const int64_t gbase = (e0 + el) * Ip->gstride + q;
-    float gx[kKB], gy[kKB];
+    const float *__restrict__ Mw = Ip->M;
+    float gx[kKB], gy[kKB], gm[VAR ? kKB : 1];
 #pragma unroll
     for (int k = 0; k < kKB; ++k) {
         const bool ok = act && k < ntest;
         gx[k] = ok ? Gx[gbase + (int64_t)k * nq] : 0.f;
         gy[k] = ok ? Gy[gbase + (int64_t)k * nq] : 0.f;
+        if (VAR) gm[k] = ok ? Mw[gbase + (int64_t)k * nq] : 0.f;
     }
-    const float2 d = act ? ub[(e0 + el) * nq + q] : make_float2(0.f, 0.f);
+    const int64_t pi = (e0 + el) * nq + q;  // the thread's point
+    const float2 d = act ? ub[pi] : make_float2(0.f, 0.f);
+    float ev = 0.f, bgu = 0.f;  // e_q and (b . grad u)_q
+    if (VAR) {
+        ev = act ? A.ebuf[Ip->ubase + pi] : 0.f;
+        bgu = fmaf(Ip->cbx, d.x, Ip->cby * d.y);
+    }
 #pragma unroll
     for (int k = 0; k < kKB; ++k)
-        if (k < ntest) cbuf[k * kCbs + tid] = fmaf(d.x, gx[k], d.y * gy[k]);
+        if (k < ntest)
+            cbuf[k * kCbs + tid] =
+                VAR ? fmaf(ev, fmaf(d.x, gx[k], d.y * gy[k]), bgu * gm[k]) : fmaf(d.x, gx[k], d.y * gy[k]);
     __syncthreads();
     for (int r8 = tid; r8 < 8 * ne * ntest; r8 += kCThreads) {
         const int r = r8 >> 3, part = r8 & 7;
@@ -697,14 +756,20 @@ __global__ __launch_bounds__(kCThreads) void k_contract_fast(ContractArgs A) {
     __syncthreads();
     if (A.want_grad && act) {
         const float *rb = rbar + el * ntest;
-        float bx = 0.f, by = 0.f;
+        float bx = 0.f, by = 0.f, bm = 0.f;
 #pragma unroll
         for (int k = 0; k < kKB; ++k)
             if (k < ntest) {
                 bx = fmaf(rb[k], gx[k], bx);
                 by = fmaf(rb[k], gy[k], by);
+                if (VAR) bm = fmaf(rb[k], gm[k], bm);
             }
-        ub[(e0 + el) * nq + q] = make_float2(eps * bx, eps * by);
+        if (VAR) {
+            ub[pi] = make_float2(fmaf(ev, bx, Ip->cbx * bm), fmaf(ev, by, Ip->cby * bm));
+            A.ebuf[Ip->ubase + pi] = fmaf(d.x, bx, d.y * by);
+        } else {
+            ub[pi] = make_float2(eps * bx, eps * by);
+        }
     }
     contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
 }
@@ -878,7 +943,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
 }
 
 // one wavefront's gradient sums in padded order -> P (op: store, or add to what P holds)
-template <int L, bool ADD>
+template <int L, bool ADD, int NH>
 __device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const float (*VA)[64], int lane) {
     const int g = lane >> 4, c = lane & 15, hi = lane ^ 32;
     const bool lo = lane < 32;
@@ -905,7 +970,13 @@ __device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const
         }
         if (lane == 0) cb = P[off_wout(L) + PW];
     }
+    float cw2 = 0.f, cb2 = 0.f;
+    if (ADD && NH == 2) {
+        if (lo) cw2 = P[off_wout2(L) + lane];
+        if (lane == 0) cb2 = P[off_wout2(L) + PW];
+    }
     const float bo = wave_sum(VA[L + 3][lane]);
+    const float bo2 = NH == 2 ? wave_sum(VA[NH == 2 ? L + 5 : 0][lane]) : 0.f;
     // the partner's sum comes first, so the pair adds as (lower wave) + (upper wave)
 #pragma unroll
     for (int l = 2; l <= L; ++l)
@@ -928,40 +999,47 @@ __device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const
         P[off_wout(L) + lane] = ADD ? vo + cv[L + 2] : vo;
     }
     if (lane == 0) P[off_wout(L) + PW] = ADD ? bo + cb : bo;
+    if (NH == 2) {
+        if (lo) {
+            const float v2 = VA[NH == 2 ? L + 4 : 0][lane] + VA[NH == 2 ? L + 4 : 0][hi];
+            P[off_wout2(L) + lane] = ADD ? v2 + cw2 : v2;
+        }
+        if (lane == 0) P[off_wout2(L) + PW] = ADD ? bo2 + cb2 : bo2;
+    }
 }
 
 // the block's gradient sums for one instance -> gradient row `row`; accumulators reset.
 // Fixed order ((w0 + w1) + (w2 + w3)) + ((w4 + w5) + (w6 + w7)): odd wavefronts store
 // into four LDS regions (red, and three over the transpose tiles, idle here), even ones
 // add theirs, and the four regions are added on the way out.
-template <int L>
-__device__ __forceinline__ void flush_grad(BwdShared<L> &S, const BwdArgs &A, int64_t row, GradAcc<L> &G, int tid,
-                                           int wave, int lane) {
+template <int L, int NH>
+__device__ __forceinline__ void flush_grad(BwdShared<L, NH> &S, const BwdArgs &A, int64_t row, GradAcc<L> &G,
+                                           int tid, int wave, int lane) {
     static_assert(kBWaves == 8, "pairwise flush assumes eight wavefronts");
     float *mine = (wave >> 1) == 0 ? S.red : S.part[(wave >> 1) - 1];
     __syncthreads();
-    if (wave & 1) put_partial<L, false>(mine, G, S.vacc[wave], lane);
+    if (wave & 1) put_partial<L, false, NH>(mine, G, S.vacc[wave], lane);
     __syncthreads();
-    if (!(wave & 1)) put_partial<L, true>(mine, G, S.vacc[wave], lane);
+    if (!(wave & 1)) put_partial<L, true, NH>(mine, G, S.vacc[wave], lane);
     __syncthreads();
-    for (int j = tid; j < n_padded(L); j += kBThreads)
+    for (int j = tid; j < n_pad_h(L, NH); j += kBThreads)
         A.gpart[row * kMaxPadded + j] = (S.red[j] + S.part[0][j]) + (S.part[1][j] + S.part[2][j]);
     zero_acc<L>(G);
-    for (int t = tid; t < kBWaves * (L + 4) * 64; t += kBThreads) (&S.vacc[0][0][0])[t] = 0.f;
+    for (int t = tid; t < kBWaves * n_vslots(L, NH) * 64; t += kBThreads) (&S.vacc[0][0][0])[t] = 0.f;
     __syncthreads();
 }
 
 // 4: reverse sweep, tiles of 16 points spread evenly over all wavefronts; the
 // forward pass of each tile is recomputed (tanh included) and kept in registers
-template <int L>
+template <int L, int NH>
 __global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
-    __shared__ BwdShared<L> S;
+    __shared__ BwdShared<L, NH> S;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     float(*T0)[kTs] = S.tt[wave][0];
     float(*T1)[kTs] = S.tt[wave][1];
     GradAcc<L> G;
     zero_acc<L>(G);
-    for (int t = tid; t < kBWaves * (L + 4) * 64; t += kBThreads) (&S.vacc[0][0][0])[t] = 0.f;
+    for (int t = tid; t < kBWaves * n_vslots(L, NH) * 64; t += kBThreads) (&S.vacc[0][0][0])[t] = 0.f;
     int64_t t = A.blk_tiles[blockIdx.x];
     const int64_t t_blk = t;
     const int64_t t_end = A.blk_tiles[blockIdx.x + 1];
@@ -972,34 +1050,38 @@ __global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
         const int64_t tile0 = Ip->tile0, n_pts = Ip->n_pts, n_all = Ip->n_pts + Ip->n_bnd + Ip->n_sen;
         const float2 *__restrict__ pts = Ip->pts;
         const float2 *__restrict__ ub_i = A.ubuf + Ip->ubase;
+        const float *__restrict__ eb_i = NH == 2 ? A.ebuf + Ip->ubase : nullptr;
         const int64_t seg_end = min(t_end, tile0 + Ip->n_tiles);
         const int64_t row = Ip->grow0 + (int64_t)(blockIdx.x - Ip->gblk0);
         __syncthreads();
-        load_weights<L, kBThreads>(S.W, S.red, A.params + (int64_t)cur * A.param_stride, A.H, tid);
+        load_weights<L, kBThreads, NH>(S.W, S.red, A.params + (int64_t)cur * A.param_stride, A.H, tid);
         __syncthreads();
         // the next tile's point and adjoint are loaded while this tile computes
-        auto fetch = [&](int64_t tt, float2 &p, float2 &d) {
+        auto fetch = [&](int64_t tt, float2 &p, float2 &d, float &ev) {
             const int64_t idx = 16 * (tt - tile0) + (lane & 15);
             const bool ok = tt < seg_end && idx < n_all;
             p = ok ? pts[idx] : make_float2(0.f, 0.f);
             d = ok ? ub_i[idx] : make_float2(0.f, 0.f);
+            ev = (NH == 2 && ok && idx < n_pts) ? eb_i[idx] : 0.f;
         };
         float2 pn, dn;
+        float en;
         // the block's tiles go round-robin over its wavefronts, continuing across instances
         const int64_t first = t + (int64_t)((wave - (int)((t - t_blk) % kBWaves) + kBWaves) % kBWaves);
-        fetch(first, pn, dn);
+        fetch(first, pn, dn, en);
         for (int64_t tt = first; tt < seg_end; tt += kBWaves) {
             const int64_t idx = 16 * (tt - tile0) + (lane & 15);
             const float2 p = pn, d = dn;
-            fetch(tt + kBWaves, pn, dn);
+            const float eb = en;
+            fetch(tt + kBWaves, pn, dn, en);
             const bool interior = idx < n_pts;
             const float ub = interior ? 0.f : d.x, uxb = interior ? d.x : 0.f, uyb = interior ? d.y : 0.f;
             Acts<L> K;
             Vec a, tx, ty;
             tile_forward<L, true>(S.W, lane, p.x, p.y, a, tx, ty, K);
-            tile_backward<L>(S.W, T0, T1, lane, p.x, p.y, ub, uxb, uyb, K, G, S.vacc[wave]);
+            tile_backward<L, NH>(S.W, T0, T1, lane, p.x, p.y, ub, uxb, uyb, eb, K, G, S.vacc[wave]);
         }
-        flush_grad<L>(S, A, row, G, tid, wave, lane);
+        flush_grad<L, NH>(S, A, row, G, tid, wave, lane);
         t = seg_end;
         ++cur;
     }
@@ -1024,7 +1106,7 @@ struct AdamArgs {
     float lr, b1, b2, eps;
 };
 
-template <int L>
+template <int L, int NH>
 __global__ __launch_bounds__(kFinThreads) void k_fused_final(
     const InstDesc *__restrict__ inst, const float *__restrict__ gpart, const double *__restrict__ lpart, int H,
     int64_t npf, float *__restrict__ loss_out, float *__restrict__ grad_out, float *__restrict__ grad_eps_out,
@@ -1049,8 +1131,11 @@ __global__ __launch_bounds__(kFinThreads) void k_fused_final(
                 const int l = 2 + (int)(r0 / lay), r = (int)(r0 % lay);
                 pj = r < H * H ? off_w(l) + (r / H) * PW + (r % H) : off_b(l) + (r - H * H);
             } else {
+                // W_out[NH][H], b_out[NH]
                 const int r = (int)(r0 - (int64_t)(L - 1) * lay);
-                pj = r < H ? off_wout(L) + r : off_wout(L) + PW;
+                if (r < H) pj = off_wout(L) + r;
+                else if (NH == 2 && r < 2 * H) pj = off_wout2(L) + (r - H);
+                else pj = (r == NH * H) ? off_wout(L) + PW : off_wout2(L) + PW;
             }
         }
     }
@@ -1149,6 +1234,8 @@ static bool tuning_valid(const vpinn_tuning &t) {
 
 struct FusedPlan {
     DevBuf inst, blk_tiles, blk_inst0, cblk_inst, ubuf, gpart, lpart;
+    DevBuf ebuf;  // two outputs: e, then dL/de, per point (point buffer order)
+    int nh = 1;   // network outputs
     vpinn_tuning tune = kDefaultTuning;
     std::vector<InstDesc> host_inst;
     int tblocks = 0, n_inst = 0, grows = 0, lrows = 0, L = 0, H = 0;
@@ -1161,6 +1248,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
                                const vpinn_tuning &tune, FusedPlan &P) {
     P.tune = tune;
     const int L = cfg->n_hidden, H = cfg->width;
+    const int nh = cfg->n_outputs == 2 ? 2 : 1;
     const int cus = cu_count(dev);
     std::vector<InstDesc> D(n);
     int64_t tiles = 0, ubase = 0, cblocks = 0;
@@ -1187,6 +1275,17 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         d.nq = p->nq;
         d.ntest = p->ntest;
         d.gstride = p->gstride();
+        if (nh == 2) {
+            // the small-element contraction is the only one with the space-dependent term
+            if (!p->vardiff) return fail(VPINN_E_INVALID, "two network outputs need space-dependent diffusion problems");
+            if (!(p->nq <= kCThreads && p->ntest <= kKB))
+                return fail(VPINN_E_UNSUPPORTED, "space-dependent diffusion needs N_quad <= " +
+                                                     std::to_string(kCThreads) + " and N_test <= " +
+                                                     std::to_string(kKB));
+            d.M = p->M.as<float>();
+            d.cbx = (float)p->vd_bx;
+            d.cby = (float)p->vd_by;
+        }
         d.path = (p->nq <= kCThreads && p->ntest <= kKB) ? kPathFast
                  : (p->nq <= 64)                          ? kPathRows1
                  : (p->nq <= 128)                         ? kPathRows2
@@ -1255,13 +1354,14 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     VP_HIP(P.ubuf.reserve(sizeof(float2) * (size_t)ubase));
     VP_HIP(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)grows));
     VP_HIP(P.lpart.reserve(sizeof(double) * 4 * (size_t)lrows));
+    if (nh == 2) VP_HIP(P.ebuf.reserve(sizeof(float) * (size_t)ubase));
     VP_HIP(hipMemcpy(P.inst.ptr, D.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
     VP_HIP(hipMemcpy(P.blk_tiles.ptr, bt.data(), sizeof(int64_t) * (tblocks + 1), hipMemcpyHostToDevice));
     VP_HIP(hipMemcpy(P.blk_inst0.ptr, binst.data(), sizeof(int) * tblocks, hipMemcpyHostToDevice));
     VP_HIP(hipMemcpy(P.cblk_inst.ptr, cinst.data(), sizeof(int) * (size_t)cblocks, hipMemcpyHostToDevice));
     if (cdyn_fast > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_contract_fast, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)cdyn_fast);
+        const void *fn = nh == 2 ? (const void *)k_contract_fast<true> : (const void *)k_contract_fast<false>;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cdyn_fast);
         if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     }
     P.host_inst = D;
@@ -1273,7 +1373,8 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     P.tiles = tiles;
     P.L = L;
     P.H = H;
-    P.npf = vpinn_n_params(H, L);
+    P.nh = nh;
+    P.npf = vpinn_n_params_out(H, L, nh);
     for (int k = 0; k < kNumPaths; ++k) P.cpath_blocks[k] = cpath_blocks[k];
     P.cdyn_fast = cdyn_fast;
     P.cdyn_generic = cdyn_generic;
@@ -1289,21 +1390,22 @@ static void launch_rows(int rp, unsigned blocks, const ContractArgs &c, hipStrea
     }
 }
 
-template <int L>
+template <int L, int NH>
 static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs &ca, const BwdArgs &ba,
                        bool want_grad, dim3 fg, int ft, float *loss, float *grad, float *grad_eps, const AdamArgs &ad,
                        hipEvent_t const *ev, hipStream_t s) {
     if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
     switch (P.tune.fwd_waves) {
-    case 8: k_fwd<L, 8><<<P.tblocks, 8 * 64, 0, s>>>(fa); break;
-    case 16: k_fwd<L, 16><<<P.tblocks, 16 * 64, 0, s>>>(fa); break;
-    default: k_fwd<L, 12><<<P.tblocks, 12 * 64, 0, s>>>(fa); break;
+    case 8: k_fwd<L, 8, NH><<<P.tblocks, 8 * 64, 0, s>>>(fa); break;
+    case 16: k_fwd<L, 16, NH><<<P.tblocks, 16 * 64, 0, s>>>(fa); break;
+    default: k_fwd<L, 12, NH><<<P.tblocks, 12 * 64, 0, s>>>(fa); break;
     }
     if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
     {
         ContractArgs c = ca;
         c.cblk_base = 0;
-        if (P.cpath_blocks[kPathFast]) k_contract_fast<<<(unsigned)P.cpath_blocks[kPathFast], kCThreads, P.cdyn_fast, s>>>(c);
+        if (P.cpath_blocks[kPathFast])
+            k_contract_fast<NH == 2><<<(unsigned)P.cpath_blocks[kPathFast], kCThreads, P.cdyn_fast, s>>>(c);
         c.cblk_base += P.cpath_blocks[kPathFast];
         const int rp = P.tune.rows_per_pass;
         if (P.cpath_blocks[kPathRows1]) launch_rows<1>(rp, (unsigned)P.cpath_blocks[kPathRows1], c, s);
@@ -1316,9 +1418,9 @@ static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs
             k_contract_generic<<<(unsigned)P.cpath_blocks[kPathGeneric], kCThreads, P.cdyn_generic, s>>>(c);
     }
     if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
-    if (want_grad) k_bwd<L><<<P.tblocks, kBThreads, 0, s>>>(ba);
+    if (want_grad) k_bwd<L, NH><<<P.tblocks, kBThreads, 0, s>>>(ba);
     if (ev && ev[3]) (void)hipEventRecord(ev[3], s);
-    k_fused_final<L><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf,
+    k_fused_final<L, NH><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf,
                                         loss, grad, grad_eps, ad);
     if (ev && ev[4]) (void)hipEventRecord(ev[4], s);
 }
@@ -1337,6 +1439,7 @@ static vpinn_status run_plan(const FusedPlan &P, const float *params, const floa
     fa.ubuf = P.ubuf.as<float2>();
     fa.lpart = P.lpart.as<double>();
     fa.step = step;
+    fa.ebuf = P.ebuf.as<float>();
     ContractArgs ca{};
     ca.inst = P.inst.as<InstDesc>();
     ca.cblk_inst = P.cblk_inst.as<int>();
@@ -1344,6 +1447,7 @@ static vpinn_status run_plan(const FusedPlan &P, const float *params, const floa
     ca.want_grad = want_grad ? 1 : 0;
     ca.ubuf = P.ubuf.as<float2>();
     ca.lpart = P.lpart.as<double>();
+    ca.ebuf = P.ebuf.as<float>();
     BwdArgs ba{};
     ba.inst = P.inst.as<InstDesc>();
     ba.blk_tiles = P.blk_tiles.as<int64_t>();
@@ -1353,13 +1457,18 @@ static vpinn_status run_plan(const FusedPlan &P, const float *params, const floa
     ba.H = P.H;
     ba.ubuf = P.ubuf.as<float2>();
     ba.gpart = P.gpart.as<float>();
+    ba.ebuf = P.ebuf.as<float>();
     const dim3 fg((unsigned)std::max<int64_t>(1, (P.npf + kFinCols - 1) / kFinCols), (unsigned)P.n_inst);
     const int ft = kFinThreads;
-    switch (P.L) {
-    case 1: launch_all<1>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
-    case 2: launch_all<2>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
-    case 3: launch_all<3>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
-    default: launch_all<4>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    switch (P.L * 2 + P.nh - 1) {
+    case 2: launch_all<1, 1>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 3: launch_all<1, 2>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 4: launch_all<2, 1>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 5: launch_all<2, 2>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 6: launch_all<3, 1>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 7: launch_all<3, 2>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    case 9: launch_all<4, 2>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
+    default: launch_all<4, 1>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
     }
     VP_HIP(hipGetLastError());
     return VPINN_OK;
@@ -1374,7 +1483,7 @@ struct SingleCache {
     bool valid = false;
     int64_t n_bnd = -1, n_sen = -1;
     const void *pts = nullptr;
-    int L = 0, H = 0, norm = -1;
+    int L = 0, H = 0, norm = -1, nh = 0;
     float tau = -1.f, gamma = -1.f;
 };
 
@@ -1387,7 +1496,8 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
         p->fused_ws_free = [](void *w) { delete reinterpret_cast<SingleCache *>(w); };
     }
     if (!c->valid || c->n_bnd != p->n_bnd || c->n_sen != p->n_sen || c->pts != p->pts.ptr || c->L != cfg->n_hidden ||
-        c->H != cfg->width || c->norm != cfg->loss_norm || c->tau != cfg->tau || c->gamma != cfg->gamma) {
+        c->H != cfg->width || c->norm != cfg->loss_norm || c->tau != cfg->tau || c->gamma != cfg->gamma ||
+        c->nh != (cfg->n_outputs == 2 ? 2 : 1)) {
         c->valid = false;
         vpinn_problem *one[1] = {p};
         vpinn_status st = build_plan(one, 1, cfg, p->device, kDefaultTuning, c->plan);
@@ -1401,6 +1511,7 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
         c->norm = cfg->loss_norm;
         c->tau = cfg->tau;
         c->gamma = cfg->gamma;
+        c->nh = cfg->n_outputs == 2 ? 2 : 1;
     }
     AdamArgs none{};
     return run_plan(c->plan, d_params, d_eps, d_grad != nullptr || d_grad_eps != nullptr, d_loss, d_grad, d_grad_eps,
@@ -1447,9 +1558,9 @@ vpinn_status batch_loss_and_grad(vpinn_batch *b, const float *d_params, const fl
                                  float *d_grads, float *d_grad_eps, hipStream_t s) {
     if (d_eps || d_grad_eps)
         for (const vpinn_problem *p : b->probs)
-            if (p->folded())
-                return fail(VPINN_E_INVALID,
-                            "a problem assembled with fixed convection-diffusion coefficients takes no eps");
+            if (p->folded() || p->vardiff)
+                return fail(VPINN_E_INVALID, "a problem assembled with fixed or space-dependent "
+                                             "convection-diffusion coefficients takes no eps");
     AdamArgs none{};
     return run_plan(b->plan, d_params, d_eps, d_grads != nullptr || d_grad_eps != nullptr, d_losses, d_grads,
                     d_grad_eps, none, nullptr, b->prof, s);

@@ -16,7 +16,9 @@ namespace vp {
 // (their activation is tanh(0) = 0 and they feed nothing).
 //   W1 [32][2] at 0, b1 [32] at 64,
 //   layer l = 2..L: W_l [32][32] at 96 + (l-2)*1056, b_l [32] right after,
-//   W_out [32] at 96 + (L-1)*1056, b_out after it.
+//   W_out [32] at 96 + (L-1)*1056, b_out after it;
+//   a second output head (the space-dependent diffusion coefficient):
+//   W_out2 [32] right after b_out, then b_out2.
 // ---------------------------------------------------------------------------
 constexpr int PW = 32;
 constexpr int kOffB1 = 64;
@@ -25,7 +27,9 @@ __host__ __device__ constexpr int off_w(int l) { return l == 1 ? 0 : 96 + (l - 2
 __host__ __device__ constexpr int off_b(int l) { return l == 1 ? kOffB1 : off_w(l) + PW * PW; }
 __host__ __device__ constexpr int off_wout(int L) { return 96 + (L - 1) * kLayerStride; }
 __host__ __device__ constexpr int n_padded(int L) { return off_wout(L) + PW + 1; }
-constexpr int kMaxPadded = n_padded(VPINN_MAX_HIDDEN);
+__host__ __device__ constexpr int off_wout2(int L) { return n_padded(L); }
+__host__ __device__ constexpr int n_padded2(int L) { return n_padded(L) + PW + 1; }
+constexpr int kMaxPadded = n_padded2(VPINN_MAX_HIDDEN);
 
 // flat (unpadded) layout offsets for width H
 __host__ __device__ inline int64_t hoff_w(int H, int l) {
@@ -95,6 +99,11 @@ struct vpinn_problem {
     // every element a translate of one shape: G is the same for all of them and is
     // stored once (Algorithm 2's single reference premultiplier), element stride 0
     bool shared_g = false;
+    // space-dependent diffusion (the network's second output): G holds the plain
+    // diffusion weights, M the convection weights w_q det J v_k, b the velocity
+    bool vardiff = false;
+    double vd_bx = 0.0, vd_by = 0.0;
+    vp::DevBuf M;            // float [n_elem][ntest][nq] (vardiff only)
     int64_t gstride() const { return shared_g ? 0 : (int64_t)ntest * nq; }
     vp::DevBuf Gx, Gy, F;    // float
     vp::DevBuf pts;          // float2 [n_pts + n_bnd + n_sen]: interior, boundary, sensors
@@ -123,7 +132,8 @@ namespace vp {
 // builds G (with p->diff, p->conv_x, p->conv_y folded in), F and the points
 vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_nodes, const int32_t *d_quad,
                              const vpinn_forcing *f, hipStream_t s);
-vpinn_status pack_params(const float *d_params, int H, int L, float *d_wpad, hipStream_t s);
+// output `head` (0-based) of a network with `heads` outputs, padded, as a one-output network
+vpinn_status pack_params(const float *d_params, int H, int L, int heads, int head, float *d_wpad, hipStream_t s);
 vpinn_status eval_network(int L, const float *d_wpad, int64_t n, const float2 *d_xy, float *d_u,
                           float *d_ux, float *d_uy, hipStream_t s);
 vpinn_status plain_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,

@@ -17,7 +17,9 @@ namespace vp {
 // ---------------------------------------------------------------------------
 // parameter layout conversion
 // ---------------------------------------------------------------------------
-__global__ void k_plain_pack(const float *__restrict__ src, int H, int L, float *__restrict__ dst) {
+// output `head` of a network with `heads` linear outputs goes to the W_out, b_out slots
+__global__ void k_plain_pack(const float *__restrict__ src, int H, int L, int heads, int head,
+                             float *__restrict__ dst) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_padded(L)) return;
     float v = 0.0f;
@@ -41,9 +43,9 @@ __global__ void k_plain_pack(const float *__restrict__ src, int H, int L, float 
         const int r = t - off_wout(L);
         const int64_t base = hoff_w(H, L + 1);
         if (r < PW) {
-            if (r < H) v = src[base + r];
+            if (r < H) v = src[base + (int64_t)head * H + r];
         } else {
-            v = src[base + H];
+            v = src[base + (int64_t)heads * H + head];
         }
     }
     dst[t] = v;
@@ -471,8 +473,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_plain_bwd(const float *__restri
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-vpinn_status pack_params(const float *d_params, int H, int L, float *d_wpad, hipStream_t s) {
-    k_plain_pack<<<(n_padded(L) + 255) / 256, 256, 0, s>>>(d_params, H, L, d_wpad);
+vpinn_status pack_params(const float *d_params, int H, int L, int heads, int head, float *d_wpad, hipStream_t s) {
+    k_plain_pack<<<(n_padded(L) + 255) / 256, 256, 0, s>>>(d_params, H, L, heads, head, d_wpad);
     VP_HIP(hipGetLastError());
     return VPINN_OK;
 }
@@ -534,7 +536,7 @@ vpinn_status plain_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
         VP_HIP(p->gpart.reserve(sizeof(float) * kMaxPadded * kBwdMaxBlocks));
     }
     float *w = p->wpad.as<float>();
-    vpinn_status st = pack_params(d_params, H, L, w, s);
+    vpinn_status st = pack_params(d_params, H, L, 1, 0, w, s);
     if (st) return st;
     st = fwd_dispatch(L, w, p->pts.as<float2>(), np, p->u.as<float>(), p->ux.as<float>(), p->uy.as<float>(),
                       want_grad ? p->act.as<float>() : nullptr, s);

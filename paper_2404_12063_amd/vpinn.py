@@ -31,7 +31,7 @@ VPINN_PATH_FUSED = 0
 VPINN_PATH_PLAIN = 1
 VPINN_NORM_TEST = 0
 VPINN_NORM_ELEM = 1
-VPINN_TENSOR_GX, VPINN_TENSOR_GY, VPINN_TENSOR_F, VPINN_TENSOR_X = 0, 1, 2, 3
+VPINN_TENSOR_GX, VPINN_TENSOR_GY, VPINN_TENSOR_F, VPINN_TENSOR_X, VPINN_TENSOR_M = 0, 1, 2, 3, 4
 PROFILE_EVENTS = 5  # VPINN_PROFILE_EVENTS: forward | contraction | backward | reduction
 
 SCALAR_FN = C.CFUNCTYPE(C.c_double, C.c_double, C.c_double, C.c_void_p)
@@ -52,12 +52,12 @@ class vpinn_problem_info(C.Structure):
                 ("n_points", C.c_int64), ("n_boundary", C.c_int64), ("n_sensors", C.c_int64),
                 ("quad_order", C.c_int32), ("test_order", C.c_int32),
                 ("diffusion", C.c_double), ("velocity_x", C.c_double), ("velocity_y", C.c_double),
-                ("shared_premultiplier", C.c_int32)]
+                ("shared_premultiplier", C.c_int32), ("variable_diffusion", C.c_int32)]
 
 
 class vpinn_loss_cfg(C.Structure):
     _fields_ = [("n_hidden", C.c_int32), ("width", C.c_int32), ("tau", C.c_float), ("gamma", C.c_float),
-                ("loss_norm", C.c_int32), ("path", C.c_int32)]
+                ("loss_norm", C.c_int32), ("path", C.c_int32), ("n_outputs", C.c_int32)]
 
 
 class vpinn_tuning(C.Structure):
@@ -85,13 +85,18 @@ _SIGNATURES = {
     "vpinn_set_sensors": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "vpinn_get_info": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_problem_info)]),
     "vpinn_read_tensor": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
+    "vpinn_assemble_vardiff": (C.c_int32, [C.POINTER(vpinn_mesh), C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                           C.POINTER(vpinn_forcing), C.c_void_p, C.POINTER(C.c_void_p)]),
     "vpinn_n_params": (C.c_int64, [C.c_int32, C.c_int32]),
+    "vpinn_n_params_out": (C.c_int64, [C.c_int32, C.c_int32, C.c_int32]),
     "vpinn_loss_and_grad": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_loss_cfg), C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vpinn_residual": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_loss_cfg), C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_void_p]),
     "vpinn_eval_network": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vpinn_eval_network_heads": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vpinn_adam_step": (C.c_int32, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "vpinn_batch_create": (C.c_int32, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vpinn_loss_cfg),
@@ -161,6 +166,10 @@ def vpinn_n_params(width: int, n_hidden: int) -> int:
     return int(lib().vpinn_n_params(width, n_hidden))
 
 
+def vpinn_n_params_out(width: int, n_hidden: int, n_outputs: int) -> int:
+    return int(lib().vpinn_n_params_out(width, n_hidden, n_outputs))
+
+
 class Problem:
     """Owner of a vpinn_problem handle (device G_x, G_y, F, points)."""
 
@@ -177,10 +186,12 @@ class Problem:
 
 
 def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0, kx: float = 0.0,
-                   ky: float = 0.0, fn=None, stream=None, cd=None) -> Problem:
+                   ky: float = 0.0, fn=None, stream=None, cd=None, vardiff=None) -> Problem:
     """xy: host [n_nodes, 2] float64; quad: host [n_elem, 4] int32.  Forcing is amp*sin(kx x)sin(ky y),
     or the Python callable fn(x, y) evaluated on the host (kind VPINN_FORCING_CALLBACK).
-    cd = (eps, bx, by): the convection-diffusion operator -eps Lap u + b . grad u (vpinn_assemble_cd2d)."""
+    cd = (eps, bx, by): the convection-diffusion operator -eps Lap u + b . grad u (vpinn_assemble_cd2d);
+    vardiff = (bx, by): -div(eps(x, y) grad u) + b . grad u with eps the network's second output
+    (vpinn_assemble_vardiff)."""
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     quad = np.ascontiguousarray(quad, dtype=np.int32)
     mesh = vpinn_mesh(xy.shape[0], xy.ctypes.data_as(C.POINTER(C.c_double)), quad.shape[0],
@@ -192,7 +203,11 @@ def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0,
         cb = SCALAR_FN(lambda x, y, u: float(fn(x, y)))
         f = vpinn_forcing(VPINN_FORCING_CALLBACK, 0.0, 0.0, 0.0, cb, None)
     out = C.c_void_p()
-    if cd is None:
+    if vardiff is not None:
+        bx, by = (float(v) for v in vardiff)
+        _check(lib().vpinn_assemble_vardiff(C.byref(mesh), quad_order, test_order, bx, by, C.byref(f),
+                                            _stream(stream), C.byref(out)))
+    elif cd is None:
         _check(lib().vpinn_assemble(C.byref(mesh), quad_order, test_order, C.byref(f), _stream(stream),
                                     C.byref(out)))
     else:
@@ -203,12 +218,14 @@ def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0,
 
 
 def assemble_problem(prob, stream=None) -> Problem:
-    """Assemble a vpinn_inputs Problem (Poisson, or convection-diffusion when it sets diff/conv) and upload its
-    boundary and sensor sets."""
+    """Assemble a vpinn_inputs Problem (Poisson, convection-diffusion when it sets diff/conv, space-dependent
+    diffusion when its network has two outputs) and upload its boundary and sensor sets."""
     diff, conv = getattr(prob, "diff", 1.0), tuple(getattr(prob, "conv", (0.0, 0.0)))
-    cd = None if (diff, conv) == (1.0, (0.0, 0.0)) else (diff, conv[0], conv[1])
+    two = getattr(prob, "heads", 1) == 2
+    cd = None if two or (diff, conv) == (1.0, (0.0, 0.0)) else (diff, conv[0], conv[1])
     p = vpinn_assemble(prob.mesh.xy, prob.mesh.quad, prob.quad_order, prob.test_order, prob.f_amp, prob.f_kx,
-                       prob.f_ky, fn=getattr(prob, "f_fn", None), stream=stream, cd=cd)
+                       prob.f_ky, fn=getattr(prob, "f_fn", None), stream=stream, cd=cd,
+                       vardiff=conv if two else None)
     vpinn_set_boundary(p, prob.bnd_xy, prob.bnd_g)
     if len(prob.sens_xy):
         vpinn_set_sensors(p, prob.sens_xy, prob.sens_u)
@@ -238,15 +255,16 @@ def vpinn_read_tensor(p: Problem, which: int) -> np.ndarray:
     shapes = {VPINN_TENSOR_GX: (info.n_elem, info.n_test, info.n_quad),
               VPINN_TENSOR_GY: (info.n_elem, info.n_test, info.n_quad),
               VPINN_TENSOR_F: (info.n_elem, info.n_test),
-              VPINN_TENSOR_X: (info.n_elem, info.n_quad, 2)}
+              VPINN_TENSOR_X: (info.n_elem, info.n_quad, 2),
+              VPINN_TENSOR_M: (info.n_elem, info.n_test, info.n_quad)}
     out = np.empty(shapes[which], dtype=np.float32)
     _check(lib().vpinn_read_tensor(p.handle, which, out.ctypes.data, out.size))
     return out
 
 
 def loss_cfg(width: int = 30, n_hidden: int = 3, tau: float = 10.0, gamma: float = 0.0,
-             loss_norm: int = VPINN_NORM_TEST, path: int = VPINN_PATH_FUSED) -> vpinn_loss_cfg:
-    return vpinn_loss_cfg(n_hidden, width, tau, gamma, loss_norm, path)
+             loss_norm: int = VPINN_NORM_TEST, path: int = VPINN_PATH_FUSED, n_outputs: int = 1) -> vpinn_loss_cfg:
+    return vpinn_loss_cfg(n_hidden, width, tau, gamma, loss_norm, path, n_outputs)
 
 
 def vpinn_loss_and_grad(p: Problem, cfg: vpinn_loss_cfg, params, eps=None, loss=None, grad=None,
@@ -263,6 +281,13 @@ def vpinn_eval_network(width: int, n_hidden: int, params, xy, u=None, ux=None, u
     n = xy.shape[0]
     _check(lib().vpinn_eval_network(width, n_hidden, _ptr(params), n, _ptr(xy), _ptr(u), _ptr(ux), _ptr(uy),
                                     _stream(stream)))
+
+
+def vpinn_eval_network_heads(width: int, n_hidden: int, n_outputs: int, params, xy, u=None, ux=None, uy=None,
+                             e=None, stream=None):
+    n = xy.shape[0]
+    _check(lib().vpinn_eval_network_heads(width, n_hidden, n_outputs, _ptr(params), n, _ptr(xy), _ptr(u),
+                                          _ptr(ux), _ptr(uy), _ptr(e), _stream(stream)))
 
 
 def vpinn_adam_step(params, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,

@@ -66,6 +66,10 @@ def test_n_params(V):
     assert V.vpinn_n_params(30, 3) == 1981 == gen.n_params(30, 3)
     assert V.vpinn_n_params(1, 1) == 5
     assert V.vpinn_n_params(0, 3) == -1
+    # a second output adds one row of W_out and one bias
+    assert V.vpinn_n_params_out(30, 3, 1) == 1981
+    assert V.vpinn_n_params_out(30, 3, 2) == 2012 == gen.n_params(30, 3, heads=2)
+    assert V.vpinn_n_params_out(30, 3, 3) == -1 and V.vpinn_n_params_out(30, 3, 0) == -1
 
 
 def _assemble_rc(V, xy, quad, n=3, nt=2, kind=1, fn=None):
@@ -152,3 +156,24 @@ def test_cd2d_rejects_bad_coefficients(V, eps, bx, by):
     out = C.c_void_p()
     rc = V.lib().vpinn_assemble_cd2d(C.byref(mesh), 4, 3, eps, bx, by, C.byref(f), None, C.byref(out))
     assert rc == V.VPINN_E_INVALID and not out.value
+
+
+@pytest.mark.parametrize("bx,by", [(float("inf"), 0.0), (0.0, float("nan"))])
+def test_vardiff_rejects_bad_velocity(V, bx, by):
+    m = gen.square_mesh(2, 2)
+    xy = np.ascontiguousarray(m.xy, dtype=np.float64)
+    quad = np.ascontiguousarray(m.quad, dtype=np.int32)
+    mesh = V.vpinn_mesh(xy.shape[0], xy.ctypes.data_as(C.POINTER(C.c_double)), quad.shape[0],
+                        quad.ctypes.data_as(C.POINTER(C.c_int32)))
+    f = V.vpinn_forcing(1, 1.0, 1.0, 1.0, V.SCALAR_FN(0), None)
+    out = C.c_void_p()
+    rc = V.lib().vpinn_assemble_vardiff(C.byref(mesh), 4, 3, bx, by, C.byref(f), None, C.byref(out))
+    assert rc == V.VPINN_E_INVALID and not out.value
+
+
+def test_eval_heads_rejects_bad_outputs(V):
+    L = V.lib()
+    one = C.c_void_p(16)  # never dereferenced: the checks come first
+    assert L.vpinn_eval_network_heads(30, 3, 3, one, 0, None, None, None, None, None, None) == V.VPINN_E_INVALID
+    assert L.vpinn_eval_network_heads(30, 3, 1, one, 0, None, None, None, None, one, None) == V.VPINN_E_INVALID
+    assert L.vpinn_eval_network_heads(33, 3, 2, one, 0, None, None, None, None, None, None) == V.VPINN_E_UNSUPPORTED

@@ -1,0 +1,256 @@
+"""Space-dependent diffusion -div(eps(x, y) grad u) + b . grad u = f with eps(x, y) the network's second
+output (the inverse problem of Sec. 4.7.2), on the fused path.
+
+Parity: the assembled G, M, F against the FP64 oracle; loss and gradient (both output heads) of single
+problems and of a batch against the oracle, to the tolerances of the Poisson problems; the two-output
+network evaluation against the oracle's; and the argument checks that keep this operator on the path that
+implements it.
+"""
+import numpy as np
+import pytest
+
+import vpinn_inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def V(torch):
+    from paper_2404_12063_amd import vpinn as V
+    V.lib()
+    return V
+
+
+def _disk(name="vd_disk", m=6, n=6, nt=4, nb=120, ns=80, seed=1, conv=(1.0, 0.0), width=30, L=3):
+    """Small disk with the manufactured solution and coefficient field; sensors of u inside."""
+    man = gen.VarDiffManufactured(b=conv)
+    mesh = gen.disk_mesh(m)
+    bxy = gen.circle_points(nb)
+    sxy = gen.disk_sensor_points(ns, seed) if ns else np.zeros((0, 2))
+    return gen.Problem(name=name, mesh=mesh, quad_order=n, test_order=nt, f_amp=0.0, f_kx=0.0, f_ky=0.0,
+                       bnd_xy=bxy, bnd_g=man.u(bxy[:, 0], bxy[:, 1]), sens_xy=sxy,
+                       sens_u=man.u(sxy[:, 0], sxy[:, 1]) if ns else np.zeros(0), tau=10.0, gamma=10.0 if ns else 0.0,
+                       seed=seed, conv=conv, f_fn=man.f, heads=2, width=width, n_hidden=L)
+
+
+def _square(name="vd_square", seed=2, conv=(0.4, -0.9), width=20, L=2):
+    """Skewed 5x7 square mesh, 7x7 GLL points (7 elements a contraction block, a ragged last block)."""
+    man = gen.VarDiffManufactured(b=conv)
+    mesh = gen.square_mesh(5, 7, perturb=0.2, seed=seed)
+    bxy = gen.square_boundary_points(60)
+    return gen.Problem(name=name, mesh=mesh, quad_order=7, test_order=3, f_amp=0.0, f_kx=0.0, f_ky=0.0,
+                       bnd_xy=bxy, bnd_g=man.u(bxy[:, 0], bxy[:, 1]), tau=5.0, gamma=0.0, seed=seed, conv=conv, f_fn=man.f,
+                       heads=2, width=width, n_hidden=L)
+
+
+CASES = {
+    "disk_L3_H30": lambda: _disk(),
+    "disk_L1_H32_nosens": lambda: _disk("vd_l1", m=5, n=5, nt=5, ns=0, seed=3, width=32, L=1),
+    "disk_L4_H16_q10t5": lambda: _disk("vd_l4", m=4, n=10, nt=5, ns=50, seed=4, conv=(0.0, 0.0), width=16, L=4),
+    "square_L2_H20": lambda: _square(),
+}
+
+
+def _cfg(V, prob, path=None, n_outputs=2):
+    return V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma, n_outputs=n_outputs,
+                      path=V.VPINN_PATH_FUSED if path is None else path)
+
+
+def _check(loss, grad, ref, tag):
+    assert abs(loss[0] - ref.loss[0]) / abs(ref.loss[0]) < 1e-5, (tag, loss[0], ref.loss[0])
+    for i in range(1, 4):
+        assert abs(loss[i] - ref.loss[i]) <= 1e-5 * abs(ref.loss[0]) + 1e-6 * abs(ref.loss[i]), (tag, i)
+    rel = np.linalg.norm(grad - ref.grad) / np.linalg.norm(ref.grad)
+    assert rel < 1e-4, (tag, rel)
+
+
+def _run(V, torch, prob, theta):
+    p = V.assemble_problem(prob)
+    dev = torch.device("cuda:0")
+    n = V.vpinn_n_params_out(prob.width, prob.n_hidden, 2)
+    assert n == theta.size
+    th = torch.tensor(theta, dtype=torch.float32, device=dev)
+    loss = torch.zeros(4, device=dev)
+    grad = torch.zeros(n, device=dev)
+    V.vpinn_loss_and_grad(p, _cfg(V, prob), th, loss=loss, grad=grad)
+    torch.cuda.synchronize()
+    return p, loss.cpu().double().numpy(), grad.cpu().double().numpy()
+
+
+def test_vardiff_tensors_match_oracle(V):
+    from oracle import oracle as O
+    prob = _disk()
+    asm = O.assemble_problem(prob)
+    p = V.assemble_problem(prob)
+    info = V.vpinn_get_info(p)
+    assert info.variable_diffusion == 1 and info.diffusion == 0.0 and info.shared_premultiplier == 0
+    assert (info.velocity_x, info.velocity_y) == prob.conv
+    for which, ref in [(V.VPINN_TENSOR_GX, asm.Gx), (V.VPINN_TENSOR_GY, asm.Gy), (V.VPINN_TENSOR_M, asm.M),
+                       (V.VPINN_TENSOR_F, asm.F)]:
+        g = V.vpinn_read_tensor(p, which).astype(np.float64).reshape(ref.shape)
+        np.testing.assert_allclose(g, ref, rtol=2e-6, atol=2e-7 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_vardiff_loss_and_grad_match_oracle(V, torch, case):
+    from oracle import oracle as O
+    prob = CASES[case]()
+    theta = prob.params(seed=7, bias_scale=0.1)
+    _, loss, grad = _run(V, torch, prob, theta)
+    ref = O.problem_loss_grad(prob, O.assemble_problem(prob), theta)
+    _check(loss, grad, ref, case)
+    # the second output's weights get a gradient of their own
+    H = prob.width
+    tail = slice(theta.size - 2 * H - 2, theta.size)
+    assert np.linalg.norm(ref.grad[theta.size - H - 2:theta.size - 2]) > 0
+    np.testing.assert_allclose(grad[tail], ref.grad[tail], rtol=0, atol=2e-4 * np.abs(ref.grad).max())
+
+
+def test_vardiff_loss_only_and_repeat_are_identical(V, torch):
+    """Loss without gradient equals the loss with it, and two calls agree bitwise."""
+    prob = _disk()
+    theta = prob.params(seed=8, bias_scale=0.1)
+    p, loss, grad = _run(V, torch, prob, theta)
+    dev = torch.device("cuda:0")
+    th = torch.tensor(theta, dtype=torch.float32, device=dev)
+    l2 = torch.zeros(4, device=dev)
+    V.vpinn_loss_and_grad(p, _cfg(V, prob), th, loss=l2)
+    g2 = torch.zeros(theta.size, device=dev)
+    l3 = torch.zeros(4, device=dev)
+    V.vpinn_loss_and_grad(p, _cfg(V, prob), th, loss=l3, grad=g2)
+    torch.cuda.synchronize()
+    assert np.array_equal(l2.cpu().double().numpy(), loss)
+    assert np.array_equal(l3.cpu().double().numpy(), loss)
+    assert np.array_equal(g2.cpu().double().numpy(), grad)
+
+
+def test_eval_network_heads_matches_oracle(V, torch):
+    from oracle import oracle as O
+    prob = _disk()
+    theta = prob.params(seed=9, bias_scale=0.2)
+    H, L = prob.width, prob.n_hidden
+    xy = np.concatenate([prob.sens_xy, prob.bnd_xy])
+    dev = torch.device("cuda:0")
+    th = torch.tensor(theta, dtype=torch.float32, device=dev)
+    X = torch.tensor(xy, dtype=torch.float32, device=dev)
+    outs = [torch.zeros(len(xy), device=dev) for _ in range(4)]
+    V.vpinn_eval_network_heads(H, L, 2, th, X, *outs)
+    torch.cuda.synchronize()
+    ref = O.mlp_eval(theta, H, L, X.cpu().double().numpy(), heads=2)
+    for got, want in zip(outs, ref):
+        np.testing.assert_allclose(got.cpu().double().numpy(), want, rtol=0, atol=2e-5 * max(1.0, np.abs(want).max()))
+    # one output: the first head of the same parameters is not a one-output network's layout
+    with pytest.raises(V.VpinnError):
+        V.vpinn_eval_network_heads(H, L, 1, th, X, e=outs[3])
+
+
+def test_vardiff_argument_checks(V, torch):
+    prob = _disk()
+    theta = prob.params(seed=10)
+    p = V.assemble_problem(prob)
+    dev = torch.device("cuda:0")
+    th = torch.tensor(theta, dtype=torch.float32, device=dev)
+    loss = torch.zeros(4, device=dev)
+    R = torch.zeros(prob.n_elem * prob.test_order ** 2, device=dev)
+    cases = [
+        (dict(cfg=_cfg(V, prob, n_outputs=1)), V.VPINN_E_INVALID),
+        (dict(cfg=_cfg(V, prob, path=V.VPINN_PATH_PLAIN)), V.VPINN_E_UNSUPPORTED),
+        (dict(cfg=_cfg(V, prob), eps=torch.ones(1, device=dev)), V.VPINN_E_INVALID),
+        (dict(cfg=_cfg(V, prob, n_outputs=3)), V.VPINN_E_INVALID),
+    ]
+    for kw, code in cases:
+        with pytest.raises(V.VpinnError) as ei:
+            V.vpinn_loss_and_grad(p, kw["cfg"], th, eps=kw.get("eps"), loss=loss)
+        assert ei.value.code == code, kw
+    with pytest.raises(V.VpinnError) as ei:
+        V.vpinn_residual(p, _cfg(V, prob), th, R)
+    assert ei.value.code == V.VPINN_E_UNSUPPORTED
+    # two outputs on a constant-coefficient problem
+    poisson = gen.poisson_sinsin_square("vd_poisson", 3, 4, 2, 1, 32, 0.1, seed=5)
+    pp = V.assemble_problem(poisson)
+    with pytest.raises(V.VpinnError) as ei:
+        V.vpinn_loss_and_grad(pp, _cfg(V, poisson), th, loss=loss)
+    assert ei.value.code == V.VPINN_E_INVALID
+    # elements beyond the small-element contraction (17 x 17 points)
+    big = _disk("vd_big", m=2, n=17, nt=3, ns=0)
+    pb = V.assemble_problem(big)
+    with pytest.raises(V.VpinnError) as ei:
+        V.vpinn_loss_and_grad(pb, _cfg(V, big), th, loss=loss)
+    assert ei.value.code == V.VPINN_E_UNSUPPORTED
+    # a batch must not mix the operators
+    with pytest.raises(V.VpinnError):
+        V.vpinn_batch_create([p, pp], _cfg(V, prob))
+
+
+def test_vardiff_batch_matches_oracle_for_every_tuning(V, torch):
+    from oracle import oracle as O
+    probs = [_disk("vd_b0", seed=11), _disk("vd_b1", m=4, n=5, nt=5, ns=40, seed=12, conv=(-0.5, 0.3)),
+             _disk("vd_b2", m=7, n=8, nt=4, ns=0, seed=13)]
+    gp = [V.assemble_problem(pr) for pr in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 10.0, n_outputs=2))
+    th = np.stack([pr.params(seed=20 + i, bias_scale=0.1) for i, pr in enumerate(probs)])
+    dev = torch.device("cuda:0")
+    T = torch.tensor(th, dtype=torch.float32, device=dev)
+    n = th.shape[1]
+    refs = []
+    for i, pr in enumerate(probs):
+        pr.tau, pr.gamma = 10.0, 10.0
+        refs.append(O.problem_loss_grad(pr, O.assemble_problem(pr), th[i]))
+    for tune in [(12, 0, 4), (8, 1, 2), (16, 2, 8)]:
+        V.vpinn_batch_set_tuning(b, *tune)
+        losses = torch.zeros((len(probs), 4), device=dev)
+        grads = torch.zeros((len(probs), n), device=dev)
+        V.vpinn_batch_loss_and_grad(b, T, losses=losses, grads=grads)
+        torch.cuda.synchronize()
+        for i, pr in enumerate(probs):
+            _check(losses[i].cpu().double().numpy(), grads[i].cpu().double().numpy(), refs[i], f"{pr.name}/{tune}")
+
+
+def test_vardiff_batch_step_graph_replays_match_eager(V, torch):
+    """Adam steps through the captured graph equal eager steps, replay after replay."""
+    probs = [_disk("vd_g0", seed=14), _disk("vd_g1", m=5, n=6, nt=3, ns=30, seed=15)]
+    gp = [V.assemble_problem(pr) for pr in probs]
+    cfg = V.loss_cfg(30, 3, 10.0, 10.0, n_outputs=2)
+    dev = torch.device("cuda:0")
+    th0 = torch.tensor(np.stack([pr.params(seed=30 + i, bias_scale=0.1) for i, pr in enumerate(probs)]),
+                       dtype=torch.float32, device=dev)
+
+    def state():
+        return th0.clone(), torch.zeros_like(th0), torch.zeros_like(th0), torch.zeros(1, dtype=torch.int64,
+                                                                                        device=dev)
+    be = V.vpinn_batch_create(gp, cfg)
+    P, M, Vv, S = state()
+    Le = torch.zeros((len(probs), 4), device=dev)
+    eager = []
+    for _ in range(3):
+        V.vpinn_batch_step(be, P, M, Vv, S, 1e-3, 0.9, 0.999, 1e-8, Le)
+        torch.cuda.synchronize()
+        eager.append((P.clone(), Le.clone()))
+    bg = V.vpinn_batch_create(gp, cfg)
+    P2, M2, V2, S2 = state()
+    Lg = torch.zeros((len(probs), 4), device=dev)
+    s = torch.cuda.Stream()
+    V.vpinn_batch_capture(bg, P2, M2, V2, S2, 1e-3, 0.9, 0.999, 1e-8, Lg, stream=s)
+    for k in range(3):
+        V.vpinn_batch_replay(bg, stream=s)
+        s.synchronize()
+        assert torch.equal(P2, eager[k][0]) and torch.equal(Lg, eager[k][1]), k
+        torch.cuda.synchronize()
+
+
+@pytest.mark.slow
+def test_disk_vareps_full_size(V, torch):
+    """The disk workload (1,024 elements of 10 x 10 points, 1,600 boundary points, 1,000 sensors)."""
+    from oracle import oracle as O
+    prob = gen.config_disk_vareps()
+    theta = prob.params(seed=3, bias_scale=0.1)
+    _, loss, grad = _run(V, torch, prob, theta)
+    ref = O.problem_loss_grad(prob, O.assemble_problem(prob), theta)
+    _check(loss, grad, ref, "disk_vareps")
