@@ -25,13 +25,16 @@ if ROOT not in sys.path:
 
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 (vector and matrix) peak
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+# VALU FP32 without packed instructions (they are switched off at build time):
+# 256 CUs x 64 lanes x 2 FLOP per FMA x 2.4 GHz
+PEAK_FP32_VALU_TFLOPS = 78.6
 
 
 def n_outputs(prob) -> int:
     return getattr(prob, "heads", 1)
 
 
-def kernel_work(prob):
+def kernel_work(prob, matrix_free: bool = False):
     """Algorithmic work of each fused-path kernel for one epoch (dense products as 2 x multiply-adds).
 
     k_fwd: values and tangents, interior 2H + 3(L-1)H^2 + 2H MACs a point, boundary/sensor 3H + (L-1)H^2;
@@ -41,17 +44,25 @@ def kernel_work(prob):
     A second network output (space-dependent diffusion e): k_fwd + H MACs an interior point; k_contract
     7 N_test MACs a point (terms e (u_x G_x + u_y G_y) + (b . grad u) M, adjoint sums of G_x, G_y, M) and
     M read once (12 N_test bytes a point) plus e in and dL/de out (8 a point); k_bwd + 2H MACs.
+    Matrix-free problems (no G stored): the sum-factorised contraction takes 6 N_t n^2 + 4 N_t^2 n MACs an
+    element (forward 3 N_t n^2 + 2 N_t^2 n, adjoint the same) and reads F, 32 B of geometry, the point buffer.
     """
     H, L = prob.width, prob.n_hidden
     nt = prob.test_order ** 2
     n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
     two = n_outputs(prob) == 2
+    if matrix_free:
+        n, t = prob.quad_order, prob.test_order
+        contract = {"flop": 2.0 * prob.n_elem * (6 * t * n * n + 4 * t * t * n),
+                    "bytes": 4.0 * nt * prob.n_elem + 32.0 * prob.n_elem + (24.0 if two else 16.0) * prob.n_points}
+    else:
+        contract = {"flop": 2.0 * prob.n_points * (7 if two else 4) * nt,
+                    "bytes": (12.0 if two else 8.0) * nt * prob.n_points + 4.0 * nt * prob.n_elem
+                    + (24.0 if two else 16.0) * prob.n_points}
     return {
         "k_fwd": {"flop": 2.0 * (prob.n_points * (2 * H + 3 * (L - 1) * H * H + 2 * H + (H if two else 0))
                                  + n_extra * (3 * H + (L - 1) * H * H))},
-        "k_contract": {"flop": 2.0 * prob.n_points * (7 if two else 4) * nt,
-                       "bytes": (12.0 if two else 8.0) * nt * prob.n_points + 4.0 * nt * prob.n_elem
-                       + (24.0 if two else 16.0) * prob.n_points},
+        "k_contract": contract,
         "k_bwd": {"flop": 2.0 * (prob.n_points * (2 * H + 6 * (L - 1) * H * H + 4 * H + (2 * H if two else 0))
                                  + n_extra * (3 * H + 2 * (L - 1) * H * H))},
     }
@@ -73,12 +84,14 @@ def flops_per_epoch(prob) -> float:
     return 2.0 * (prob.n_points * mac_int + n_extra * mac_bnd)
 
 
-def bytes_per_epoch(prob) -> float:
-    """Algorithmic HBM bytes: G_x and G_y once, F, quadrature and boundary points, parameters."""
+def bytes_per_epoch(prob, matrix_free: bool = False) -> float:
+    """Algorithmic HBM bytes: G_x and G_y once (matrix-free: 32 B of geometry an element instead), F,
+    quadrature and boundary points, parameters."""
     nt = prob.test_order ** 2
     n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
     g = 12.0 if n_outputs(prob) == 2 else 8.0  # G_x, G_y (and M)
-    return (g * nt * prob.n_points + 4.0 * nt * prob.n_elem + 8.0 * prob.n_points + 12.0 * n_extra)
+    tensors = 32.0 * prob.n_elem if matrix_free else g * nt * prob.n_points
+    return (tensors + 4.0 * nt * prob.n_elem + 8.0 * prob.n_points + 12.0 * n_extra)
 
 
 def source_digest() -> str:
@@ -425,11 +438,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
-    ap.add_argument("--workload", choices=["c2", "c5", "probe", "gear_cd", "disk_vareps"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c5", "probe", "gear_cd", "disk_vareps", "c2_mf", "probe_mf"],
+                    default="c2",
                     help="c2 (default, the headline): one 1,024-element problem; c5: 64-instance batch; probe: "
                          "20x20 test functions on 4,096 elements (G-stream bound); gear_cd: the convection-diffusion "
                          "gear problem on 14,000 elements; disk_vareps: space-dependent diffusion inverse problem, "
-                         "a two-output network on a 1,024-element disk")
+                         "a two-output network on a 1,024-element disk; c2_mf, probe_mf: the same as c2, probe with "
+                         "G regenerated per step from the element geometry (matrix-free)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times: a kernel of known traffic that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -483,6 +498,10 @@ WORKLOAD_TEXT = {
                    "(0.5, 0.5) and radius 0.5 (32x32 quads of a squircle-mapped grid), eps = 0.5 (sin x + cos y) and "
                    "u = sin(2pi x) sin(2pi y) manufactured, 10x10 GLL points, 5x5 test functions, 1600 boundary "
                    "points, 1000 sensors of u, tau = gamma = 10, MLP 2-30-30-30-2 tanh whose second output is eps",
+    "c2_mf": "c2_mf: c2 with no stored G: the contraction regenerates G every step from the 8 geometry floats of "
+             "each element by sum factorisation (matrix-free)",
+    "probe_mf": "probe_mf: probe with no stored G (matrix-free): 1.3 GB of G a step replaced by 32 B of geometry per "
+                "element and a sum-factorised contraction",
     "probe": "probe: the c4 mesh (64x64 jittered, 4096 elements) with 10x10 GLL points and 20x20 test functions "
              "(the paper's largest p-refinement), u*=sin(2pi x)sin(2pi y), 1600 boundary points, MLP "
              "2-30-30-30-1 tanh: the only shape whose G stream (1.3 GB) outweighs the network arithmetic",
@@ -490,9 +509,10 @@ WORKLOAD_TEXT = {
 
 
 def bench_single(args, V, torch, gen):
-    prob = gen.CONFIGS[args.workload]()
+    mf = args.workload.endswith("_mf")
+    prob = gen.CONFIGS[args.workload[:-3] if mf else args.workload]()
     theta = prob.params()
-    p = V.assemble_problem(prob)
+    p = V.assemble_problem(prob, matrix_free=mf)
     print(f"[bench] workload {args.workload}: {prob.n_elem} elements, {prob.n_points} quadrature points, "
           f"{len(prob.bnd_xy)} boundary points", file=sys.stderr, flush=True)
 
@@ -512,7 +532,7 @@ def bench_single(args, V, torch, gen):
     else:
         res = {"wall_s": eager["wall_s"] * args.steps / eager_steps}
     plain = None
-    if not args.no_plain and fused and n_outputs(prob) == 1:
+    if not args.no_plain and fused and n_outputs(prob) == 1 and not mf:
         plain = time_path(V, torch, p, prob, theta, V.VPINN_PATH_PLAIN, min(args.steps, 300), 20)
         print(f"[bench] plain eager: {plain['wall_s'] / min(args.steps, 300) * 1e3:.4f} ms/step", file=sys.stderr,
               flush=True)
@@ -530,7 +550,7 @@ def bench_single(args, V, torch, gen):
     ms = res["wall_s"] / args.steps * 1e3
     eps_s = 1e3 / ms
     flops = flops_per_epoch(prob)
-    work = kernel_work(prob)
+    work = kernel_work(prob, mf)
     kernels = {}
     if fused:
         km = res["kernel_ms"]
@@ -545,7 +565,12 @@ def bench_single(args, V, torch, gen):
         kernels["k_fused_final"] = {"ms": round(km["k_fused_final"], 5), "note": "reduction + Adam"}
         dom = max(("k_fwd", "k_contract", "k_bwd"), key=lambda k: km[k])
         k_ms = km[dom]
-        if dom == "k_contract" and work[dom]["flop"] / work[dom]["bytes"] < 1.0:
+        if dom == "k_contract" and mf:
+            achieved = work[dom]["flop"] / (k_ms * 1e-3) / 1e12
+            roof = {"bound": "alu", "kernel": dom + " (matrix-free)", "achieved": round(achieved, 3),
+                    "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
+                    "algorithmic_flop_per_launch": work[dom]["flop"]}
+        elif dom == "k_contract" and work[dom]["flop"] / work[dom]["bytes"] < 1.0:
             achieved = work[dom]["bytes"] / (k_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
@@ -583,10 +608,10 @@ def bench_single(args, V, torch, gen):
                    "boundary_points": len(prob.bnd_xy), "parallelism": "single GPU"},
         "mquadpts_per_s": round(prob.n_points * eps_s / 1e6, 2),
         "roofline": roof,
-        "whole_step": {"algorithmic_flop": flops, "algorithmic_bytes": bytes_per_epoch(prob),
+        "whole_step": {"algorithmic_flop": flops, "algorithmic_bytes": bytes_per_epoch(prob, mf),
                        "achieved_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
                        "frac_of_fp32_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
-                       "effective_gbs": round(bytes_per_epoch(prob) / (ms * 1e-3) / 1e9, 1)},
+                       "effective_gbs": round(bytes_per_epoch(prob, mf) / (ms * 1e-3) / 1e9, 1)},
     }
     if fused:
         out["step_ms_p10_p50_p90"] = [round(res["step_ms_p10"], 5), round(res["step_ms_p50"], 5),

@@ -141,6 +141,27 @@ vpinn_status vpinn_assemble_vardiff(const vpinn_mesh *mesh, int32_t quad_order, 
                                     double by, const vpinn_forcing *forcing, void *stream, vpinn_problem **out);
 
 /*
+ * vpinn_assemble_matrix_free -- the same operators without the premultiplied
+ * tensors: only F, the points and 8 floats of geometry per element are stored
+ * (the bilinear map's coefficients, App. A.1), and every loss call regenerates
+ * w_q (d v_xi - b v_eta, -c v_xi + a v_eta) for the tensor-product test functions
+ * by sum factorisation, first along xi and then along eta (the closed form of G
+ * in Sec. 4.2 and App. A.1).  HBM per element drops from 8 N_test N_quad bytes to
+ * 32; the results equal those of the stored tensors up to FP32 rounding.
+ *   eps, bx, by: the constant convection-diffusion coefficients, as
+ *     vpinn_assemble_cd2d (1, 0, 0: Poisson, where a trainable eps is accepted);
+ *   variable_diffusion = 1: the space-dependent operator of vpinn_assemble_vardiff
+ *     (eps ignored; the network's second output is the coefficient).
+ * Needs quad_order <= 16 (N_quad <= 256); the fused path only (the plain path and
+ * vpinn_residual return VPINN_E_UNSUPPORTED, vpinn_read_tensor of G or M
+ * VPINN_E_INVALID).  Errors: as vpinn_assemble_cd2d, plus VPINN_E_UNSUPPORTED for
+ * quad_order > 16.
+ */
+vpinn_status vpinn_assemble_matrix_free(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double eps,
+                                        double bx, double by, int32_t variable_diffusion,
+                                        const vpinn_forcing *forcing, void *stream, vpinn_problem **out);
+
+/*
  * Dirichlet points x_b and values g_b of the boundary term (Sec. 2.2), and
  * sensor points x_s with observations d_s of the data term of the inverse
  * problem (Sec. 4.7).  Host arrays xy [n][2] and values [n] are copied to the
@@ -160,6 +181,7 @@ typedef struct vpinn_problem_info {
                                         stored once (Algorithm 2's reference premultiplier) */
     int32_t variable_diffusion;      /* 1: from vpinn_assemble_vardiff (diffusion = 0: it is the
                                         network's second output) */
+    int32_t matrix_free;             /* 1: from vpinn_assemble_matrix_free (no G stored) */
 } vpinn_problem_info;
 
 vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info);

@@ -163,8 +163,8 @@ int64_t vpinn_n_params_out(int32_t width, int32_t n_hidden, int32_t n_outputs) {
 const char *vpinn_last_error(void) { return vp::g_err.c_str(); }
 
 static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double diff,
-                                      double conv_x, double conv_y, bool vardiff, const vpinn_forcing *forcing,
-                                      void *stream, vpinn_problem **out) {
+                                      double conv_x, double conv_y, bool vardiff, bool matfree,
+                                      const vpinn_forcing *forcing, void *stream, vpinn_problem **out) {
     using namespace vp;
     if (!out) return fail(VPINN_E_INVALID, "out is null");
     *out = nullptr;
@@ -174,6 +174,8 @@ static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order
         return fail(VPINN_E_INVALID, "quad_order must be in 2.." + std::to_string(VPINN_MAX_QUAD_ORDER));
     if (test_order < 1 || test_order > VPINN_MAX_TEST_ORDER)
         return fail(VPINN_E_INVALID, "test_order must be in 1.." + std::to_string(VPINN_MAX_TEST_ORDER));
+    if (matfree && quad_order > 16)
+        return fail(VPINN_E_UNSUPPORTED, "the matrix-free contraction needs quad_order <= 16");
     if (!forcing) return fail(VPINN_E_INVALID, "forcing is null");
     if (forcing->kind == VPINN_FORCING_CALLBACK) {
         if (!forcing->fn) return fail(VPINN_E_INVALID, "callback forcing without a function");
@@ -187,7 +189,8 @@ static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order
     if (st) return st;
     const int64_t nq = (int64_t)quad_order * quad_order, ntest = (int64_t)test_order * test_order;
     const int64_t n_elem = mesh->n_elem;
-    if (n_elem > (int64_t(1) << 40) / (nq * ntest)) return fail(VPINN_E_INVALID, "tensor size overflows");
+    if (n_elem > (int64_t(1) << 40) / (matfree ? nq : nq * ntest))
+        return fail(VPINN_E_INVALID, "tensor size overflows");
 
     ProblemWithSets *p = new (std::nothrow) ProblemWithSets();
     if (!p) return fail(VPINN_E_NOMEM, "host allocation failed");
@@ -212,14 +215,19 @@ static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order
         p->conv_x = conv_x;
         p->conv_y = conv_y;
     }
-    p->shared_g = !vardiff && congruent_elements(mesh);
+    p->matfree = matfree;
+    p->shared_g = !vardiff && !matfree && congruent_elements(mesh);
     hipStream_t s = (hipStream_t)stream;
     const size_t gbytes = sizeof(float) * (size_t)((p->shared_g ? 1 : n_elem) * ntest * nq);
-    if (p->Gx.reserve(gbytes) != hipSuccess || p->Gy.reserve(gbytes) != hipSuccess ||
-        p->F.reserve(sizeof(float) * n_elem * ntest) != hipSuccess ||
-        p->pts.reserve(sizeof(float2) * p->n_pts) != hipSuccess ||
-        (vardiff && p->M.reserve(sizeof(float) * (size_t)(n_elem * ntest * nq)) != hipSuccess))
-        return bail(fail(VPINN_E_NOMEM, "device allocation of the assembled tensors failed"));
+    bool ok = p->F.reserve(sizeof(float) * n_elem * ntest) == hipSuccess &&
+              p->pts.reserve(sizeof(float2) * p->n_pts) == hipSuccess;
+    if (matfree)
+        ok = ok && p->geo.reserve(sizeof(float) * 8 * (size_t)n_elem) == hipSuccess &&
+             p->tab.reserve(sizeof(float) * (size_t)(2 * quad_order + 2 * quad_order * test_order)) == hipSuccess;
+    else
+        ok = ok && p->Gx.reserve(gbytes) == hipSuccess && p->Gy.reserve(gbytes) == hipSuccess &&
+             (!vardiff || p->M.reserve(sizeof(float) * (size_t)(n_elem * ntest * nq)) == hipSuccess);
+    if (!ok) return bail(fail(VPINN_E_NOMEM, "device allocation of the assembled tensors failed"));
     DevBuf d_nodes, d_quad;
     if (d_nodes.reserve(sizeof(double) * 2 * mesh->n_nodes) != hipSuccess ||
         d_quad.reserve(sizeof(int32_t) * 4 * n_elem) != hipSuccess)
@@ -235,18 +243,29 @@ static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order
 
 vpinn_status vpinn_assemble(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order,
                             const vpinn_forcing *forcing, void *stream, vpinn_problem **out) {
-    return assemble_operator(mesh, quad_order, test_order, 1.0, 0.0, 0.0, false, forcing, stream, out);
+    return assemble_operator(mesh, quad_order, test_order, 1.0, 0.0, 0.0, false, false, forcing, stream, out);
+}
+
+vpinn_status vpinn_assemble_matrix_free(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double eps,
+                                        double bx, double by, int32_t variable_diffusion,
+                                        const vpinn_forcing *forcing, void *stream, vpinn_problem **out) {
+    if (variable_diffusion != 0 && variable_diffusion != 1) {
+        if (out) *out = nullptr;
+        return vp::fail(VPINN_E_INVALID, "variable_diffusion must be 0 or 1");
+    }
+    return assemble_operator(mesh, quad_order, test_order, variable_diffusion ? 1.0 : eps, bx, by,
+                             variable_diffusion == 1, true, forcing, stream, out);
 }
 
 vpinn_status vpinn_assemble_vardiff(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double bx,
                                     double by, const vpinn_forcing *forcing, void *stream, vpinn_problem **out) {
-    return assemble_operator(mesh, quad_order, test_order, 1.0, bx, by, true, forcing, stream, out);
+    return assemble_operator(mesh, quad_order, test_order, 1.0, bx, by, true, false, forcing, stream, out);
 }
 
 vpinn_status vpinn_assemble_cd2d(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double eps,
                                  double bx, double by, const vpinn_forcing *forcing, void *stream,
                                  vpinn_problem **out) {
-    return assemble_operator(mesh, quad_order, test_order, eps, bx, by, false, forcing, stream, out);
+    return assemble_operator(mesh, quad_order, test_order, eps, bx, by, false, false, forcing, stream, out);
 }
 
 vpinn_status vpinn_set_boundary(vpinn_problem *pp, int64_t n, const double *xy, const double *g) {
@@ -297,6 +316,7 @@ vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info) {
     info->velocity_y = p->vardiff ? p->vd_by : p->conv_y;
     info->shared_premultiplier = p->shared_g ? 1 : 0;
     info->variable_diffusion = p->vardiff ? 1 : 0;
+    info->matrix_free = p->matfree ? 1 : 0;
     return VPINN_OK;
 }
 
@@ -305,6 +325,8 @@ vpinn_status vpinn_read_tensor(const vpinn_problem *p, int32_t which, float *hos
     if (!p || !host_dst) return fail(VPINN_E_INVALID, "null argument");
     const void *src = nullptr;
     int64_t want = 0;
+    if (p->matfree && (which == VPINN_TENSOR_GX || which == VPINN_TENSOR_GY || which == VPINN_TENSOR_M))
+        return fail(VPINN_E_INVALID, "a matrix-free problem stores no G or M");
     switch (which) {
     case VPINN_TENSOR_GX: src = p->Gx.ptr; want = p->n_elem * p->ntest * p->nq; break;
     case VPINN_TENSOR_GY: src = p->Gy.ptr; want = p->n_elem * p->ntest * p->nq; break;
@@ -359,6 +381,8 @@ static vpinn_status check_outputs(const vpinn_problem *p, const vpinn_loss_cfg *
         return fail(VPINN_E_UNSUPPORTED, "space-dependent diffusion runs on the fused path only");
     if (two && scalar_eps)
         return fail(VPINN_E_INVALID, "a space-dependent diffusion problem takes no scalar eps");
+    if (p->matfree && cfg->path != VPINN_PATH_FUSED)
+        return fail(VPINN_E_UNSUPPORTED, "a matrix-free problem runs on the fused path only");
     return VPINN_OK;
 }
 
@@ -391,6 +415,7 @@ vpinn_status vpinn_residual(vpinn_problem *p, const vpinn_loss_cfg *cfg, const f
     if (st) return st;
     if (p->vardiff || cfg->n_outputs == 2)
         return fail(VPINN_E_UNSUPPORTED, "vpinn_residual (plain path) has no space-dependent diffusion");
+    if (p->matfree) return fail(VPINN_E_UNSUPPORTED, "vpinn_residual (plain path) needs the stored G");
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
     return plain_loss_grad(p, cfg, d_params, d_eps, nullptr, nullptr, nullptr, d_R, (hipStream_t)stream);

@@ -158,8 +158,8 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(
                 f = f_vals[e * nq + q];
             }
             wdf[threadIdx.x] = w * D * f;
-            // a shared premultiplier is written once, from element 0
-            for (int s = 0; s < ((shared_g && e > 0) ? 0 : nt); ++s) {
+            // a shared premultiplier is written once, from element 0; none for matrix-free problems
+            for (int s = 0; s < ((Gx == nullptr || (shared_g && e > 0)) ? 0 : nt); ++s) {
                 const double ps = phi[s * n + j], dps = dphi[s * n + j];
                 for (int r = 0; r < nt; ++r) {
                     const double pr = phi[r * n + i], dpr = dphi[r * n + i];
@@ -192,6 +192,39 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(
         const int k = threadIdx.x + m * kAsmThreads;
         if (k < ntest) F[e * ntest + k] = (float)Fk[m];
     }
+}
+
+// matrix-free problems: the bilinear map's coefficients of each element (xc1, xc2, xc3,
+// yc1, yc2, yc3, xc0, yc0; the Jacobian needs only the first six) ...
+__global__ void k_geometry(const double *__restrict__ nodes, const int32_t *__restrict__ quad, int64_t n_elem,
+                           float *__restrict__ geo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_elem) return;
+    const Geo g = load_geo(nodes, quad, e);
+    float *o = geo + e * 8;
+    o[0] = (float)g.xc[1];
+    o[1] = (float)g.xc[2];
+    o[2] = (float)g.xc[3];
+    o[3] = (float)g.yc[1];
+    o[4] = (float)g.yc[2];
+    o[5] = (float)g.yc[3];
+    o[6] = (float)g.xc[0];
+    o[7] = (float)g.yc[0];
+}
+
+// ... and the 1D tables in FP32: nodes [n], weights [n], phi [nt][n], phi' [nt][n]
+__global__ void k_tables_f32(const double *__restrict__ xg, const double *__restrict__ wg,
+                             const double *__restrict__ phi, const double *__restrict__ dphi, int n, int nt,
+                             float *__restrict__ tab) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nn = n * nt;
+    if (t >= 2 * n + 2 * nn) return;
+    double v;
+    if (t < n) v = xg[t];
+    else if (t < 2 * n) v = wg[t - n];
+    else if (t < 2 * n + nn) v = phi[t - 2 * n];
+    else v = dphi[t - 2 * n - nn];
+    tab[t] = (float)v;
 }
 
 vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_nodes, const int32_t *d_quad,
@@ -237,9 +270,18 @@ vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_
     k_assemble<<<dim3((unsigned)p->n_elem), kAsmThreads, 0, s>>>(
         d_nodes, d_quad, n, nt, d_xg.as<double>(), d_wg.as<double>(), d_phi.as<double>(), d_dphi.as<double>(),
         f->kind, f->amp, f->kx, f->ky, callback ? d_f.as<double>() : nullptr, p->diff, p->conv_x, p->conv_y,
-        p->shared_g ? 1 : 0, p->Gx.as<float>(), p->Gy.as<float>(), p->F.as<float>(),
-        p->vardiff ? p->M.as<float>() : nullptr);
+        p->shared_g ? 1 : 0, p->matfree ? nullptr : p->Gx.as<float>(), p->matfree ? nullptr : p->Gy.as<float>(),
+        p->F.as<float>(), (p->vardiff && !p->matfree) ? p->M.as<float>() : nullptr);
     VP_HIP(hipGetLastError());
+    if (p->matfree) {
+        k_geometry<<<dim3((unsigned)((p->n_elem + 255) / 256)), 256, 0, s>>>(d_nodes, d_quad, p->n_elem,
+                                                                          p->geo.as<float>());
+        VP_HIP(hipGetLastError());
+        const int ntab = 2 * n + 2 * n * nt;
+        k_tables_f32<<<dim3((unsigned)((ntab + 255) / 256)), 256, 0, s>>>(
+            d_xg.as<double>(), d_wg.as<double>(), d_phi.as<double>(), d_dphi.as<double>(), n, nt, p->tab.as<float>());
+        VP_HIP(hipGetLastError());
+    }
     VP_HIP(hipStreamSynchronize(s));
     return VPINN_OK;
 }

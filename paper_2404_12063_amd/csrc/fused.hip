@@ -60,7 +60,8 @@ constexpr int kRowQ = 4;             // quadrature points per lane in the row-st
 // (nq <= kCThreads, ntest <= kKB); wavefront per test-function row, G read once,
 // with Q = 1, 2 or 4 points a lane (nq <= 64 Q; one kernel per Q keeps each at
 // the occupancy its registers allow); two passes over G for larger elements
-enum { kPathFast = 0, kPathRows1 = 1, kPathRows2 = 2, kPathRows4 = 3, kPathGeneric = 4, kNumPaths = 5 };
+// (and a matrix-free path, wavefront per element, for problems that store no G)
+enum { kPathFast = 0, kPathRows1 = 1, kPathRows2 = 2, kPathRows4 = 3, kPathGeneric = 4, kPathMF = 5, kNumPaths = 6 };
 constexpr int kCbs = kCThreads + 1;  // row stride of the per-point term buffer
 
 // NH = 2: the network has a second linear output, the space-dependent diffusion
@@ -131,9 +132,12 @@ struct InstDesc {
     int64_t cblk0, n_chunks;  // contraction blocks cblk0 .. (epc elements each)
     int64_t gstride;          // floats between elements in G_x, G_y (0: one shared premultiplier)
     const float *M;           // space-dependent diffusion: convection weights w_q det J v_k (else null)
-    float cbx, cby;           // and the velocity
+    float cbx, cby;           // and the velocity (also of a matrix-free problem)
+    const float *geo, *tab;   // matrix-free: bilinear map coefficients [n_elem][8], 1D tables
+    float kdiff;              // matrix-free: constant diffusion coefficient
+    int qn, tn;               // matrix-free: quadrature points and test functions per direction
     int nq, ntest, epc;
-    int path;                 // contraction path (kPathFast .. kPathGeneric)
+    int path;                 // contraction path (kPathFast .. kPathMF)
     // loss partial rows lrow0 .. lrow0 + ln_rows - 1: first one per tile block
     // (gblk0 ..), then one per contraction block
     int lrow0, ln_rows;
@@ -942,6 +946,127 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
     contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
 }
 
+// Matrix-free contraction: no stored G; one wavefront per element rebuilds it from
+// the element's bilinear map by sum factorisation.  With v_k = phi_r(xi) phi_s(eta)
+// (k = s N_t + r), Jacobian entries a, b, c, d at point (i, j) and w = w_i w_j,
+//   sum_q (u_x G_x + u_y G_y)[k, q]
+//     = sum_{i,j} P_ij phi_r'(xi_i) phi_s(eta_j) + Q_ij phi_r(xi_i) phi_s'(eta_j),
+//   P = kd w (d u_x - c u_y),  Q = kd w (a u_y - b u_x),
+// kd the constant diffusion coefficient (or e_q of a space-dependent one); the
+// convection term adds Mq = w det J (b . grad u) against phi_r phi_s.  Each double
+// sum runs along xi first (N_t n partial sums per array, in LDS), then along eta:
+// 2 (N_t n^2 + N_t^2 n) multiply-adds an element instead of 2 N_t^2 n^2, and no G
+// from HBM.  The adjoint applies the transposed transforms to 2 c_v R.
+template <bool VAR>
+__global__ __launch_bounds__(kCThreads) void k_contract_mf(ContractArgs A) {
+    extern __shared__ float dyn[];
+    __shared__ double lp[kCWaves][2];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const ContractCtx c = contract_ctx(A);
+    const InstDesc *Ip = c.I;
+    const int n = Ip->qn, nt = Ip->tn, nq = n * n, ntest = nt * nt, nn = nt * n;
+    const int ntab = 2 * n + 2 * nn;
+    float *tab = dyn;  // nodes [n], weights [n], phi [nt][n], phi' [nt][n]
+    for (int t = tid; t < ntab; t += kCThreads) tab[t] = Ip->tab[t];
+    const float *xg = tab, *wg = tab + n, *ph = tab + 2 * n, *dph = tab + 2 * n + nn;
+    // per wavefront: P, Q, Mq [nq] | V, W [nt][n] (then the adjoint's X1, X2) | 2 c_v R [ntest]
+    float *Pv = dyn + ntab + wave * (3 * nq + 2 * nn + ntest);
+    float *Qv = Pv + nq, *Mv = Qv + nq, *Vv = Mv + nq, *Wv = Vv + nn, *rb = Wv + nn;
+    __syncthreads();
+    const int64_t e = c.e0 + wave;
+    double lrr = 0.0, lra = 0.0;
+    if (e < Ip->n_elem) {
+        const float *gp = Ip->geo + e * 8;
+        const float x1 = gp[0], x2 = gp[1], x3 = gp[2], y1 = gp[3], y2 = gp[4], y3 = gp[5];
+        const float eps = c.eps, two_cv = Ip->two_cv, kdiff = Ip->kdiff, cbx = Ip->cbx, cby = Ip->cby;
+        float2 *__restrict__ ub = A.ubuf + Ip->ubase + e * nq;
+        float *__restrict__ eb = VAR ? A.ebuf + Ip->ubase + e * nq : nullptr;
+        // Jacobian entries and weight at point q = j n + i
+        auto geom = [&](int q, float &a, float &b, float &cc, float &d, float &w) {
+            const int j = q / n, i = q - j * n;
+            const float xi = xg[i], eta = xg[j];
+            w = wg[i] * wg[j];
+            a = fmaf(x3, eta, x1);
+            b = fmaf(y3, eta, y1);
+            cc = fmaf(x3, xi, x2);
+            d = fmaf(y3, xi, y2);
+        };
+        for (int q = lane; q < nq; q += 64) {
+            float a, b, cc, d, w;
+            geom(q, a, b, cc, d, w);
+            const float2 g = ub[q];
+            const float kd = VAR ? eb[q] : kdiff;
+            Pv[q] = kd * w * (d * g.x - cc * g.y);
+            Qv[q] = kd * w * (a * g.y - b * g.x);
+            Mv[q] = w * (a * d - b * cc) * fmaf(cbx, g.x, cby * g.y);
+        }
+        wave_sync();
+        // along xi: V[r][j] = sum_i P_ij phi_r'(xi_i) + Mq_ij phi_r(xi_i),  W[r][j] = sum_i Q_ij phi_r(xi_i)
+        for (int t = lane; t < nn; t += 64) {
+            const int r = t / n, j = t - r * n;
+            const float *pr = ph + r * n, *dpr = dph + r * n;
+            const float *Pj = Pv + j * n, *Qj = Qv + j * n, *Mj = Mv + j * n;
+            float v = 0.f, wv = 0.f;
+            for (int i = 0; i < n; ++i) {
+                v = fmaf(Pj[i], dpr[i], fmaf(Mj[i], pr[i], v));
+                wv = fmaf(Qj[i], pr[i], wv);
+            }
+            Vv[t] = v;
+            Wv[t] = wv;
+        }
+        wave_sync();
+        // along eta: A_k = sum_j V[r][j] phi_s(eta_j) + W[r][j] phi_s'(eta_j)
+        const float *__restrict__ F = Ip->F + e * ntest;
+        for (int k = lane; k < ntest; k += 64) {
+            const int s = k / nt, r = k - s * nt;
+            const float *Vr = Vv + r * n, *Wr = Wv + r * n, *ps = ph + s * n, *dps = dph + s * n;
+            float a = 0.f;
+            for (int j = 0; j < n; ++j) a = fmaf(Vr[j], ps[j], fmaf(Wr[j], dps[j], a));
+            const float R = eps * a - F[k];
+            rb[k] = two_cv * R;
+            lrr += (double)R * (double)R;
+            lra += (double)R * (double)a;
+        }
+        if (A.want_grad) {
+            wave_sync();
+            // transposed, along eta: X1[r][j] = sum_s rb_rs phi_s(eta_j), X2[r][j] = sum_s rb_rs phi_s'(eta_j)
+            for (int t = lane; t < nn; t += 64) {
+                const int r = t / n, j = t - r * n;
+                float s1 = 0.f, s2 = 0.f;
+                for (int s = 0; s < nt; ++s) {
+                    const float rv = rb[s * nt + r];
+                    s1 = fmaf(rv, ph[s * n + j], s1);
+                    s2 = fmaf(rv, dph[s * n + j], s2);
+                }
+                Vv[t] = s1;
+                Wv[t] = s2;
+            }
+            wave_sync();
+            // along xi at each point: S_xi = sum_r phi_r'(xi_i) X1, S_eta = sum_r phi_r(xi_i) X2,
+            // S_v = sum_r phi_r(xi_i) X1; then dL/du = eps (kd (G_x, G_y)-sums + b Mq-sum)
+            for (int q = lane; q < nq; q += 64) {
+                float a, b, cc, d, w;
+                geom(q, a, b, cc, d, w);
+                const int j = q / n, i = q - j * n;
+                float sxi = 0.f, seta = 0.f, sv = 0.f;
+                for (int r = 0; r < nt; ++r) {
+                    const float x1v = Vv[r * n + j], x2v = Wv[r * n + j], p = ph[r * n + i];
+                    sxi = fmaf(dph[r * n + i], x1v, sxi);
+                    seta = fmaf(p, x2v, seta);
+                    sv = fmaf(p, x1v, sv);
+                }
+                const float gx = w * (d * sxi - b * seta), gy = w * (a * seta - cc * sxi);
+                const float gm = w * (a * d - b * cc) * sv;
+                const float2 g = ub[q];
+                const float kd = VAR ? eb[q] : kdiff;
+                ub[q] = make_float2(eps * fmaf(kd, gx, cbx * gm), eps * fmaf(kd, gy, cby * gm));
+                if (VAR) eb[q] = fmaf(g.x, gx, g.y * gy);
+            }
+        }
+    }
+    contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
+}
+
 // one wavefront's gradient sums in padded order -> P (op: store, or add to what P holds)
 template <int L, bool ADD, int NH>
 __device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const float (*VA)[64], int lane) {
@@ -1242,6 +1367,7 @@ struct FusedPlan {
     int64_t cblocks = 0, tiles = 0, npf = 0;
     int64_t cpath_blocks[kNumPaths] = {};  // contraction blocks of each path, in path order
     size_t cdyn_fast = 0, cdyn_generic = 0;  // dynamic LDS of k_contract_fast / k_contract_generic
+    size_t cdyn_mf = 0;                      // and of k_contract_mf
 };
 
 static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_loss_cfg *cfg, int dev,
@@ -1252,7 +1378,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     const int cus = cu_count(dev);
     std::vector<InstDesc> D(n);
     int64_t tiles = 0, ubase = 0, cblocks = 0;
-    size_t cdyn_fast = 16, cdyn_generic = 16;
+    size_t cdyn_fast = 16, cdyn_generic = 16, cdyn_mf = 16;
     for (int i = 0; i < n; ++i) {
         const vpinn_problem *p = probs[i];
         const int64_t tot = p->n_pts + p->n_bnd + p->n_sen;
@@ -1276,9 +1402,9 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         d.ntest = p->ntest;
         d.gstride = p->gstride();
         if (nh == 2) {
-            // the small-element contraction is the only one with the space-dependent term
+            // the small-element and matrix-free contractions are the ones with the space-dependent term
             if (!p->vardiff) return fail(VPINN_E_INVALID, "two network outputs need space-dependent diffusion problems");
-            if (!(p->nq <= kCThreads && p->ntest <= kKB))
+            if (!p->matfree && !(p->nq <= kCThreads && p->ntest <= kKB))
                 return fail(VPINN_E_UNSUPPORTED, "space-dependent diffusion needs N_quad <= " +
                                                      std::to_string(kCThreads) + " and N_test <= " +
                                                      std::to_string(kKB));
@@ -1286,16 +1412,33 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
             d.cbx = (float)p->vd_bx;
             d.cby = (float)p->vd_by;
         }
-        d.path = (p->nq <= kCThreads && p->ntest <= kKB) ? kPathFast
+        if (p->matfree) {
+            d.geo = p->geo.as<float>();
+            d.tab = p->tab.as<float>();
+            d.kdiff = (float)p->diff;
+            d.cbx = (float)(p->vardiff ? p->vd_bx : p->conv_x);
+            d.cby = (float)(p->vardiff ? p->vd_by : p->conv_y);
+            d.qn = p->n;
+            d.tn = p->nt;
+        }
+        d.path = p->matfree                               ? kPathMF
+                 : (p->nq <= kCThreads && p->ntest <= kKB) ? kPathFast
                  : (p->nq <= 64)                          ? kPathRows1
                  : (p->nq <= 128)                         ? kPathRows2
                  : (p->nq <= 64 * kRowQ)                  ? kPathRows4
                                                           : kPathGeneric;
-        d.epc = d.path == kPathFast ? std::max(1, (kCThreads / p->nq) >> tune.chunk_shift) : 1;
+        d.epc = d.path == kPathFast ? std::max(1, (kCThreads / p->nq) >> tune.chunk_shift)
+                : d.path == kPathMF ? kCWaves
+                                    : 1;
         d.n_chunks = (p->n_elem + d.epc - 1) / d.epc;
         if (d.path == kPathFast)
             cdyn_fast = std::max(cdyn_fast, sizeof(float) * ((size_t)d.ntest * kCbs + (size_t)d.epc * d.ntest));
         if (d.path == kPathGeneric) cdyn_generic = std::max(cdyn_generic, sizeof(float) * (size_t)d.ntest);
+        if (d.path == kPathMF) {
+            const size_t nn = (size_t)p->n * p->nt;
+            cdyn_mf = std::max(cdyn_mf, sizeof(float) * (2 * (size_t)p->n + 2 * nn +
+                                                         kCWaves * (3 * (size_t)p->nq + 2 * nn + (size_t)p->ntest)));
+        }
         d.cv = cfg->loss_norm == VPINN_NORM_ELEM ? 1.0 / (double)p->n_elem : 1.0 / (double)p->ntest;
         d.two_cv = (float)(2.0 * d.cv);
         d.wb2 = p->n_bnd ? (float)(2.0 * cfg->tau / (double)p->n_bnd) : 0.f;
@@ -1313,7 +1456,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
                 cpath_blocks[path] += D[i].n_chunks;
             }
     if (cblocks > (int64_t)INT32_MAX) return fail(VPINN_E_UNSUPPORTED, "fused path: too many elements for one launch");
-    if (cdyn_fast > 64 * 1024 || cdyn_generic > 64 * 1024)
+    if (cdyn_fast > 64 * 1024 || cdyn_generic > 64 * 1024 || cdyn_mf > 64 * 1024)
         return fail(VPINN_E_UNSUPPORTED, "fused path: test-function count exceeds the LDS budget");
     // tile blocks (k_fwd and k_bwd): one per CU, equal shares of the tile list
     const int tblocks = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus, kMaxBlocks), tiles);
@@ -1364,6 +1507,11 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cdyn_fast);
         if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     }
+    if (cdyn_mf > 48 * 1024) {
+        const void *fn = nh == 2 ? (const void *)k_contract_mf<true> : (const void *)k_contract_mf<false>;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cdyn_mf);
+        if (e != hipSuccess) return fail(VPINN_E_DEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
     P.host_inst = D;
     P.tblocks = tblocks;
     P.cblocks = cblocks;
@@ -1378,6 +1526,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     for (int k = 0; k < kNumPaths; ++k) P.cpath_blocks[k] = cpath_blocks[k];
     P.cdyn_fast = cdyn_fast;
     P.cdyn_generic = cdyn_generic;
+    P.cdyn_mf = cdyn_mf;
     return VPINN_OK;
 }
 
@@ -1416,6 +1565,9 @@ static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs
         c.cblk_base += P.cpath_blocks[kPathRows4];
         if (P.cpath_blocks[kPathGeneric])
             k_contract_generic<<<(unsigned)P.cpath_blocks[kPathGeneric], kCThreads, P.cdyn_generic, s>>>(c);
+        c.cblk_base += P.cpath_blocks[kPathGeneric];
+        if (P.cpath_blocks[kPathMF])
+            k_contract_mf<NH == 2><<<(unsigned)P.cpath_blocks[kPathMF], kCThreads, P.cdyn_mf, s>>>(c);
     }
     if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
     if (want_grad) k_bwd<L, NH><<<P.tblocks, kBThreads, 0, s>>>(ba);

@@ -104,6 +104,10 @@ struct vpinn_problem {
     bool vardiff = false;
     double vd_bx = 0.0, vd_by = 0.0;
     vp::DevBuf M;            // float [n_elem][ntest][nq] (vardiff only)
+    // matrix-free: no G or M; the bilinear map's coefficients and the 1D tables
+    bool matfree = false;
+    vp::DevBuf geo;          // float [n_elem][8]: xc1, xc2, xc3, yc1, yc2, yc3, xc0, yc0
+    vp::DevBuf tab;          // float [2 n + 2 nt n]: GLL nodes, weights, phi_r(x_i), phi_r'(x_i)
     int64_t gstride() const { return shared_g ? 0 : (int64_t)ntest * nq; }
     vp::DevBuf Gx, Gy, F;    // float
     vp::DevBuf pts;          // float2 [n_pts + n_bnd + n_sen]: interior, boundary, sensors

@@ -52,7 +52,7 @@ class vpinn_problem_info(C.Structure):
                 ("n_points", C.c_int64), ("n_boundary", C.c_int64), ("n_sensors", C.c_int64),
                 ("quad_order", C.c_int32), ("test_order", C.c_int32),
                 ("diffusion", C.c_double), ("velocity_x", C.c_double), ("velocity_y", C.c_double),
-                ("shared_premultiplier", C.c_int32), ("variable_diffusion", C.c_int32)]
+                ("shared_premultiplier", C.c_int32), ("variable_diffusion", C.c_int32), ("matrix_free", C.c_int32)]
 
 
 class vpinn_loss_cfg(C.Structure):
@@ -87,6 +87,9 @@ _SIGNATURES = {
     "vpinn_read_tensor": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
     "vpinn_assemble_vardiff": (C.c_int32, [C.POINTER(vpinn_mesh), C.c_int32, C.c_int32, C.c_double, C.c_double,
                                            C.POINTER(vpinn_forcing), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "vpinn_assemble_matrix_free": (C.c_int32, [C.POINTER(vpinn_mesh), C.c_int32, C.c_int32, C.c_double,
+                                               C.c_double, C.c_double, C.c_int32, C.POINTER(vpinn_forcing),
+                                               C.c_void_p, C.POINTER(C.c_void_p)]),
     "vpinn_n_params": (C.c_int64, [C.c_int32, C.c_int32]),
     "vpinn_n_params_out": (C.c_int64, [C.c_int32, C.c_int32, C.c_int32]),
     "vpinn_loss_and_grad": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_loss_cfg), C.c_void_p, C.c_void_p,
@@ -186,12 +189,12 @@ class Problem:
 
 
 def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0, kx: float = 0.0,
-                   ky: float = 0.0, fn=None, stream=None, cd=None, vardiff=None) -> Problem:
+                   ky: float = 0.0, fn=None, stream=None, cd=None, vardiff=None, matrix_free: bool = False) -> Problem:
     """xy: host [n_nodes, 2] float64; quad: host [n_elem, 4] int32.  Forcing is amp*sin(kx x)sin(ky y),
     or the Python callable fn(x, y) evaluated on the host (kind VPINN_FORCING_CALLBACK).
     cd = (eps, bx, by): the convection-diffusion operator -eps Lap u + b . grad u (vpinn_assemble_cd2d);
     vardiff = (bx, by): -div(eps(x, y) grad u) + b . grad u with eps the network's second output
-    (vpinn_assemble_vardiff)."""
+    (vpinn_assemble_vardiff).  matrix_free: store no G (vpinn_assemble_matrix_free), for any of the three."""
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     quad = np.ascontiguousarray(quad, dtype=np.int32)
     mesh = vpinn_mesh(xy.shape[0], xy.ctypes.data_as(C.POINTER(C.c_double)), quad.shape[0],
@@ -203,7 +206,14 @@ def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0,
         cb = SCALAR_FN(lambda x, y, u: float(fn(x, y)))
         f = vpinn_forcing(VPINN_FORCING_CALLBACK, 0.0, 0.0, 0.0, cb, None)
     out = C.c_void_p()
-    if vardiff is not None:
+    if matrix_free:
+        eps, bx, by = (1.0, 0.0, 0.0) if cd is None else (float(v) for v in cd)
+        if vardiff is not None:
+            bx, by = (float(v) for v in vardiff)
+        _check(lib().vpinn_assemble_matrix_free(C.byref(mesh), quad_order, test_order, eps, bx, by,
+                                                1 if vardiff is not None else 0, C.byref(f), _stream(stream),
+                                                C.byref(out)))
+    elif vardiff is not None:
         bx, by = (float(v) for v in vardiff)
         _check(lib().vpinn_assemble_vardiff(C.byref(mesh), quad_order, test_order, bx, by, C.byref(f),
                                             _stream(stream), C.byref(out)))
@@ -217,7 +227,7 @@ def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0,
     return Problem(out.value)
 
 
-def assemble_problem(prob, stream=None) -> Problem:
+def assemble_problem(prob, stream=None, matrix_free: bool = False) -> Problem:
     """Assemble a vpinn_inputs Problem (Poisson, convection-diffusion when it sets diff/conv, space-dependent
     diffusion when its network has two outputs) and upload its boundary and sensor sets."""
     diff, conv = getattr(prob, "diff", 1.0), tuple(getattr(prob, "conv", (0.0, 0.0)))
@@ -225,7 +235,7 @@ def assemble_problem(prob, stream=None) -> Problem:
     cd = None if two or (diff, conv) == (1.0, (0.0, 0.0)) else (diff, conv[0], conv[1])
     p = vpinn_assemble(prob.mesh.xy, prob.mesh.quad, prob.quad_order, prob.test_order, prob.f_amp, prob.f_kx,
                        prob.f_ky, fn=getattr(prob, "f_fn", None), stream=stream, cd=cd,
-                       vardiff=conv if two else None)
+                       vardiff=conv if two else None, matrix_free=matrix_free)
     vpinn_set_boundary(p, prob.bnd_xy, prob.bnd_g)
     if len(prob.sens_xy):
         vpinn_set_sensors(p, prob.sens_xy, prob.sens_u)

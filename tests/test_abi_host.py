@@ -177,3 +177,16 @@ def test_eval_heads_rejects_bad_outputs(V):
     assert L.vpinn_eval_network_heads(30, 3, 3, one, 0, None, None, None, None, None, None) == V.VPINN_E_INVALID
     assert L.vpinn_eval_network_heads(30, 3, 1, one, 0, None, None, None, None, one, None) == V.VPINN_E_INVALID
     assert L.vpinn_eval_network_heads(33, 3, 2, one, 0, None, None, None, None, None, None) == V.VPINN_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n,vd,code", [(17, 0, "VPINN_E_UNSUPPORTED"), (4, 2, "VPINN_E_INVALID")])
+def test_matrix_free_rejects_before_device_work(V, n, vd, code):
+    m = gen.square_mesh(2, 2)
+    xy = np.ascontiguousarray(m.xy, dtype=np.float64)
+    quad = np.ascontiguousarray(m.quad, dtype=np.int32)
+    mesh = V.vpinn_mesh(xy.shape[0], xy.ctypes.data_as(C.POINTER(C.c_double)), quad.shape[0],
+                        quad.ctypes.data_as(C.POINTER(C.c_int32)))
+    f = V.vpinn_forcing(1, 1.0, 1.0, 1.0, V.SCALAR_FN(0), None)
+    out = C.c_void_p()
+    rc = V.lib().vpinn_assemble_matrix_free(C.byref(mesh), n, 3, 1.0, 0.0, 0.0, vd, C.byref(f), None, C.byref(out))
+    assert rc == getattr(V, code) and not out.value
