@@ -169,6 +169,24 @@ vpinn_status vpinn_assemble_matrix_free(const vpinn_mesh *mesh, int32_t quad_ord
  * Synchronous.  Errors: VPINN_E_INVALID, VPINN_E_NOMEM, VPINN_E_DEVICE.
  */
 vpinn_status vpinn_set_boundary(vpinn_problem *p, int64_t n, const double *xy, const double *g);
+/*
+ * vpinn_set_shared_points -- with enable = 1, the fused path evaluates the network
+ * once per distinct interior quadrature point instead of once per (element, point)
+ * slot: GLL points on an edge or a vertex shared by several elements (Sec. 3.1
+ * places them at the same physical location) are found from the mesh topology
+ * (vertex ids, and the position along an edge from its lower-numbered vertex),
+ * the contraction reads each slot's (u_x, u_y) from its point, and the adjoints
+ * of a point's slots are added in slot order before the reverse sweep.  The
+ * result is that of per-slot evaluation up to FP32 rounding; the network work
+ * falls by up to 1 - ((n-1)/n)^2.  `mesh` must be the mesh the problem was
+ * assembled from (checked: element count, and every shared slot's point within
+ * 1e-6 of its partner's).  enable = 0 returns to per-slot evaluation.  The plain
+ * path ignores the setting.
+ * Errors: VPINN_E_INVALID (null, counts differ), VPINN_E_MESH (a shared slot's
+ * point differs), VPINN_E_DEVICE.
+ */
+vpinn_status vpinn_set_shared_points(vpinn_problem *p, const vpinn_mesh *mesh, int32_t enable);
+
 vpinn_status vpinn_set_sensors(vpinn_problem *p, int64_t n, const double *xy, const double *d);
 
 typedef struct vpinn_problem_info {
@@ -182,6 +200,7 @@ typedef struct vpinn_problem_info {
     int32_t variable_diffusion;      /* 1: from vpinn_assemble_vardiff (diffusion = 0: it is the
                                         network's second output) */
     int32_t matrix_free;             /* 1: from vpinn_assemble_matrix_free (no G stored) */
+    int64_t n_distinct_points;       /* vpinn_set_shared_points: distinct interior points (0: off) */
 } vpinn_problem_info;
 
 vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info);

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -94,6 +95,63 @@ static bool congruent_elements(const vpinn_mesh *m) {
     return true;
 }
 
+// Shared GLL points from the mesh topology: a vertex point is keyed by its vertex id,
+// an edge point by the edge's vertex pair and its position counted from the
+// lower-numbered vertex (the GLL nodes are symmetric, so both elements place it at
+// the same physical point), an element-interior point is its own.  Distinct points
+// are numbered in order of first appearance over slots s = e nq + q.
+static vpinn_status shared_point_map(const vpinn_mesh *m, int n, std::vector<int32_t> &umap, int64_t &n_uniq) {
+    const int nq = n * n;
+    const int64_t n_slots = m->n_elem * nq;
+    if (n_slots > INT32_MAX) return fail(VPINN_E_UNSUPPORTED, "too many quadrature points for shared points");
+    umap.assign((size_t)n_slots, -1);
+    std::vector<int32_t> vid((size_t)m->n_nodes, -1);
+    std::unordered_map<uint64_t, int64_t> edge_base;  // edge -> first of its n - 2 point ids in edge_ids
+    std::vector<int32_t> edge_ids;
+    int64_t next = 0;
+    // corners of the reference square in vertex order, and the edges (from vertex, to vertex)
+    // with the local index walked from the first: bottom (0 -> 1, i), right (1 -> 2, j),
+    // top (3 -> 2, i), left (0 -> 3, j)
+    for (int64_t e = 0; e < m->n_elem; ++e) {
+        const int32_t *v = m->quad + 4 * e;
+        for (int q = 0; q < nq; ++q) {
+            const int i = q % n, j = q / n;
+            const bool xi_end = i == 0 || i == n - 1, eta_end = j == 0 || j == n - 1;
+            int32_t *slot = &umap[(size_t)(e * nq + q)];
+            if (xi_end && eta_end) {
+                const int c = (j == 0) ? (i == 0 ? 0 : 1) : (i == 0 ? 3 : 2);
+                int32_t &id = vid[(size_t)v[c]];
+                if (id < 0) id = (int32_t)next++;
+                *slot = id;
+            } else if (xi_end || eta_end) {
+                int a, b, pos;
+                if (j == 0) a = 0, b = 1, pos = i;
+                else if (i == n - 1) a = 1, b = 2, pos = j;
+                else if (j == n - 1) a = 3, b = 2, pos = i;
+                else a = 0, b = 3, pos = j;
+                int64_t va = v[a], vb = v[b];
+                if (va > vb) {
+                    std::swap(va, vb);
+                    pos = n - 1 - pos;
+                }
+                const uint64_t key = (uint64_t)va * (uint64_t)m->n_nodes + (uint64_t)vb;
+                auto it = edge_base.find(key);
+                if (it == edge_base.end()) {
+                    it = edge_base.emplace(key, (int64_t)edge_ids.size()).first;
+                    edge_ids.resize(edge_ids.size() + (size_t)(n - 2), -1);
+                }
+                int32_t &id = edge_ids[(size_t)(it->second + pos - 1)];
+                if (id < 0) id = (int32_t)next++;
+                *slot = id;
+            } else {
+                *slot = (int32_t)next++;
+            }
+        }
+    }
+    n_uniq = next;
+    return VPINN_OK;
+}
+
 static vpinn_status rebuild_points(vpinn_problem *p, const std::vector<float> &bxy, const std::vector<float> &bg,
                                    const std::vector<float> &sxy, const std::vector<float> &sd, int64_t nb,
                                    int64_t ns) {
@@ -161,6 +219,71 @@ int64_t vpinn_n_params_out(int32_t width, int32_t n_hidden, int32_t n_outputs) {
 }
 
 const char *vpinn_last_error(void) { return vp::g_err.c_str(); }
+
+vpinn_status vpinn_set_shared_points(vpinn_problem *p, const vpinn_mesh *mesh, int32_t enable) {
+    using namespace vp;
+    if (!p) return fail(VPINN_E_INVALID, "problem is null");
+    if (enable != 0 && enable != 1) return fail(VPINN_E_INVALID, "enable must be 0 or 1");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the problem's device");
+    if (!enable) {
+        p->n_uniq = 0;
+        p->umap.release();
+        p->usoff.release();
+        p->uslot.release();
+        p->upts.release();
+        ++p->share_gen;
+        return VPINN_OK;
+    }
+    if (!mesh || !mesh->xy || !mesh->quad) return fail(VPINN_E_INVALID, "mesh is null");
+    if (mesh->n_elem != p->n_elem) return fail(VPINN_E_INVALID, "the mesh's element count differs from the problem's");
+    for (int64_t k = 0; k < 4 * mesh->n_elem; ++k)
+        if (mesh->quad[k] < 0 || mesh->quad[k] >= mesh->n_nodes)
+            return fail(VPINN_E_MESH, "element " + std::to_string(k / 4) + ": vertex index out of range");
+    std::vector<int32_t> umap;
+    int64_t n_uniq = 0;
+    vpinn_status st = shared_point_map(mesh, p->n, umap, n_uniq);
+    if (st) return st;
+    // the problem's own points: the first slot of each distinct point gives its
+    // coordinates, and every other slot must lie on it
+    std::vector<float2> pts((size_t)p->n_pts), upts((size_t)n_uniq);
+    VP_HIP(hipMemcpy(pts.data(), p->pts.ptr, sizeof(float2) * p->n_pts, hipMemcpyDeviceToHost));
+    std::vector<int32_t> first((size_t)n_uniq, -1), count((size_t)n_uniq + 1, 0);
+    for (int64_t s = 0; s < p->n_pts; ++s) {
+        const int32_t u = umap[(size_t)s];
+        if (first[(size_t)u] < 0) {
+            first[(size_t)u] = (int32_t)s;
+            upts[(size_t)u] = pts[(size_t)s];
+        } else {
+            const float2 a = pts[(size_t)s], b = upts[(size_t)u];
+            const float tol = 1e-6f * std::max(1.0f, std::max(std::fabs(b.x), std::fabs(b.y)));
+            if (std::fabs(a.x - b.x) > tol || std::fabs(a.y - b.y) > tol)
+                return fail(VPINN_E_MESH, "element " + std::to_string(s / p->nq) +
+                                              ": a shared quadrature point does not match its partner (not the "
+                                              "problem's mesh?)");
+        }
+        ++count[(size_t)u + 1];
+    }
+    for (int64_t u = 0; u < n_uniq; ++u) count[(size_t)u + 1] += count[(size_t)u];
+    std::vector<int32_t> slots((size_t)p->n_pts), fill(count.begin(), count.end() - 1);
+    for (int64_t s = 0; s < p->n_pts; ++s) slots[(size_t)fill[(size_t)umap[(size_t)s]]++] = (int32_t)s;
+    DevBuf dm, doff, dsl, dpts;
+    VP_HIP(dm.reserve(sizeof(int32_t) * p->n_pts));
+    VP_HIP(doff.reserve(sizeof(int32_t) * (n_uniq + 1)));
+    VP_HIP(dsl.reserve(sizeof(int32_t) * p->n_pts));
+    VP_HIP(dpts.reserve(sizeof(float2) * n_uniq));
+    VP_HIP(hipMemcpy(dm.ptr, umap.data(), sizeof(int32_t) * p->n_pts, hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(doff.ptr, count.data(), sizeof(int32_t) * (n_uniq + 1), hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(dsl.ptr, slots.data(), sizeof(int32_t) * p->n_pts, hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(dpts.ptr, upts.data(), sizeof(float2) * n_uniq, hipMemcpyHostToDevice));
+    p->umap = std::move(dm);
+    p->usoff = std::move(doff);
+    p->uslot = std::move(dsl);
+    p->upts = std::move(dpts);
+    p->n_uniq = n_uniq;
+    ++p->share_gen;
+    return VPINN_OK;
+}
 
 static vpinn_status assemble_operator(const vpinn_mesh *mesh, int32_t quad_order, int32_t test_order, double diff,
                                       double conv_x, double conv_y, bool vardiff, bool matfree,
@@ -317,6 +440,7 @@ vpinn_status vpinn_get_info(const vpinn_problem *p, vpinn_problem_info *info) {
     info->shared_premultiplier = p->shared_g ? 1 : 0;
     info->variable_diffusion = p->vardiff ? 1 : 0;
     info->matrix_free = p->matfree ? 1 : 0;
+    info->n_distinct_points = p->n_uniq;
     return VPINN_OK;
 }
 

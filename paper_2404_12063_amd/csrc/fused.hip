@@ -136,6 +136,12 @@ struct InstDesc {
     const float *geo, *tab;   // matrix-free: bilinear map coefficients [n_elem][8], 1D tables
     float kdiff;              // matrix-free: constant diffusion coefficient
     int qn, tn;               // matrix-free: quadrature points and test functions per direction
+    // shared points (else null): slot e nq + q reads point umap[slot]; the adjoint of
+    // the contraction goes per slot to adj (eadj: dL/de), and the slots of point u are
+    // uslot[usoff[u] .. usoff[u + 1]).  Unshared, adj and eadj are the point buffers.
+    const int *umap, *usoff, *uslot;
+    float2 *adj;
+    float *eadj;
     int nq, ntest, epc;
     int path;                 // contraction path (kPathFast .. kPathMF)
     // loss partial rows lrow0 .. lrow0 + ln_rows - 1: first one per tile block
@@ -664,6 +670,9 @@ __global__ __launch_bounds__(NW * 64, 1) void k_fwd(FwdArgs A) {
 //     with G read again (cache-resident by then).
 // In every case G is read from HBM once; loss partials go to one row per block.
 
+// point of slot s (shared points) or the slot itself
+__device__ __forceinline__ int64_t upoint(const InstDesc *I, int64_t s) { return I->umap ? (int64_t)I->umap[s] : s; }
+
 struct ContractCtx {
     const InstDesc *I;
     int64_t chunk, e0;
@@ -712,7 +721,8 @@ __global__ __launch_bounds__(kCThreads) void k_contract_fast(ContractArgs A) {
     const float *__restrict__ Gy = Ip->Gy;
     const float *__restrict__ F = Ip->F;
     const float two_cv = Ip->two_cv, eps = c.eps;
-    float2 *__restrict__ ub = A.ubuf + Ip->ubase;
+    // not restrict: unshared, the adjoint is written in place over these entries
+    const float2 *ub = A.ubuf + Ip->ubase;
     double lrr = 0.0, lra = 0.0;
     float *cbuf = dyn;                  // [ntest][kCbs] per-point terms
     float *rbar = dyn + ntest * kCbs;   // [ne][ntest] 2 c_v R
@@ -728,11 +738,12 @@ __global__ __launch_bounds__(kCThreads) void k_contract_fast(ContractArgs A) {
         gy[k] = ok ? Gy[gbase + (int64_t)k * nq] : 0.f;
         if (VAR) gm[k] = ok ? Mw[gbase + (int64_t)k * nq] : 0.f;
     }
-    const int64_t pi = (e0 + el) * nq + q;  // the thread's point
-    const float2 d = act ? ub[pi] : make_float2(0.f, 0.f);
+    const int64_t pi = (e0 + el) * nq + q;  // the thread's slot
+    const int64_t pu = act ? upoint(Ip, pi) : 0;
+    const float2 d = act ? ub[pu] : make_float2(0.f, 0.f);
     float ev = 0.f, bgu = 0.f;  // e_q and (b . grad u)_q
     if (VAR) {
-        ev = act ? A.ebuf[Ip->ubase + pi] : 0.f;
+        ev = act ? A.ebuf[Ip->ubase + pu] : 0.f;
         bgu = fmaf(Ip->cbx, d.x, Ip->cby * d.y);
     }
 #pragma unroll
@@ -769,10 +780,10 @@ __global__ __launch_bounds__(kCThreads) void k_contract_fast(ContractArgs A) {
                 if (VAR) bm = fmaf(rb[k], gm[k], bm);
             }
         if (VAR) {
-            ub[pi] = make_float2(fmaf(ev, bx, Ip->cbx * bm), fmaf(ev, by, Ip->cby * bm));
-            A.ebuf[Ip->ubase + pi] = fmaf(d.x, bx, d.y * by);
+            Ip->adj[pi] = make_float2(fmaf(ev, bx, Ip->cbx * bm), fmaf(ev, by, Ip->cby * bm));
+            Ip->eadj[pi] = fmaf(d.x, bx, d.y * by);
         } else {
-            ub[pi] = make_float2(eps * bx, eps * by);
+            Ip->adj[pi] = make_float2(eps * bx, eps * by);
         }
     }
     contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
@@ -840,13 +851,14 @@ __device__ __forceinline__ void contract_rows(const ContractArgs &A, const Contr
     const float *__restrict__ Gy = Ip->Gy;
     const float *__restrict__ F = Ip->F;
     const float two_cv = Ip->two_cv, eps = c.eps;
-    float2 *__restrict__ ub = A.ubuf + Ip->ubase;
+    // not restrict: unshared, the adjoint is written in place over these entries
+    const float2 *ub = A.ubuf + Ip->ubase;
     const int64_t e0 = c.e0, ebase = e0 * ntest, gbase = e0 * Ip->gstride;
     float ux[Q], uy[Q], bx[Q], by[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int q = lane + 64 * i;
-        const float2 d = q < nq ? ub[e0 * nq + q] : make_float2(0.f, 0.f);
+        const float2 d = q < nq ? ub[upoint(Ip, e0 * nq + q)] : make_float2(0.f, 0.f);
         ux[i] = d.x;
         uy[i] = d.y;
         bx[i] = 0.f;
@@ -874,7 +886,7 @@ __device__ __forceinline__ void contract_rows(const ContractArgs &A, const Contr
                     sx += bsum[((w * 2 + 0) * Q + i) * 64 + l];
                     sy += bsum[((w * 2 + 1) * Q + i) * 64 + l];
                 }
-                ub[e0 * nq + q] = make_float2(eps * sx, eps * sy);
+                Ip->adj[e0 * nq + q] = make_float2(eps * sx, eps * sy);
             }
         }
     }
@@ -903,11 +915,11 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
     const float *__restrict__ Gy = Ip->Gy;
     const float *__restrict__ F = Ip->F;
     const float two_cv = Ip->two_cv, eps = c.eps;
-    float2 *__restrict__ ub = A.ubuf + Ip->ubase;
+    // not restrict: unshared, the adjoint is written in place over these entries
+    const float2 *ub = A.ubuf + Ip->ubase;
     double lrr = 0.0, lra = 0.0;
     float *rbar = dyn;  // [ntest] 2 c_v R of the block's element
     const int64_t ebase = e0 * ntest, gbase = e0 * Ip->gstride;
-    const float2 *__restrict__ uxy = ub + e0 * nq;
     constexpr int kRG = kCThreads / 16;
     const int rg = tid >> 4, rl = tid & 15;
     for (int k0 = 0; k0 < ntest; k0 += kRG) {
@@ -916,7 +928,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
         if (k < ntest) {
             const float *gxr = Gx + gbase + (int64_t)k * nq, *gyr = Gy + gbase + (int64_t)k * nq;
             for (int q = rl; q < nq; q += 16) {
-                const float2 d = uxy[q];
+                const float2 d = ub[upoint(Ip, e0 * nq + q)];
                 acc = fmaf(d.x, gxr[q], fmaf(d.y, gyr[q], acc));
             }
         }
@@ -940,7 +952,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
                 bx = fmaf(rbar[k], Gx[o], bx);
                 by = fmaf(rbar[k], Gy[o], by);
             }
-            ub[e0 * nq + q] = make_float2(eps * bx, eps * by);
+            Ip->adj[e0 * nq + q] = make_float2(eps * bx, eps * by);
         }
     }
     contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
@@ -979,8 +991,11 @@ __global__ __launch_bounds__(kCThreads) void k_contract_mf(ContractArgs A) {
         const float *gp = Ip->geo + e * 8;
         const float x1 = gp[0], x2 = gp[1], x3 = gp[2], y1 = gp[3], y2 = gp[4], y3 = gp[5];
         const float eps = c.eps, two_cv = Ip->two_cv, kdiff = Ip->kdiff, cbx = Ip->cbx, cby = Ip->cby;
-        float2 *__restrict__ ub = A.ubuf + Ip->ubase + e * nq;
-        float *__restrict__ eb = VAR ? A.ebuf + Ip->ubase + e * nq : nullptr;
+        // not restrict: unshared, adj and eadj are these buffers
+        const float2 *ub = A.ubuf + Ip->ubase;
+        const float *eb = VAR ? A.ebuf + Ip->ubase : nullptr;
+        float2 *adj = Ip->adj + e * nq;
+        float *eadj = VAR ? Ip->eadj + e * nq : nullptr;
         // Jacobian entries and weight at point q = j n + i
         auto geom = [&](int q, float &a, float &b, float &cc, float &d, float &w) {
             const int j = q / n, i = q - j * n;
@@ -994,8 +1009,9 @@ __global__ __launch_bounds__(kCThreads) void k_contract_mf(ContractArgs A) {
         for (int q = lane; q < nq; q += 64) {
             float a, b, cc, d, w;
             geom(q, a, b, cc, d, w);
-            const float2 g = ub[q];
-            const float kd = VAR ? eb[q] : kdiff;
+            const int64_t pu = upoint(Ip, e * nq + q);
+            const float2 g = ub[pu];
+            const float kd = VAR ? eb[pu] : kdiff;
             Pv[q] = kd * w * (d * g.x - cc * g.y);
             Qv[q] = kd * w * (a * g.y - b * g.x);
             Mv[q] = w * (a * d - b * cc) * fmaf(cbx, g.x, cby * g.y);
@@ -1057,10 +1073,11 @@ __global__ __launch_bounds__(kCThreads) void k_contract_mf(ContractArgs A) {
                 }
                 const float gx = w * (d * sxi - b * seta), gy = w * (a * seta - cc * sxi);
                 const float gm = w * (a * d - b * cc) * sv;
-                const float2 g = ub[q];
-                const float kd = VAR ? eb[q] : kdiff;
-                ub[q] = make_float2(eps * fmaf(kd, gx, cbx * gm), eps * fmaf(kd, gy, cby * gm));
-                if (VAR) eb[q] = fmaf(g.x, gx, g.y * gy);
+                const int64_t pu = upoint(Ip, e * nq + q);
+                const float2 g = ub[pu];
+                const float kd = VAR ? eb[pu] : kdiff;
+                adj[q] = make_float2(eps * fmaf(kd, gx, cbx * gm), eps * fmaf(kd, gy, cby * gm));
+                if (VAR) eadj[q] = fmaf(g.x, gx, g.y * gy);
             }
         }
     }
@@ -1176,6 +1193,11 @@ __global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
         const float2 *__restrict__ pts = Ip->pts;
         const float2 *__restrict__ ub_i = A.ubuf + Ip->ubase;
         const float *__restrict__ eb_i = NH == 2 ? A.ebuf + Ip->ubase : nullptr;
+        // shared points: the adjoints of a point's slots are added in slot order
+        const int *__restrict__ usoff = Ip->usoff;
+        const int *__restrict__ uslot = Ip->uslot;
+        const float2 *__restrict__ adj = Ip->adj;
+        const float *__restrict__ eadj = Ip->eadj;
         const int64_t seg_end = min(t_end, tile0 + Ip->n_tiles);
         const int64_t row = Ip->grow0 + (int64_t)(blockIdx.x - Ip->gblk0);
         __syncthreads();
@@ -1186,8 +1208,20 @@ __global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
             const int64_t idx = 16 * (tt - tile0) + (lane & 15);
             const bool ok = tt < seg_end && idx < n_all;
             p = ok ? pts[idx] : make_float2(0.f, 0.f);
-            d = ok ? ub_i[idx] : make_float2(0.f, 0.f);
-            ev = (NH == 2 && ok && idx < n_pts) ? eb_i[idx] : 0.f;
+            if (usoff && ok && idx < n_pts) {
+                d = make_float2(0.f, 0.f);
+                ev = 0.f;
+                for (int k = usoff[idx], k1 = usoff[idx + 1]; k < k1; ++k) {
+                    const int s = uslot[k];
+                    const float2 a = adj[s];
+                    d.x += a.x;
+                    d.y += a.y;
+                    if (NH == 2) ev += eadj[s];
+                }
+            } else {
+                d = ok ? ub_i[idx] : make_float2(0.f, 0.f);
+                ev = (NH == 2 && ok && idx < n_pts) ? eb_i[idx] : 0.f;
+            }
         };
         float2 pn, dn;
         float en;
@@ -1360,6 +1394,8 @@ static bool tuning_valid(const vpinn_tuning &t) {
 struct FusedPlan {
     DevBuf inst, blk_tiles, blk_inst0, cblk_inst, ubuf, gpart, lpart;
     DevBuf ebuf;  // two outputs: e, then dL/de, per point (point buffer order)
+    // shared points: the instances' point lists, and the per-slot adjoints of the contraction
+    DevBuf dpts, abuf, eabuf;
     int nh = 1;   // network outputs
     vpinn_tuning tune = kDefaultTuning;
     std::vector<InstDesc> host_inst;
@@ -1377,11 +1413,17 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     const int nh = cfg->n_outputs == 2 ? 2 : 1;
     const int cus = cu_count(dev);
     std::vector<InstDesc> D(n);
+    // shared-point instances: their point list (distinct points, boundary, sensors) at
+    // dbase[i] of the plan's dpts, their adjoint slots at sbase[i] of abuf (eabuf)
+    std::vector<int64_t> dbase(n, -1), sbase(n, -1);
+    int64_t n_dpts = 0, n_slots = 0;
     int64_t tiles = 0, ubase = 0, cblocks = 0;
     size_t cdyn_fast = 16, cdyn_generic = 16, cdyn_mf = 16;
     for (int i = 0; i < n; ++i) {
         const vpinn_problem *p = probs[i];
-        const int64_t tot = p->n_pts + p->n_bnd + p->n_sen;
+        const bool shared = p->n_uniq > 0;
+        const int64_t n_int = shared ? p->n_uniq : p->n_pts;
+        const int64_t tot = n_int + p->n_bnd + p->n_sen;
         InstDesc &d = D[i];
         d = InstDesc{};
         d.Gx = p->Gx.as<float>();
@@ -1390,7 +1432,16 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         d.pts = p->pts.as<float2>();
         d.tgt = p->tgt.as<float>();
         d.n_elem = p->n_elem;
-        d.n_pts = p->n_pts;
+        d.n_pts = n_int;
+        if (shared) {
+            d.umap = p->umap.as<int>();
+            d.usoff = p->usoff.as<int>();
+            d.uslot = p->uslot.as<int>();
+            dbase[i] = n_dpts;
+            n_dpts += tot;
+            sbase[i] = n_slots;
+            n_slots += p->n_pts;
+        }
         d.n_bnd = p->n_bnd;
         d.n_sen = p->n_sen;
         d.n_tiles = (tot + 15) / 16;
@@ -1498,6 +1549,28 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     VP_HIP(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)grows));
     VP_HIP(P.lpart.reserve(sizeof(double) * 4 * (size_t)lrows));
     if (nh == 2) VP_HIP(P.ebuf.reserve(sizeof(float) * (size_t)ubase));
+    if (n_slots) {
+        VP_HIP(P.dpts.reserve(sizeof(float2) * (size_t)n_dpts));
+        VP_HIP(P.abuf.reserve(sizeof(float2) * (size_t)n_slots));
+        if (nh == 2) VP_HIP(P.eabuf.reserve(sizeof(float) * (size_t)n_slots));
+    }
+    for (int i = 0; i < n; ++i) {
+        const vpinn_problem *p = probs[i];
+        InstDesc &d = D[i];
+        if (dbase[i] >= 0) {
+            float2 *dp = P.dpts.as<float2>() + dbase[i];
+            VP_HIP(hipMemcpy(dp, p->upts.ptr, sizeof(float2) * p->n_uniq, hipMemcpyDeviceToDevice));
+            if (p->n_bnd + p->n_sen)
+                VP_HIP(hipMemcpy(dp + p->n_uniq, p->pts.as<float2>() + p->n_pts, sizeof(float2) * (p->n_bnd + p->n_sen),
+                                 hipMemcpyDeviceToDevice));
+            d.pts = dp;
+            d.adj = P.abuf.as<float2>() + sbase[i];
+            d.eadj = nh == 2 ? P.eabuf.as<float>() + sbase[i] : nullptr;
+        } else {
+            d.adj = P.ubuf.as<float2>() + d.ubase;
+            d.eadj = nh == 2 ? P.ebuf.as<float>() + d.ubase : nullptr;
+        }
+    }
     VP_HIP(hipMemcpy(P.inst.ptr, D.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
     VP_HIP(hipMemcpy(P.blk_tiles.ptr, bt.data(), sizeof(int64_t) * (tblocks + 1), hipMemcpyHostToDevice));
     VP_HIP(hipMemcpy(P.blk_inst0.ptr, binst.data(), sizeof(int) * tblocks, hipMemcpyHostToDevice));
@@ -1637,6 +1710,7 @@ struct SingleCache {
     const void *pts = nullptr;
     int L = 0, H = 0, norm = -1, nh = 0;
     float tau = -1.f, gamma = -1.f;
+    int64_t share_gen = -1;
 };
 
 vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
@@ -1649,7 +1723,7 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
     }
     if (!c->valid || c->n_bnd != p->n_bnd || c->n_sen != p->n_sen || c->pts != p->pts.ptr || c->L != cfg->n_hidden ||
         c->H != cfg->width || c->norm != cfg->loss_norm || c->tau != cfg->tau || c->gamma != cfg->gamma ||
-        c->nh != (cfg->n_outputs == 2 ? 2 : 1)) {
+        c->nh != (cfg->n_outputs == 2 ? 2 : 1) || c->share_gen != p->share_gen) {
         c->valid = false;
         vpinn_problem *one[1] = {p};
         vpinn_status st = build_plan(one, 1, cfg, p->device, kDefaultTuning, c->plan);
@@ -1664,6 +1738,7 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
         c->tau = cfg->tau;
         c->gamma = cfg->gamma;
         c->nh = cfg->n_outputs == 2 ? 2 : 1;
+        c->share_gen = p->share_gen;
     }
     AdamArgs none{};
     return run_plan(c->plan, d_params, d_eps, d_grad != nullptr || d_grad_eps != nullptr, d_loss, d_grad, d_grad_eps,

@@ -109,6 +109,15 @@ struct vpinn_problem {
     vp::DevBuf geo;          // float [n_elem][8]: xc1, xc2, xc3, yc1, yc2, yc3, xc0, yc0
     vp::DevBuf tab;          // float [2 n + 2 nt n]: GLL nodes, weights, phi_r(x_i), phi_r'(x_i)
     int64_t gstride() const { return shared_g ? 0 : (int64_t)ntest * nq; }
+    // shared quadrature points (vpinn_set_shared_points): the fused path evaluates the
+    // network once per distinct interior point; slot (e, q) reads point umap[e nq + q],
+    // and the slots of point u are uslot[usoff[u] .. usoff[u + 1]) in increasing order
+    int64_t n_uniq = 0;      // 0: every slot is its own point
+    vp::DevBuf umap;         // int32 [n_pts]
+    vp::DevBuf usoff;        // int32 [n_uniq + 1]
+    vp::DevBuf uslot;        // int32 [n_pts]
+    vp::DevBuf upts;         // float2 [n_uniq]
+    int64_t share_gen = 0;   // bumped whenever the sharing changes (cached plans rebuild)
     vp::DevBuf Gx, Gy, F;    // float
     vp::DevBuf pts;          // float2 [n_pts + n_bnd + n_sen]: interior, boundary, sensors
     vp::DevBuf tgt;          // float [n_bnd + n_sen]: g_b then d_s

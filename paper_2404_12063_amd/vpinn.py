@@ -52,7 +52,8 @@ class vpinn_problem_info(C.Structure):
                 ("n_points", C.c_int64), ("n_boundary", C.c_int64), ("n_sensors", C.c_int64),
                 ("quad_order", C.c_int32), ("test_order", C.c_int32),
                 ("diffusion", C.c_double), ("velocity_x", C.c_double), ("velocity_y", C.c_double),
-                ("shared_premultiplier", C.c_int32), ("variable_diffusion", C.c_int32), ("matrix_free", C.c_int32)]
+                ("shared_premultiplier", C.c_int32), ("variable_diffusion", C.c_int32), ("matrix_free", C.c_int32),
+                ("n_distinct_points", C.c_int64)]
 
 
 class vpinn_loss_cfg(C.Structure):
@@ -83,6 +84,7 @@ _SIGNATURES = {
                                    C.c_void_p, C.POINTER(C.c_void_p)]),
     "vpinn_set_boundary": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "vpinn_set_sensors": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "vpinn_set_shared_points": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_mesh), C.c_int32]),
     "vpinn_get_info": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_problem_info)]),
     "vpinn_read_tensor": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
     "vpinn_assemble_vardiff": (C.c_int32, [C.POINTER(vpinn_mesh), C.c_int32, C.c_int32, C.c_double, C.c_double,
@@ -227,7 +229,7 @@ def vpinn_assemble(xy, quad, quad_order: int, test_order: int, amp: float = 0.0,
     return Problem(out.value)
 
 
-def assemble_problem(prob, stream=None, matrix_free: bool = False) -> Problem:
+def assemble_problem(prob, stream=None, matrix_free: bool = False, shared_points: bool = False) -> Problem:
     """Assemble a vpinn_inputs Problem (Poisson, convection-diffusion when it sets diff/conv, space-dependent
     diffusion when its network has two outputs) and upload its boundary and sensor sets."""
     diff, conv = getattr(prob, "diff", 1.0), tuple(getattr(prob, "conv", (0.0, 0.0)))
@@ -239,7 +241,18 @@ def assemble_problem(prob, stream=None, matrix_free: bool = False) -> Problem:
     vpinn_set_boundary(p, prob.bnd_xy, prob.bnd_g)
     if len(prob.sens_xy):
         vpinn_set_sensors(p, prob.sens_xy, prob.sens_u)
+    if shared_points:
+        vpinn_set_shared_points(p, prob.mesh.xy, prob.mesh.quad)
     return p
+
+
+def vpinn_set_shared_points(p: Problem, xy, quad, enable: bool = True):
+    """Evaluate the network once per distinct interior point of the mesh (xy, quad) the problem came from."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    quad = np.ascontiguousarray(quad, dtype=np.int32)
+    mesh = vpinn_mesh(xy.shape[0], xy.ctypes.data_as(C.POINTER(C.c_double)), quad.shape[0],
+                      quad.ctypes.data_as(C.POINTER(C.c_int32)))
+    _check(lib().vpinn_set_shared_points(p.handle, C.byref(mesh), 1 if enable else 0))
 
 
 def vpinn_set_boundary(p: Problem, xy, g):
