@@ -208,6 +208,18 @@ def mlp_vjp(theta, H: int, L: int, xy, ub, uxb, uyb, eb=None, heads: int = 1):
     return g
 
 
+def prediction_error(theta, H: int, L: int, xy, ref, heads: int = 1, output: int = 0):
+    """Accuracy of a network prediction against reference values at points (Sec. 4 reports the mean absolute
+    error of u on a grid and point-wise absolute errors of u and of the predicted diffusion coefficient):
+    mean |p - ref|, max |p - ref|, and the relative L2 error ||p - ref|| / ||ref||, where p is output 0 (u)
+    or, for a two-output network, output 1 (e)."""
+    outs = mlp_eval(theta, H, L, xy, heads)
+    p = outs[0] if output == 0 else outs[3]
+    d = p - _f64(ref).ravel()
+    nr = float(np.sqrt(np.sum(_f64(ref) ** 2)))
+    return float(np.mean(np.abs(d))), float(np.max(np.abs(d))), float(np.sqrt(np.sum(d * d))) / nr
+
+
 def _conv_args(asm: Assembled, conv):
     if conv is None or tuple(conv) == (0.0, 0.0):
         return None, 0.0, 0.0

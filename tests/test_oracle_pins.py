@@ -622,3 +622,29 @@ def test_disk_mesh_is_valid_and_has_disk_area(oracle):
     shoelace = 0.5 * np.sum(x * np.roll(y, -1, 1) - y * np.roll(x, -1, 1), axis=1)
     assert (shoelace > 0).all()
     assert 0.0 < math.pi * 0.25 - shoelace.sum() < 2e-3
+
+
+def test_prediction_error_of_a_constant_network(oracle):
+    """Zero weights: every output is its bias, so the three errors have closed forms."""
+    H, L = 4, 2
+    theta = np.zeros(gen.n_params(H, L, heads=2))
+    theta[-2], theta[-1] = 0.75, -1.5          # b_out of u and of e
+    xy = gen.uniform(3, "errpts", 40, 0, 1).reshape(20, 2)
+    ref = np.full(20, 0.25)
+    mae, mx, rel = oracle.prediction_error(theta, H, L, xy, ref, heads=2)
+    assert abs(mae - 0.5) < 1e-15 and abs(mx - 0.5) < 1e-15 and abs(rel - 2.0) < 1e-14
+    mae, mx, rel = oracle.prediction_error(theta, H, L, xy, ref, heads=2, output=1)
+    assert abs(mae - 1.75) < 1e-15 and abs(mx - 1.75) < 1e-15 and abs(rel - 7.0) < 1e-14
+
+
+def test_prediction_error_picks_the_worst_point(oracle):
+    """A single tanh neuron against a reference equal to it except at one point: that point sets the max and
+    the L2 error, and the mean is its error over n."""
+    theta = np.array([0.7, -1.3, 0.2, 1.9, -0.4])
+    xy = gen.uniform(4, "errpts1", 20, -1, 1).reshape(10, 2)
+    u = 1.9 * np.tanh(0.7 * xy[:, 0] - 1.3 * xy[:, 1] + 0.2) - 0.4
+    ref = u.copy()
+    ref[6] += 0.3
+    mae, mx, rel = oracle.prediction_error(theta, 1, 1, xy, ref)
+    assert abs(mae - 0.03) < 1e-14 and abs(mx - 0.3) < 1e-14
+    assert abs(rel - 0.3 / np.linalg.norm(ref)) < 1e-14
