@@ -34,7 +34,7 @@ def n_outputs(prob) -> int:
     return getattr(prob, "heads", 1)
 
 
-def kernel_work(prob, matrix_free: bool = False):
+def kernel_work(prob, matrix_free: bool = False, n_interior=None):
     """Algorithmic work of each fused-path kernel for one epoch (dense products as 2 x multiply-adds).
 
     k_fwd: values and tangents, interior 2H + 3(L-1)H^2 + 2H MACs a point, boundary/sensor 3H + (L-1)H^2;
@@ -46,11 +46,13 @@ def kernel_work(prob, matrix_free: bool = False):
     M read once (12 N_test bytes a point) plus e in and dL/de out (8 a point); k_bwd + 2H MACs.
     Matrix-free problems (no G stored): the sum-factorised contraction takes 6 N_t n^2 + 4 N_t^2 n MACs an
     element (forward 3 N_t n^2 + 2 N_t^2 n, adjoint the same) and reads F, 32 B of geometry, the point buffer.
+    n_interior: the network's interior points when shared points are on (distinct points, not slots).
     """
     H, L = prob.width, prob.n_hidden
     nt = prob.test_order ** 2
     n_extra = len(prob.bnd_xy) + len(prob.sens_xy)
     two = n_outputs(prob) == 2
+    ni = prob.n_points if n_interior is None else n_interior
     if matrix_free:
         n, t = prob.quad_order, prob.test_order
         contract = {"flop": 2.0 * prob.n_elem * (6 * t * n * n + 4 * t * t * n),
@@ -60,10 +62,10 @@ def kernel_work(prob, matrix_free: bool = False):
                     "bytes": (12.0 if two else 8.0) * nt * prob.n_points + 4.0 * nt * prob.n_elem
                     + (24.0 if two else 16.0) * prob.n_points}
     return {
-        "k_fwd": {"flop": 2.0 * (prob.n_points * (2 * H + 3 * (L - 1) * H * H + 2 * H + (H if two else 0))
+        "k_fwd": {"flop": 2.0 * (ni * (2 * H + 3 * (L - 1) * H * H + 2 * H + (H if two else 0))
                                  + n_extra * (3 * H + (L - 1) * H * H))},
         "k_contract": contract,
-        "k_bwd": {"flop": 2.0 * (prob.n_points * (2 * H + 6 * (L - 1) * H * H + 4 * H + (2 * H if two else 0))
+        "k_bwd": {"flop": 2.0 * (ni * (2 * H + 6 * (L - 1) * H * H + 4 * H + (2 * H if two else 0))
                                  + n_extra * (3 * H + 2 * (L - 1) * H * H))},
     }
 
@@ -328,7 +330,10 @@ def bench_batched(args, V, torch, gen):
     for pr in probs:
         p = V.vpinn_assemble(pr.mesh.xy, pr.mesh.quad, pr.quad_order, pr.test_order, pr.f_amp, pr.f_kx, pr.f_ky)
         V.vpinn_set_boundary(p, pr.bnd_xy, pr.bnd_g)
+        if args.shared_points:
+            V.vpinn_set_shared_points(p, pr.mesh.xy, pr.mesh.quad)
         gp.append(p)
+    n_int = [V.vpinn_get_info(p).n_distinct_points or pr.n_points for p, pr in zip(gp, probs)]
     P = sum(pr.n_points for pr in probs)
     print(f"[bench] workload c5: 64 instances, {sum(pr.n_elem for pr in probs)} elements, {P} quadrature points",
           file=sys.stderr, flush=True)
@@ -364,8 +369,8 @@ def bench_batched(args, V, torch, gen):
     with torch.cuda.stream(s):
         kms = profile_batch_kernels(V, torch, b, s, T, M, Vv, step, losses, n_steps=10)
     work = {}
-    for pr in probs:
-        for name, w in kernel_work(pr).items():
+    for pr, ni in zip(probs, n_int):
+        for name, w in kernel_work(pr, n_interior=ni).items():
             for key, val in w.items():
                 work.setdefault(name, {}).setdefault(key, 0.0)
                 work[name][key] += val
@@ -411,7 +416,8 @@ def bench_batched(args, V, torch, gen):
                                "counts log-uniform in [256,16384], GLL n in {4,6,10}, test N_t in {3,5}, "
                                "k in 1..16, each with its own 2-30-30-30-1 tanh MLP; one batched "
                                "forward+adjoint+Adam step per epoch replayed from a HIP graph",
-                   "instances": 64, "quad_points": P, "parallelism": "single GPU", "tuning": list(tuning)},
+                   "instances": 64, "quad_points": P, "parallelism": "single GPU", "tuning": list(tuning),
+                   "shared_points": bool(args.shared_points), "network_interior_points": sum(n_int)},
         "mquadpts_per_s": round(P * eps_s / 1e6, 2),
         "step_ms_p10_p50_p90": [round(st[len(st) // 10], 4), round(st[len(st) // 2], 4),
                                 round(st[(9 * len(st)) // 10], 4)],
@@ -445,6 +451,9 @@ def main():
                          "gear problem on 14,000 elements; disk_vareps: space-dependent diffusion inverse problem, "
                          "a two-output network on a 1,024-element disk; c2_mf, probe_mf: the same as c2, probe with "
                          "G regenerated per step from the element geometry (matrix-free)")
+    ap.add_argument("--shared-points", action="store_true",
+                    help="evaluate the network once per distinct interior GLL point (vpinn_set_shared_points); the "
+                         "result equals per-slot evaluation up to rounding")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times: a kernel of known traffic that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -512,7 +521,8 @@ def bench_single(args, V, torch, gen):
     mf = args.workload.endswith("_mf")
     prob = gen.CONFIGS[args.workload[:-3] if mf else args.workload]()
     theta = prob.params()
-    p = V.assemble_problem(prob, matrix_free=mf)
+    p = V.assemble_problem(prob, matrix_free=mf, shared_points=args.shared_points)
+    n_int = V.vpinn_get_info(p).n_distinct_points or prob.n_points
     print(f"[bench] workload {args.workload}: {prob.n_elem} elements, {prob.n_points} quadrature points, "
           f"{len(prob.bnd_xy)} boundary points", file=sys.stderr, flush=True)
 
@@ -550,7 +560,7 @@ def bench_single(args, V, torch, gen):
     ms = res["wall_s"] / args.steps * 1e3
     eps_s = 1e3 / ms
     flops = flops_per_epoch(prob)
-    work = kernel_work(prob, mf)
+    work = kernel_work(prob, mf, n_int)
     kernels = {}
     if fused:
         km = res["kernel_ms"]
@@ -605,6 +615,7 @@ def bench_single(args, V, torch, gen):
                    "path": args.path + (" (HIP graph replay of the batch-of-one step)" if fused else " (eager)"),
                    "tuning": res.get("tuning"),
                    "n_elem": prob.n_elem, "quad_points": prob.n_points,
+                   "shared_points": bool(args.shared_points), "network_interior_points": n_int,
                    "boundary_points": len(prob.bnd_xy), "parallelism": "single GPU"},
         "mquadpts_per_s": round(prob.n_points * eps_s / 1e6, 2),
         "roofline": roof,

@@ -283,6 +283,22 @@ vpinn_status vpinn_eval_network_heads(int32_t width, int32_t n_hidden, int32_t n
                                       float *d_e, void *stream);
 
 /*
+ * vpinn_eval_error -- accuracy of a prediction (Sec. 4 reports the mean absolute
+ * error of u on a 100 x 100 grid and point-wise errors of u and of the predicted
+ * diffusion coefficient): with p the network's output `output` (0: u, 1: the
+ * second output of a two-output network) at the n points d_xy (device [n][2]
+ * floats) and d_ref (device [n] floats) the reference values,
+ *   d_out[0] = (1/n) sum |p - ref|,  d_out[1] = max |p - ref|,
+ *   d_out[2] = ||p - ref||_2 / ||ref||_2   (inf or nan if ref is all zero),
+ * d_out a device array of 3 doubles, sums in FP64 in a fixed order.  Uses a
+ * per-thread device workspace of n floats.  Errors: VPINN_E_INVALID (n < 1, null
+ * pointer, output not below n_outputs), VPINN_E_UNSUPPORTED (shape).
+ */
+vpinn_status vpinn_eval_error(int32_t width, int32_t n_hidden, int32_t n_outputs, int32_t output,
+                              const float *d_params, int64_t n, const float *d_xy, const float *d_ref, double *d_out,
+                              void *stream);
+
+/*
  * vpinn_adam_step -- Kingma-Ba Adam (Algorithm 1 of that paper, the optimiser of
  * Sec. 4.6.3), in place on n device floats:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

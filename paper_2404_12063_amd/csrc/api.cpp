@@ -580,6 +580,35 @@ vpinn_status vpinn_eval_network_heads(int32_t width, int32_t n_hidden, int32_t n
     return st;
 }
 
+vpinn_status vpinn_eval_error(int32_t width, int32_t n_hidden, int32_t n_outputs, int32_t output,
+                              const float *d_params, int64_t n, const float *d_xy, const float *d_ref, double *d_out,
+                              void *stream) {
+    using namespace vp;
+    if (width < 1 || width > VPINN_MAX_WIDTH || n_hidden < 1 || n_hidden > VPINN_MAX_HIDDEN)
+        return fail(VPINN_E_UNSUPPORTED, "width or n_hidden out of range");
+    if (n_outputs < 1 || n_outputs > 2 || output < 0 || output >= n_outputs)
+        return fail(VPINN_E_INVALID, "n_outputs must be 1 or 2 and output in 0 .. n_outputs - 1");
+    if (!d_params || !d_xy || !d_ref || !d_out || n < 1) return fail(VPINN_E_INVALID, "null argument or n < 1");
+    static thread_local DevBuf wpad, pbuf, part;
+    static thread_local int ws_dev = -1;
+    int dev = 0;
+    VP_HIP(hipGetDevice(&dev));
+    if (ws_dev != dev) {
+        wpad.release();
+        pbuf.release();
+        part.release();
+        ws_dev = dev;
+    }
+    VP_HIP(wpad.reserve(sizeof(float) * kMaxPadded));
+    VP_HIP(pbuf.reserve(sizeof(float) * (size_t)n));
+    VP_HIP(part.reserve(sizeof(double) * 4 * 512));
+    hipStream_t s = (hipStream_t)stream;
+    vpinn_status st = pack_params(d_params, width, n_hidden, n_outputs, output, wpad.as<float>(), s);
+    if (st) return st;
+    return eval_error(n_hidden, wpad.as<float>(), n, reinterpret_cast<const float2 *>(d_xy), d_ref, pbuf.as<float>(),
+                      part.as<double>(), d_out, s);
+}
+
 vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_params, int64_t n, const float *d_xy,
                                 float *d_u, float *d_ux, float *d_uy, void *stream) {
     return vpinn_eval_network_heads(width, n_hidden, 1, d_params, n, d_xy, d_u, d_ux, d_uy, nullptr, stream);

@@ -504,6 +504,74 @@ vpinn_status eval_network(int L, const float *d_wpad, int64_t n, const float2 *d
     return fwd_dispatch(L, d_wpad, d_xy, n, d_u, d_ux, d_uy, nullptr, s);
 }
 
+// prediction error against reference values: blocks stride over the points and keep
+// FP64 sums of |d|, d^2, ref^2 and the max |d| (d = p - ref); each block's four
+// values go to part[block] (wavefronts added in order), and one block adds the
+// partials in block order, so the result does not depend on timing
+constexpr int kErrThreads = 256, kErrMaxBlocks = 512;
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(kErrThreads) void k_err_partial(const float *__restrict__ p, const float *__restrict__ ref,
+                                                              int64_t n, double *__restrict__ part) {
+    __shared__ double red[kErrThreads / 64][4];
+    double sa = 0.0, mx = 0.0, sd = 0.0, sr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kErrThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kErrThreads) {
+        const double r = (double)ref[i], d = (double)p[i] - r;
+        sa += fabs(d);
+        mx = fmax(mx, fabs(d));
+        sd += d * d;
+        sr += r * r;
+    }
+    sa = wave_sum(sa);
+    sd = wave_sum(sd);
+    sr = wave_sum(sr);
+    mx = wave_max(mx);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = sa;
+        red[w][1] = mx;
+        red[w][2] = sd;
+        red[w][3] = sr;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = red[0][threadIdx.x];
+        for (int k = 1; k < kErrThreads / 64; ++k)
+            v = threadIdx.x == 1 ? fmax(v, red[k][1]) : v + red[k][threadIdx.x];
+        part[blockIdx.x * 4 + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_err_final(const double *__restrict__ part, int blocks, int64_t n, double *__restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double sa = 0.0, mx = 0.0, sd = 0.0, sr = 0.0;
+    for (int b = 0; b < blocks; ++b) {
+        sa += part[4 * b];
+        mx = fmax(mx, part[4 * b + 1]);
+        sd += part[4 * b + 2];
+        sr += part[4 * b + 3];
+    }
+    out[0] = sa / (double)n;
+    out[1] = mx;
+    out[2] = sqrt(sd) / sqrt(sr);
+}
+
+vpinn_status eval_error(int L, const float *d_wpad, int64_t n, const float2 *d_xy, const float *d_ref, float *d_p,
+                        double *d_part, double *d_out, hipStream_t s) {
+    vpinn_status st = eval_network(L, d_wpad, n, d_xy, d_p, nullptr, nullptr, s);
+    if (st) return st;
+    const int blocks = (int)std::min<int64_t>(kErrMaxBlocks, (n + kErrThreads - 1) / kErrThreads);
+    k_err_partial<<<blocks, kErrThreads, 0, s>>>(d_p, d_ref, n, d_part);
+    k_err_final<<<1, 64, 0, s>>>(d_part, blocks, n, d_out);
+    VP_HIP(hipGetLastError());
+    return VPINN_OK;
+}
+
 constexpr int kBwdMaxBlocks = 512;
 
 template <int L>

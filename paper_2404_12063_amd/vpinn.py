@@ -102,6 +102,8 @@ _SIGNATURES = {
                                        C.c_void_p, C.c_void_p, C.c_void_p]),
     "vpinn_eval_network_heads": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
                                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vpinn_eval_error": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "vpinn_adam_step": (C.c_int32, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "vpinn_batch_create": (C.c_int32, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vpinn_loss_cfg),
@@ -311,6 +313,13 @@ def vpinn_eval_network_heads(width: int, n_hidden: int, n_outputs: int, params, 
     n = xy.shape[0]
     _check(lib().vpinn_eval_network_heads(width, n_hidden, n_outputs, _ptr(params), n, _ptr(xy), _ptr(u),
                                           _ptr(ux), _ptr(uy), _ptr(e), _stream(stream)))
+
+
+def vpinn_eval_error(width: int, n_hidden: int, params, xy, ref, out, n_outputs: int = 1, output: int = 0,
+                     stream=None):
+    """out: device float64 tensor of 3: mean |p - ref|, max |p - ref|, relative L2 error."""
+    _check(lib().vpinn_eval_error(width, n_hidden, n_outputs, output, _ptr(params), xy.shape[0], _ptr(xy), _ptr(ref),
+                                  _ptr(out), _stream(stream)))
 
 
 def vpinn_adam_step(params, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,

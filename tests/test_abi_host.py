@@ -190,3 +190,13 @@ def test_matrix_free_rejects_before_device_work(V, n, vd, code):
     out = C.c_void_p()
     rc = V.lib().vpinn_assemble_matrix_free(C.byref(mesh), n, 3, 1.0, 0.0, 0.0, vd, C.byref(f), None, C.byref(out))
     assert rc == getattr(V, code) and not out.value
+
+
+def test_eval_error_rejects_before_device_work(V):
+    L = V.lib()
+    one = C.c_void_p(16)  # never dereferenced: the checks come first
+    assert L.vpinn_eval_error(30, 3, 1, 1, one, 4, one, one, one, None) == V.VPINN_E_INVALID
+    assert L.vpinn_eval_error(30, 3, 2, 2, one, 4, one, one, one, None) == V.VPINN_E_INVALID
+    assert L.vpinn_eval_error(30, 3, 1, 0, one, 0, one, one, one, None) == V.VPINN_E_INVALID
+    assert L.vpinn_eval_error(30, 3, 1, 0, one, 4, one, None, one, None) == V.VPINN_E_INVALID
+    assert L.vpinn_eval_error(40, 3, 1, 0, one, 4, one, one, one, None) == V.VPINN_E_UNSUPPORTED
