@@ -223,7 +223,11 @@ def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
 
 
 def profile_batch_kernels(V, torch, b, s, T, M, Vv, step, losses, n_steps: int):
-    """Mean duration of each fused-path kernel over eager batched steps of plan `b` (its profiling events)."""
+    """Mean duration of each fused-path kernel over eager batched steps of plan `b` (its profiling events).
+
+    An event pair around a kernel also times the event markers themselves; that overhead, measured as the
+    mean interval of back-to-back event pairs with nothing between them on the same stream, is subtracted
+    (reported as event_overhead_ms)."""
     NE = V.PROFILE_EVENTS
     pev = [[torch.cuda.Event(enable_timing=True) for _ in range(NE)] for _ in range(n_steps)]
     for e in pev:
@@ -233,10 +237,16 @@ def profile_batch_kernels(V, torch, b, s, T, M, Vv, step, losses, n_steps: int):
         V.vpinn_batch_set_profile_events(b, pev[i])
         V.vpinn_batch_step(b, T, M, Vv, step, lr=1e-3, losses=losses, stream=s)
     V.vpinn_batch_set_profile_events(b, None)
+    empty = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_steps)]
+    for e0, e1 in empty:
+        e0.record(s)
+        e1.record(s)
     torch.cuda.synchronize()
-    out = {name: sum(e[k].elapsed_time(e[k + 1]) for e in pev) / n_steps
+    over = sum(e0.elapsed_time(e1) for e0, e1 in empty) / n_steps
+    out = {name: max(0.0, sum(e[k].elapsed_time(e[k + 1]) for e in pev) / n_steps - over)
            for k, name in enumerate(["k_fwd", "k_contract", "k_bwd", "k_fused_final"])}
     out["steps"] = n_steps
+    out["event_overhead_ms"] = over
     return out
 
 
@@ -428,6 +438,7 @@ def bench_batched(args, V, torch, gen):
         "whole_step": {"algorithmic_flop": flops, "algorithmic_bytes": sum(bytes_per_epoch(pr) for pr in probs),
                        "achieved_tflops": round(achieved, 3), "frac_of_fp32_peak": round(achieved / PEAK_FP32_TFLOPS, 4)},
         "eager_kernels": kernels,
+        "event_overhead_ms": round(kms["event_overhead_ms"], 5),
         "plain_hip": {"ms_per_step": round(pms, 4), "epochs_per_s": round(1e3 / pms, 3),
                       "note": "64 x (unfused loss/grad + Adam) per step"},
         "speedup_vs_plain": round(pms / ms, 3),
@@ -630,7 +641,8 @@ def bench_single(args, V, torch, gen):
         out["gpu_event_ms_per_step"] = round(res["event_ms_total"] / args.steps, 5)
         out["kernels"] = kernels
         out["kernels_note"] = ("mean durations over eager batched steps of the same tuned plan as the timed graph, "
-                               "from the library's profiling events")
+                               "from the library's profiling events, less the event-pair overhead")
+        out["event_overhead_ms"] = round(res["kernel_ms"]["event_overhead_ms"], 5)
         if eager is not None:
             out["single_problem_api_eager_ms_per_step"] = round(eager["wall_s"] / eager_steps * 1e3, 5)
     if plain is not None:

@@ -1298,6 +1298,15 @@ __global__ __launch_bounds__(kFinThreads) void k_fused_final(
             }
         }
     }
+    // Adam's operands are loaded now, so their latency overlaps the row sums
+    float am = 0.f, av = 0.f, ap = 0.f, ast = 0.f;
+    if (w == 0 && pj >= 0 && ad.params) {
+        const int64_t k = (int64_t)ii * npf + j;
+        am = ad.m[k];
+        av = ad.v[k];
+        ap = ad.params[k];
+        ast = (float)*ad.step;
+    }
     float acc = 0.f;
     if (pj >= 0) {
         for (int b0 = w; b0 < rows; b0 += kFinBatch * kFinWaves) {
@@ -1335,13 +1344,12 @@ __global__ __launch_bounds__(kFinThreads) void k_fused_final(
         if (grad_out) grad_out[(int64_t)ii * npf + j] = g;
         if (ad.params) {
             const int64_t k = (int64_t)ii * npf + j;
-            const float st = (float)*ad.step;
-            const float c1 = 1.0f - powf(ad.b1, st), c2 = 1.0f - powf(ad.b2, st);
-            const float mi = fmaf(ad.b1, ad.m[k], (1.0f - ad.b1) * g);
-            const float vi = fmaf(ad.b2, ad.v[k], (1.0f - ad.b2) * g * g);
+            const float c1 = 1.0f - powf(ad.b1, ast), c2 = 1.0f - powf(ad.b2, ast);
+            const float mi = fmaf(ad.b1, am, (1.0f - ad.b1) * g);
+            const float vi = fmaf(ad.b2, av, (1.0f - ad.b2) * g * g);
             ad.m[k] = mi;
             ad.v[k] = vi;
-            ad.params[k] -= ad.lr * (mi / c1) / (sqrtf(vi / c2) + ad.eps);
+            ad.params[k] = ap - ad.lr * (mi / c1) / (sqrtf(vi / c2) + ad.eps);
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 64) {
