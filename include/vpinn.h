@@ -318,8 +318,11 @@ typedef struct vpinn_batch vpinn_batch;
  * vpinn_batch_create -- plan a batch over n >= 1 assembled problems that share
  * the network shape and loss weighting in `cfg` (cfg->path is ignored: batches
  * always use the fused kernel).  The batch borrows the problems' device data:
- * they must outlive it, and a later vpinn_set_boundary/vpinn_set_sensors on
- * any of them requires a new batch.  Work is split into tiles of 16 points
+ * they must outlive it, and after a vpinn_set_boundary, vpinn_set_sensors or
+ * vpinn_set_shared_points on any of them the batch's calls return
+ * VPINN_E_INVALID until it is planned again (a new batch, or
+ * vpinn_batch_set_tuning / vpinn_batch_autotune, which rebuild the plan and
+ * drop a captured graph).  Work is split into tiles of 16 points
  * (forward and reverse sweeps: equal shares, one block per compute unit) and
  * chunks of whole elements (contraction), with the tuning {12, 0, 4} (see
  * vpinn_tuning).  Allocates its workspace here; later loss/step/capture/replay

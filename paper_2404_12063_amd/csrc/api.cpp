@@ -173,6 +173,7 @@ static vpinn_status rebuild_points(vpinn_problem *p, const std::vector<float> &b
     std::swap(p->tgt.bytes, ntgt.bytes);
     p->n_bnd = nb;
     p->n_sen = ns;
+    ++p->gen;
     return VPINN_OK;
 }
 
@@ -232,7 +233,7 @@ vpinn_status vpinn_set_shared_points(vpinn_problem *p, const vpinn_mesh *mesh, i
         p->usoff.release();
         p->uslot.release();
         p->upts.release();
-        ++p->share_gen;
+        ++p->gen;
         return VPINN_OK;
     }
     if (!mesh || !mesh->xy || !mesh->quad) return fail(VPINN_E_INVALID, "mesh is null");
@@ -281,7 +282,7 @@ vpinn_status vpinn_set_shared_points(vpinn_problem *p, const vpinn_mesh *mesh, i
     p->uslot = std::move(dsl);
     p->upts = std::move(dpts);
     p->n_uniq = n_uniq;
-    ++p->share_gen;
+    ++p->gen;
     return VPINN_OK;
 }
 

@@ -1718,7 +1718,7 @@ struct SingleCache {
     const void *pts = nullptr;
     int L = 0, H = 0, norm = -1, nh = 0;
     float tau = -1.f, gamma = -1.f;
-    int64_t share_gen = -1;
+    int64_t gen = -1;
 };
 
 vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
@@ -1731,7 +1731,7 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
     }
     if (!c->valid || c->n_bnd != p->n_bnd || c->n_sen != p->n_sen || c->pts != p->pts.ptr || c->L != cfg->n_hidden ||
         c->H != cfg->width || c->norm != cfg->loss_norm || c->tau != cfg->tau || c->gamma != cfg->gamma ||
-        c->nh != (cfg->n_outputs == 2 ? 2 : 1) || c->share_gen != p->share_gen) {
+        c->nh != (cfg->n_outputs == 2 ? 2 : 1) || c->gen != p->gen) {
         c->valid = false;
         vpinn_problem *one[1] = {p};
         vpinn_status st = build_plan(one, 1, cfg, p->device, kDefaultTuning, c->plan);
@@ -1746,7 +1746,7 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
         c->tau = cfg->tau;
         c->gamma = cfg->gamma;
         c->nh = cfg->n_outputs == 2 ? 2 : 1;
-        c->share_gen = p->share_gen;
+        c->gen = p->gen;
     }
     AdamArgs none{};
     return run_plan(c->plan, d_params, d_eps, d_grad != nullptr || d_grad_eps != nullptr, d_loss, d_grad, d_grad_eps,
@@ -1762,6 +1762,7 @@ struct vpinn_batch {
     int device = 0;
     vpinn_loss_cfg cfg{};
     std::vector<vpinn_problem *> probs;  // borrowed; kept to rebuild the plan with another tuning
+    std::vector<int64_t> gens;           // the problems' generations the plan was built from
     vp::FusedPlan plan;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1785,12 +1786,27 @@ vpinn_status batch_create(int32_t n, vpinn_problem *const *problems, const vpinn
         delete b;
         return st;
     }
+    for (const vpinn_problem *p : b->probs) b->gens.push_back(p->gen);
     *out = b;
+    return VPINN_OK;
+}
+
+// the plan holds pointers into the problems' point buffers: after a problem's
+// point sets or sharing changed, only a rebuilt plan (a new batch, or a new tuning)
+// may run
+static vpinn_status batch_fresh(const vpinn_batch *b) {
+    for (size_t i = 0; i < b->probs.size(); ++i)
+        if (b->probs[i]->gen != b->gens[i])
+            return fail(VPINN_E_INVALID, "problem " + std::to_string(i) +
+                                             " changed its boundary, sensors or shared points after the batch "
+                                             "was planned: create the batch again");
     return VPINN_OK;
 }
 
 vpinn_status batch_loss_and_grad(vpinn_batch *b, const float *d_params, const float *d_eps, float *d_losses,
                                  float *d_grads, float *d_grad_eps, hipStream_t s) {
+    vpinn_status fr = batch_fresh(b);
+    if (fr) return fr;
     if (d_eps || d_grad_eps)
         for (const vpinn_problem *p : b->probs)
             if (p->folded() || p->vardiff)
@@ -1803,6 +1819,8 @@ vpinn_status batch_loss_and_grad(vpinn_batch *b, const float *d_params, const fl
 
 vpinn_status batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr, float b1,
                         float b2, float eps, float *d_losses, hipStream_t s) {
+    vpinn_status fr = batch_fresh(b);
+    if (fr) return fr;
     AdamArgs ad{d_params, d_m, d_v, d_step, lr, b1, b2, eps};
     return run_plan(b->plan, d_params, nullptr, true, d_losses, nullptr, nullptr, ad, d_step, b->prof, s);
 }
@@ -1810,6 +1828,8 @@ vpinn_status batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v,
 vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
                            float b1, float b2, float eps, float *d_losses, hipStream_t s) {
     if (!s) return fail(VPINN_E_INVALID, "capture needs a non-null stream");
+    vpinn_status fr = batch_fresh(b);
+    if (fr) return fr;
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
@@ -1865,6 +1885,7 @@ vpinn_status batch_set_tuning(vpinn_batch *b, const vpinn_tuning *t) {
     if (st) return st;
     drop_graph(b);
     b->plan = std::move(np);
+    for (size_t i = 0; i < b->probs.size(); ++i) b->gens[i] = b->probs[i]->gen;
     return VPINN_OK;
 }
 
@@ -1927,6 +1948,8 @@ vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps,
 
 vpinn_status batch_replay(vpinn_batch *b, hipStream_t s) {
     if (!b->exec) return fail(VPINN_E_INVALID, "no captured step: call vpinn_batch_capture first");
+    vpinn_status fr = batch_fresh(b);
+    if (fr) return fr;
     VP_HIP(hipGraphLaunch(b->exec, s));
     return VPINN_OK;
 }

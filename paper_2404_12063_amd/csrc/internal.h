@@ -117,7 +117,9 @@ struct vpinn_problem {
     vp::DevBuf usoff;        // int32 [n_uniq + 1]
     vp::DevBuf uslot;        // int32 [n_pts]
     vp::DevBuf upts;         // float2 [n_uniq]
-    int64_t share_gen = 0;   // bumped whenever the sharing changes (cached plans rebuild)
+    // bumped whenever the point sets or their sharing change: a cached single-problem
+    // plan rebuilds, and a batch built before the change refuses to run
+    int64_t gen = 0;
     vp::DevBuf Gx, Gy, F;    // float
     vp::DevBuf pts;          // float2 [n_pts + n_bnd + n_sen]: interior, boundary, sensors
     vp::DevBuf tgt;          // float [n_bnd + n_sen]: g_b then d_s

@@ -285,3 +285,43 @@ def test_capture_after_tuning_replays(V, torch):
     s.synchronize()
     assert int(step.item()) == 3 and int(step2.item()) == 3
     assert torch.equal(T, T2) and torch.equal(M, M2) and torch.equal(Vv, V2)
+
+
+def test_changed_problem_makes_the_batch_refuse_until_replanned(V, torch):
+    """The plan points into the problems' point buffers: after a boundary, sensor or shared-point change every
+    batch call is refused (no stale pointers are used) until the plan is rebuilt, which then matches the oracle
+    on the new data."""
+    from oracle import oracle as O
+    probs = _mixed_instances()[:3]
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
+    n = V.vpinn_n_params(30, 3)
+    th = _params(probs)
+    T = torch.tensor(th, dtype=torch.float32, device="cuda:0")
+    _batch_eval(V, torch, b, T, len(probs), n)
+    dev = torch.device("cuda:0")
+    M, Vv = torch.zeros_like(T), torch.zeros_like(T)
+    S = torch.zeros(1, dtype=torch.int64, device=dev)
+    s = torch.cuda.Stream()
+    V.vpinn_batch_capture(b, T.clone(), M, Vv, S, stream=s)
+    probs[1].bnd_xy = gen.square_boundary_points(48)
+    probs[1].bnd_g = np.zeros(48)
+    V.vpinn_set_boundary(gp[1], probs[1].bnd_xy, probs[1].bnd_g)
+    for call in (lambda: _batch_eval(V, torch, b, T, len(probs), n),
+                 lambda: V.vpinn_batch_replay(b, stream=s),
+                 lambda: V.vpinn_batch_step(b, T.clone(), M, Vv, S),
+                 lambda: V.vpinn_batch_capture(b, T.clone(), M, Vv, S, stream=s)):
+        with pytest.raises(V.VpinnError) as ei:
+            call()
+        assert ei.value.code == V.VPINN_E_INVALID
+    V.vpinn_batch_set_tuning(b, 12, 0, 4)
+    L, G = _batch_eval(V, torch, b, T, len(probs), n)
+    for i, p in enumerate(probs):
+        ref = O.problem_loss_grad(p, O.assemble_problem(p), th[i])
+        assert abs(L[i, 0] - ref.loss[0]) / ref.loss[0] < 1e-5, i
+        assert np.linalg.norm(G[i] - ref.grad) / np.linalg.norm(ref.grad) < 1e-4, i
+    with pytest.raises(V.VpinnError):  # the graph captured before the change is gone
+        V.vpinn_batch_replay(b, stream=s)
+    V.vpinn_set_shared_points(gp[0], probs[0].mesh.xy, probs[0].mesh.quad)
+    with pytest.raises(V.VpinnError):
+        _batch_eval(V, torch, b, T, len(probs), n)
