@@ -239,14 +239,16 @@ int64_t vpinn_n_params_out(int32_t width, int32_t n_hidden, int32_t n_outputs);
 
 /*
  * vpinn_loss_and_grad -- one forward + adjoint evaluation.
- *   d_params   device, vpinn_n_params(width, n_hidden) floats
+ *   d_params   device, vpinn_n_params_out(width, n_hidden, n_outputs) floats
+ *              (vpinn_n_params for one output)
  *   d_eps      device, 1 float: the diffusion coefficient eps of -eps Lap u = f
  *              (Sec. 4.7.1); NULL means eps = 1; must be NULL for a problem from
- *              vpinn_assemble_cd2d (its coefficients are folded into G)
+ *              vpinn_assemble_cd2d or vpinn_assemble_vardiff (or their
+ *              matrix-free forms), whose coefficients are fixed or a network output
  *   d_loss     device, 4 floats written: L, L_v, L_b, L_s (L_b and L_s are the
  *              unweighted means; L = L_v + tau L_b + gamma L_s)
- *   d_grad     device, vpinn_n_params floats written: dL/dtheta; NULL skips the
- *              backward pass
+ *   d_grad     device, as many floats as d_params, written: dL/dtheta; NULL skips
+ *              the backward pass
  *   d_grad_eps device, 1 float written: dL/deps; may be NULL
  * The problem keeps a device workspace that the first call of each path
  * allocates (and a call with more boundary or sensor points grows); later calls
