@@ -80,7 +80,7 @@ double orc_legendre_deriv(int m, double t)
 /* ------------------------------------------------------------------------- */
 int orc_gll(int n, double *x, double *w)
 {
-    if (n < 2 || n > 64 || !x || !w) return ORC_E_ARG;
+    if (n < 2 || n > 128 || !x || !w) return ORC_E_ARG;
     const int m = n - 1;
     x[0] = -1.0;
     x[n - 1] = 1.0;
@@ -182,8 +182,7 @@ int orc_assemble(int64_t n_nodes, const double *xy, int64_t n_elem, const int32_
     if (f_kind == 0 && !f_fn) return ORC_E_ARG;
     const int nq = n * n, ntest = nt * nt;
     double *gx = malloc(sizeof(double) * n), *gw = malloc(sizeof(double) * n);
-    orc_gll(n, gx, gw);
-    int status = ORC_OK;
+    int status = orc_gll(n, gx, gw);
     for (int64_t e = 0; e < n_elem && status == ORC_OK; ++e) {
         double v[8];
         for (int c = 0; c < 4; ++c) {

@@ -104,7 +104,7 @@ def test_gll_degree_of_exactness(oracle, n):
     assert abs(2.0 / (n - 1) - 2.0 / (2 * n - 1)) > 0.05
 
 
-@pytest.mark.parametrize("n", [3, 7, 10, 16, 25])
+@pytest.mark.parametrize("n", [3, 7, 10, 16, 25, 40, 64, 65, 80, 100])
 def test_gll_matches_numpy_legendre_roots(oracle, n):
     x, w = oracle.gll(n)
     xn, wn = _numpy_gll(n)
@@ -648,3 +648,10 @@ def test_prediction_error_picks_the_worst_point(oracle):
     mae, mx, rel = oracle.prediction_error(theta, 1, 1, xy, ref)
     assert abs(mae - 0.03) < 1e-14 and abs(mx - 0.3) < 1e-14
     assert abs(rel - 0.3 / np.linalg.norm(ref)) < 1e-14
+
+
+def test_assembly_refuses_an_order_the_rule_does_not_cover(oracle):
+    """An order beyond the GLL routine's range is an error of the assembly, never garbage nodes."""
+    m = gen.square_mesh(1, 1)
+    with pytest.raises(Exception):
+        oracle.assemble(m.xy, m.quad, 129, 2, 1.0, 1.0, 1.0)
