@@ -69,6 +69,14 @@ def _problem(name):
         return gen.poisson_sinsin_square("uniform16", 16, 8, 5, 4, 200, 0.0, seed=1)
     if name == "q17":         # 289 points per element: the two-pass contraction for large elements
         return gen.poisson_sinsin_square("q17", 2, 17, 3, 2, 40, 0.2, seed=7)
+    if name == "q80t20":      # the p-refinement study's element: 80 x 80 points, 20 x 20 test functions
+        return gen.poisson_sinsin_square("q80t20", 1, 80, 20, 2, 80, 0.0, seed=10)
+    if name == "q40t5":       # 2 x 2 skewed elements of 40 x 40 points, as in the constant-eps inverse problem
+        return gen.poisson_sinsin_square("q40t5", 2, 40, 5, 2, 40, 0.2, seed=11)
+    if name == "q100t3":      # the largest quadrature order (10,000 points an element)
+        return gen.poisson_sinsin_square("q100t3", 1, 100, 3, 2, 40, 0.0, seed=12)
+    if name == "q8t30":       # the largest test order (900 test functions) on 64-point elements
+        return gen.poisson_sinsin_square("q8t30", 2, 8, 30, 2, 40, 0.2, seed=13)
     if name == "gear_small":  # a small toothed annulus: skewed elements, nonzero boundary data
         import math
         kp = 4 * math.pi
@@ -187,7 +195,7 @@ def test_network_values_and_tangents(V, torch, H, L):
 
 @pytest.mark.parametrize("path", ["plain", "fused"])
 @pytest.mark.parametrize("name", ["c1", "c2", "gear_small", "ragged", "tiny_n2", "deep32", "nobnd", "p20", "q6t7",
-                                  "q12t6", "q17", "uniform16"])
+                                  "q12t6", "q17", "uniform16", "q80t20", "q40t5", "q100t3", "q8t30"])
 def test_loss_and_grad_match_oracle(V, torch, path, name):
     prob = _problem(name)
     theta = _params(prob)
