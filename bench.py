@@ -475,7 +475,7 @@ def main():
                     help="counter runs: time only the tuned batch-of-one plan (no single-problem-API steps, no "
                          "loss check), so every fused kernel in the trace belongs to that plan; implies no CPU baseline")
     ap.add_argument("--tuning", type=lambda t: tuple(int(x) for x in t.split(",")), default=None,
-                    metavar="FWD_WAVES,CHUNK_SHIFT,ROWS_PER_PASS",
+                    metavar="FWD_WAVES,CHUNK_SHIFT,ROWS_PER_PASS[,STORE_ACTIVATIONS]",
                     help="use this tile-shape tuning instead of autotuning (profiling runs)")
     args = ap.parse_args()
     if args.traffic_from:

@@ -382,12 +382,17 @@ void vpinn_batch_free(vpinn_batch *b);
  *                  0..2
  *   rows_per_pass  larger test spaces: test-function rows of G a wavefront
  *                  streams per pass, 2, 4 or 8
- * A new batch starts with {12, 0, 4}.
+ *   store_activations  0: the reverse sweep recomputes each layer's activations
+ *                  (tanh included); 1: the forward pass stores them (L x 2 KB per
+ *                  16 points of device memory, held by the plan) and the reverse
+ *                  sweep reads them, recomputing only the tangents
+ * A new batch starts with {12, 0, 4, 0}.
  */
 typedef struct {
     int32_t fwd_waves;
     int32_t chunk_shift;
     int32_t rows_per_pass;
+    int32_t store_activations;
 } vpinn_tuning;
 
 /* The batch's current tuning.  Errors: VPINN_E_INVALID (null argument). */
@@ -402,9 +407,9 @@ vpinn_status vpinn_batch_set_tuning(vpinn_batch *b, const vpinn_tuning *t);
 
 /*
  * vpinn_batch_autotune -- the project's tile-shape autotuner.  Times every
- * tuning that matters for this batch (forward block sizes always; contraction
- * chunking only if some problem has small elements; rows per pass only if some
- * problem streams rows) by `reps` loss-and-gradient evaluations at d_params
+ * tuning that matters for this batch (forward block sizes and storing
+ * activations always; contraction chunking only if some problem has small
+ * elements; rows per pass only if some problem streams rows) by `reps` loss-and-gradient evaluations at d_params
  * (device [n][n_params], not modified) after one warm-up each, keeps the one
  * with the lowest median time, and returns it in *best (may be NULL).
  * Synchronous on `stream`; allocates scratch outputs and each candidate plan;

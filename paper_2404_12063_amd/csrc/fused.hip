@@ -164,6 +164,7 @@ struct FwdArgs {
     double *lpart;              // [loss rows][4]
     int64_t *step;              // optional step counter, incremented once per launch
     float *ebuf;                // two outputs: second output e at interior points (point buffer order)
+    float *act;                 // optional: activations a_1 .. a_L of every tile, [tile][L][2][64][4]
 };
 
 struct ContractArgs {
@@ -187,6 +188,7 @@ struct BwdArgs {
     const float2 *ubuf;
     float *gpart;               // [gradient rows][kMaxPadded]
     const float *ebuf;          // two outputs: dL/de at interior points
+    const float *act;           // activations stored by k_fwd (with the loading instantiation of k_bwd)
 };
 
 // ---------------------------------------------------------------------------
@@ -201,9 +203,13 @@ struct Acts {
     Vec py[L];
 };
 
+// activations of one tile in the layout [layer][m][lane][4]: each lane's chained
+// vector is two 16-byte pieces, so a layer is two fully coalesced 1 KB accesses
+constexpr int kActTile = 2 * 64 * 4;  // floats per layer and tile
+
 template <int L, bool KEEP>
 __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane, float x, float y, Vec &A_, Vec &TX,
-                                             Vec &TY, Acts<L> &keep) {
+                                             Vec &TY, Acts<L> &keep, float *act = nullptr) {
     const int g = lane >> 4;
 #pragma unroll
     for (int m = 0; m < 2; ++m)
@@ -217,6 +223,11 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
             TX.v[m][r] = s * w0;
             TY.v[m][r] = s * w1v;
         }
+    if (act) {
+        f4 *o = reinterpret_cast<f4 *>(act);
+        o[lane] = A_.v[0];
+        o[64 + lane] = A_.v[1];
+    }
     if (KEEP) keep.a[0] = A_;
 #pragma unroll
     for (int l = 2; l <= L; ++l) {
@@ -257,11 +268,73 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
                 TX.v[m][r] = s * PX.v[m][r];
                 TY.v[m][r] = s * PY.v[m][r];
             }
+        if (act) {
+            f4 *o = reinterpret_cast<f4 *>(act + (l - 1) * kActTile);
+            o[lane] = A_.v[0];
+            o[64 + lane] = A_.v[1];
+        }
         if (KEEP) {
             keep.a[l - 1] = A_;
             keep.px[l - 1] = PX;
             keep.py[l - 1] = PY;
         }
+    }
+}
+
+// the reverse sweep's forward state from stored activations: a_l is read, s_l =
+// 1 - a_l^2, and only the tangent products are recomputed (no tanh, no value products)
+template <int L>
+__device__ __forceinline__ void tile_forward_loaded(const WeightsShared<L> &S, int lane, const float *act,
+                                                    Acts<L> &K) {
+    const int g = lane >> 4;
+    const f4 *in = reinterpret_cast<const f4 *>(act);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        K.a[l].v[0] = in[l * (kActTile / 4) + lane];
+        K.a[l].v[1] = in[l * (kActTile / 4) + 64 + lane];
+    }
+    Vec TX, TY;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * m + 4 * g + r;
+            const float a = K.a[0].v[m][r];
+            const float s = 1.0f - a * a;
+            TX.v[m][r] = s * S.w1[n][0];
+            TY.v[m][r] = s * S.w1[n][1];
+        }
+#pragma unroll
+    for (int l = 2; l <= L; ++l) {
+        Vec PX, PY;
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo) {
+            f4 px = {0.f, 0.f, 0.f, 0.f}, py = {0.f, 0.f, 0.f, 0.f};
+            float wv[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) wv[s] = S.wf[l - 2][0][mo][s][lane];
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                px = mfma(wv[s], TX.v[s >> 2][s & 3], px);
+                py = mfma(wv[s], TY.v[s >> 2][s & 3], py);
+            }
+            __builtin_amdgcn_s_setprio(0);
+            PX.v[mo] = px;
+            PY.v[mo] = py;
+        }
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float a = K.a[l - 1].v[m][r];
+                const float s = 1.0f - a * a;
+                TX.v[m][r] = s * PX.v[m][r];
+                TY.v[m][r] = s * PY.v[m][r];
+            }
+        K.px[l - 1] = PX;
+        K.py[l - 1] = PY;
     }
 }
 
@@ -580,7 +653,7 @@ __device__ __forceinline__ void zero_acc(GradAcc<L> &G) {
 // 1: forward values and tangents at every point.  Blocks own contiguous tile ranges
 // (the same ranges as k_bwd), possibly spanning instances; the tiles of a range go
 // round-robin over the block's wavefronts.
-template <int L, int NW, int NH>
+template <int L, int NW, int NH, bool ST>
 __global__ __launch_bounds__(NW * 64, 1) void k_fwd(FwdArgs A) {
     constexpr int kFwThreads = NW * 64, kFwWaves = NW;
     __shared__ FwdShared<L, NW> S;
@@ -617,7 +690,9 @@ __global__ __launch_bounds__(NW * 64, 1) void k_fwd(FwdArgs A) {
             pn = fetch(tt + kFwWaves);
             Vec a, tx, ty;
             Acts<L> unused;
-            tile_forward<L, false>(S.W, lane, p.x, p.y, a, tx, ty, unused);
+            // ST: keep every layer's activations for the reverse sweep
+            tile_forward<L, false>(S.W, lane, p.x, p.y, a, tx, ty, unused,
+                                   ST ? A.act + tt * (int64_t)(L * kActTile) : nullptr);
             float u, ux, uy;
             tile_outputs<L>(S.W, lane, a, tx, ty, u, ux, uy);
             const float e = NH == 2 ? tile_second<L>(S.W, lane, a) : 0.f;
@@ -1173,7 +1248,7 @@ __device__ __forceinline__ void flush_grad(BwdShared<L, NH> &S, const BwdArgs &A
 
 // 4: reverse sweep, tiles of 16 points spread evenly over all wavefronts; the
 // forward pass of each tile is recomputed (tanh included) and kept in registers
-template <int L, int NH>
+template <int L, int NH, bool LOADA>
 __global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
     __shared__ BwdShared<L, NH> S;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1236,8 +1311,12 @@ __global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
             const bool interior = idx < n_pts;
             const float ub = interior ? 0.f : d.x, uxb = interior ? d.x : 0.f, uyb = interior ? d.y : 0.f;
             Acts<L> K;
-            Vec a, tx, ty;
-            tile_forward<L, true>(S.W, lane, p.x, p.y, a, tx, ty, K);
+            if (LOADA) {
+                tile_forward_loaded<L>(S.W, lane, A.act + tt * (int64_t)(L * kActTile), K);
+            } else {
+                Vec a, tx, ty;
+                tile_forward<L, true>(S.W, lane, p.x, p.y, a, tx, ty, K);
+            }
             tile_backward<L, NH>(S.W, T0, T1, lane, p.x, p.y, ub, uxb, uyb, eb, K, G, S.vacc[wave]);
         }
         flush_grad<L, NH>(S, A, row, G, tid, wave, lane);
@@ -1393,10 +1472,11 @@ static int cu_count(int dev) {
 // tile shapes a plan is built with (vpinn_tuning): forward wavefronts per block,
 // elements per small-element contraction block (shift), rows per pass of the
 // row-streaming contraction
-static const vpinn_tuning kDefaultTuning = {12, 0, 4};
+static const vpinn_tuning kDefaultTuning = {12, 0, 4, 0};
 static bool tuning_valid(const vpinn_tuning &t) {
     return (t.fwd_waves == 8 || t.fwd_waves == 12 || t.fwd_waves == 16) && t.chunk_shift >= 0 && t.chunk_shift <= 2 &&
-           (t.rows_per_pass == 2 || t.rows_per_pass == 4 || t.rows_per_pass == 8);
+           (t.rows_per_pass == 2 || t.rows_per_pass == 4 || t.rows_per_pass == 8) &&
+           (t.store_activations == 0 || t.store_activations == 1);
 }
 
 struct FusedPlan {
@@ -1404,6 +1484,7 @@ struct FusedPlan {
     DevBuf ebuf;  // two outputs: e, then dL/de, per point (point buffer order)
     // shared points: the instances' point lists, and the per-slot adjoints of the contraction
     DevBuf dpts, abuf, eabuf;
+    DevBuf act;  // store_activations: [tiles][L][kActTile]
     int nh = 1;   // network outputs
     vpinn_tuning tune = kDefaultTuning;
     std::vector<InstDesc> host_inst;
@@ -1557,6 +1638,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     VP_HIP(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)grows));
     VP_HIP(P.lpart.reserve(sizeof(double) * 4 * (size_t)lrows));
     if (nh == 2) VP_HIP(P.ebuf.reserve(sizeof(float) * (size_t)ubase));
+    if (tune.store_activations) VP_HIP(P.act.reserve(sizeof(float) * (size_t)tiles * L * kActTile));
     if (n_slots) {
         VP_HIP(P.dpts.reserve(sizeof(float2) * (size_t)n_dpts));
         VP_HIP(P.abuf.reserve(sizeof(float2) * (size_t)n_slots));
@@ -1625,10 +1707,14 @@ static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs
                        bool want_grad, dim3 fg, int ft, float *loss, float *grad, float *grad_eps, const AdamArgs &ad,
                        hipEvent_t const *ev, hipStream_t s) {
     if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
-    switch (P.tune.fwd_waves) {
-    case 8: k_fwd<L, 8, NH><<<P.tblocks, 8 * 64, 0, s>>>(fa); break;
-    case 16: k_fwd<L, 16, NH><<<P.tblocks, 16 * 64, 0, s>>>(fa); break;
-    default: k_fwd<L, 12, NH><<<P.tblocks, 12 * 64, 0, s>>>(fa); break;
+    const bool st = fa.act != nullptr;
+    switch (P.tune.fwd_waves * 2 + (st ? 1 : 0)) {
+    case 16: k_fwd<L, 8, NH, false><<<P.tblocks, 8 * 64, 0, s>>>(fa); break;
+    case 17: k_fwd<L, 8, NH, true><<<P.tblocks, 8 * 64, 0, s>>>(fa); break;
+    case 32: k_fwd<L, 16, NH, false><<<P.tblocks, 16 * 64, 0, s>>>(fa); break;
+    case 33: k_fwd<L, 16, NH, true><<<P.tblocks, 16 * 64, 0, s>>>(fa); break;
+    case 25: k_fwd<L, 12, NH, true><<<P.tblocks, 12 * 64, 0, s>>>(fa); break;
+    default: k_fwd<L, 12, NH, false><<<P.tblocks, 12 * 64, 0, s>>>(fa); break;
     }
     if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
     {
@@ -1651,7 +1737,10 @@ static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs
             k_contract_mf<NH == 2><<<(unsigned)P.cpath_blocks[kPathMF], kCThreads, P.cdyn_mf, s>>>(c);
     }
     if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
-    if (want_grad) k_bwd<L, NH><<<P.tblocks, kBThreads, 0, s>>>(ba);
+    if (want_grad) {
+        if (P.tune.store_activations) k_bwd<L, NH, true><<<P.tblocks, kBThreads, 0, s>>>(ba);
+        else k_bwd<L, NH, false><<<P.tblocks, kBThreads, 0, s>>>(ba);
+    }
     if (ev && ev[3]) (void)hipEventRecord(ev[3], s);
     k_fused_final<L, NH><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf,
                                         loss, grad, grad_eps, ad);
@@ -1673,6 +1762,8 @@ static vpinn_status run_plan(const FusedPlan &P, const float *params, const floa
     fa.lpart = P.lpart.as<double>();
     fa.step = step;
     fa.ebuf = P.ebuf.as<float>();
+    // activations are stored only when the reverse sweep will read them
+    fa.act = (want_grad && P.tune.store_activations) ? P.act.as<float>() : nullptr;
     ContractArgs ca{};
     ca.inst = P.inst.as<InstDesc>();
     ca.cblk_inst = P.cblk_inst.as<int>();
@@ -1691,6 +1782,7 @@ static vpinn_status run_plan(const FusedPlan &P, const float *params, const floa
     ba.ubuf = P.ubuf.as<float2>();
     ba.gpart = P.gpart.as<float>();
     ba.ebuf = P.ebuf.as<float>();
+    ba.act = P.act.as<float>();
     const dim3 fg((unsigned)std::max<int64_t>(1, (P.npf + kFinCols - 1) / kFinCols), (unsigned)P.n_inst);
     const int ft = kFinThreads;
     switch (P.L * 2 + P.nh - 1) {
@@ -1900,7 +1992,8 @@ vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps,
     for (int fw : {8, 12, 16})
         for (int cs = 0; cs <= (has_fast ? 2 : 0); ++cs)
             for (int rp : {2, 4, 8})
-                if (has_rows || rp == 4) cand.push_back(vpinn_tuning{fw, cs, rp});
+                for (int sa : {0, 1})
+                    if (has_rows || rp == 4) cand.push_back(vpinn_tuning{fw, cs, rp, sa});
     const int n = (int)b->probs.size();
     DevBuf losses, grads;
     VP_HIP(losses.reserve(sizeof(float) * 4 * (size_t)n));

@@ -219,12 +219,12 @@ def test_tunings_agree_with_oracle(V, torch):
     probs = _all_shapes()
     gp = [_gpu(V, p) for p in probs]
     b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
-    assert V.vpinn_batch_get_tuning(b) == (12, 0, 4)
+    assert V.vpinn_batch_get_tuning(b) == (12, 0, 4, 0)
     n = V.vpinn_n_params(30, 3)
     th = _params(probs)
     T = torch.tensor(th, dtype=torch.float32, device="cuda:0")
     refs = [O.problem_loss_grad(p, O.assemble_problem(p), th[i]) for i, p in enumerate(probs)]
-    for tune in [(8, 2, 2), (16, 1, 8), (12, 0, 4)]:
+    for tune in [(8, 2, 2, 0), (16, 1, 8, 1), (12, 0, 4, 1), (12, 0, 4, 0)]:
         V.vpinn_batch_set_tuning(b, *tune)
         assert V.vpinn_batch_get_tuning(b) == tune
         L, G = _batch_eval(V, torch, b, T, len(probs), n)
@@ -245,7 +245,7 @@ def test_autotune_picks_a_valid_tuning_and_keeps_parity(V, torch):
     L0, G0 = _batch_eval(V, torch, b, T, len(probs), n)
     best = V.vpinn_batch_autotune(b, T, reps=2)
     assert best == V.vpinn_batch_get_tuning(b)
-    assert best[0] in (8, 12, 16) and 0 <= best[1] <= 2 and best[2] in (2, 4, 8)
+    assert best[0] in (8, 12, 16) and 0 <= best[1] <= 2 and best[2] in (2, 4, 8) and best[3] in (0, 1)
     L1, G1 = _batch_eval(V, torch, b, T, len(probs), n)
     np.testing.assert_allclose(L1, L0, rtol=1e-5)
     for i in range(len(probs)):
@@ -254,6 +254,8 @@ def test_autotune_picks_a_valid_tuning_and_keeps_parity(V, torch):
     np.testing.assert_array_equal(T.cpu().numpy(), _params(probs).astype(np.float32))
     with pytest.raises(V.VpinnError):
         V.vpinn_batch_set_tuning(b, 10, 0, 4)
+    with pytest.raises(V.VpinnError):
+        V.vpinn_batch_set_tuning(b, 12, 0, 4, 2)
     with pytest.raises(V.VpinnError):
         V.vpinn_batch_autotune(b, T, reps=0)
 
@@ -325,3 +327,21 @@ def test_changed_problem_makes_the_batch_refuse_until_replanned(V, torch):
     V.vpinn_set_shared_points(gp[0], probs[0].mesh.xy, probs[0].mesh.quad)
     with pytest.raises(V.VpinnError):
         _batch_eval(V, torch, b, T, len(probs), n)
+
+
+def test_stored_activations_match_recompute(V, torch):
+    """Reading the forward pass's activations instead of recomputing them gives the same loss and gradient
+    (the same arithmetic, so equal up to FP32 summation order), for one and two network outputs."""
+    probs = _all_shapes()
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
+    n = V.vpinn_n_params(30, 3)
+    T = torch.tensor(_params(probs), dtype=torch.float32, device="cuda:0")
+    for fw in (8, 16):
+        V.vpinn_batch_set_tuning(b, fw, 0, 4, 0)
+        L0, G0 = _batch_eval(V, torch, b, T, len(probs), n)
+        V.vpinn_batch_set_tuning(b, fw, 0, 4, 1)
+        L1, G1 = _batch_eval(V, torch, b, T, len(probs), n)
+        np.testing.assert_allclose(L1, L0, rtol=1e-6)
+        for i in range(len(probs)):
+            assert np.linalg.norm(G1[i] - G0[i]) <= 1e-6 * np.linalg.norm(G0[i]), (fw, i)
