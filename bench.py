@@ -106,9 +106,9 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str, kernel: str):
+def traffic_from_profile(workload: str, kernel: str, tuning=None):
     """HBM bytes per launch of `kernel` on `workload` from the committed counter summary, if it was taken on
-    the current sources (else None)."""
+    the current sources and, when the summary names one, with the same tuning (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -116,6 +116,12 @@ def traffic_from_profile(workload: str, kernel: str):
         rec = json.load(f)
     entry = rec.get(workload, {}).get(kernel)
     if not entry or entry.get("source_digest") != source_digest():
+        return None
+    # only the tuning fields that change the kernel's own memory traffic must agree: forward wavefronts and
+    # stored activations for k_fwd, stored activations for k_bwd, chunking and rows per pass for the contraction
+    fields = {"k_fwd": (0, 3), "k_bwd": (3,), "k_contract": (1, 2)}.get(kernel, (0, 1, 2, 3))
+    tr = entry.get("tuning")
+    if tuning is not None and tr is not None and any(list(tr)[i] != list(tuning)[i] for i in fields):
         return None
     return entry.get("hbm_bytes_per_launch")
 
@@ -129,7 +135,7 @@ def _pmc_rows(path):
         return list(csv.DictReader(f))
 
 
-def write_traffic(workload: str, fetch_csv: str, write_csv: str):
+def write_traffic(workload: str, fetch_csv: str, write_csv: str, tuning=None):
     """Scale the per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of each fused-path kernel by what the same
     counters read for the 256 MiB copy (known: 256 MiB read, 256 MiB written); store under `workload`."""
     def per_kernel(path, counter):
@@ -156,7 +162,8 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str):
             continue
         fb = fk[len(fk) // 2] * 1024.0 * f_scale
         wb = wk[len(wk) // 2] * 1024.0 * w_scale
-        out[name] = {"source_digest": source_digest(), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+        out[name] = {"source_digest": source_digest(), "tuning": None if tuning is None else list(tuning),
+                     "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                      "hbm_bytes_per_launch": fb + wb, "fetch_scale": f_scale, "write_scale": w_scale,
                      "dispatches": len(fk)}
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -433,7 +440,8 @@ def bench_batched(args, V, torch, gen):
                                 round(st[(9 * len(st)) // 10], 4)],
         "roofline": {"bound": "mfma", "kernel": dom + " (all 64 instances in one launch)",
                      "achieved": round(dom_tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(dom_tf / PEAK_FP32_TFLOPS, 4), "traffic": traffic_from_profile("c5", dom),
+                     "frac": round(dom_tf / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic_from_profile("c5", dom, tuning),
                      "algorithmic_flop_per_launch": work[dom]["flop"], "launch_ms_mean": round(kms[dom], 4)},
         "whole_step": {"algorithmic_flop": flops, "algorithmic_bytes": sum(bytes_per_epoch(pr) for pr in probs),
                        "achieved_tflops": round(achieved, 3), "frac_of_fp32_peak": round(achieved / PEAK_FP32_TFLOPS, 4)},
@@ -470,7 +478,8 @@ def main():
                          "the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, then "
-                         "WRITE_SIZE, taken with --copy-probe on --workload W) into profiles/traffic.json[W]")
+                         "WRITE_SIZE, taken with --copy-probe on --workload W and --tuning T) into "
+                         "profiles/traffic.json[W] (give the same --tuning T)")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter runs: time only the tuned batch-of-one plan (no single-problem-API steps, no "
                          "loss check), so every fused kernel in the trace belongs to that plan; implies no CPU baseline")
@@ -479,7 +488,7 @@ def main():
                     help="use this tile-shape tuning instead of autotuning (profiling runs)")
     args = ap.parse_args()
     if args.traffic_from:
-        write_traffic(args.workload, *args.traffic_from)
+        write_traffic(args.workload, *args.traffic_from, tuning=args.tuning)
         return
     if args.profile_run:
         args.no_cpu_baseline = True
@@ -601,7 +610,7 @@ def bench_single(args, V, torch, gen):
             roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                     "algorithmic_flop_per_launch": work[dom]["flop"]}
-        roof["traffic"] = traffic_from_profile(args.workload, dom)
+        roof["traffic"] = traffic_from_profile(args.workload, dom, res.get("tuning"))
         roof["launch_ms_mean"] = round(k_ms, 5)
     else:
         k_ms = eager["lg_ms_mean"]
