@@ -345,3 +345,40 @@ def test_stored_activations_match_recompute(V, torch):
         np.testing.assert_allclose(L1, L0, rtol=1e-6)
         for i in range(len(probs)):
             assert np.linalg.norm(G1[i] - G0[i]) <= 1e-6 * np.linalg.norm(G0[i]), (fw, i)
+
+
+def test_c2_in_the_bench_launch_configuration(V, torch):
+    """C2 exactly as bench.py times it: a batch of one, autotuned, one Adam step captured in a HIP graph and
+    replayed.  The loss each replay reports is the oracle's at the parameters it started from, and the first
+    replay's update is the oracle's Adam step (Kingma-Ba, lr 1e-3)."""
+    from oracle import oracle as O
+    prob = gen.config_c2()
+    theta = prob.params()
+    p = V.assemble_problem(prob)
+    b = V.vpinn_batch_create([p], V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma))
+    dev = torch.device("cuda:0")
+    th = torch.tensor(theta, dtype=torch.float32, device=dev).reshape(1, -1).contiguous()
+    V.vpinn_batch_autotune(b, th, reps=2)
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    step = torch.zeros(1, dtype=torch.int64, device=dev)
+    losses = torch.zeros((1, 4), device=dev)
+    s = torch.cuda.Stream()
+    V.vpinn_batch_capture(b, th, m, v, step, lr=1e-3, losses=losses, stream=s)
+    asm = O.assemble_problem(prob)
+    th32 = th.cpu().double().numpy()[0]
+    V.vpinn_batch_replay(b, stream=s)
+    s.synchronize()
+    ref = O.problem_loss_grad(prob, asm, th32)
+    assert abs(losses[0, 0].item() - ref.loss[0]) / ref.loss[0] < 1e-5
+    t_ref, m_ref, v_ref = th32.copy(), np.zeros_like(th32), np.zeros_like(th32)
+    O.adam(t_ref, ref.grad, m_ref, v_ref, 1, lr=1e-3)
+    got = th.cpu().double().numpy()[0]
+    # the update is lr * sign(g) on the first step, except where |g| is tiny: compare the step taken
+    np.testing.assert_allclose(got - th32, t_ref - th32, rtol=0, atol=2e-5 * 1e-3 + 1e-7)
+    # a second replay reports the loss at the updated parameters
+    th_after = th.cpu().double().numpy()[0]
+    V.vpinn_batch_replay(b, stream=s)
+    s.synchronize()
+    ref2 = O.problem_loss_grad(prob, asm, th_after, want_grad=False)
+    assert abs(losses[0, 0].item() - ref2.loss[0]) / ref2.loss[0] < 1e-5
+    assert int(step.item()) == 2
