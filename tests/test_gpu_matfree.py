@@ -143,7 +143,7 @@ def test_batch_mixing_stored_and_matrix_free(V, torch):
     dev = torch.device("cuda:0")
     T = torch.tensor(th, dtype=torch.float32, device=dev)
     refs = [O.problem_loss_grad(pr, O.assemble_problem(pr), th[i]) for i, pr in enumerate(probs)]
-    for tune in [(12, 0, 4), (16, 2, 2)]:
+    for tune in [(12, 0, 4), (16, 2, 2), (12, 0, 4, 1)]:
         V.vpinn_batch_set_tuning(b, *tune)
         losses = torch.zeros((len(probs), 4), device=dev)
         grads = torch.zeros((len(probs), th.shape[1]), device=dev)

@@ -203,7 +203,7 @@ def test_vardiff_batch_matches_oracle_for_every_tuning(V, torch):
     for i, pr in enumerate(probs):
         pr.tau, pr.gamma = 10.0, 10.0
         refs.append(O.problem_loss_grad(pr, O.assemble_problem(pr), th[i]))
-    for tune in [(12, 0, 4), (8, 1, 2), (16, 2, 8)]:
+    for tune in [(12, 0, 4), (8, 1, 2), (16, 2, 8), (12, 0, 4, 1), (16, 2, 4, 1)]:
         V.vpinn_batch_set_tuning(b, *tune)
         losses = torch.zeros((len(probs), 4), device=dev)
         grads = torch.zeros((len(probs), n), device=dev)
