@@ -328,3 +328,20 @@ def test_shared_premultiplier_detection(V, name, shared):
     """Uniform meshes store G once (Algorithm 2); jittered and curved ones per element."""
     p = _gpu_problem(V, _problem(name))
     assert V.vpinn_get_info(p).shared_premultiplier == shared
+
+
+@pytest.mark.parametrize("path", ["plain", "fused"])
+@pytest.mark.parametrize("tau,gamma", [(0.0, 0.0), (1.0, 0.0), (0.0, 1.0), (1.0, 1.0)])
+def test_boundary_and_sensor_weights(V, torch, path, tau, gamma):
+    """tau and gamma are arguments of the call: 0 removes a term from the gradient (its loss component is still
+    reported), 1 weighs it as the plain mean."""
+    import dataclasses
+    from oracle import oracle as O
+    base = _problem("ragged")
+    sxy = gen.sensor_points(40, 9)
+    prob = dataclasses.replace(base, name=f"w{tau}{gamma}", tau=tau, gamma=gamma, sens_xy=sxy,
+                               sens_u=gen.uniform(9, "wsu", 40, -1, 1))
+    theta = _params(prob)
+    p = _gpu_problem(V, prob)
+    loss, grad, _ = _run(V, torch, p, prob, theta, _path_or_skip(V, path))
+    _check(loss, grad, O.problem_loss_grad(prob, _oracle_asm("ragged"), theta), tag=f"tau={tau}/gamma={gamma}/{path}")
