@@ -210,7 +210,7 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str, tuning=None):
     w_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(write)
     out = {}
     # kernel families (template arguments vary with the tuning); a --profile-run bench runs one plan only
-    for name, key in [("k_bwd", "k_bwd<"), ("k_fwd", "k_fwd<"), ("k_contract", "k_contract_")]:
+    for name, key in [("k_bwd", "k_bwd<"), ("k_fwd", "k_fwd<"), ("k_contract", "k_contract_"), ("k_eval", "k_eval<")]:
         fk = sorted(v for k, vs in fetch.items() if key in k for v in vs)
         wk = sorted(v for k, vs in write.items() if key in k for v in vs)
         if not fk or not wk:
@@ -518,13 +518,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
-    ap.add_argument("--workload", choices=["c2", "c5", "probe", "gear_cd", "disk_vareps", "c2_mf", "probe_mf"],
+    ap.add_argument("--workload", choices=["c2", "c5", "probe", "gear_cd", "disk_vareps", "c2_mf", "probe_mf",
+                                           "predict"],
                     default="c2",
                     help="c2 (default, the headline): one 1,024-element problem; c5: 64-instance batch; probe: "
                          "20x20 test functions on 4,096 elements (G-stream bound); gear_cd: the convection-diffusion "
                          "gear problem on 14,000 elements; disk_vareps: space-dependent diffusion inverse problem, "
                          "a two-output network on a 1,024-element disk; c2_mf, probe_mf: the same as c2, probe with "
-                         "G regenerated per step from the element geometry (matrix-free)")
+                         "G regenerated per step from the element geometry (matrix-free); predict: network values "
+                         "of a trained-size MLP at the six point counts of the paper's prediction-time table")
     ap.add_argument("--shared-points", action="store_true",
                     help="evaluate the network once per distinct interior GLL point (vpinn_set_shared_points); the "
                          "result equals per-slot evaluation up to rounding")
@@ -567,7 +569,106 @@ def main():
     if args.workload == "c5":
         bench_batched(args, V, torch, gen)
         return
+    if args.workload == "predict":
+        bench_predict(args, V, torch, gen)
+        return
     bench_single(args, V, torch, gen)
+
+
+# point counts of the paper's prediction-time table (Appendix, FastVPINNs vs FEM) and its network times there
+# (NVIDIA RTX A6000, TensorFlow): context, not a target
+PREDICT_SIZES = [29302, 115868, 259698, 460792, 719150, 1034772]
+PREDICT_PAPER_S = [7.807e-4, 7.978e-4, 1.777e-3, 3.139e-3, 4.890e-3, 7.023e-3]
+
+
+def predict_flop_per_point(H: int, L: int) -> int:
+    """Algorithmic FLOPs of one network value: input layer (2 products and a bias, per neuron), L - 1 hidden
+    products, the output layer; the H L tanh are not counted."""
+    return 2 * 2 * H + (L - 1) * 2 * H * H + 2 * H
+
+
+def bench_predict(args, V, torch, gen):
+    """Network values at N points (the prediction step timed in the paper's Appendix table), for each of its six
+    point counts: seeded uniform points in the unit square stand in for the FEM mesh's degrees of freedom, with
+    the C2 network (2-30-30-30-1 tanh).  Points and weights are resident in device memory; each call is timed
+    between HIP events on the stream it is launched on."""
+    import numpy as np
+    prob = gen.config_c2()
+    H, L = prob.width, prob.n_hidden
+    theta = prob.params(seed=8, bias_scale=0.1)
+    dev = torch.device("cuda:0")
+    th = torch.tensor(theta, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    reps = args.steps
+    rows = []
+    # a counter run times the largest size only, so every k_eval dispatch in it has the same size
+    sizes = list(zip(PREDICT_SIZES, PREDICT_PAPER_S))[-1:] if args.profile_run else zip(PREDICT_SIZES, PREDICT_PAPER_S)
+    for n, paper_s in sizes:
+        X = torch.tensor(gen.uniform(11, "predict", 2 * n, 0.0, 1.0).reshape(n, 2), dtype=torch.float32,
+                         device=dev)
+        u = torch.empty(n, dtype=torch.float32, device=dev)
+        for _ in range(args.warmup):
+            V.vpinn_eval_network(H, L, th, X, u, stream=stream)
+        torch.cuda.synchronize()
+        # per-call events, so the mean is over launches; the event-pair cost is taken off
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            V.vpinn_eval_network(H, L, th, X, u, stream=stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        e0 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in e0:
+            a.record(stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        over = float(np.mean([a.elapsed_time(b) for a, b in e0]))
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev])) - over
+        assert torch.isfinite(u).all()
+        rows.append({"n_points": n, "kernel_ms": round(ms, 5), "wall_ms_per_call": round(wall * 1e3, 5),
+                     "mpoints_per_s": round(n / (ms * 1e-3) / 1e6, 1), "paper_s": paper_s,
+                     "ratio_vs_paper": round(paper_s / (ms * 1e-3), 1)})
+        print(f"[bench] predict n={n}: {ms * 1e3:.2f} us/call ({rows[-1]['mpoints_per_s']} Mpoints/s), "
+              f"wall {wall * 1e6:.1f} us/call", file=sys.stderr, flush=True)
+        del X, u
+    big = rows[-1]
+    fpp = predict_flop_per_point(H, L)
+    achieved = fpp * big["n_points"] / (big["kernel_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": "prediction Mpoints/s (network values at N points, paper's FEM-vs-network timing table)",
+        "value": big["mpoints_per_s"], "unit": "Mpoints/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": big["kernel_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "predict: MLP 2-30-30-30-1 tanh (the C2 network) evaluated at N seeded uniform "
+                               "points of the unit square, N = 29,302 .. 1,034,772 (the paper's prediction-time "
+                               "table; value at the largest)", "parallelism": "single GPU"},
+        "sizes": rows,
+        "roofline": {"bound": "mfma", "kernel": "k_eval<3,1,false>", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic_from_profile("predict", "k_eval"),
+                     "algorithmic_bytes_per_point": 12, "algorithmic_flop_per_point": fpp,
+                     "algorithmic_flop_per_launch": fpp * big["n_points"], "launch_ms_mean": big["kernel_ms"]},
+        "paper_context": {"hardware": "NVIDIA RTX A6000, TensorFlow", "seconds_at_largest": PREDICT_PAPER_S[-1],
+                          "note": "the paper does not state the network used for the timing"},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        n_s = 20000
+        xs = gen.uniform(11, "predict", 2 * n_s, 0.0, 1.0).reshape(n_s, 2)
+        calls, t0 = 0, time.perf_counter()
+        while True:
+            O.mlp_eval(theta, H, L, xs)
+            calls += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds:
+                break
+        out["cpu_baseline"] = {"value": round(calls * n_s / el / 1e6, 4), "unit": "Mpoints/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{calls} oracle evaluations (FP64, single-threaded C, values and tangents) "
+                                         f"of {n_s} of the same points in {el:.1f} s", **host_info()}
+    print(json.dumps(out), flush=True)
 
 
 WORKLOAD_TEXT = {

@@ -266,8 +266,13 @@ vpinn_status vpinn_residual(vpinn_problem *p, const vpinn_loss_cfg *cfg, const f
                             const float *d_eps, float *d_R, void *stream);
 
 /*
- * vpinn_eval_network -- u, du/dx, du/dy of the network (Sec. 2.2) at n points.
+ * vpinn_eval_network -- u, du/dx, du/dy of the network (Sec. 2.2) at n points:
+ * the prediction step whose time the paper's Appendix table sets against FEM.
  *   d_xy device [n][2] floats; d_u, d_ux, d_uy device [n] floats (any may be NULL).
+ * One kernel launch on `stream`, no allocation; with d_ux and d_uy both NULL only
+ * the value products run (a third of the matrix work).  n = 0 does nothing.
+ * Errors: VPINN_E_INVALID (null params, null d_xy with n > 0, n < 0),
+ * VPINN_E_UNSUPPORTED (width or n_hidden out of range), VPINN_E_HIP.
  */
 vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_params, int64_t n,
                                 const float *d_xy, float *d_u, float *d_ux, float *d_uy, void *stream);

@@ -555,30 +555,8 @@ vpinn_status vpinn_eval_network_heads(int32_t width, int32_t n_hidden, int32_t n
     if (n_outputs < 1 || n_outputs > 2) return fail(VPINN_E_INVALID, "n_outputs must be 1 or 2");
     if (d_e && n_outputs != 2) return fail(VPINN_E_INVALID, "d_e needs a network with two outputs");
     if (!d_params || (n > 0 && !d_xy) || n < 0) return fail(VPINN_E_INVALID, "null argument or negative n");
-    // one padded copy per output: the second output is evaluated as a one-output
-    // network that shares the hidden layers
-    static thread_local DevBuf wpad;
-    static thread_local int wpad_dev = -1;
-    int dev = 0;
-    VP_HIP(hipGetDevice(&dev));
-    if (wpad_dev != dev) {
-        wpad.release();
-        wpad_dev = dev;
-    }
-    VP_HIP(wpad.reserve(sizeof(float) * 2 * kMaxPadded));
-    hipStream_t s = (hipStream_t)stream;
-    const float2 *xy = reinterpret_cast<const float2 *>(d_xy);
-    vpinn_status st = VPINN_OK;
-    if (d_u || d_ux || d_uy) {
-        st = pack_params(d_params, width, n_hidden, n_outputs, 0, wpad.as<float>(), s);
-        if (!st) st = eval_network(n_hidden, wpad.as<float>(), n, xy, d_u, d_ux, d_uy, s);
-    }
-    if (!st && d_e) {
-        float *w2 = wpad.as<float>() + kMaxPadded;
-        st = pack_params(d_params, width, n_hidden, n_outputs, 1, w2, s);
-        if (!st) st = eval_network(n_hidden, w2, n, xy, d_e, nullptr, nullptr, s);
-    }
-    return st;
+    return eval_mfma(n_hidden, width, n_outputs, d_params, n, reinterpret_cast<const float2 *>(d_xy), d_u, d_ux, d_uy,
+                     d_e, (hipStream_t)stream);
 }
 
 vpinn_status vpinn_eval_error(int32_t width, int32_t n_hidden, int32_t n_outputs, int32_t output,
@@ -590,24 +568,24 @@ vpinn_status vpinn_eval_error(int32_t width, int32_t n_hidden, int32_t n_outputs
     if (n_outputs < 1 || n_outputs > 2 || output < 0 || output >= n_outputs)
         return fail(VPINN_E_INVALID, "n_outputs must be 1 or 2 and output in 0 .. n_outputs - 1");
     if (!d_params || !d_xy || !d_ref || !d_out || n < 1) return fail(VPINN_E_INVALID, "null argument or n < 1");
-    static thread_local DevBuf wpad, pbuf, part;
+    static thread_local DevBuf pbuf, part;
     static thread_local int ws_dev = -1;
     int dev = 0;
     VP_HIP(hipGetDevice(&dev));
     if (ws_dev != dev) {
-        wpad.release();
         pbuf.release();
         part.release();
         ws_dev = dev;
     }
-    VP_HIP(wpad.reserve(sizeof(float) * kMaxPadded));
     VP_HIP(pbuf.reserve(sizeof(float) * (size_t)n));
     VP_HIP(part.reserve(sizeof(double) * 4 * 512));
     hipStream_t s = (hipStream_t)stream;
-    vpinn_status st = pack_params(d_params, width, n_hidden, n_outputs, output, wpad.as<float>(), s);
+    const float2 *xy = reinterpret_cast<const float2 *>(d_xy);
+    float *pv = pbuf.as<float>();
+    vpinn_status st = eval_mfma(n_hidden, width, n_outputs, d_params, n, xy, output == 0 ? pv : nullptr, nullptr,
+                                nullptr, output == 1 ? pv : nullptr, s);
     if (st) return st;
-    return eval_error(n_hidden, wpad.as<float>(), n, reinterpret_cast<const float2 *>(d_xy), d_ref, pbuf.as<float>(),
-                      part.as<double>(), d_out, s);
+    return error_stats(n, pv, d_ref, part.as<double>(), d_out, s);
 }
 
 vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_params, int64_t n, const float *d_xy,

@@ -1452,6 +1452,127 @@ __global__ __launch_bounds__(kFinThreads) void k_fused_final(
 }
 
 // ---------------------------------------------------------------------------
+// prediction: the network (and optionally its tangents, and its second output)
+// at n arbitrary points, tiles of 16 points dealt round-robin over the
+// wavefronts of one block per CU, weights read once per block
+// ---------------------------------------------------------------------------
+// values only: the hidden-to-hidden value products, no tangents
+template <int L>
+__device__ __forceinline__ void tile_values(const WeightsShared<L> &S, int lane, float x, float y, Vec &A_) {
+    const int g = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * m + 4 * g + r;
+            A_.v[m][r] = tanh_f32(fmaf(S.w1[n][0], x, fmaf(S.w1[n][1], y, S.b[0][n])));
+        }
+#pragma unroll
+    for (int l = 2; l <= L; ++l) {
+        Vec Z;
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo) {
+            f4 z;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) z[r] = S.b[l - 1][16 * mo + 4 * g + r];
+            float wv[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) wv[s] = S.wf[l - 2][0][mo][s][lane];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) z = mfma(wv[s], A_.v[s >> 2][s & 3], z);
+            Z.v[mo] = z;
+        }
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) A_.v[m][r] = tanh_f32(Z.v[m][r]);
+    }
+}
+
+struct EvalArgs {
+    const float *params;  // flat layout, width H, NH outputs
+    int H;
+    int64_t n;
+    const float2 *xy;
+    float *u, *ux, *uy, *e;  // any may be null (ux, uy only with TAN)
+};
+
+constexpr int kEvalWaves = 12;
+
+template <int L, int NH, bool TAN>
+__global__ __launch_bounds__(kEvalWaves * 64, 1) void k_eval(EvalArgs A) {
+    __shared__ FwdShared<L, kEvalWaves> S;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    load_weights<L, kEvalWaves * 64, NH>(S.W, S.stage, A.params, A.H, tid);
+    __syncthreads();
+    const int64_t tiles = (A.n + 15) / 16;
+    const int64_t t0 = (int64_t)blockIdx.x * tiles / gridDim.x, t1 = (int64_t)(blockIdx.x + 1) * tiles / gridDim.x;
+    for (int64_t tt = t0 + wave; tt < t1; tt += kEvalWaves) {
+        const int64_t idx = 16 * tt + (lane & 15);
+        const bool ok = idx < A.n;
+        const float2 p = ok ? A.xy[idx] : make_float2(0.f, 0.f);
+        Vec a;
+        float u, ux = 0.f, uy = 0.f;
+        if (TAN) {
+            Vec tx, ty;
+            Acts<L> unused;
+            tile_forward<L, false>(S.W, lane, p.x, p.y, a, tx, ty, unused);
+            tile_outputs<L>(S.W, lane, a, tx, ty, u, ux, uy);
+        } else {
+            tile_values<L>(S.W, lane, p.x, p.y, a);
+            const int g = lane >> 4;
+            float su = 0.f;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) su = fmaf(S.W.wo[16 * m + 4 * g + r], a.v[m][r], su);
+            u = group_sum(su) + S.W.bo;
+        }
+        const float e = NH == 2 ? tile_second<L>(S.W, lane, a) : 0.f;
+        if (lane < 16 && ok) {
+            if (A.u) A.u[idx] = u;
+            if (TAN && A.ux) A.ux[idx] = ux;
+            if (TAN && A.uy) A.uy[idx] = uy;
+            if (NH == 2 && A.e) A.e[idx] = e;
+        }
+    }
+}
+
+template <int L>
+static void launch_eval(int nh, bool tan, unsigned blocks, const EvalArgs &a, hipStream_t s) {
+    const int th = kEvalWaves * 64;
+    if (nh == 2) {
+        if (tan) k_eval<L, 2, true><<<blocks, th, 0, s>>>(a);
+        else k_eval<L, 2, false><<<blocks, th, 0, s>>>(a);
+    } else {
+        if (tan) k_eval<L, 1, true><<<blocks, th, 0, s>>>(a);
+        else k_eval<L, 1, false><<<blocks, th, 0, s>>>(a);
+    }
+}
+
+static int cu_count(int dev);
+
+vpinn_status eval_mfma(int L, int H, int nh, const float *params, int64_t n, const float2 *xy, float *u, float *ux,
+                       float *uy, float *e, hipStream_t s) {
+    if (n == 0) return VPINN_OK;
+    int dev = 0;
+    VP_HIP(hipGetDevice(&dev));
+    const int64_t tiles = (n + 15) / 16;
+    const unsigned blocks = (unsigned)std::min<int64_t>(cu_count(dev), tiles);
+    EvalArgs a{params, H, n, xy, u, ux, uy, e};
+    const bool tan = ux != nullptr || uy != nullptr;
+    switch (L) {
+    case 1: launch_eval<1>(nh, tan, blocks, a, s); break;
+    case 2: launch_eval<2>(nh, tan, blocks, a, s); break;
+    case 3: launch_eval<3>(nh, tan, blocks, a, s); break;
+    default: launch_eval<4>(nh, tan, blocks, a, s); break;
+    }
+    VP_HIP(hipGetLastError());
+    return VPINN_OK;
+}
+
+// ---------------------------------------------------------------------------
 // host side: work plans
 // ---------------------------------------------------------------------------
 static int cu_count(int dev) {

@@ -149,11 +149,13 @@ vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_
                              const vpinn_forcing *f, hipStream_t s);
 // output `head` (0-based) of a network with `heads` outputs, padded, as a one-output network
 vpinn_status pack_params(const float *d_params, int H, int L, int heads, int head, float *d_wpad, hipStream_t s);
-vpinn_status eval_network(int L, const float *d_wpad, int64_t n, const float2 *d_xy, float *d_u,
-                          float *d_ux, float *d_uy, hipStream_t s);
-// mean |p - ref|, max |p - ref|, ||p - ref|| / ||ref|| -> d_out[3]; d_p [n], d_part [512][4] workspace
-vpinn_status eval_error(int L, const float *d_wpad, int64_t n, const float2 *d_xy, const float *d_ref, float *d_p,
-                        double *d_part, double *d_out, hipStream_t s);
+// the network with `nh` outputs (flat parameters, width H) at n points: u and, if
+// either is non-null, its tangents; e the second output (nh = 2); null outputs are skipped
+vpinn_status eval_mfma(int L, int H, int nh, const float *d_params, int64_t n, const float2 *d_xy, float *d_u,
+                       float *d_ux, float *d_uy, float *d_e, hipStream_t s);
+// mean |p - ref|, max |p - ref|, ||p - ref|| / ||ref|| -> d_out[3]; d_part [512][4] workspace
+vpinn_status error_stats(int64_t n, const float *d_p, const float *d_ref, double *d_part, double *d_out,
+                         hipStream_t s);
 vpinn_status plain_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
                              const float *d_eps, float *d_loss, float *d_grad, float *d_grad_eps,
                              float *d_R_out, hipStream_t s);

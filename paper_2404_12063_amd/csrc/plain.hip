@@ -499,11 +499,6 @@ static vpinn_status fwd_dispatch(int L, const float *w, const float2 *pts, int64
     return VPINN_OK;
 }
 
-vpinn_status eval_network(int L, const float *d_wpad, int64_t n, const float2 *d_xy, float *d_u, float *d_ux,
-                          float *d_uy, hipStream_t s) {
-    return fwd_dispatch(L, d_wpad, d_xy, n, d_u, d_ux, d_uy, nullptr, s);
-}
-
 // prediction error against reference values: blocks stride over the points and keep
 // FP64 sums of |d|, d^2, ref^2 and the max |d| (d = p - ref); each block's four
 // values go to part[block] (wavefronts added in order), and one block adds the
@@ -561,10 +556,8 @@ __global__ void k_err_final(const double *__restrict__ part, int blocks, int64_t
     out[2] = sqrt(sd) / sqrt(sr);
 }
 
-vpinn_status eval_error(int L, const float *d_wpad, int64_t n, const float2 *d_xy, const float *d_ref, float *d_p,
-                        double *d_part, double *d_out, hipStream_t s) {
-    vpinn_status st = eval_network(L, d_wpad, n, d_xy, d_p, nullptr, nullptr, s);
-    if (st) return st;
+vpinn_status error_stats(int64_t n, const float *d_p, const float *d_ref, double *d_part, double *d_out,
+                         hipStream_t s) {
     const int blocks = (int)std::min<int64_t>(kErrMaxBlocks, (n + kErrThreads - 1) / kErrThreads);
     k_err_partial<<<blocks, kErrThreads, 0, s>>>(d_p, d_ref, n, d_part);
     k_err_final<<<1, 64, 0, s>>>(d_part, blocks, n, d_out);

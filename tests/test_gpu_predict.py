@@ -74,3 +74,59 @@ def test_second_output_error_matches_oracle(V, torch):
     for output, ref in [(0, man.u(xy[:, 0], xy[:, 1])), (1, man.eps(xy[:, 0], xy[:, 1]))]:
         got = _err(V, torch, 30, 3, theta, xy, ref, heads=2, output=output)
         _close(got, _expect(O, 30, 3, theta, xy, ref, heads=2, output=output), ref)
+
+
+# ----------------------------------------------------------------------------- the prediction kernel itself
+
+def _eval(V, torch, H, L, theta, xy, heads=1, want=("u", "ux", "uy")):
+    dev = torch.device("cuda:0")
+    X = torch.tensor(xy, dtype=torch.float32, device=dev)
+    outs = {k: (torch.full((len(xy),), float("nan"), device=dev) if k in want else None)
+            for k in ("u", "ux", "uy", "e")}
+    V.vpinn_eval_network_heads(H, L, heads, torch.tensor(theta, dtype=torch.float32, device=dev), X, **outs)
+    torch.cuda.synchronize()
+    return X.cpu().double().numpy(), {k: v.cpu().double().numpy() for k, v in outs.items() if v is not None}
+
+
+@pytest.mark.parametrize("n", [29302, 1034772])
+def test_prediction_at_the_papers_sizes(V, torch, n):
+    """The smallest and largest point counts of the paper's prediction-time table (Appendix, FastVPINNs vs FEM),
+    both with a ragged last tile (n mod 16 = 6 and 4): values alone (the timed prediction) and with tangents,
+    every output finite, 4,096 sampled points and the last 40 against the oracle."""
+    from oracle import oracle as O
+    theta = gen.config_c2().params(seed=8, bias_scale=0.1)
+    xy = gen.uniform(11, "predict", 2 * n, 0.0, 1.0).reshape(n, 2)
+    X, vals = _eval(V, torch, 30, 3, theta, xy, want=("u",))
+    _, full = _eval(V, torch, 30, 3, theta, xy)
+    assert np.isfinite(vals["u"]).all() and all(np.isfinite(a).all() for a in full.values())
+    assert np.array_equal(vals["u"], full["u"])  # the value chain is the same with or without tangents
+    rng = np.random.default_rng(n)
+    idx = np.concatenate([rng.choice(n - 40, 4096, replace=False), np.arange(n - 40, n)])
+    ref = O.mlp_eval(theta, 30, 3, X[idx])
+    for k, want in zip(("u", "ux", "uy"), ref):
+        np.testing.assert_allclose(full[k][idx], want, rtol=1e-5, atol=2e-6 * np.abs(want).max(), err_msg=k)
+
+
+def test_prediction_output_combinations(V, torch):
+    """Each subset of outputs of a two-output network writes exactly those outputs, with the same values."""
+    from oracle import oracle as O
+    theta = gen.glorot_params(30, 3, seed=12, bias_scale=0.1, heads=2)
+    xy = gen.uniform(12, "predict2", 2 * 1001, 0.0, 1.0).reshape(-1, 2)
+    X, all4 = _eval(V, torch, 30, 3, theta, xy, heads=2, want=("u", "ux", "uy", "e"))
+    ref = dict(zip(("u", "ux", "uy", "e"), O.mlp_eval(theta, 30, 3, X, heads=2)))
+    for k in all4:
+        np.testing.assert_allclose(all4[k], ref[k], rtol=1e-5, atol=2e-6 * np.abs(ref[k]).max(), err_msg=k)
+    for want in [("e",), ("u",), ("u", "e"), ("ux",), ("uy", "e")]:
+        _, got = _eval(V, torch, 30, 3, theta, xy, heads=2, want=want)
+        assert set(got) == set(want)
+        for k in want:
+            assert np.array_equal(got[k], all4[k]), (want, k)
+
+
+def test_prediction_of_no_points(V, torch):
+    dev = torch.device("cuda:0")
+    theta = torch.tensor(gen.config_c2().params(seed=1), dtype=torch.float32, device=dev)
+    u = torch.full((4,), 7.0, device=dev)
+    V.vpinn_eval_network(30, 3, theta, torch.zeros((0, 2), device=dev), u)
+    torch.cuda.synchronize()
+    assert (u == 7.0).all()
