@@ -130,3 +130,21 @@ def test_prediction_of_no_points(V, torch):
     V.vpinn_eval_network(30, 3, theta, torch.zeros((0, 2), device=dev), u)
     torch.cuda.synchronize()
     assert (u == 7.0).all()
+
+
+@pytest.mark.parametrize("H,L,heads", [(1, 1, 1), (17, 2, 2), (30, 3, 2), (32, 4, 1), (8, 4, 2)])
+def test_prediction_values_only_every_shape(V, torch, H, L, heads):
+    """The values-only kernel (no tangent products) for each depth and both output counts, on a ragged point
+    count: against the oracle, and equal to the values the tangent kernel writes."""
+    from oracle import oracle as O
+    theta = gen.glorot_params(H, L, seed=20 + H + L, bias_scale=0.2, heads=heads)
+    xy = gen.uniform(13, f"predict/{H}/{L}", 2 * 777, -1.0, 1.0).reshape(-1, 2)
+    want = ("u", "e") if heads == 2 else ("u",)
+    X, vals = _eval(V, torch, H, L, theta, xy, heads=heads, want=want)
+    _, full = _eval(V, torch, H, L, theta, xy, heads=heads, want=want + ("ux", "uy"))
+    ref = O.mlp_eval(theta, H, L, X, heads=heads)
+    for k, r in zip(("u", "e"), (ref[0], ref[3] if heads == 2 else None)):
+        if k not in want:
+            continue
+        np.testing.assert_allclose(vals[k], r, rtol=1e-5, atol=2e-6 * np.abs(r).max(), err_msg=k)
+        assert np.array_equal(vals[k], full[k]), k
