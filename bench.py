@@ -544,6 +544,10 @@ def main():
                     metavar="FWD_WAVES,CHUNK_SHIFT,ROWS_PER_PASS[,STORE_ACTIVATIONS]",
                     help="use this tile-shape tuning instead of autotuning (profiling runs)")
     args = ap.parse_args()
+    if args.tuning is not None and len(args.tuning) not in (3, 4):
+        ap.error("--tuning takes 3 or 4 comma-separated integers")
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be at least 1 and --warmup at least 0")
     if args.traffic_from:
         write_traffic(args.workload, *args.traffic_from, tuning=args.tuning)
         return
