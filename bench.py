@@ -30,6 +30,15 @@ PAPER_CONTEXT = {
                 "hardware": "NVIDIA RTX A6000, TensorFlow, FP32",
                 "workload": "CD2D on a 14,192-quad Gmsh gear, 25 quadrature points an element, 4x4 test functions, "
                             "MLP 3x50 tanh, 6,096 boundary points: about 13 ms a training iteration (Sec. 4.6.4)"},
+    "inverse_const": {"value": 500.0, "unit": "epochs/s", "mquadpts_per_s": 3.2,
+                      "hardware": "NVIDIA RTX A6000, TensorFlow, FP32",
+                      "workload": "constant-eps inverse problem on (-1,1)^2, 2x2 elements with 40x40 quadrature points, "
+                                  "30x3 network, 50 sensors: 2 ms mean time per epoch, 8,909 epochs in about 18 s "
+                                  "(Sec. 4.7.1)"},
+    "disk_vareps": {"value": 500.0, "unit": "epochs/s", "bound": "at least",
+                    "hardware": "NVIDIA RTX A6000, TensorFlow, FP32",
+                    "workload": "space-dependent eps on a 1,024-quad disk: under 200 s for 100,000 epochs "
+                                "(Sec. 4.7.2 and the conclusions; quadrature and test orders not stated)"},
 }
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 (vector and matrix) peak
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
@@ -234,9 +243,11 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str, tuning=None):
     print(json.dumps(out))
 
 
-def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
+def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int, eps0=None):
     """Eager steps: vpinn_loss_and_grad then vpinn_adam_step.  On the fused path the library records
-    events between its kernels, which gives the per-kernel durations of every timed step."""
+    events between its kernels, which gives the per-kernel durations of every timed step.  eps0: the
+    inverse problem's trainable diffusion coefficient (its gradient comes from the same call and Adam
+    updates it too)."""
     dev = torch.device("cuda:0")
     n = V.vpinn_n_params_out(prob.width, prob.n_hidden, n_outputs(prob))
     th = torch.tensor(theta, dtype=torch.float32, device=dev)
@@ -248,11 +259,26 @@ def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
                      n_outputs=n_outputs(prob))
     stream = torch.cuda.current_stream()
     fused = path == V.VPINN_PATH_FUSED
+    if eps0 is not None:
+        ep = torch.tensor([eps0], dtype=torch.float32, device=dev)
+        gep, mep, vep = (torch.zeros(1, dtype=torch.float32, device=dev) for _ in range(3))
+
+    def step(t):
+        if eps0 is None:
+            V.vpinn_loss_and_grad(p, cfg, th, loss=loss, grad=g, stream=stream)
+        else:
+            V.vpinn_loss_and_grad(p, cfg, th, eps=ep, loss=loss, grad=g, grad_eps=gep, stream=stream)
+
+    def update(t):
+        V.vpinn_adam_step(th, g, m, v, t, lr=1e-3, stream=stream)
+        if eps0 is not None:
+            V.vpinn_adam_step(ep, gep, mep, vep, t, lr=1e-3, stream=stream)
+
     t = 0
     for _ in range(warmup):
         t += 1
-        V.vpinn_loss_and_grad(p, cfg, th, loss=loss, grad=g, stream=stream)
-        V.vpinn_adam_step(th, g, m, v, t, lr=1e-3, stream=stream)
+        step(t)
+        update(t)
     NE = V.PROFILE_EVENTS
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(NE + 1)] for _ in range(steps)]
     for e in ev:
@@ -266,10 +292,10 @@ def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
             V.vpinn_set_profile_events(p, ev[i][:NE])
         else:
             ev[i][0].record(stream)
-        V.vpinn_loss_and_grad(p, cfg, th, loss=loss, grad=g, stream=stream)
+        step(t)
         if not fused:
             ev[i][NE - 1].record(stream)
-        V.vpinn_adam_step(th, g, m, v, t, lr=1e-3, stream=stream)
+        update(t)
         ev[i][NE].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -278,6 +304,8 @@ def time_path(V, torch, p, prob, theta, path: int, steps: int, warmup: int):
     mean = lambda xs: sum(xs) / len(xs)  # noqa: E731
     out = {"wall_s": wall, "lg_ms_mean": mean([e[0].elapsed_time(e[NE - 1]) for e in ev]),
            "step_ms_mean": mean([e[0].elapsed_time(e[NE]) for e in ev])}
+    if eps0 is not None:
+        out["eps_final"] = float(ep.item())
     if fused:
         for k, name in enumerate(["k_fwd_ms", "k_contract_ms", "k_bwd_ms", "k_final_ms"]):
             out[name] = mean([e[k].elapsed_time(e[k + 1]) for e in ev])
@@ -370,7 +398,8 @@ def time_graph(V, torch, p, prob, theta, steps: int, warmup: int, fixed_tuning=N
 
 
 def cpu_baseline(prob, theta, seconds: float):
-    """The FP64 oracle (single-threaded C) on full epochs of the same workload, as many as fit in ~seconds."""
+    """The FP64 oracle (single-threaded C) on full epochs of the same workload, as many as fit in ~seconds
+    (the inverse problem at its initial eps, which is then held: the work of an epoch does not depend on it)."""
     from oracle import oracle as O
     import numpy as np
     asm = O.assemble_problem(prob)
@@ -381,7 +410,7 @@ def cpu_baseline(prob, theta, seconds: float):
     first = None
     t0 = time.perf_counter()
     while True:
-        r = O.problem_loss_grad(prob, asm, th)
+        r = O.problem_loss_grad(prob, asm, th, eps=prob.eps_init)
         if first is None:
             first = r.loss[0]
         O.adam(th, r.grad, m, v, n_ep + 1, lr=1e-3)
@@ -519,14 +548,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
     ap.add_argument("--workload", choices=["c2", "c5", "probe", "gear_cd", "disk_vareps", "c2_mf", "probe_mf",
-                                           "predict"],
+                                           "predict", "inverse_const"],
                     default="c2",
                     help="c2 (default, the headline): one 1,024-element problem; c5: 64-instance batch; probe: "
                          "20x20 test functions on 4,096 elements (G-stream bound); gear_cd: the convection-diffusion "
                          "gear problem on 14,000 elements; disk_vareps: space-dependent diffusion inverse problem, "
                          "a two-output network on a 1,024-element disk; c2_mf, probe_mf: the same as c2, probe with "
                          "G regenerated per step from the element geometry (matrix-free); predict: network values "
-                         "of a trained-size MLP at the six point counts of the paper's prediction-time table")
+                         "of a trained-size MLP at the six point counts of the paper's prediction-time table; "
+                         "inverse_const: the constant-eps inverse problem at the paper's sizes (2x2 elements, 40x40 "
+                         "points), eps trained beside the weights")
     ap.add_argument("--shared-points", action="store_true",
                     help="evaluate the network once per distinct interior GLL point (vpinn_set_shared_points); the "
                          "result equals per-slot evaluation up to rounding")
@@ -687,6 +718,10 @@ WORKLOAD_TEXT = {
                    "(0.5, 0.5) and radius 0.5 (32x32 quads of a squircle-mapped grid), eps = 0.5 (sin x + cos y) and "
                    "u = sin(2pi x) sin(2pi y) manufactured, 10x10 GLL points, 5x5 test functions, 1600 boundary "
                    "points, 1000 sensors of u, tau = gamma = 10, MLP 2-30-30-30-2 tanh whose second output is eps",
+    "inverse_const": "inverse_const: -eps Lap u = f on (-1,1)^2 (the paper's constant-eps inverse problem), 2x2 "
+                     "elements, 40x40 GLL points, 5x5 test functions, u = 10 sin(x) tanh(x) exp(-0.3 x^2), 50 "
+                     "sensors of u, 400 boundary points, tau = gamma = 10, eps trainable (init 2.0, true 0.3), MLP "
+                     "2-30-30-30-1 tanh, Adam lr 1e-3 on the weights and on eps",
     "c2_mf": "c2_mf: c2 with no stored G: the contraction regenerates G every step from the 8 geometry floats of "
              "each element by sum factorisation (matrix-free)",
     "probe_mf": "probe_mf: probe with no stored G (matrix-free): 1.3 GB of G a step replaced by 32 B of geometry per "
@@ -708,22 +743,30 @@ def bench_single(args, V, torch, gen):
 
     main_path = V.VPINN_PATH_FUSED if args.path == "fused" else V.VPINN_PATH_PLAIN
     fused = main_path == V.VPINN_PATH_FUSED
-    eager_steps = min(args.steps, 300)
-    if args.profile_run and fused:
+    # the inverse problem trains a scalar eps beside the weights; the captured batch step updates the
+    # weights only, so its step is timed eagerly (loss and gradient, then Adam on the weights and on eps)
+    inverse = prob.eps_init is not None
+    graph = fused and not inverse
+    eager_steps = args.steps if inverse else min(args.steps, 300)
+    if args.profile_run and graph:
         eager = None
     else:
-        eager = time_path(V, torch, p, prob, theta, main_path, eager_steps, args.warmup)
+        eager = time_path(V, torch, p, prob, theta, main_path, eager_steps, args.warmup, eps0=prob.eps_init)
         print(f"[bench] {args.path} eager: {eager['wall_s'] / eager_steps * 1e3:.4f} ms/step", file=sys.stderr,
               flush=True)
-    if fused:
+    if graph:
         res = time_graph(V, torch, p, prob, theta, args.steps, args.warmup, args.tuning)
         assert res["steps_done"] == args.warmup + args.steps
         print(f"[bench] fused graph: {res['wall_s'] / args.steps * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
     else:
         res = {"wall_s": eager["wall_s"] * args.steps / eager_steps}
+        if fused:
+            res["kernel_ms"] = {"k_fwd": eager["k_fwd_ms"], "k_contract": eager["k_contract_ms"],
+                                "k_bwd": eager["k_bwd_ms"], "k_fused_final": eager["k_final_ms"]}
     plain = None
     if not args.no_plain and fused and n_outputs(prob) == 1 and not mf:
-        plain = time_path(V, torch, p, prob, theta, V.VPINN_PATH_PLAIN, min(args.steps, 300), 20)
+        plain = time_path(V, torch, p, prob, theta, V.VPINN_PATH_PLAIN, min(args.steps, 300), 20,
+                          eps0=prob.eps_init)
         print(f"[bench] plain eager: {plain['wall_s'] / min(args.steps, 300) * 1e3:.4f} ms/step", file=sys.stderr,
               flush=True)
 
@@ -731,9 +774,10 @@ def bench_single(args, V, torch, gen):
     dev = torch.device("cuda:0")
     loss0 = torch.zeros(4, dtype=torch.float32, device=dev)
     if not args.profile_run:
+        ep0 = None if not inverse else torch.tensor([prob.eps_init], dtype=torch.float32, device=dev)
         V.vpinn_loss_and_grad(p, V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma, 0, main_path,
                                             n_outputs=n_outputs(prob)),
-                              torch.tensor(theta, dtype=torch.float32, device=dev), loss=loss0)
+                              torch.tensor(theta, dtype=torch.float32, device=dev), eps=ep0, loss=loss0)
         torch.cuda.synchronize()
     gpu_loss0 = float(loss0[0].item())
 
@@ -772,6 +816,8 @@ def bench_single(args, V, torch, gen):
                     "algorithmic_flop_per_launch": work[dom]["flop"]}
         roof["traffic"] = traffic_from_profile(args.workload, dom, res.get("tuning"))
         roof["launch_ms_mean"] = round(k_ms, 5)
+        if not graph:
+            roof["note"] = "event-timed in eager steps (the event-pair overhead not subtracted)"
     else:
         k_ms = eager["lg_ms_mean"]
         achieved = flops / (k_ms * 1e-3) / 1e12
@@ -792,7 +838,8 @@ def bench_single(args, V, torch, gen):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
-                   "path": args.path + (" (HIP graph replay of the batch-of-one step)" if fused else " (eager)"),
+                   "path": args.path + (" (HIP graph replay of the batch-of-one step)" if graph else
+                                        " (eager; Adam on the weights and on eps)" if inverse else " (eager)"),
                    "tuning": res.get("tuning"),
                    "n_elem": prob.n_elem, "quad_points": prob.n_points,
                    "shared_points": bool(args.shared_points), "network_interior_points": n_int,
@@ -801,7 +848,7 @@ def bench_single(args, V, torch, gen):
         "roofline": roof,
         "whole_step": whole_step_rates(flops, bytes_per_epoch(prob, mf), ms),
     }
-    if fused:
+    if graph:
         out["step_ms_p10_p50_p90"] = [round(res["step_ms_p10"], 5), round(res["step_ms_p50"], 5),
                                       round(res["step_ms_p90"], 5)]
         out["gpu_event_ms_per_step"] = round(res["event_ms_total"] / args.steps, 5)
@@ -809,6 +856,12 @@ def bench_single(args, V, torch, gen):
         out["kernels_note"] = ("mean durations over eager batched steps of the same tuned plan as the timed graph, "
                                "from the library's profiling events, less the event-pair overhead")
         out["event_overhead_ms"] = round(res["kernel_ms"]["event_overhead_ms"], 5)
+    elif fused:
+        out["kernels"] = kernels
+        out["kernels_note"] = "mean durations over the timed eager steps, from the library's profiling events"
+        if inverse:
+            out["eps_after_steps"] = {"initial": prob.eps_init, "after": round(eager["eps_final"], 6),
+                                      "true": prob.eps_true, "steps": args.warmup + eager_steps}
         if eager is not None:
             out["single_problem_api_eager_ms_per_step"] = round(eager["wall_s"] / eager_steps * 1e3, 5)
     if plain is not None:

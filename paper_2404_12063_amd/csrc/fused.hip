@@ -1012,7 +1012,22 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
         float acc = 0.f;
         if (k < ntest) {
             const float *gxr = Gx + gbase + (int64_t)k * nq, *gyr = Gy + gbase + (int64_t)k * nq;
-            for (int q = rl; q < nq; q += 16) {
+            // eight points a lane per round with every load issued before the products: a few
+            // large elements give few blocks, so each must keep many loads in flight
+            int q = rl;
+            for (; q + 16 * 7 < nq; q += 16 * 8) {
+                float2 d[8];
+                float gx[8], gy[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    d[i] = ub[upoint(Ip, e0 * nq + q + 16 * i)];
+                    gx[i] = gxr[q + 16 * i];
+                    gy[i] = gyr[q + 16 * i];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) acc = fmaf(d[i].x, gx[i], fmaf(d[i].y, gy[i], acc));
+            }
+            for (; q < nq; q += 16) {
                 const float2 d = ub[upoint(Ip, e0 * nq + q)];
                 acc = fmaf(d.x, gxr[q], fmaf(d.y, gyr[q], acc));
             }
@@ -1032,7 +1047,22 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
     if (A.want_grad) {
         for (int q = tid; q < nq; q += kCThreads) {
             float bx = 0.f, by = 0.f;
-            for (int k = 0; k < ntest; ++k) {
+            int k = 0;
+            for (; k + 7 < ntest; k += 8) {
+                float gx[8], gy[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int64_t o = gbase + (int64_t)(k + i) * nq + q;
+                    gx[i] = Gx[o];
+                    gy[i] = Gy[o];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    bx = fmaf(rbar[k + i], gx[i], bx);
+                    by = fmaf(rbar[k + i], gy[i], by);
+                }
+            }
+            for (; k < ntest; ++k) {
                 const int64_t o = gbase + (int64_t)k * nq + q;
                 bx = fmaf(rbar[k], Gx[o], bx);
                 by = fmaf(rbar[k], Gy[o], by);

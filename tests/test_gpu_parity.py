@@ -224,6 +224,21 @@ def test_inverse_problem_eps_gradient(V, torch, path, orders):
 
 
 @pytest.mark.parametrize("path", ["plain", "fused"])
+def test_inverse_const_at_the_papers_sizes(V, torch, path):
+    """The constant-eps inverse problem of Sec. 4.7.1 exactly as the bench runs it (2 x 2 elements of
+    (-1, 1)^2, 40 x 40 GLL points: the large-element contraction), loss, weight gradient and d loss / d eps
+    at the initial, the true and a negative eps."""
+    prob = gen.config_inverse_const()
+    from oracle import oracle as O
+    asm = O.assemble_problem(prob)
+    theta = _params(prob)
+    p = V.assemble_problem(prob)
+    for eps in (2.0, 0.3, -0.5):
+        loss, grad, geps = _run(V, torch, p, prob, theta, PATHS[path], eps=eps)
+        _check(loss, grad, O.problem_loss_grad(prob, asm, theta, eps=eps), geps=geps, tag=f"eps={eps}")
+
+
+@pytest.mark.parametrize("path", ["plain", "fused"])
 def test_element_normalisation(V, torch, path):
     prob = _problem("c1")
     theta = _params(prob)

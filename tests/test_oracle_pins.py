@@ -655,3 +655,25 @@ def test_assembly_refuses_an_order_the_rule_does_not_cover(oracle):
     m = gen.square_mesh(1, 1)
     with pytest.raises(Exception):
         oracle.assemble(m.xy, m.quad, 129, 2, 1.0, 1.0, 1.0)
+
+
+def test_inverse_const_data_residual_vanishes_at_the_true_eps(oracle):
+    """The constant-diffusion inverse problem of Sec. 4.7.1 at its sizes (2 x 2 elements of (-1, 1)^2, 40 x 40
+    GLL points, 5 x 5 tests): with the exact gradient of u = 10 sin x tanh x exp(-0.3 x^2) at the quadrature
+    points, eps A - F vanishes to quadrature error at the true eps = 0.3 and not at the initial 2.0.  The
+    forcing's closed form is checked against a central second difference of u."""
+    prob = gen.config_inverse_const()
+    man = gen.InverseConstManufactured(0.3)
+    x = np.linspace(-1.0, 1.0, 41)
+    h = 1e-4
+    fd = -0.3 * (man.u(x + h, 0.0) - 2.0 * man.u(x, 0.0) + man.u(x - h, 0.0)) / (h * h)
+    assert np.abs(fd - man.f(x, 0.0)).max() < 1e-6 * np.abs(fd).max()
+    asm = oracle.assemble_problem(prob)
+    X = asm.X[..., 0]
+    s, c, t, r = np.sin(X), np.cos(X), np.tanh(X), np.exp(-0.3 * X * X)
+    ux = 10.0 * (c * t * r + s * (1.0 - t * t) * r + s * t * (-0.6 * X * r))
+    uy = np.zeros_like(ux)
+    scale = np.abs(asm.F).max()
+    assert np.abs(oracle.residual(asm, ux, uy, eps=0.3)).max() < 1e-11 * scale
+    assert np.abs(oracle.residual(asm, ux, uy, eps=2.0)).max() > 0.1 * scale
+    assert np.allclose(prob.bnd_g, man.u(prob.bnd_xy[:, 0], prob.bnd_xy[:, 1]))

@@ -429,5 +429,41 @@ def batched_instances(n_inst: int = 64, seed: int = 0, lo: int = 256, hi: int = 
     return out
 
 
+class InverseConstManufactured:
+    """Data of the constant-diffusion inverse problem of Sec. 4.7.1 on (-1, 1)^2: the solution
+    u = 10 sin(x) tanh(x) exp(-eps x^2), a function of x alone, with eps = 0.3, and the forcing
+    f = -eps u''(x) that makes it exact (u'' by the product rule over sin, tanh and the Gaussian)."""
+
+    def __init__(self, eps: float = 0.3):
+        self.eps = eps
+
+    def u(self, x, y):
+        return 10.0 * np.sin(x) * np.tanh(x) * np.exp(-self.eps * x * x)
+
+    def f(self, x, y):
+        a = self.eps
+        s, c, t = np.sin(x), np.cos(x), np.tanh(x)
+        dt = 1.0 - t * t
+        ddt = -2.0 * t * dt
+        r = np.exp(-a * x * x)
+        dr = -2.0 * a * x * r
+        ddr = (4.0 * a * a * x * x - 2.0 * a) * r
+        upp = 10.0 * (-s * t * r + s * ddt * r + s * t * ddr + 2.0 * (c * dt * r + c * t * dr + s * dt * dr))
+        return -a * upp
+
+
+def config_inverse_const(seed: int = 0) -> Problem:
+    """The inverse problem of Sec. 4.7.1 at the paper's sizes: -eps Lap u = f on (-1, 1)^2, 2x2 elements,
+    40x40 GLL points an element, 5x5 test functions, 50 sensors of the exact u, eps trainable (init 2.0,
+    true 0.3), 400 boundary points, 30x3 network."""
+    man = InverseConstManufactured(0.3)
+    mesh = square_mesh(2, 2, 0.0, seed, -1.0, 1.0, -1.0, 1.0)
+    bxy = square_boundary_points(400, -1.0, 1.0, -1.0, 1.0)
+    sxy = uniform(seed, "inverse_const/sensors", 100, -1.0, 1.0).reshape(50, 2)
+    return Problem(name="inverse_const", mesh=mesh, quad_order=40, test_order=5, f_amp=0.0, f_kx=0.0, f_ky=0.0,
+                   bnd_xy=bxy, bnd_g=man.u(bxy[:, 0], bxy[:, 1]), sens_xy=sxy, sens_u=man.u(sxy[:, 0], sxy[:, 1]),
+                   tau=10.0, gamma=10.0, eps_init=2.0, eps_true=man.eps, seed=seed, f_fn=man.f)
+
+
 CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4, "probe": config_probe,
-           "gear_cd": config_gear_cd, "disk_vareps": config_disk_vareps}
+           "gear_cd": config_gear_cd, "disk_vareps": config_disk_vareps, "inverse_const": config_inverse_const}
