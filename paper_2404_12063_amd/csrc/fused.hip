@@ -47,6 +47,8 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // contraction: many small blocks, one chunk of whole elements each
 constexpr int kCThreads = 256;
 constexpr int kCWaves = kCThreads / 64;
+constexpr int kGThreads = 1024;  // large-element contraction: one element per block
+constexpr int kGWaves = kGThreads / 64;
 // backward: one block of eight wavefronts per CU (two per SIMD, register-limited at ~250
 // VGPRs); tiles are dealt round-robin over the eight, which bounds every SIMD's share
 // within one tile of the mean, and the weights are held once per CU
@@ -776,6 +778,7 @@ __device__ __forceinline__ ContractCtx contract_ctx(const ContractArgs &A) {
 }
 
 // the block's loss sums (sum R^2, sum R A), wavefronts added in order -> its loss row
+template <int NWV = kCWaves>
 __device__ __forceinline__ void contract_flush(const ContractArgs &A, const ContractCtx &c, double lrr, double lra,
                                                double (*lp)[2], int tid, int wave, int lane) {
     const double vr = wave_sum(lrr), va = wave_sum(lra);
@@ -787,7 +790,7 @@ __device__ __forceinline__ void contract_flush(const ContractArgs &A, const Cont
     if (tid < 4) {
         double v = 0.0;
         if (tid < 2)
-            for (int w = 0; w < kCWaves; ++w) v += lp[w][tid];
+            for (int w = 0; w < NWV; ++w) v += lp[w][tid];
         A.lpart[(c.I->lrow0 + c.I->gn_rows + c.chunk) * 4 + tid] = v;
     }
 }
@@ -988,9 +991,9 @@ __global__ __launch_bounds__(kCThreads) void k_contract_rows(ContractArgs A) {
     contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
 }
 
-__global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) {
+__global__ __launch_bounds__(kGThreads) void k_contract_generic(ContractArgs A) {
     extern __shared__ float dyn[];
-    __shared__ double lp[kCWaves][2];
+    __shared__ double lp[kGWaves][2];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const ContractCtx c = contract_ctx(A);
     const InstDesc *Ip = c.I;
@@ -1005,38 +1008,31 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
     double lrr = 0.0, lra = 0.0;
     float *rbar = dyn;  // [ntest] 2 c_v R of the block's element
     const int64_t ebase = e0 * ntest, gbase = e0 * Ip->gstride;
-    constexpr int kRG = kCThreads / 16;
-    const int rg = tid >> 4, rl = tid & 15;
-    for (int k0 = 0; k0 < ntest; k0 += kRG) {
-        const int k = k0 + rg;
+    // a wavefront per test-function row, its lanes striding over the points eight a round
+    // with every load issued before the products: a few large elements give few blocks,
+    // so each block must keep many loads in flight
+    for (int k = wave; k < ntest; k += kGWaves) {
+        const float *gxr = Gx + gbase + (int64_t)k * nq, *gyr = Gy + gbase + (int64_t)k * nq;
         float acc = 0.f;
-        if (k < ntest) {
-            const float *gxr = Gx + gbase + (int64_t)k * nq, *gyr = Gy + gbase + (int64_t)k * nq;
-            // eight points a lane per round with every load issued before the products: a few
-            // large elements give few blocks, so each must keep many loads in flight
-            int q = rl;
-            for (; q + 16 * 7 < nq; q += 16 * 8) {
-                float2 d[8];
-                float gx[8], gy[8];
+        int q = lane;
+        for (; q + 64 * 7 < nq; q += 64 * 8) {
+            float2 d[8];
+            float gx[8], gy[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    d[i] = ub[upoint(Ip, e0 * nq + q + 16 * i)];
-                    gx[i] = gxr[q + 16 * i];
-                    gy[i] = gyr[q + 16 * i];
-                }
+            for (int i = 0; i < 8; ++i) {
+                d[i] = ub[upoint(Ip, e0 * nq + q + 64 * i)];
+                gx[i] = gxr[q + 64 * i];
+                gy[i] = gyr[q + 64 * i];
+            }
 #pragma unroll
-                for (int i = 0; i < 8; ++i) acc = fmaf(d[i].x, gx[i], fmaf(d[i].y, gy[i], acc));
-            }
-            for (; q < nq; q += 16) {
-                const float2 d = ub[upoint(Ip, e0 * nq + q)];
-                acc = fmaf(d.x, gxr[q], fmaf(d.y, gyr[q], acc));
-            }
+            for (int i = 0; i < 8; ++i) acc = fmaf(d[i].x, gx[i], fmaf(d[i].y, gy[i], acc));
         }
-        acc += __shfl_xor(acc, 8, 16);
-        acc += __shfl_xor(acc, 4, 16);
-        acc += __shfl_xor(acc, 2, 16);
-        acc += __shfl_xor(acc, 1, 16);
-        if (rl == 0 && k < ntest) {
+        for (; q < nq; q += 64) {
+            const float2 d = ub[upoint(Ip, e0 * nq + q)];
+            acc = fmaf(d.x, gxr[q], fmaf(d.y, gyr[q], acc));
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) {
             const float R = eps * acc - F[ebase + k];
             rbar[k] = two_cv * R;
             lrr += (double)R * (double)R;
@@ -1045,7 +1041,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
     }
     __syncthreads();
     if (A.want_grad) {
-        for (int q = tid; q < nq; q += kCThreads) {
+        for (int q = tid; q < nq; q += kGThreads) {
             float bx = 0.f, by = 0.f;
             int k = 0;
             for (; k + 7 < ntest; k += 8) {
@@ -1070,7 +1066,7 @@ __global__ __launch_bounds__(kCThreads) void k_contract_generic(ContractArgs A) 
             Ip->adj[e0 * nq + q] = make_float2(eps * bx, eps * by);
         }
     }
-    contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
+    contract_flush<kGWaves>(A, c, lrr, lra, lp, tid, wave, lane);
 }
 
 // Matrix-free contraction: no stored G; one wavefront per element rebuilds it from
@@ -1892,7 +1888,7 @@ static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs
         if (P.cpath_blocks[kPathRows4]) launch_rows<4>(rp, (unsigned)P.cpath_blocks[kPathRows4], c, s);
         c.cblk_base += P.cpath_blocks[kPathRows4];
         if (P.cpath_blocks[kPathGeneric])
-            k_contract_generic<<<(unsigned)P.cpath_blocks[kPathGeneric], kCThreads, P.cdyn_generic, s>>>(c);
+            k_contract_generic<<<(unsigned)P.cpath_blocks[kPathGeneric], kGThreads, P.cdyn_generic, s>>>(c);
         c.cblk_base += P.cpath_blocks[kPathGeneric];
         if (P.cpath_blocks[kPathMF])
             k_contract_mf<NH == 2><<<(unsigned)P.cpath_blocks[kPathMF], kCThreads, P.cdyn_mf, s>>>(c);
