@@ -61,8 +61,9 @@ constexpr int kRowQ = 4;             // quadrature points per lane in the row-st
 // contraction paths: thread per point with every test function in registers
 // (nq <= kCThreads, ntest <= kKB); wavefront per test-function row, G read once,
 // with Q = 1, 2 or 4 points a lane (nq <= 64 Q; one kernel per Q keeps each at
-// the occupancy its registers allow); two passes over G for larger elements
-// (and a matrix-free path, wavefront per element, for problems that store no G)
+// the occupancy its registers allow); two launches (row sums, then adjoint) for
+// larger elements (and a matrix-free path, wavefront per element, for problems that
+// store no G)
 enum { kPathFast = 0, kPathRows1 = 1, kPathRows2 = 2, kPathRows4 = 3, kPathGeneric = 4, kPathMF = 5, kNumPaths = 6 };
 constexpr int kCbs = kCThreads + 1;  // row stride of the per-point term buffer
 
@@ -146,6 +147,11 @@ struct InstDesc {
     float *eadj;
     int nq, ntest, epc;
     int path;                 // contraction path (kPathFast .. kPathMF)
+    // large elements (kPathGeneric): row-sum blocks rblk0 .. (element, row block of 16, point
+    // block of kSplitQ; nkb x nqb per element) write partial sums at apart[abase ..]; the
+    // adjoint blocks (npb per element, 64 points each) are this instance's contraction blocks
+    int64_t rblk0, abase;
+    int nkb, nqb, npb;
     // loss partial rows lrow0 .. lrow0 + ln_rows - 1: first one per tile block
     // (gblk0 ..), then one per contraction block
     int lrow0, ln_rows;
@@ -753,8 +759,9 @@ __global__ __launch_bounds__(NW * 64, 1) void k_fwd(FwdArgs A) {
 //     registers, and the adjoint adds dL/de_q = sum_k 2 c_v R_k (u_x G_x + u_y G_y);
 //   rows (nq <= 64 kRowQ, any ntest): one element per block, G streamed row by row,
 //     each row used twice from registers;
-//   generic (larger elements): rows by 16-lane groups, then the adjoint thread per q
-//     with G read again (cache-resident by then).
+//   split (larger elements): two launches, row sums by (element, rows, points) into
+//     partials, then R, loss and the adjoint by (element, points), G read again
+//     (cache-resident by then), so even one element spreads over the chip.
 // In every case G is read from HBM once; loss partials go to one row per block.
 
 // point of slot s (shared points) or the slot itself
@@ -991,66 +998,89 @@ __global__ __launch_bounds__(kCThreads) void k_contract_rows(ContractArgs A) {
     contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
 }
 
-__global__ __launch_bounds__(kGThreads) void k_contract_generic(ContractArgs A) {
+// Large elements (N_quad > 256) in two launches, so that any number of blocks share an
+// element and a problem of one large element still fills the chip.  k_split_rows: block
+// (element, 16 test-function rows, kSplitQ points), a wavefront per row, sixteen points a
+// lane with every load issued before the products, the lane sums added by a fixed
+// butterfly -> partial row sums apart[e][point block][k].  k_split_adj: block (element, 64
+// points) adds an element's partials in point-block order, forms R = eps A - F, 2 c_v R
+// and (in the element's first block only) the loss terms, then the adjoint of its points,
+// test functions split over the 16 wavefronts and the wavefront sums added in order.  The
+// adjoint is written over the point buffer, whose readers (the row sums) have finished.
+constexpr int kSplitQ = 64 * 16;
+
+__global__ __launch_bounds__(kGThreads) void k_split_rows(ContractArgs A, const int *__restrict__ rblk_inst,
+                                                          float *__restrict__ apart) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t b = blockIdx.x;
+    const InstDesc *Ip = A.inst + rblk_inst[b];
+    const int nq = Ip->nq, ntest = Ip->ntest, nkb = Ip->nkb, nqb = Ip->nqb;
+    const int64_t r = b - Ip->rblk0;
+    const int qb = (int)(r % nqb), kb = (int)((r / nqb) % nkb);
+    const int64_t e = r / ((int64_t)nqb * nkb);
+    const int k = kb * kGWaves + wave;
+    if (k >= ntest) return;  // whole wavefronts; nothing below synchronises the block
+    const int64_t gbase = e * Ip->gstride;
+    const float *gxr = Ip->Gx + gbase + (int64_t)k * nq, *gyr = Ip->Gy + gbase + (int64_t)k * nq;
+    const float2 *ub = A.ubuf + Ip->ubase;
+    const int q0 = qb * kSplitQ, q1 = min(nq, q0 + kSplitQ);
+    float2 d[16];
+    float gx[16], gy[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int q = q0 + lane + 64 * i;
+        const bool ok = q < q1;
+        d[i] = ok ? ub[upoint(Ip, e * nq + q)] : make_float2(0.f, 0.f);
+        gx[i] = ok ? gxr[q] : 0.f;
+        gy[i] = ok ? gyr[q] : 0.f;
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc = fmaf(d[i].x, gx[i], fmaf(d[i].y, gy[i], acc));
+    acc = wave_sum(acc);
+    if (lane == 0) apart[Ip->abase + (e * nqb + qb) * ntest + k] = acc;
+}
+
+__global__ __launch_bounds__(kGThreads) void k_split_adj(ContractArgs A, const float *__restrict__ apart) {
     extern __shared__ float dyn[];
     __shared__ double lp[kGWaves][2];
+    __shared__ float2 red[kGWaves][64];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const ContractCtx c = contract_ctx(A);
     const InstDesc *Ip = c.I;
-    const int nq = Ip->nq, ntest = Ip->ntest;
-    const int64_t e0 = c.e0;
-    const float *__restrict__ Gx = Ip->Gx;
-    const float *__restrict__ Gy = Ip->Gy;
-    const float *__restrict__ F = Ip->F;
+    const int nq = Ip->nq, ntest = Ip->ntest, npb = Ip->npb, nqb = Ip->nqb;
+    const int64_t e = c.chunk / npb;
+    const int pb = (int)(c.chunk % npb);
     const float two_cv = Ip->two_cv, eps = c.eps;
-    // not restrict: unshared, the adjoint is written in place over these entries
-    const float2 *ub = A.ubuf + Ip->ubase;
+    float *rbar = dyn;  // [ntest] 2 c_v R of the element
     double lrr = 0.0, lra = 0.0;
-    float *rbar = dyn;  // [ntest] 2 c_v R of the block's element
-    const int64_t ebase = e0 * ntest, gbase = e0 * Ip->gstride;
-    // a wavefront per test-function row, its lanes striding over the points eight a round
-    // with every load issued before the products: a few large elements give few blocks,
-    // so each block must keep many loads in flight
-    for (int k = wave; k < ntest; k += kGWaves) {
-        const float *gxr = Gx + gbase + (int64_t)k * nq, *gyr = Gy + gbase + (int64_t)k * nq;
-        float acc = 0.f;
-        int q = lane;
-        for (; q + 64 * 7 < nq; q += 64 * 8) {
-            float2 d[8];
-            float gx[8], gy[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                d[i] = ub[upoint(Ip, e0 * nq + q + 64 * i)];
-                gx[i] = gxr[q + 64 * i];
-                gy[i] = gyr[q + 64 * i];
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) acc = fmaf(d[i].x, gx[i], fmaf(d[i].y, gy[i], acc));
-        }
-        for (; q < nq; q += 64) {
-            const float2 d = ub[upoint(Ip, e0 * nq + q)];
-            acc = fmaf(d.x, gxr[q], fmaf(d.y, gyr[q], acc));
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) {
-            const float R = eps * acc - F[ebase + k];
-            rbar[k] = two_cv * R;
+    const float *ap = apart + Ip->abase + e * nqb * ntest;
+    for (int k = tid; k < ntest; k += kGThreads) {
+        float a = 0.f;
+        for (int j = 0; j < nqb; ++j) a += ap[(int64_t)j * ntest + k];
+        const float R = eps * a - Ip->F[e * ntest + k];
+        rbar[k] = two_cv * R;
+        if (pb == 0) {
             lrr += (double)R * (double)R;
-            lra += (double)R * (double)acc;
+            lra += (double)R * (double)a;
         }
     }
     __syncthreads();
     if (A.want_grad) {
-        for (int q = tid; q < nq; q += kGThreads) {
-            float bx = 0.f, by = 0.f;
-            int k = 0;
-            for (; k + 7 < ntest; k += 8) {
+        const int q = pb * 64 + lane;
+        const int kc = (ntest + kGWaves - 1) / kGWaves;
+        const int k0 = min(ntest, wave * kc), k1 = min(ntest, k0 + kc);
+        float bx = 0.f, by = 0.f;
+        if (q < nq) {
+            const int64_t gbase = e * Ip->gstride;
+            int k = k0;
+            for (; k + 7 < k1; k += 8) {
                 float gx[8], gy[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int64_t o = gbase + (int64_t)(k + i) * nq + q;
-                    gx[i] = Gx[o];
-                    gy[i] = Gy[o];
+                    gx[i] = Ip->Gx[o];
+                    gy[i] = Ip->Gy[o];
                 }
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
@@ -1058,12 +1088,21 @@ __global__ __launch_bounds__(kGThreads) void k_contract_generic(ContractArgs A) 
                     by = fmaf(rbar[k + i], gy[i], by);
                 }
             }
-            for (; k < ntest; ++k) {
+            for (; k < k1; ++k) {
                 const int64_t o = gbase + (int64_t)k * nq + q;
-                bx = fmaf(rbar[k], Gx[o], bx);
-                by = fmaf(rbar[k], Gy[o], by);
+                bx = fmaf(rbar[k], Ip->Gx[o], bx);
+                by = fmaf(rbar[k], Ip->Gy[o], by);
             }
-            Ip->adj[e0 * nq + q] = make_float2(eps * bx, eps * by);
+        }
+        red[wave][lane] = make_float2(bx, by);
+        __syncthreads();
+        if (wave == 0 && q < nq) {
+            float sx = 0.f, sy = 0.f;
+            for (int w = 0; w < kGWaves; ++w) {
+                sx += red[w][lane].x;
+                sy += red[w][lane].y;
+            }
+            Ip->adj[e * nq + q] = make_float2(eps * sx, eps * sy);
         }
     }
     contract_flush<kGWaves>(A, c, lrr, lra, lp, tid, wave, lane);
@@ -1642,13 +1681,15 @@ struct FusedPlan {
     // shared points: the instances' point lists, and the per-slot adjoints of the contraction
     DevBuf dpts, abuf, eabuf;
     DevBuf act;  // store_activations: [tiles][L][kActTile]
+    DevBuf rblk_inst, apart;  // large elements: instance of each row-sum block; partial row sums
+    int64_t rblocks = 0;
     int nh = 1;   // network outputs
     vpinn_tuning tune = kDefaultTuning;
     std::vector<InstDesc> host_inst;
     int tblocks = 0, n_inst = 0, grows = 0, lrows = 0, L = 0, H = 0;
     int64_t cblocks = 0, tiles = 0, npf = 0;
     int64_t cpath_blocks[kNumPaths] = {};  // contraction blocks of each path, in path order
-    size_t cdyn_fast = 0, cdyn_generic = 0;  // dynamic LDS of k_contract_fast / k_contract_generic
+    size_t cdyn_fast = 0, cdyn_generic = 0;  // dynamic LDS of k_contract_fast / k_split_adj
     size_t cdyn_mf = 0;                      // and of k_contract_mf
 };
 
@@ -1663,7 +1704,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     // dbase[i] of the plan's dpts, their adjoint slots at sbase[i] of abuf (eabuf)
     std::vector<int64_t> dbase(n, -1), sbase(n, -1);
     int64_t n_dpts = 0, n_slots = 0;
-    int64_t tiles = 0, ubase = 0, cblocks = 0;
+    int64_t tiles = 0, ubase = 0, cblocks = 0, rblocks = 0, n_apart = 0;
     size_t cdyn_fast = 16, cdyn_generic = 16, cdyn_mf = 16;
     for (int i = 0; i < n; ++i) {
         const vpinn_problem *p = probs[i];
@@ -1728,6 +1769,16 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
                 : d.path == kPathMF ? kCWaves
                                     : 1;
         d.n_chunks = (p->n_elem + d.epc - 1) / d.epc;
+        if (d.path == kPathGeneric) {
+            d.nkb = (p->ntest + kGWaves - 1) / kGWaves;
+            d.nqb = (p->nq + kSplitQ - 1) / kSplitQ;
+            d.npb = (p->nq + 63) / 64;
+            d.n_chunks = p->n_elem * d.npb;
+            d.rblk0 = rblocks;
+            rblocks += p->n_elem * d.nkb * d.nqb;
+            d.abase = n_apart;
+            n_apart += p->n_elem * d.nqb * p->ntest;
+        }
         if (d.path == kPathFast)
             cdyn_fast = std::max(cdyn_fast, sizeof(float) * ((size_t)d.ntest * kCbs + (size_t)d.epc * d.ntest));
         if (d.path == kPathGeneric) cdyn_generic = std::max(cdyn_generic, sizeof(float) * (size_t)d.ntest);
@@ -1752,7 +1803,8 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
                 cblocks += D[i].n_chunks;
                 cpath_blocks[path] += D[i].n_chunks;
             }
-    if (cblocks > (int64_t)INT32_MAX) return fail(VPINN_E_UNSUPPORTED, "fused path: too many elements for one launch");
+    if (cblocks > (int64_t)INT32_MAX || rblocks > (int64_t)INT32_MAX)
+        return fail(VPINN_E_UNSUPPORTED, "fused path: too many elements for one launch");
     if (cdyn_fast > 64 * 1024 || cdyn_generic > 64 * 1024 || cdyn_mf > 64 * 1024)
         return fail(VPINN_E_UNSUPPORTED, "fused path: test-function count exceeds the LDS budget");
     // tile blocks (k_fwd and k_bwd): one per CU, equal shares of the tile list
@@ -1791,6 +1843,16 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
     VP_HIP(P.blk_tiles.reserve(sizeof(int64_t) * (tblocks + 1)));
     VP_HIP(P.blk_inst0.reserve(sizeof(int) * tblocks));
     VP_HIP(P.cblk_inst.reserve(sizeof(int) * (size_t)cblocks));
+    if (rblocks) {
+        VP_HIP(P.rblk_inst.reserve(sizeof(int) * (size_t)rblocks));
+        VP_HIP(P.apart.reserve(sizeof(float) * (size_t)n_apart));
+        std::vector<int> rinst((size_t)rblocks);
+        for (int i = 0; i < n; ++i)
+            if (D[i].path == kPathGeneric)
+                for (int64_t j = 0; j < D[i].n_elem * D[i].nkb * D[i].nqb; ++j) rinst[(size_t)(D[i].rblk0 + j)] = i;
+        VP_HIP(hipMemcpy(P.rblk_inst.ptr, rinst.data(), sizeof(int) * (size_t)rblocks, hipMemcpyHostToDevice));
+    }
+    P.rblocks = rblocks;
     VP_HIP(P.ubuf.reserve(sizeof(float2) * (size_t)ubase));
     VP_HIP(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)grows));
     VP_HIP(P.lpart.reserve(sizeof(double) * 4 * (size_t)lrows));
@@ -1887,8 +1949,10 @@ static void launch_all(const FusedPlan &P, const FwdArgs &fa, const ContractArgs
         c.cblk_base += P.cpath_blocks[kPathRows2];
         if (P.cpath_blocks[kPathRows4]) launch_rows<4>(rp, (unsigned)P.cpath_blocks[kPathRows4], c, s);
         c.cblk_base += P.cpath_blocks[kPathRows4];
-        if (P.cpath_blocks[kPathGeneric])
-            k_contract_generic<<<(unsigned)P.cpath_blocks[kPathGeneric], kGThreads, P.cdyn_generic, s>>>(c);
+        if (P.cpath_blocks[kPathGeneric]) {
+            k_split_rows<<<(unsigned)P.rblocks, kGThreads, 0, s>>>(c, P.rblk_inst.as<int>(), P.apart.as<float>());
+            k_split_adj<<<(unsigned)P.cpath_blocks[kPathGeneric], kGThreads, P.cdyn_generic, s>>>(c, P.apart.as<float>());
+        }
         c.cblk_base += P.cpath_blocks[kPathGeneric];
         if (P.cpath_blocks[kPathMF])
             k_contract_mf<NH == 2><<<(unsigned)P.cpath_blocks[kPathMF], kCThreads, P.cdyn_mf, s>>>(c);
