@@ -548,7 +548,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the unfused comparator")
     ap.add_argument("--workload", choices=["c2", "c5", "probe", "gear_cd", "disk_vareps", "c2_mf", "probe_mf",
-                                           "predict", "inverse_const"],
+                                           "predict", "inverse_const", "p_refine", "h_refine"],
                     default="c2",
                     help="c2 (default, the headline): one 1,024-element problem; c5: 64-instance batch; probe: "
                          "20x20 test functions on 4,096 elements (G-stream bound); gear_cd: the convection-diffusion "
@@ -557,7 +557,8 @@ def main():
                          "G regenerated per step from the element geometry (matrix-free); predict: network values "
                          "of a trained-size MLP at the six point counts of the paper's prediction-time table; "
                          "inverse_const: the constant-eps inverse problem at the paper's sizes (2x2 elements, 40x40 "
-                         "points), eps trained beside the weights")
+                         "points), eps trained beside the weights; p_refine, h_refine: the paper's p- and "
+                         "h-refinement shapes (one element, or 8x8 elements, of 80x80 points)")
     ap.add_argument("--shared-points", action="store_true",
                     help="evaluate the network once per distinct interior GLL point (vpinn_set_shared_points); the "
                          "result equals per-slot evaluation up to rounding")
@@ -722,6 +723,11 @@ WORKLOAD_TEXT = {
                      "elements, 40x40 GLL points, 5x5 test functions, u = 10 sin(x) tanh(x) exp(-0.3 x^2), 50 "
                      "sensors of u, 400 boundary points, tau = gamma = 10, eps trainable (init 2.0, true 0.3), MLP "
                      "2-30-30-30-1 tanh, Adam lr 1e-3 on the weights and on eps",
+    "p_refine": "p_refine: Poisson on the unit square as one element (the paper's p-refinement study), 80x80 GLL "
+                "points, 20x20 test functions, u* = sin(4pi x) sin(4pi y), 400 boundary points, MLP 2-30-30-30-1 tanh",
+    "h_refine": "h_refine: Poisson on the unit square, 8x8 uniform elements (the paper's finest h-refinement), 80x80 "
+                "GLL points and 5x5 test functions each (409,600 points), u* = sin(4pi x) sin(4pi y), 1600 boundary "
+                "points, MLP 2-30-30-30-1 tanh",
     "c2_mf": "c2_mf: c2 with no stored G: the contraction regenerates G every step from the 8 geometry floats of "
              "each element by sum factorisation (matrix-free)",
     "probe_mf": "probe_mf: probe with no stored G (matrix-free): 1.3 GB of G a step replaced by 32 B of geometry per "

@@ -152,6 +152,7 @@ struct InstDesc {
     // adjoint blocks (npb per element, 64 points each) are this instance's contraction blocks
     int64_t rblk0, abase;
     int nkb, nqb, npb;
+    int kw;                   // adjoint: wavefronts sharing one group of 64 points (1, 2, 4, 8 or 16)
     // loss partial rows lrow0 .. lrow0 + ln_rows - 1: first one per tile block
     // (gblk0 ..), then one per contraction block
     int lrow0, ln_rows;
@@ -1002,11 +1003,13 @@ __global__ __launch_bounds__(kCThreads) void k_contract_rows(ContractArgs A) {
 // element and a problem of one large element still fills the chip.  k_split_rows: block
 // (element, 16 test-function rows, kSplitQ points), a wavefront per row, sixteen points a
 // lane with every load issued before the products, the lane sums added by a fixed
-// butterfly -> partial row sums apart[e][point block][k].  k_split_adj: block (element, 64
-// points) adds an element's partials in point-block order, forms R = eps A - F, 2 c_v R
-// and (in the element's first block only) the loss terms, then the adjoint of its points,
-// test functions split over the 16 wavefronts and the wavefront sums added in order.  The
-// adjoint is written over the point buffer, whose readers (the row sums) have finished.
+// butterfly -> partial row sums apart[e][point block][k].  k_split_adj: block (element,
+// 64 x 16 / kw points) adds an element's partials in point-block order, forms R = eps A - F,
+// 2 c_v R and (in the element's first block only) the loss terms, then the adjoint of its
+// points: the 16 wavefronts form groups of kw, each group 64 points with the test functions
+// split over its kw wavefronts, whose sums are added in order (kw grows with the test
+// count, and with the blocks a small problem needs).  The adjoint is written over the point
+// buffer, whose readers (the row sums) have finished.
 constexpr int kSplitQ = 64 * 16;
 
 __global__ __launch_bounds__(kGThreads) void k_split_rows(ContractArgs A, const int *__restrict__ rblk_inst,
@@ -1067,9 +1070,10 @@ __global__ __launch_bounds__(kGThreads) void k_split_adj(ContractArgs A, const f
     }
     __syncthreads();
     if (A.want_grad) {
-        const int q = pb * 64 + lane;
-        const int kc = (ntest + kGWaves - 1) / kGWaves;
-        const int k0 = min(ntest, wave * kc), k1 = min(ntest, k0 + kc);
+        const int kw = Ip->kw, pg = wave / kw, ks = wave - pg * kw;
+        const int q = pb * (64 * (kGWaves / kw)) + pg * 64 + lane;
+        const int kc = (ntest + kw - 1) / kw;
+        const int k0 = min(ntest, ks * kc), k1 = min(ntest, k0 + kc);
         float bx = 0.f, by = 0.f;
         if (q < nq) {
             const int64_t gbase = e * Ip->gstride;
@@ -1096,9 +1100,9 @@ __global__ __launch_bounds__(kGThreads) void k_split_adj(ContractArgs A, const f
         }
         red[wave][lane] = make_float2(bx, by);
         __syncthreads();
-        if (wave == 0 && q < nq) {
+        if (ks == 0 && q < nq) {
             float sx = 0.f, sy = 0.f;
-            for (int w = 0; w < kGWaves; ++w) {
+            for (int w = wave; w < wave + kw; ++w) {
                 sx += red[w][lane].x;
                 sy += red[w][lane].y;
             }
@@ -1772,7 +1776,13 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         if (d.path == kPathGeneric) {
             d.nkb = (p->ntest + kGWaves - 1) / kGWaves;
             d.nqb = (p->nq + kSplitQ - 1) / kSplitQ;
-            d.npb = (p->nq + 63) / 64;
+            // wavefronts per point group: enough that each takes at most 32 test functions, and
+            // more while the problem has fewer than 512 adjoint blocks
+            d.kw = 1;
+            while (d.kw < kGWaves && (d.kw * 32 < p->ntest ||
+                                      p->n_elem * ((p->nq + 64 * (kGWaves / d.kw) - 1) / (64 * (kGWaves / d.kw))) < 512))
+                d.kw *= 2;
+            d.npb = (p->nq + 64 * (kGWaves / d.kw) - 1) / (64 * (kGWaves / d.kw));
             d.n_chunks = p->n_elem * d.npb;
             d.rblk0 = rblocks;
             rblocks += p->n_elem * d.nkb * d.nqb;

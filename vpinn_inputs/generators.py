@@ -465,5 +465,19 @@ def config_inverse_const(seed: int = 0) -> Problem:
                    tau=10.0, gamma=10.0, eps_init=2.0, eps_true=man.eps, seed=seed, f_fn=man.f)
 
 
+def config_p_refine(seed: int = 0) -> Problem:
+    """The p-refinement study of Sec. 4.1 at its largest test space: one element (the unit square), 80x80 GLL
+    points, 20x20 test functions, u* = sin(4 pi x) sin(4 pi y), 400 boundary points."""
+    return poisson_sinsin_square("p_refine", 1, 80, 20, 4, 400, 0.0, seed)
+
+
+def config_h_refine(seed: int = 0) -> Problem:
+    """The h-refinement study of Sec. 4.1 at its finest mesh: 8x8 uniform elements of the unit square, 80x80
+    GLL points and 5x5 test functions each (409,600 points), u* = sin(4 pi x) sin(4 pi y), 1,600 boundary
+    points."""
+    return poisson_sinsin_square("h_refine", 8, 80, 5, 4, 1600, 0.0, seed)
+
+
 CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4, "probe": config_probe,
-           "gear_cd": config_gear_cd, "disk_vareps": config_disk_vareps, "inverse_const": config_inverse_const}
+           "gear_cd": config_gear_cd, "disk_vareps": config_disk_vareps, "inverse_const": config_inverse_const,
+           "p_refine": config_p_refine, "h_refine": config_h_refine}
