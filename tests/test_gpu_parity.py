@@ -360,3 +360,53 @@ def test_boundary_and_sensor_weights(V, torch, path, tau, gamma):
     p = _gpu_problem(V, prob)
     loss, grad, _ = _run(V, torch, p, prob, theta, _path_or_skip(V, path))
     _check(loss, grad, O.problem_loss_grad(prob, _oracle_asm("ragged"), theta), tag=f"tau={tau}/gamma={gamma}/{path}")
+
+
+@pytest.mark.parametrize("m,n,nt,kw,eps", [(23, 17, 3, 1, 2.0), (16, 23, 3, 2, 2.0), (16, 17, 3, 4, 2.0),
+                                           (16, 17, 7, 4, None)])
+def test_large_element_contraction_every_wavefront_grouping(V, torch, m, n, nt, kw, eps):
+    """Many elements of more than 256 points: the adjoint blocks of the two-launch contraction then group
+    kw = 1, 2 or 4 wavefronts per 64 points (the small shapes above use 16); loss and gradient against the
+    oracle on a skewed mesh with sensors, and the eps gradient where it is resolvable in FP32: with 7 x 7
+    test functions the stiffness sums A of this random network cancel to about 1e-6 of their terms, so
+    d loss / d eps (proportional to A) is checked on the 3 x 3 cases only."""
+    from oracle import oracle as O
+    prob = gen.poisson_sinsin_square(f"split_{m}_{n}_{nt}", m, n, nt, 3, 400, 0.2, seed=m + n + nt)
+    prob.sens_xy = gen.uniform(5, "split/sens", 2 * 60, 0.0, 1.0).reshape(60, 2)
+    prob.sens_u = np.sin(3 * np.pi * prob.sens_xy[:, 0]) * np.sin(3 * np.pi * prob.sens_xy[:, 1])
+    prob.gamma = 5.0
+    # the grouping rule: at most 32 test functions a wavefront, more wavefronts below 512 blocks
+    g = 1
+    while g < 16 and (g * 32 < nt * nt or m * m * -(-n * n // (64 * (16 // g))) < 512):
+        g *= 2
+    assert g == kw
+    asm = O.assemble_problem(prob)
+    theta = _params(prob)
+    p = _gpu_problem(V, prob)
+    for path in ("fused", "plain"):
+        loss, grad, geps = _run(V, torch, p, prob, theta, PATHS[path], eps=eps)
+        _check(loss, grad, O.problem_loss_grad(prob, asm, theta, eps=eps), geps=geps, tag=f"{path}")
+
+
+def test_batch_mixing_every_contraction_path(V, torch):
+    """One batch holding a small-element instance, a row-streaming instance (N_test > 32), a one-element
+    80 x 80 instance and a many-element large-element instance: each against the oracle."""
+    from oracle import oracle as O
+    probs = [gen.poisson_sinsin_square("mix_fast", 6, 6, 4, 2, 80, 0.2, seed=1),
+             gen.poisson_sinsin_square("mix_rows", 3, 10, 8, 2, 80, 0.2, seed=2),
+             gen.poisson_sinsin_square("mix_one", 1, 80, 12, 2, 80, 0.0, seed=3),
+             gen.poisson_sinsin_square("mix_split", 16, 17, 3, 2, 80, 0.2, seed=4)]
+    gp = [_gpu_problem(V, pr) for pr in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 0.0))
+    th = np.stack([pr.params(seed=50 + i, bias_scale=0.1) for i, pr in enumerate(probs)])
+    dev = torch.device("cuda:0")
+    T = torch.tensor(th, dtype=torch.float32, device=dev)
+    refs = [O.problem_loss_grad(pr, O.assemble_problem(pr), th[i]) for i, pr in enumerate(probs)]
+    for tune in [(12, 0, 4, 0), (16, 2, 2, 1)]:
+        V.vpinn_batch_set_tuning(b, *tune)
+        losses = torch.zeros((len(probs), 4), device=dev)
+        grads = torch.zeros((len(probs), th.shape[1]), device=dev)
+        V.vpinn_batch_loss_and_grad(b, T, losses=losses, grads=grads)
+        torch.cuda.synchronize()
+        for i, pr in enumerate(probs):
+            _check(losses[i].cpu().double().numpy(), grads[i].cpu().double().numpy(), refs[i], tag=f"{pr.name}/{tune}")
