@@ -7,7 +7,7 @@ every quadrature point, contraction with G_x/G_y and F, loss, adjoint through th
 contraction and the network, and an Adam update.  Inputs (premultiplied tensors,
 points, parameters) are resident in device memory before the timed region.
 
-Prints one JSON line (rank 0).  --gpus above 1 is rejected: this build runs on one GPU.
+Prints one JSON line (rank 0).  --gpus above 1 is rejected: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -586,7 +586,7 @@ def main():
     if args.profile_run:
         args.no_cpu_baseline = True
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); no multi-GPU path is implemented",
               file=sys.stderr)
         sys.exit(2)
 
