@@ -410,3 +410,25 @@ def test_batch_mixing_every_contraction_path(V, torch):
         torch.cuda.synchronize()
         for i, pr in enumerate(probs):
             _check(losses[i].cpu().double().numpy(), grads[i].cpu().double().numpy(), refs[i], tag=f"{pr.name}/{tune}")
+
+
+@pytest.mark.parametrize("m,n,nt", [(1, 40, 10), (16, 17, 3)])
+def test_large_element_loss_without_gradient(V, torch, m, n, nt):
+    """A loss-only call (no gradient buffer) on the two-launch contraction: the adjoint is skipped and the loss
+    still matches the oracle, and a following call with a gradient gives the same loss bit for bit."""
+    from oracle import oracle as O
+    prob = gen.poisson_sinsin_square(f"lossonly_{m}_{n}_{nt}", m, n, nt, 2, 200, 0.2 if m > 1 else 0.0, seed=9)
+    theta = _params(prob)
+    p = _gpu_problem(V, prob)
+    dev = torch.device("cuda:0")
+    th = torch.tensor(theta, dtype=torch.float32, device=dev)
+    cfg = V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma)
+    l1 = torch.full((4,), float("nan"), device=dev)
+    V.vpinn_loss_and_grad(p, cfg, th, loss=l1)
+    l2 = torch.full((4,), float("nan"), device=dev)
+    g = torch.zeros(V.vpinn_n_params(prob.width, prob.n_hidden), device=dev)
+    V.vpinn_loss_and_grad(p, cfg, th, loss=l2, grad=g)
+    torch.cuda.synchronize()
+    ref = O.problem_loss_grad(prob, O.assemble_problem(prob), theta, want_grad=False)
+    assert abs(float(l1[0]) - ref.loss[0]) <= LOSS_RTOL * abs(ref.loss[0])
+    assert torch.equal(l1, l2)
