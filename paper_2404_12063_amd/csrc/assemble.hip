@@ -118,8 +118,10 @@ __global__ void k_points(const double *__restrict__ nodes, const int32_t *__rest
     xq32[t] = make_float2((float)x, (float)y);
 }
 
-// G_x, G_y, F for one element per block.  Threads stride over quadrature points;
-// F[e,k] is reduced over q in fixed order through shared memory.  With a
+// G_x, G_y, F of one element and one test-function index s along eta per block
+// (grid: elements x N_t), so a few large elements still spread over the chip.
+// Threads stride over quadrature points; F[e, s N_t + r] is reduced over q in fixed
+// order through shared memory, thread r per entry.  With a
 // convection-diffusion operator -diff Lap u + (cx, cy) . grad u the convection
 // term's weights w_q det J v_k are folded in: G_x = w_q det J (diff v_x + cx v),
 // G_y = w_q det J (diff v_y + cy v) (Poisson: diff = 1, cx = cy = 0).  With M
@@ -134,12 +136,10 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(
     float *__restrict__ Gy, float *__restrict__ F, float *__restrict__ M) {
     __shared__ double wdf[kAsmThreads];
     const int64_t e = blockIdx.x;
+    const int s = blockIdx.y;  // test function phi_s along eta
     const int nq = n * n, ntest = nt * nt;
     const Geo g = load_geo(nodes, quad, e);
-    constexpr int kMaxK = (VPINN_MAX_TEST_ORDER * VPINN_MAX_TEST_ORDER + kAsmThreads - 1) / kAsmThreads;
-    double Fk[kMaxK];  // thread t accumulates F[e, t + m * kAsmThreads]
-#pragma unroll
-    for (int m = 0; m < kMaxK; ++m) Fk[m] = 0.0;
+    double Fr = 0.0;  // thread r < nt accumulates F[e, s nt + r]
     for (int q0 = 0; q0 < nq; q0 += kAsmThreads) {
         const int q = q0 + threadIdx.x;
         if (q < nq) {
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(
             }
             wdf[threadIdx.x] = w * D * f;
             // a shared premultiplier is written once, from element 0; none for matrix-free problems
-            for (int s = 0; s < ((Gx == nullptr || (shared_g && e > 0)) ? 0 : nt); ++s) {
+            if (Gx != nullptr && !(shared_g && e > 0)) {
                 const double ps = phi[s * n + j], dps = dphi[s * n + j];
                 for (int r = 0; r < nt; ++r) {
                     const double pr = phi[r * n + i], dpr = dphi[r * n + i];
@@ -174,24 +174,16 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(
         }
         __syncthreads();
         const int lim = min(kAsmThreads, nq - q0);
-#pragma unroll
-        for (int m = 0; m < kMaxK; ++m) {
-            const int k = threadIdx.x + m * kAsmThreads;
-            if (k < ntest) {
-                const int rk = k % nt, sk = k / nt;
-                for (int t = 0; t < lim; ++t) {
-                    const int q = q0 + t;
-                    Fk[m] += wdf[t] * phi[rk * n + q % n] * phi[sk * n + q / n];
-                }
+        if (threadIdx.x < nt) {
+            const int r = threadIdx.x;
+            for (int t = 0; t < lim; ++t) {
+                const int q = q0 + t;
+                Fr += wdf[t] * phi[r * n + q % n] * phi[s * n + q / n];
             }
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int m = 0; m < kMaxK; ++m) {
-        const int k = threadIdx.x + m * kAsmThreads;
-        if (k < ntest) F[e * ntest + k] = (float)Fk[m];
-    }
+    if (threadIdx.x < nt) F[e * ntest + s * nt + threadIdx.x] = (float)Fr;
 }
 
 // matrix-free problems: the bilinear map's coefficients of each element (xc1, xc2, xc3,
@@ -267,7 +259,7 @@ vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_
         VP_HIP(hipMemcpyAsync(d_f.ptr, hf.data(), sizeof(double) * npts, hipMemcpyHostToDevice, s));
         VP_HIP(hipStreamSynchronize(s));
     }
-    k_assemble<<<dim3((unsigned)p->n_elem), kAsmThreads, 0, s>>>(
+    k_assemble<<<dim3((unsigned)p->n_elem, (unsigned)nt), kAsmThreads, 0, s>>>(
         d_nodes, d_quad, n, nt, d_xg.as<double>(), d_wg.as<double>(), d_phi.as<double>(), d_dphi.as<double>(),
         f->kind, f->amp, f->kx, f->ky, callback ? d_f.as<double>() : nullptr, p->diff, p->conv_x, p->conv_y,
         p->shared_g ? 1 : 0, p->matfree ? nullptr : p->Gx.as<float>(), p->matfree ? nullptr : p->Gy.as<float>(),
