@@ -118,10 +118,8 @@ __global__ void k_points(const double *__restrict__ nodes, const int32_t *__rest
     xq32[t] = make_float2((float)x, (float)y);
 }
 
-// G_x, G_y, F of one element and one test-function index s along eta per block
-// (grid: elements x N_t), so a few large elements still spread over the chip.
-// Threads stride over quadrature points; F[e, s N_t + r] is reduced over q in fixed
-// order through shared memory, thread r per entry.  With a
+// G_x, G_y, F for one element per block.  Threads stride over quadrature points;
+// F[e,k] is reduced over q in fixed order through shared memory.  With a
 // convection-diffusion operator -diff Lap u + (cx, cy) . grad u the convection
 // term's weights w_q det J v_k are folded in: G_x = w_q det J (diff v_x + cx v),
 // G_y = w_q det J (diff v_y + cy v) (Poisson: diff = 1, cx = cy = 0).  With M
@@ -129,6 +127,84 @@ __global__ void k_points(const double *__restrict__ nodes, const int32_t *__rest
 // w_q det J v_k are stored there instead.
 constexpr int kAsmThreads = 256;
 __global__ __launch_bounds__(kAsmThreads) void k_assemble(
+    const double *__restrict__ nodes, const int32_t *__restrict__ quad, int n, int nt,
+    const double *__restrict__ xg, const double *__restrict__ wg, const double *__restrict__ phi,
+    const double *__restrict__ dphi, int f_kind, double f_amp, double f_kx, double f_ky,
+    const double *__restrict__ f_vals, double diff, double cx, double cy, int shared_g, float *__restrict__ Gx,
+    float *__restrict__ Gy, float *__restrict__ F, float *__restrict__ M) {
+    __shared__ double wdf[kAsmThreads];
+    const int64_t e = blockIdx.x;
+    const int nq = n * n, ntest = nt * nt;
+    const Geo g = load_geo(nodes, quad, e);
+    constexpr int kMaxK = (VPINN_MAX_TEST_ORDER * VPINN_MAX_TEST_ORDER + kAsmThreads - 1) / kAsmThreads;
+    double Fk[kMaxK];  // thread t accumulates F[e, t + m * kAsmThreads]
+#pragma unroll
+    for (int m = 0; m < kMaxK; ++m) Fk[m] = 0.0;
+    for (int q0 = 0; q0 < nq; q0 += kAsmThreads) {
+        const int q = q0 + threadIdx.x;
+        if (q < nq) {
+            const int i = q % n, j = q / n;
+            const double xi = xg[i], eta = xg[j];
+            const double w = wg[i] * wg[j];
+            const double a = g.xc[1] + g.xc[3] * eta, b = g.yc[1] + g.yc[3] * eta;
+            const double c = g.xc[2] + g.xc[3] * xi, d = g.yc[2] + g.yc[3] * xi;
+            const double D = a * d - b * c;
+            double f;
+            if (f_kind == VPINN_FORCING_SINSIN) {
+                const double x = g.xc[0] + g.xc[1] * xi + g.xc[2] * eta + g.xc[3] * xi * eta;
+                const double y = g.yc[0] + g.yc[1] * xi + g.yc[2] * eta + g.yc[3] * xi * eta;
+                f = f_amp * sin(f_kx * x) * sin(f_ky * y);
+            } else {
+                f = f_vals[e * nq + q];
+            }
+            wdf[threadIdx.x] = w * D * f;
+            // a shared premultiplier is written once, from element 0; none for matrix-free problems
+            for (int s = 0; s < ((Gx == nullptr || (shared_g && e > 0)) ? 0 : nt); ++s) {
+                const double ps = phi[s * n + j], dps = dphi[s * n + j];
+                for (int r = 0; r < nt; ++r) {
+                    const double pr = phi[r * n + i], dpr = dphi[r * n + i];
+                    const double vxi = dpr * ps, veta = pr * dps, dv = D * pr * ps;
+                    const int64_t o = ((shared_g ? 0 : e * ntest) + s * nt + r) * (int64_t)nq + q;
+                    // det J * physical gradient = (d v_xi - b v_eta, -c v_xi + a v_eta)
+                    Gx[o] = (float)(w * (diff * (d * vxi - b * veta) + cx * dv));
+                    Gy[o] = (float)(w * (diff * (-c * vxi + a * veta) + cy * dv));
+                    if (M) M[o] = (float)(w * dv);
+                }
+            }
+        }
+        __syncthreads();
+        const int lim = min(kAsmThreads, nq - q0);
+#pragma unroll
+        for (int m = 0; m < kMaxK; ++m) {
+            const int k = threadIdx.x + m * kAsmThreads;
+            if (k < ntest) {
+                const int rk = k % nt, sk = k / nt;
+                for (int t = 0; t < lim; ++t) {
+                    const int q = q0 + t;
+                    Fk[m] += wdf[t] * phi[rk * n + q % n] * phi[sk * n + q / n];
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxK; ++m) {
+        const int k = threadIdx.x + m * kAsmThreads;
+        if (k < ntest) F[e * ntest + k] = (float)Fk[m];
+    }
+}
+
+// The same for problems with fewer elements than CUs: one block per element and
+// test-function index s along eta (grid: elements x N_t), so a few large elements
+// still spread over the chip (each block re-evaluates the forcing at its points).
+// Threads stride over quadrature points; F[e, s N_t + r] is reduced over q in fixed
+// order through shared memory, thread r per entry.  With a
+// convection-diffusion operator -diff Lap u + (cx, cy) . grad u the convection
+// term's weights w_q det J v_k are folded in: G_x = w_q det J (diff v_x + cx v),
+// G_y = w_q det J (diff v_y + cy v) (Poisson: diff = 1, cx = cy = 0).  With M
+// non-null (space-dependent diffusion, nothing folded) the convection weights
+// w_q det J v_k are stored there instead.
+__global__ __launch_bounds__(kAsmThreads) void k_assemble_split(
     const double *__restrict__ nodes, const int32_t *__restrict__ quad, int n, int nt,
     const double *__restrict__ xg, const double *__restrict__ wg, const double *__restrict__ phi,
     const double *__restrict__ dphi, int f_kind, double f_amp, double f_kx, double f_ky,
@@ -259,11 +335,23 @@ vpinn_status assemble_device(vpinn_problem *p, const double *d_nodes, int64_t n_
         VP_HIP(hipMemcpyAsync(d_f.ptr, hf.data(), sizeof(double) * npts, hipMemcpyHostToDevice, s));
         VP_HIP(hipStreamSynchronize(s));
     }
-    k_assemble<<<dim3((unsigned)p->n_elem, (unsigned)nt), kAsmThreads, 0, s>>>(
-        d_nodes, d_quad, n, nt, d_xg.as<double>(), d_wg.as<double>(), d_phi.as<double>(), d_dphi.as<double>(),
-        f->kind, f->amp, f->kx, f->ky, callback ? d_f.as<double>() : nullptr, p->diff, p->conv_x, p->conv_y,
-        p->shared_g ? 1 : 0, p->matfree ? nullptr : p->Gx.as<float>(), p->matfree ? nullptr : p->Gy.as<float>(),
-        p->F.as<float>(), (p->vardiff && !p->matfree) ? p->M.as<float>() : nullptr);
+    int cus = 0;
+    VP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
+    // one block per element when there are enough elements to fill the CUs, else one per
+    // element and test-function row (a few large elements)
+    if (p->n_elem >= cus) {
+        k_assemble<<<dim3((unsigned)p->n_elem), kAsmThreads, 0, s>>>(
+            d_nodes, d_quad, n, nt, d_xg.as<double>(), d_wg.as<double>(), d_phi.as<double>(), d_dphi.as<double>(),
+            f->kind, f->amp, f->kx, f->ky, callback ? d_f.as<double>() : nullptr, p->diff, p->conv_x, p->conv_y,
+            p->shared_g ? 1 : 0, p->matfree ? nullptr : p->Gx.as<float>(), p->matfree ? nullptr : p->Gy.as<float>(),
+            p->F.as<float>(), (p->vardiff && !p->matfree) ? p->M.as<float>() : nullptr);
+    } else {
+        k_assemble_split<<<dim3((unsigned)p->n_elem, (unsigned)nt), kAsmThreads, 0, s>>>(
+            d_nodes, d_quad, n, nt, d_xg.as<double>(), d_wg.as<double>(), d_phi.as<double>(), d_dphi.as<double>(),
+            f->kind, f->amp, f->kx, f->ky, callback ? d_f.as<double>() : nullptr, p->diff, p->conv_x, p->conv_y,
+            p->shared_g ? 1 : 0, p->matfree ? nullptr : p->Gx.as<float>(), p->matfree ? nullptr : p->Gy.as<float>(),
+            p->F.as<float>(), (p->vardiff && !p->matfree) ? p->M.as<float>() : nullptr);
+    }
     VP_HIP(hipGetLastError());
     if (p->matfree) {
         k_geometry<<<dim3((unsigned)((p->n_elem + 255) / 256)), 256, 0, s>>>(d_nodes, d_quad, p->n_elem,
