@@ -677,3 +677,49 @@ def test_inverse_const_data_residual_vanishes_at_the_true_eps(oracle):
     assert np.abs(oracle.residual(asm, ux, uy, eps=0.3)).max() < 1e-11 * scale
     assert np.abs(oracle.residual(asm, ux, uy, eps=2.0)).max() > 0.1 * scale
     assert np.allclose(prob.bnd_g, man.u(prob.bnd_xy[:, 0], prob.bnd_xy[:, 1]))
+
+
+# ----------------------------------------------------------------------------- the loss tied to the residual
+
+@pytest.mark.parametrize("eps,conv,heads", [(0.3, None, 1), (2.0, None, 1), (0.3, (1.1, -0.6), 1),
+                                            (2.0, (0.4, 0.9), 1), (1.0, (1.0, 0.0), 2), (1.0, None, 2)])
+def test_loss_residual_equals_pinned_residual_at_a_random_network(oracle, eps, conv, heads):
+    """At a Glorot network with non-zero biases (so grad u != 0 and, with two outputs, e(x) varies), the
+    residual the loss evaluates equals orc_residual fed with the network's own tangents at the quadrature
+    points: R = eps A + sum_q (b . grad u) M - F (Sec. 2.3 cell residual, Sec. 4.7.1 eps scaling the
+    diffusion term, the convection term of Sec. 4.6.4), or sum_q e_q (grad u . G) + ... - F with two outputs
+    (Sec. 4.7.2).  orc_residual is pinned by the manufactured solutions above and the network tangents by
+    finite differences, so a misplaced eps (eps (A - F), A - eps F), a swapped x/y or a dropped convection
+    term in the loss fails here.  The loss terms are then the stated sums of that residual and of the
+    boundary and sensor mismatches at the network's values."""
+    H, L = 6, 2
+    mesh = gen.square_mesh(3, 2, 0.2, seed=21)
+    asm = oracle.assemble(mesh.xy, mesh.quad, 5, 3, 4.0, 3.0, 2.0, want_M=conv is not None)
+    theta = gen.glorot_params(H, L, seed=22, bias_scale=0.5, heads=heads)
+    bxy = gen.square_boundary_points(12)
+    bg = gen.uniform(23, "bg", 12, -0.5, 0.5)
+    sxy = gen.sensor_points(7, 24)
+    su = gen.uniform(23, "su", 7, -0.5, 0.5)
+    tau, gamma = 2.0, 3.0
+    r = oracle.loss_grad(asm, theta, H, L, bxy, bg, sxy, su, eps=eps, tau=tau, gamma=gamma, want_R=True,
+                         conv=conv, heads=heads)
+    outs = oracle.mlp_eval(theta, H, L, asm.X.reshape(-1, 2), heads=heads)
+    ux = outs[1].reshape(asm.n_elem, -1)
+    uy = outs[2].reshape(asm.n_elem, -1)
+    epsq = outs[3].reshape(asm.n_elem, -1) if heads == 2 else None
+    assert np.abs(ux).max() > 0.02 and np.abs(uy).max() > 0.02
+    if heads == 2:
+        assert np.ptp(epsq) > 0.05
+    R = oracle.residual(asm, ux, uy, eps=eps, conv=conv, epsq=epsq)
+    scale = np.abs(R).max()
+    np.testing.assert_allclose(r.R, R, rtol=0, atol=1e-13 * scale)
+    # the diffusion term carries signal of its own, so the placement of eps is tested
+    A = oracle.residual(asm, ux, uy, eps=1.0, epsq=epsq) + asm.F
+    assert np.abs(A).max() > 0.01 * np.abs(asm.F).max()
+    cv = 1.0 / 9
+    assert abs(r.loss[1] - cv * np.sum(R ** 2)) <= 1e-13 * r.loss[1]
+    ub = oracle.mlp_eval(theta, H, L, bxy, heads=heads)[0]
+    us = oracle.mlp_eval(theta, H, L, sxy, heads=heads)[0]
+    assert abs(r.loss[2] - np.mean((ub - bg) ** 2)) <= 1e-13 * r.loss[2]
+    assert abs(r.loss[3] - np.mean((us - su) ** 2)) <= 1e-13 * r.loss[3]
+    assert abs(r.loss[0] - (r.loss[1] + tau * r.loss[2] + gamma * r.loss[3])) <= 1e-13 * r.loss[0]
