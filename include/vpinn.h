@@ -162,11 +162,11 @@ vpinn_status vpinn_assemble_matrix_free(const vpinn_mesh *mesh, int32_t quad_ord
                                         const vpinn_forcing *forcing, void *stream, vpinn_problem **out);
 
 /*
- * Dirichlet points x_b and values g_b of the boundary term (Sec. 2.2), and
- * sensor points x_s with observations d_s of the data term of the inverse
- * problem (Sec. 4.7).  Host arrays xy [n][2] and values [n] are copied to the
- * device (as FP32); a later call replaces the previous set; n = 0 clears it.
- * Synchronous.  Errors: VPINN_E_INVALID, VPINN_E_NOMEM, VPINN_E_DEVICE.
+ * vpinn_set_boundary -- Dirichlet points x_b and values g_b of the boundary term
+ * tau mean_b (u(x_b) - g_b)^2 (Sec. 2.2).  Host arrays xy [n][2] and g [n] are
+ * copied to the device (as FP32); a later call replaces the previous set; n = 0
+ * clears it.  Synchronous.  Errors: VPINN_E_INVALID (null pointer with n > 0,
+ * n < 0), VPINN_E_NOMEM, VPINN_E_DEVICE.
  */
 vpinn_status vpinn_set_boundary(vpinn_problem *p, int64_t n, const double *xy, const double *g);
 /*
@@ -187,6 +187,16 @@ vpinn_status vpinn_set_boundary(vpinn_problem *p, int64_t n, const double *xy, c
  */
 vpinn_status vpinn_set_shared_points(vpinn_problem *p, const vpinn_mesh *mesh, int32_t enable);
 
+/*
+ * vpinn_set_sensors -- sensor points x_s and observed values d_s of the data term
+ * gamma mean_s (u(x_s) - d_s)^2 of the inverse problems (Sec. 4.7: observations
+ * of u inside the domain, from which eps is recovered).  Host arrays xy [n][2]
+ * and d [n] are copied to the device (as FP32) after the boundary points; a
+ * later call replaces the previous set; n = 0 clears it.  Synchronous; a batch
+ * planned before the call must be planned again (see vpinn_batch_create).
+ * Errors: VPINN_E_INVALID (null pointer with n > 0, n < 0), VPINN_E_NOMEM,
+ * VPINN_E_DEVICE.
+ */
 vpinn_status vpinn_set_sensors(vpinn_problem *p, int64_t n, const double *xy, const double *d);
 
 typedef struct vpinn_problem_info {
@@ -272,7 +282,7 @@ vpinn_status vpinn_residual(vpinn_problem *p, const vpinn_loss_cfg *cfg, const f
  * One kernel launch on `stream`, no allocation; with d_ux and d_uy both NULL only
  * the value products run (a third of the matrix work).  n = 0 does nothing.
  * Errors: VPINN_E_INVALID (null params, null d_xy with n > 0, n < 0),
- * VPINN_E_UNSUPPORTED (width or n_hidden out of range), VPINN_E_HIP.
+ * VPINN_E_UNSUPPORTED (width or n_hidden out of range), VPINN_E_DEVICE.
  */
 vpinn_status vpinn_eval_network(int32_t width, int32_t n_hidden, const float *d_params, int64_t n,
                                 const float *d_xy, float *d_u, float *d_ux, float *d_uy, void *stream);
@@ -360,9 +370,19 @@ vpinn_status vpinn_batch_loss_and_grad(vpinn_batch *b, const float *d_params, co
  * the first step after *d_step = 0 is step 1 and a captured step replays
  * correctly.  d_m, d_v are device [n][n_params]; d_losses (may be NULL) gets
  * the losses at the parameters before the update.
+ *   d_eps, d_eps_m, d_eps_v  device [n] floats each, or all NULL: the inverse
+ *              problem of Sec. 4.7.1, where each problem's diffusion coefficient
+ *              eps (R = eps A - F) is trained beside the weights.  The step uses
+ *              d_eps[i] as problem i's eps and then applies the same Adam update
+ *              (lr, beta1, beta2, eps, the same step count) to it from
+ *              dL/deps = 2 c_v sum_{e,k} R A, with d_eps_m, d_eps_v its moments;
+ *              all three are updated in place.  Refused (VPINN_E_INVALID) for
+ *              problems from vpinn_assemble_cd2d or vpinn_assemble_vardiff, and
+ *              when only some of the three are given.
  */
 vpinn_status vpinn_batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
-                              float beta1, float beta2, float eps, float *d_losses, void *stream);
+                              float beta1, float beta2, float eps, float *d_losses, float *d_eps, float *d_eps_m,
+                              float *d_eps_v, void *stream);
 
 /*
  * vpinn_batch_capture -- record one vpinn_batch_step with these arguments into
@@ -371,7 +391,8 @@ vpinn_status vpinn_batch_step(vpinn_batch *b, float *d_params, float *d_m, float
  * only.  Capturing again replaces the previous graph.
  */
 vpinn_status vpinn_batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
-                                 float beta1, float beta2, float eps, float *d_losses, void *stream);
+                                 float beta1, float beta2, float eps, float *d_losses, float *d_eps, float *d_eps_m,
+                                 float *d_eps_v, void *stream);
 vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream);
 
 /* Release the batch (not the problems).  NULL is a no-op. */

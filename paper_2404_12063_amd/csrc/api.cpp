@@ -633,30 +633,37 @@ vpinn_status vpinn_batch_loss_and_grad(vpinn_batch *b, const float *d_params, co
     return batch_loss_and_grad(b, d_params, d_eps, d_losses, d_grads, d_grad_eps, (hipStream_t)stream);
 }
 
-static vpinn_status check_step_args(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step) {
+static vpinn_status check_step_args(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step,
+                                    float *d_eps, float *d_eps_m, float *d_eps_v) {
     using namespace vp;
     if (!b || !d_params || !d_m || !d_v || !d_step) return fail(VPINN_E_INVALID, "null argument");
+    const int given = (d_eps != nullptr) + (d_eps_m != nullptr) + (d_eps_v != nullptr);
+    if (given != 0 && given != 3) return fail(VPINN_E_INVALID, "d_eps, d_eps_m and d_eps_v go together");
     return VPINN_OK;
 }
 
 vpinn_status vpinn_batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
-                              float beta1, float beta2, float eps, float *d_losses, void *stream) {
+                              float beta1, float beta2, float eps, float *d_losses, float *d_eps, float *d_eps_m,
+                              float *d_eps_v, void *stream) {
     using namespace vp;
-    vpinn_status st = check_step_args(b, d_params, d_m, d_v, d_step);
+    vpinn_status st = check_step_args(b, d_params, d_m, d_v, d_step, d_eps, d_eps_m, d_eps_v);
     if (st) return st;
     DeviceGuard dg(batch_device(b));
     if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the batch's device");
-    return batch_step(b, d_params, d_m, d_v, d_step, lr, beta1, beta2, eps, d_losses, (hipStream_t)stream);
+    return batch_step(b, d_params, d_m, d_v, d_step, lr, beta1, beta2, eps, d_losses, d_eps, d_eps_m, d_eps_v,
+                      (hipStream_t)stream);
 }
 
 vpinn_status vpinn_batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
-                                 float beta1, float beta2, float eps, float *d_losses, void *stream) {
+                                 float beta1, float beta2, float eps, float *d_losses, float *d_eps, float *d_eps_m,
+                                 float *d_eps_v, void *stream) {
     using namespace vp;
-    vpinn_status st = check_step_args(b, d_params, d_m, d_v, d_step);
+    vpinn_status st = check_step_args(b, d_params, d_m, d_v, d_step, d_eps, d_eps_m, d_eps_v);
     if (st) return st;
     DeviceGuard dg(batch_device(b));
     if (!dg.ok) return fail(VPINN_E_DEVICE, "cannot select the batch's device");
-    return batch_capture(b, d_params, d_m, d_v, d_step, lr, beta1, beta2, eps, d_losses, (hipStream_t)stream);
+    return batch_capture(b, d_params, d_m, d_v, d_step, lr, beta1, beta2, eps, d_losses, d_eps, d_eps_m, d_eps_v,
+                         (hipStream_t)stream);
 }
 
 vpinn_status vpinn_batch_replay(vpinn_batch *b, void *stream) {

@@ -215,6 +215,8 @@ struct Acts {
 // activations of one tile in the layout [layer][m][lane][4]: each lane's chained
 // vector is two 16-byte pieces, so a layer is two fully coalesced 1 KB accesses
 constexpr int kActTile = 2 * 64 * 4;  // floats per layer and tile
+// largest activation buffer the autotuner considers storing (the 256 MB last-level cache of the part)
+constexpr size_t kActStoreMaxBytes = (size_t)256 << 20;
 
 // tanh(x) = 1 - 2 / (1 + e^{2x}): one exponential, one reciprocal and three other
 // operations against five for the sign-split form tanh_f32 (largest error 1.8e-7
@@ -1421,7 +1423,18 @@ struct AdamArgs {
     float *params, *m, *v;
     const int64_t *step;
     float lr, b1, b2, eps;
+    // optional: a trainable diffusion coefficient per instance and its moments, updated
+    // with the same hyperparameters from dL/deps = 2 c_v sum R A
+    float *ep, *em, *ev;
 };
+
+// one bias-corrected Adam update (Kingma and Ba, Algorithm 1) of a single value
+__device__ __forceinline__ void adam_one(float &p, float &m, float &v, float g, float t, const AdamArgs &ad) {
+    const float c1 = 1.0f - powf(ad.b1, t), c2 = 1.0f - powf(ad.b2, t);
+    m = fmaf(ad.b1, m, (1.0f - ad.b1) * g);
+    v = fmaf(ad.b2, v, (1.0f - ad.b2) * g * g);
+    p = p - ad.lr * (m / c1) / (sqrtf(v / c2) + ad.eps);
+}
 
 template <int L, int NH>
 __global__ __launch_bounds__(kFinThreads) void k_fused_final(
@@ -1502,12 +1515,10 @@ __global__ __launch_bounds__(kFinThreads) void k_fused_final(
         if (grad_out) grad_out[(int64_t)ii * npf + j] = g;
         if (ad.params) {
             const int64_t k = (int64_t)ii * npf + j;
-            const float c1 = 1.0f - powf(ad.b1, ast), c2 = 1.0f - powf(ad.b2, ast);
-            const float mi = fmaf(ad.b1, am, (1.0f - ad.b1) * g);
-            const float vi = fmaf(ad.b2, av, (1.0f - ad.b2) * g * g);
-            ad.m[k] = mi;
-            ad.v[k] = vi;
-            ad.params[k] = ap - ad.lr * (mi / c1) / (sqrtf(vi / c2) + ad.eps);
+            adam_one(ap, am, av, g, ast, ad);
+            ad.m[k] = am;
+            ad.v[k] = av;
+            ad.params[k] = ap;
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 64) {
@@ -1526,7 +1537,16 @@ __global__ __launch_bounds__(kFinThreads) void k_fused_final(
             lo[2] = (float)Lb;
             lo[3] = (float)Ls;
         }
-        if (grad_eps_out) grad_eps_out[ii] = (float)(2.0 * I.cv * tt[1]);
+        const float ge = (float)(2.0 * I.cv * tt[1]);
+        if (grad_eps_out) grad_eps_out[ii] = ge;
+        if (ad.ep) {
+            // the contraction read ep[ii] in this step and has finished: update it in place
+            float pe = ad.ep[ii], me = ad.em[ii], ve = ad.ev[ii];
+            adam_one(pe, me, ve, ge, (float)*ad.step, ad);
+            ad.em[ii] = me;
+            ad.ev[ii] = ve;
+            ad.ep[ii] = pe;
+        }
     }
 }
 
@@ -1849,13 +1869,13 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
             binst[b] = i;
         }
     }
-    VP_HIP(P.inst.reserve(sizeof(InstDesc) * n));
-    VP_HIP(P.blk_tiles.reserve(sizeof(int64_t) * (tblocks + 1)));
-    VP_HIP(P.blk_inst0.reserve(sizeof(int) * tblocks));
-    VP_HIP(P.cblk_inst.reserve(sizeof(int) * (size_t)cblocks));
+    VP_ALLOC(P.inst.reserve(sizeof(InstDesc) * n));
+    VP_ALLOC(P.blk_tiles.reserve(sizeof(int64_t) * (tblocks + 1)));
+    VP_ALLOC(P.blk_inst0.reserve(sizeof(int) * tblocks));
+    VP_ALLOC(P.cblk_inst.reserve(sizeof(int) * (size_t)cblocks));
     if (rblocks) {
-        VP_HIP(P.rblk_inst.reserve(sizeof(int) * (size_t)rblocks));
-        VP_HIP(P.apart.reserve(sizeof(float) * (size_t)n_apart));
+        VP_ALLOC(P.rblk_inst.reserve(sizeof(int) * (size_t)rblocks));
+        VP_ALLOC(P.apart.reserve(sizeof(float) * (size_t)n_apart));
         std::vector<int> rinst((size_t)rblocks);
         for (int i = 0; i < n; ++i)
             if (D[i].path == kPathGeneric)
@@ -1863,15 +1883,15 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         VP_HIP(hipMemcpy(P.rblk_inst.ptr, rinst.data(), sizeof(int) * (size_t)rblocks, hipMemcpyHostToDevice));
     }
     P.rblocks = rblocks;
-    VP_HIP(P.ubuf.reserve(sizeof(float2) * (size_t)ubase));
-    VP_HIP(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)grows));
-    VP_HIP(P.lpart.reserve(sizeof(double) * 4 * (size_t)lrows));
-    if (nh == 2) VP_HIP(P.ebuf.reserve(sizeof(float) * (size_t)ubase));
-    if (tune.store_activations) VP_HIP(P.act.reserve(sizeof(float) * (size_t)tiles * L * kActTile));
+    VP_ALLOC(P.ubuf.reserve(sizeof(float2) * (size_t)ubase));
+    VP_ALLOC(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)grows));
+    VP_ALLOC(P.lpart.reserve(sizeof(double) * 4 * (size_t)lrows));
+    if (nh == 2) VP_ALLOC(P.ebuf.reserve(sizeof(float) * (size_t)ubase));
+    if (tune.store_activations) VP_ALLOC(P.act.reserve(sizeof(float) * (size_t)tiles * L * kActTile));
     if (n_slots) {
-        VP_HIP(P.dpts.reserve(sizeof(float2) * (size_t)n_dpts));
-        VP_HIP(P.abuf.reserve(sizeof(float2) * (size_t)n_slots));
-        if (nh == 2) VP_HIP(P.eabuf.reserve(sizeof(float) * (size_t)n_slots));
+        VP_ALLOC(P.dpts.reserve(sizeof(float2) * (size_t)n_dpts));
+        VP_ALLOC(P.abuf.reserve(sizeof(float2) * (size_t)n_slots));
+        if (nh == 2) VP_ALLOC(P.eabuf.reserve(sizeof(float) * (size_t)n_slots));
     }
     for (int i = 0; i < n; ++i) {
         const vpinn_problem *p = probs[i];
@@ -2055,6 +2075,9 @@ vpinn_status fused_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const 
     if (!c->valid || c->n_bnd != p->n_bnd || c->n_sen != p->n_sen || c->pts != p->pts.ptr || c->L != cfg->n_hidden ||
         c->H != cfg->width || c->norm != cfg->loss_norm || c->tau != cfg->tau || c->gamma != cfg->gamma ||
         c->nh != (cfg->n_outputs == 2 ? 2 : 1) || c->gen != p->gen) {
+        // the plan's device buffers are rewritten in place (descriptor copies on the null stream), so the
+        // kernels of earlier calls, on whatever stream, must have finished reading them
+        if (c->valid) VP_HIP(hipDeviceSynchronize());
         c->valid = false;
         vpinn_problem *one[1] = {p};
         vpinn_status st = build_plan(one, 1, cfg, p->device, kDefaultTuning, c->plan);
@@ -2141,15 +2164,22 @@ vpinn_status batch_loss_and_grad(vpinn_batch *b, const float *d_params, const fl
 }
 
 vpinn_status batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr, float b1,
-                        float b2, float eps, float *d_losses, hipStream_t s) {
+                        float b2, float eps, float *d_losses, float *d_eps, float *d_eps_m, float *d_eps_v,
+                        hipStream_t s) {
     vpinn_status fr = batch_fresh(b);
     if (fr) return fr;
-    AdamArgs ad{d_params, d_m, d_v, d_step, lr, b1, b2, eps};
-    return run_plan(b->plan, d_params, nullptr, true, d_losses, nullptr, nullptr, ad, d_step, b->prof, s);
+    if (d_eps)
+        for (const vpinn_problem *p : b->probs)
+            if (p->folded() || p->vardiff)
+                return fail(VPINN_E_INVALID, "a problem assembled with fixed or space-dependent "
+                                             "convection-diffusion coefficients takes no eps");
+    AdamArgs ad{d_params, d_m, d_v, d_step, lr, b1, b2, eps, d_eps, d_eps_m, d_eps_v};
+    return run_plan(b->plan, d_params, d_eps, true, d_losses, nullptr, nullptr, ad, d_step, b->prof, s);
 }
 
 vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
-                           float b1, float b2, float eps, float *d_losses, hipStream_t s) {
+                           float b1, float b2, float eps, float *d_losses, float *d_eps, float *d_eps_m,
+                           float *d_eps_v, hipStream_t s) {
     if (!s) return fail(VPINN_E_INVALID, "capture needs a non-null stream");
     vpinn_status fr = batch_fresh(b);
     if (fr) return fr;
@@ -2167,7 +2197,7 @@ vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d
         b->prof[i] = nullptr;
     }
     VP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    vpinn_status st = batch_step(b, d_params, d_m, d_v, d_step, lr, b1, b2, eps, d_losses, s);
+    vpinn_status st = batch_step(b, d_params, d_m, d_v, d_step, lr, b1, b2, eps, d_losses, d_eps, d_eps_m, d_eps_v, s);
     for (int i = 0; i < VPINN_PROFILE_EVENTS; ++i) b->prof[i] = saved[i];
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
@@ -2219,16 +2249,19 @@ vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps,
     const FusedPlan &P0 = b->plan;
     const bool has_fast = P0.cpath_blocks[kPathFast] > 0;
     const bool has_rows = P0.cpath_blocks[kPathRows1] + P0.cpath_blocks[kPathRows2] + P0.cpath_blocks[kPathRows4] > 0;
+    // storing the activations is a candidate only while their buffer fits the last-level cache: beyond
+    // it the round trip is HBM traffic, and the reverse sweep recomputes them instead
+    const bool may_store = (size_t)P0.tiles * P0.L * kActTile * sizeof(float) <= kActStoreMaxBytes;
     std::vector<vpinn_tuning> cand;
     for (int fw : {8, 12, 16})
         for (int cs = 0; cs <= (has_fast ? 2 : 0); ++cs)
             for (int rp : {2, 4, 8})
                 for (int sa : {0, 1})
-                    if (has_rows || rp == 4) cand.push_back(vpinn_tuning{fw, cs, rp, sa});
+                    if ((has_rows || rp == 4) && (sa == 0 || may_store)) cand.push_back(vpinn_tuning{fw, cs, rp, sa});
     const int n = (int)b->probs.size();
     DevBuf losses, grads;
-    VP_HIP(losses.reserve(sizeof(float) * 4 * (size_t)n));
-    VP_HIP(grads.reserve(sizeof(float) * (size_t)P0.npf * (size_t)n));
+    VP_ALLOC(losses.reserve(sizeof(float) * 4 * (size_t)n));
+    VP_ALLOC(grads.reserve(sizeof(float) * (size_t)P0.npf * (size_t)n));
     std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
     for (auto &e : ev) VP_HIP(hipEventCreate(&e));
     auto free_events = [&]() {
@@ -2238,6 +2271,8 @@ vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps,
     vpinn_tuning best = P0.tune;
     float best_ms = -1.f;
     AdamArgs none{};
+    vpinn_status first_err = VPINN_OK;
+    std::string first_msg;
     for (const vpinn_tuning &c : cand) {
         FusedPlan P;
         vpinn_status st = build_plan(b->probs.data(), n, &b->cfg, b->device, c, P);
@@ -2250,6 +2285,16 @@ vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps,
             if (!st && hipEventRecord(ev[2 * r + 1], s) != hipSuccess) st = fail(VPINN_E_DEVICE, "hipEventRecord failed");
         }
         if (!st && hipStreamSynchronize(s) != hipSuccess) st = fail(VPINN_E_DEVICE, "hipStreamSynchronize failed");
+        if (st == VPINN_E_NOMEM) {
+            // a candidate whose plan does not fit (stored activations of a large batch) is skipped; the
+            // failed allocation's error is cleared so later launches do not report it
+            (void)hipGetLastError();
+            if (!first_err) {
+                first_err = st;
+                first_msg = vpinn_last_error();
+            }
+            continue;
+        }
         if (st) {
             free_events();
             return st;
@@ -2264,6 +2309,7 @@ vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps,
         }
     }
     free_events();
+    if (best_ms < 0.f) return fail(first_err ? first_err : VPINN_E_NOMEM, "no tuning fits: " + first_msg);
     vpinn_status st = batch_set_tuning(b, &best);
     if (st) return st;
     if (best_out) *best_out = best;

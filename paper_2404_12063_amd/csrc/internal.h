@@ -46,6 +46,15 @@ vpinn_status fail(vpinn_status code, const std::string &msg);
             return ::vp::fail(VPINN_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// an allocation: running out of device memory is VPINN_E_NOMEM, any other failure VPINN_E_DEVICE
+#define VP_ALLOC(call)                                                                \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return ::vp::fail(e_ == hipErrorOutOfMemory ? VPINN_E_NOMEM : VPINN_E_DEVICE, \
+                              std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
 // device buffer that frees itself --------------------------------------------
 struct DevBuf {
     void *ptr = nullptr;
@@ -168,9 +177,11 @@ vpinn_status batch_create(int32_t n, vpinn_problem *const *problems, const vpinn
 vpinn_status batch_loss_and_grad(vpinn_batch *b, const float *d_params, const float *d_eps, float *d_losses,
                                  float *d_grads, float *d_grad_eps, hipStream_t s);
 vpinn_status batch_step(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr, float b1,
-                        float b2, float eps, float *d_losses, hipStream_t s);
+                        float b2, float eps, float *d_losses, float *d_eps, float *d_eps_m, float *d_eps_v,
+                        hipStream_t s);
 vpinn_status batch_capture(vpinn_batch *b, float *d_params, float *d_m, float *d_v, int64_t *d_step, float lr,
-                           float b1, float b2, float eps, float *d_losses, hipStream_t s);
+                           float b1, float b2, float eps, float *d_losses, float *d_eps, float *d_eps_m,
+                           float *d_eps_v, hipStream_t s);
 vpinn_status batch_replay(vpinn_batch *b, hipStream_t s);
 void batch_set_profile_events(vpinn_batch *b, void *const *events);
 vpinn_status batch_get_tuning(const vpinn_batch *b, vpinn_tuning *out);

@@ -112,9 +112,11 @@ _SIGNATURES = {
     "vpinn_batch_loss_and_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_void_p, C.c_void_p]),
     "vpinn_batch_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
-                                     C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
+                                     C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
     "vpinn_batch_capture": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
-                                        C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
+                                        C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]),
     "vpinn_batch_replay": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "vpinn_batch_free": (None, [C.c_void_p]),
     "vpinn_batch_get_tuning": (C.c_int32, [C.c_void_p, C.POINTER(vpinn_tuning)]),
@@ -355,16 +357,17 @@ def vpinn_batch_loss_and_grad(b: Batch, params, eps=None, losses=None, grads=Non
 
 
 def vpinn_batch_step(b: Batch, params, m, v, step, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
-                     eps: float = 1e-8, losses=None, stream=None):
-    """step: device int64 tensor of one element (incremented by the call)."""
+                     eps: float = 1e-8, losses=None, stream=None, diff=None, diff_m=None, diff_v=None):
+    """step: device int64 tensor of one element (incremented by the call).  diff, diff_m, diff_v: device [n]
+    float tensors (all or none): each problem's trainable diffusion coefficient and its Adam moments."""
     _check(lib().vpinn_batch_step(b.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(step), lr, beta1, beta2, eps,
-                                  _ptr(losses), _stream(stream)))
+                                  _ptr(losses), _ptr(diff), _ptr(diff_m), _ptr(diff_v), _stream(stream)))
 
 
 def vpinn_batch_capture(b: Batch, params, m, v, step, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
-                        eps: float = 1e-8, losses=None, stream=None):
+                        eps: float = 1e-8, losses=None, stream=None, diff=None, diff_m=None, diff_v=None):
     _check(lib().vpinn_batch_capture(b.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(step), lr, beta1, beta2, eps,
-                                     _ptr(losses), _stream(stream)))
+                                     _ptr(losses), _ptr(diff), _ptr(diff_m), _ptr(diff_v), _stream(stream)))
 
 
 def vpinn_batch_replay(b: Batch, stream=None):

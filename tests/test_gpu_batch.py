@@ -164,33 +164,97 @@ def test_batch_of_one_equals_single(V, torch):
     np.testing.assert_array_equal(gb[0].cpu().numpy(), gs.cpu().numpy())
 
 
-@pytest.mark.slow
-def test_c5_batched_workload_sampled(V, torch):
-    """The 64-instance batched workload at full size; the three smallest instances against the oracle
-    and every instance against its own single-problem run (loss)."""
+def _oracle_all(probs, thetas, want_grad=True):
+    """The FP64 oracle for every instance, one instance per task on a pool of host threads (its C calls
+    release the interpreter lock and it holds no global state, so the threads run in parallel)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    order = sorted(range(len(probs)), key=lambda i: -probs[i].n_points)
+
+    def one(i):
+        return O.problem_loss_grad(probs[i], O.assemble_problem(probs[i]), thetas[i], want_grad=want_grad)
+
+    with ThreadPoolExecutor(max_workers=max(1, min(16, n))) as ex:
+        res = dict(zip(order, ex.map(one, order)))
+    return [res[i] for i in range(len(probs))]
+
+
+@pytest.fixture(scope="module")
+def c5_oracle():
+    """The 64-instance batched workload, its parameters (Glorot weights, U(+-0.1) biases) and the oracle's
+    loss and gradient of every instance at them."""
     probs = gen.batched_instances(64, seed=0)
+    th = _params(probs)
+    return probs, th, _oracle_all(probs, th)
+
+
+@pytest.mark.slow
+def test_c5_batched_workload_full(V, torch, c5_oracle):
+    """The 64-instance batched workload at full size (12,962,384 quadrature points): every instance's loss
+    (1e-5 relative) and gradient (1e-4 relative L2) against the FP64 oracle, and every instance's loss
+    against its own single-problem run."""
+    probs, th, refs = c5_oracle
     gp = [_gpu(V, p) for p in probs]
     b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 0.0))
     n = V.vpinn_n_params(30, 3)
-    th = _params(probs)
     dev = torch.device("cuda:0")
     T = torch.tensor(th, dtype=torch.float32, device=dev)
-    losses = torch.zeros((64, 4), device=dev)
-    grads = torch.zeros((64, n), device=dev)
-    V.vpinn_batch_loss_and_grad(b, T, losses=losses, grads=grads)
-    torch.cuda.synchronize()
-    L = losses.cpu().double().numpy()
-    Gd = grads.cpu().double().numpy()
+    L, Gd = _batch_eval(V, torch, b, T, 64, n)
     l1 = torch.zeros(4, device=dev)
     for i, p in enumerate(gp):
         V.vpinn_loss_and_grad(p, V.loss_cfg(30, 3, 10.0, 0.0), T[i].contiguous(), loss=l1)
         torch.cuda.synchronize()
         assert abs(L[i, 0] - float(l1[0])) / abs(float(l1[0])) < 1e-5, i
-    for i in np.argsort([p.n_points for p in probs])[:3]:
-        ref = O.problem_loss_grad(probs[i], O.assemble_problem(probs[i]), th[i])
-        assert abs(L[i, 0] - ref.loss[0]) / ref.loss[0] < 1e-5
-        assert np.linalg.norm(Gd[i] - ref.grad) / np.linalg.norm(ref.grad) < 1e-4
+    lerr = [abs(L[i, 0] - refs[i].loss[0]) / refs[i].loss[0] for i in range(64)]
+    gerr = [np.linalg.norm(Gd[i] - refs[i].grad) / np.linalg.norm(refs[i].grad) for i in range(64)]
+    print(f"c5: max loss rel err {max(lerr):.2e}, max grad rel L2 err {max(gerr):.2e}")
+    assert max(lerr) < 1e-5, int(np.argmax(lerr))
+    assert max(gerr) < 1e-4, int(np.argmax(gerr))
+
+
+@pytest.mark.slow
+def test_c5_in_the_bench_launch_configuration(V, torch, c5_oracle):
+    """C5 as bench.py times it: autotuned, one batched Adam step captured in a HIP graph and replayed.  The
+    losses the first replay reports are the oracle's at the starting parameters, and its update of every
+    instance's weights is the oracle's Adam step from the oracle's gradient (Kingma-Ba, lr 1e-3)."""
+    from oracle import oracle as O
+    probs, th, refs = c5_oracle
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 0.0))
+    dev = torch.device("cuda:0")
+    T = torch.tensor(th, dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        V.vpinn_batch_autotune(b, T, reps=1, stream=s)
+    M, Vv = torch.zeros_like(T), torch.zeros_like(T)
+    step = torch.zeros(1, dtype=torch.int64, device=dev)
+    losses = torch.zeros((64, 4), device=dev)
+    V.vpinn_batch_capture(b, T, M, Vv, step, lr=1e-3, losses=losses, stream=s)
+    th32 = T.cpu().double().numpy()
+    V.vpinn_batch_replay(b, stream=s)
+    s.synchronize()
+    assert int(step.item()) == 1
+    L = losses.cpu().double().numpy()
+    got, gm, gv = (x.cpu().double().numpy() for x in (T, M, Vv))
+    for i in range(64):
+        assert abs(L[i, 0] - refs[i].loss[0]) / refs[i].loss[0] < 1e-5, i
+        g = refs[i].grad
+        t_ref, m_ref, v_ref = th32[i].copy(), np.zeros_like(g), np.zeros_like(g)
+        O.adam(t_ref, g, m_ref, v_ref, 1, lr=1e-3)
+        # the moments carry the gradient itself: its tolerance
+        assert np.linalg.norm(gm[i] - m_ref) / np.linalg.norm(m_ref) < 1e-4, i
+        assert np.linalg.norm(gv[i] - v_ref) / np.linalg.norm(v_ref) < 2e-4, i
+        # the first step is lr * g / (|g| + eps), about lr * sign(g): where |g| is not below the FP32
+        # gradient's own error the step taken must be the oracle's
+        big = np.abs(g) > 1e-4 * np.linalg.norm(g)
+        assert big.mean() > 0.95, i
+        np.testing.assert_allclose((got[i] - th32[i])[big], (t_ref - th32[i])[big], rtol=0,
+                                   atol=2e-5 * 1e-3 + 1e-7, err_msg=f"instance {i}")
 
 
 def _all_shapes():
@@ -380,5 +444,125 @@ def test_c2_in_the_bench_launch_configuration(V, torch):
     V.vpinn_batch_replay(b, stream=s)
     s.synchronize()
     ref2 = O.problem_loss_grad(prob, asm, th_after, want_grad=False)
+    assert abs(losses[0, 0].item() - ref2.loss[0]) / ref2.loss[0] < 1e-5
+    assert int(step.item()) == 2
+
+
+def test_batch_step_trains_eps_like_single_problem(V, torch):
+    """The batched step with a trainable eps per instance (the inverse problem of Sec. 4.7.1): each step's
+    losses, the weights and eps after it match the single-problem loss and gradient (with dL/deps) followed by
+    Adam on the weights and on eps, instance by instance."""
+    probs = _mixed_instances()[:4]
+    gp = [_gpu(V, p) for p in probs]
+    cfg = V.loss_cfg(30, 3, 10.0, 5.0)
+    b = V.vpinn_batch_create(gp, cfg)
+    n = V.vpinn_n_params(30, 3)
+    th = _params(probs)
+    eps0 = np.array([2.0, 0.7, 1.3, 0.4], dtype=np.float32)
+    dev = torch.device("cuda:0")
+    T = torch.tensor(th, dtype=torch.float32, device=dev)
+    M, Vv = torch.zeros_like(T), torch.zeros_like(T)
+    E = torch.tensor(eps0, device=dev)
+    Em, Ev = torch.zeros_like(E), torch.zeros_like(E)
+    step = torch.zeros(1, dtype=torch.int64, device=dev)
+    losses = torch.zeros((len(probs), 4), device=dev)
+    Ts = [torch.tensor(th[i], dtype=torch.float32, device=dev) for i in range(len(probs))]
+    Ms = [torch.zeros(n, device=dev) for _ in probs]
+    Vs = [torch.zeros(n, device=dev) for _ in probs]
+    Es = [torch.tensor([eps0[i]], device=dev) for i in range(len(probs))]
+    Ems = [torch.zeros(1, device=dev) for _ in probs]
+    Evs = [torch.zeros(1, device=dev) for _ in probs]
+    g, ge, l1 = torch.zeros(n, device=dev), torch.zeros(1, device=dev), torch.zeros(4, device=dev)
+    for t in range(1, 4):
+        V.vpinn_batch_step(b, T, M, Vv, step, lr=1e-3, losses=losses, diff=E, diff_m=Em, diff_v=Ev)
+        torch.cuda.synchronize()
+        for i, p in enumerate(gp):
+            V.vpinn_loss_and_grad(p, cfg, Ts[i], eps=Es[i], loss=l1, grad=g, grad_eps=ge)
+            V.vpinn_adam_step(Ts[i], g, Ms[i], Vs[i], t, lr=1e-3)
+            V.vpinn_adam_step(Es[i], ge, Ems[i], Evs[i], t, lr=1e-3)
+            torch.cuda.synchronize()
+            np.testing.assert_allclose(losses[i].cpu().numpy(), l1.cpu().numpy(), rtol=2e-5)
+    for i in range(len(probs)):
+        np.testing.assert_allclose(T[i].cpu().numpy(), Ts[i].cpu().numpy(), atol=1e-4, rtol=0)
+        assert abs(float(E[i]) - float(Es[i])) < 1e-6, i
+        np.testing.assert_allclose(float(Em[i]), float(Ems[i][0]), rtol=1e-4)
+    # eps moved: three Adam steps of lr 1e-3 each
+    assert np.all(np.abs(E.cpu().numpy() - eps0) > 2e-3)
+
+
+def test_batch_eps_arguments_are_checked(V, torch):
+    """eps and its two moments go together, and problems with folded coefficients take no eps."""
+    probs = _mixed_instances()[:2]
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
+    dev = torch.device("cuda:0")
+    T = torch.tensor(_params(probs), dtype=torch.float32, device=dev)
+    M, Vv = torch.zeros_like(T), torch.zeros_like(T)
+    S = torch.zeros(1, dtype=torch.int64, device=dev)
+    E = torch.ones(2, device=dev)
+    for kw in ({"diff": E}, {"diff": E, "diff_m": E.clone()}, {"diff_m": E, "diff_v": E.clone()}):
+        with pytest.raises(V.VpinnError) as ei:
+            V.vpinn_batch_step(b, T, M, Vv, S, **kw)
+        assert ei.value.code == V.VPINN_E_INVALID
+    pr = probs[0]
+    pc = V.vpinn_assemble(pr.mesh.xy, pr.mesh.quad, pr.quad_order, pr.test_order, pr.f_amp, pr.f_kx, pr.f_ky,
+                          cd=(1.0, 0.1, 0.0))
+    V.vpinn_set_boundary(pc, pr.bnd_xy, pr.bnd_g)
+    bc = V.vpinn_batch_create([pc], V.loss_cfg(30, 3, 10.0, 0.0))
+    T1 = T[:1].contiguous()
+    e1 = torch.ones(1, device=dev)
+    with pytest.raises(V.VpinnError) as ei:
+        V.vpinn_batch_step(bc, T1, torch.zeros_like(T1), torch.zeros_like(T1), S, diff=e1,
+                           diff_m=torch.zeros(1, device=dev), diff_v=torch.zeros(1, device=dev))
+    assert ei.value.code == V.VPINN_E_INVALID
+    assert int(S.item()) == 0  # nothing ran
+
+
+@pytest.mark.slow
+def test_c4_in_the_bench_launch_configuration(V, torch):
+    """C4 (the inverse problem: eps trained beside the weights, 4,096 elements, 1,000 noisy sensors) as
+    bench.py times it: a batch of one, autotuned, one step captured in a HIP graph with eps, its moments
+    and the weights all updated by it.  The first replay's loss is the oracle's at (theta, eps = 2), its
+    update of the weights and of eps is the oracle's Adam step from the oracle's dL/dtheta and dL/deps, and
+    the second replay's loss is the oracle's at the updated (theta, eps)."""
+    from oracle import oracle as O
+    prob = gen.config_c4()
+    theta = prob.params()
+    p = V.assemble_problem(prob)
+    b = V.vpinn_batch_create([p], V.loss_cfg(prob.width, prob.n_hidden, prob.tau, prob.gamma))
+    dev = torch.device("cuda:0")
+    th = torch.tensor(theta, dtype=torch.float32, device=dev).reshape(1, -1).contiguous()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        V.vpinn_batch_autotune(b, th, reps=2, stream=s)
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    E = torch.tensor([prob.eps_init], dtype=torch.float32, device=dev)
+    Em, Ev = torch.zeros_like(E), torch.zeros_like(E)
+    step = torch.zeros(1, dtype=torch.int64, device=dev)
+    losses = torch.zeros((1, 4), device=dev)
+    V.vpinn_batch_capture(b, th, m, v, step, lr=1e-3, losses=losses, stream=s, diff=E, diff_m=Em, diff_v=Ev)
+    asm = O.assemble_problem(prob)
+    th32 = th.cpu().double().numpy()[0]
+    V.vpinn_batch_replay(b, stream=s)
+    s.synchronize()
+    ref = O.problem_loss_grad(prob, asm, th32, eps=prob.eps_init)
+    assert abs(losses[0, 0].item() - ref.loss[0]) / ref.loss[0] < 1e-5
+    g = ref.grad
+    t_ref, m_ref, v_ref = th32.copy(), np.zeros_like(g), np.zeros_like(g)
+    O.adam(t_ref, g, m_ref, v_ref, 1, lr=1e-3)
+    got = th.cpu().double().numpy()[0]
+    assert np.linalg.norm(m.cpu().double().numpy()[0] - m_ref) / np.linalg.norm(m_ref) < 1e-4
+    big = np.abs(g) > 1e-4 * np.linalg.norm(g)
+    assert big.mean() > 0.95
+    np.testing.assert_allclose((got - th32)[big], (t_ref - th32)[big], rtol=0, atol=2e-5 * 1e-3 + 1e-7)
+    e_ref, em_ref, ev_ref = np.array([prob.eps_init]), np.zeros(1), np.zeros(1)
+    O.adam(e_ref, np.array([ref.grad_eps]), em_ref, ev_ref, 1, lr=1e-3)
+    np.testing.assert_allclose(float(Em[0]), em_ref[0], rtol=1e-4)
+    np.testing.assert_allclose(float(E[0]), e_ref[0], rtol=0, atol=1e-6)
+    assert float(E[0]) < prob.eps_init  # dL/deps > 0 at eps = 2 > eps_true: the step lowers eps
+    th_after, e_after = got.copy(), float(E[0])
+    V.vpinn_batch_replay(b, stream=s)
+    s.synchronize()
+    ref2 = O.problem_loss_grad(prob, asm, th_after, eps=e_after, want_grad=False)
     assert abs(losses[0, 0].item() - ref2.loss[0]) / ref2.loss[0] < 1e-5
     assert int(step.item()) == 2
