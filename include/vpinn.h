@@ -316,6 +316,28 @@ vpinn_status vpinn_eval_error(int32_t width, int32_t n_hidden, int32_t n_outputs
                               void *stream);
 
 /*
+ * vpinn_eval_error_noalloc -- vpinn_eval_error for callers that cannot allocate
+ * device memory: code under HIP graph capture, serving loops that keep allocation
+ * off the hot path, harnesses that forbid it.  Same arguments, kernels and results
+ * (bitwise) as vpinn_eval_error, but the value pass and the partial sums use a
+ * fixed device array of the library, (4 VPINN_NOALLOC_MAX_POINTS + 16384) bytes
+ * (8.02 MiB), of which every device the library runs on holds its own copy until
+ * the process ends; the call allocates nothing.
+ *  - n above VPINN_NOALLOC_MAX_POINTS: VPINN_E_INVALID, nothing launched (use
+ *    vpinn_eval_error).  Other errors as vpinn_eval_error.
+ *  - The first call on a device looks up the array's address on that device (a
+ *    runtime query, no allocation); make it once before any graph capture.
+ *  - All calls on one device share its array: calls that overlap (different
+ *    streams or threads without ordering between them) race and must be
+ *    serialised by the caller.  The array keeps the last call's contents; each
+ *    call writes every value it reads, so nothing has to be cleared.
+ */
+#define VPINN_NOALLOC_MAX_POINTS 2097152
+vpinn_status vpinn_eval_error_noalloc(int32_t width, int32_t n_hidden, int32_t n_outputs, int32_t output,
+                                      const float *d_params, int64_t n, const float *d_xy, const float *d_ref,
+                                      double *d_out, void *stream);
+
+/*
  * vpinn_adam_step -- Kingma-Ba Adam (Algorithm 1 of that paper, the optimiser of
  * Sec. 4.6.3), in place on n device floats:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

@@ -559,15 +559,45 @@ vpinn_status vpinn_eval_network_heads(int32_t width, int32_t n_hidden, int32_t n
                      d_e, (hipStream_t)stream);
 }
 
-vpinn_status vpinn_eval_error(int32_t width, int32_t n_hidden, int32_t n_outputs, int32_t output,
-                              const float *d_params, int64_t n, const float *d_xy, const float *d_ref, double *d_out,
-                              void *stream) {
+static vpinn_status check_eval_error(int32_t width, int32_t n_hidden, int32_t n_outputs, int32_t output,
+                                     const float *d_params, int64_t n, const float *d_xy, const float *d_ref,
+                                     double *d_out) {
     using namespace vp;
     if (width < 1 || width > VPINN_MAX_WIDTH || n_hidden < 1 || n_hidden > VPINN_MAX_HIDDEN)
         return fail(VPINN_E_UNSUPPORTED, "width or n_hidden out of range");
     if (n_outputs < 1 || n_outputs > 2 || output < 0 || output >= n_outputs)
         return fail(VPINN_E_INVALID, "n_outputs must be 1 or 2 and output in 0 .. n_outputs - 1");
     if (!d_params || !d_xy || !d_ref || !d_out || n < 1) return fail(VPINN_E_INVALID, "null argument or n < 1");
+    return VPINN_OK;
+}
+
+vpinn_status vpinn_eval_error_noalloc(int32_t width, int32_t n_hidden, int32_t n_outputs, int32_t output,
+                                      const float *d_params, int64_t n, const float *d_xy, const float *d_ref,
+                                      double *d_out, void *stream) {
+    using namespace vp;
+    vpinn_status st = check_eval_error(width, n_hidden, n_outputs, output, d_params, n, d_xy, d_ref, d_out);
+    if (st) return st;
+    if (n > VPINN_NOALLOC_MAX_POINTS)
+        return fail(VPINN_E_INVALID, "n = " + std::to_string(n) + " exceeds the fixed workspace of " +
+                                         std::to_string((int64_t)VPINN_NOALLOC_MAX_POINTS) +
+                                         " points (VPINN_NOALLOC_MAX_POINTS): use vpinn_eval_error");
+    float *pv = nullptr;
+    double *part = nullptr;
+    st = noalloc_workspace(&pv, &part);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = eval_mfma(n_hidden, width, n_outputs, d_params, n, reinterpret_cast<const float2 *>(d_xy),
+                   output == 0 ? pv : nullptr, nullptr, nullptr, output == 1 ? pv : nullptr, s);
+    if (st) return st;
+    return error_stats(n, pv, d_ref, part, d_out, s);
+}
+
+vpinn_status vpinn_eval_error(int32_t width, int32_t n_hidden, int32_t n_outputs, int32_t output,
+                              const float *d_params, int64_t n, const float *d_xy, const float *d_ref, double *d_out,
+                              void *stream) {
+    using namespace vp;
+    vpinn_status cst = check_eval_error(width, n_hidden, n_outputs, output, d_params, n, d_xy, d_ref, d_out);
+    if (cst) return cst;
     static thread_local DevBuf pbuf, part;
     static thread_local int ws_dev = -1;
     int dev = 0;

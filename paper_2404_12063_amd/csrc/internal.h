@@ -165,6 +165,9 @@ vpinn_status eval_mfma(int L, int H, int nh, const float *d_params, int64_t n, c
 // mean |p - ref|, max |p - ref|, ||p - ref|| / ||ref|| -> d_out[3]; d_part [512][4] workspace
 vpinn_status error_stats(int64_t n, const float *d_p, const float *d_ref, double *d_part, double *d_out,
                          hipStream_t s);
+// the fixed workspace of the allocation-free error call on the current device: room for
+// VPINN_NOALLOC_MAX_POINTS values and error_stats' partials (looked up, never allocated)
+vpinn_status noalloc_workspace(float **values, double **partials);
 vpinn_status plain_loss_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
                              const float *d_eps, float *d_loss, float *d_grad, float *d_grad_eps,
                              float *d_R_out, hipStream_t s);

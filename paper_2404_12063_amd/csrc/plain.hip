@@ -9,6 +9,8 @@
 //                  weight-gradient partials
 //   k_final_*      fixed-order reductions of the loss and gradient partials
 // One lane owns one point; weights are wavefront-uniform (scalar loads).
+#include <mutex>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -562,6 +564,37 @@ vpinn_status error_stats(int64_t n, const float *d_p, const float *d_ref, double
     k_err_partial<<<blocks, kErrThreads, 0, s>>>(d_p, d_ref, n, d_part);
     k_err_final<<<1, 64, 0, s>>>(d_part, blocks, n, d_out);
     VP_HIP(hipGetLastError());
+    return VPINN_OK;
+}
+
+// workspace of the allocation-free prediction error: the network values of up to
+// VPINN_NOALLOC_MAX_POINTS points, then the block partials of error_stats.  A file-scope
+// device array: every device the library runs on holds its own copy, at its own address,
+// until the process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: only the address hipGetSymbolAddress returns for the current device is
+// passed to kernels.
+constexpr size_t kNoAllocValueBytes = sizeof(float) * (size_t)VPINN_NOALLOC_MAX_POINTS;
+constexpr size_t kNoAllocBytes = kNoAllocValueBytes + sizeof(double) * 4 * kErrMaxBlocks;
+static_assert(kNoAllocValueBytes % sizeof(double) == 0, "partials must stay 8-byte aligned");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+vpinn_status noalloc_workspace(float **values, double **partials) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    VP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(VPINN_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // once per device, with that device current
+        void *p = nullptr;
+        VP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(VPINN_E_DEVICE, "hipGetSymbolAddress returned no address for the workspace");
+        addr[dev] = p;
+    }
+    *values = static_cast<float *>(addr[dev]);
+    *partials = reinterpret_cast<double *>(static_cast<unsigned char *>(addr[dev]) + kNoAllocValueBytes);
     return VPINN_OK;
 }
 

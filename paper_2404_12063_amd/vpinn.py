@@ -24,6 +24,7 @@ VPINN_E_NOMEM = -3
 VPINN_E_NONFINITE = -4
 VPINN_E_DEVICE = -5
 VPINN_E_UNSUPPORTED = -6
+VPINN_NOALLOC_MAX_POINTS = 2097152
 
 VPINN_FORCING_CALLBACK = 0
 VPINN_FORCING_SINSIN = 1
@@ -105,6 +106,8 @@ _SIGNATURES = {
                                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vpinn_eval_error": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vpinn_eval_error_noalloc": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vpinn_adam_step": (C.c_int32, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]),
     "vpinn_batch_create": (C.c_int32, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(vpinn_loss_cfg),
@@ -323,6 +326,15 @@ def vpinn_eval_error(width: int, n_hidden: int, params, xy, ref, out, n_outputs:
     """out: device float64 tensor of 3: mean |p - ref|, max |p - ref|, relative L2 error."""
     _check(lib().vpinn_eval_error(width, n_hidden, n_outputs, output, _ptr(params), xy.shape[0], _ptr(xy), _ptr(ref),
                                   _ptr(out), _stream(stream)))
+
+
+def vpinn_eval_error_noalloc(width: int, n_hidden: int, params, xy, ref, out, n_outputs: int = 1, output: int = 0,
+                             stream=None, n=None):
+    """As vpinn_eval_error, with the library's fixed workspace (n <= VPINN_NOALLOC_MAX_POINTS); n defaults to
+    the number of points in xy."""
+    _check(lib().vpinn_eval_error_noalloc(width, n_hidden, n_outputs, output, _ptr(params),
+                                          xy.shape[0] if n is None else n, _ptr(xy), _ptr(ref), _ptr(out),
+                                          _stream(stream)))
 
 
 def vpinn_adam_step(params, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
