@@ -80,13 +80,18 @@ def kernel_work(prob, matrix_free: bool = False, n_interior=None):
         contract = {"flop": 2.0 * prob.n_points * (7 if two else 4) * nt,
                     "bytes": (12.0 if two else 8.0) * nt * prob.n_points + 4.0 * nt * prob.n_elem
                     + (24.0 if two else 16.0) * prob.n_points}
-    return {
+    out = {
         "k_fwd": {"flop": 2.0 * (ni * (2 * H + 3 * (L - 1) * H * H + 2 * H + (H if two else 0))
                                  + n_extra * (3 * H + (L - 1) * H * H))},
         "k_contract": contract,
         "k_bwd": {"flop": 2.0 * (ni * (2 * H + 6 * (L - 1) * H * H + 4 * H + (2 * H if two else 0))
                                  + n_extra * (3 * H + 2 * (L - 1) * H * H))},
     }
+    # the one-pass kernel does all three; it reads G, F and the points once and keeps the rest on chip
+    out["k_step"] = {"flop": out["k_fwd"]["flop"] + contract["flop"] + out["k_bwd"]["flop"],
+                     "bytes": 8.0 * nt * prob.n_points + 4.0 * nt * prob.n_elem + 8.0 * prob.n_points
+                     + 12.0 * n_extra}
+    return out
 
 
 def flops_per_epoch(prob) -> float:
@@ -185,7 +190,7 @@ def traffic_from_profile(workload: str, kernel: str, tuning=None):
         return None
     # only the tuning fields that change the kernel's own memory traffic must agree: forward wavefronts and
     # stored activations for k_fwd, stored activations for k_bwd, chunking and rows per pass for the contraction
-    fields = {"k_fwd": (0, 3), "k_bwd": (3,), "k_contract": (1, 2)}.get(kernel, (0, 1, 2, 3))
+    fields = {"k_fwd": (0, 3), "k_bwd": (3,), "k_contract": (1, 2), "k_step": ()}.get(kernel, (0, 1, 2, 3))
     tr = entry.get("tuning")
     if tuning is not None and tr is not None and any(list(tr)[i] != list(tuning)[i] for i in fields):
         return None
@@ -221,7 +226,8 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str, tuning=None):
     w_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(write)
     out = {}
     # kernel families (template arguments vary with the tuning); a --profile-run bench runs one plan only
-    for name, key in [("k_bwd", "k_bwd<"), ("k_fwd", "k_fwd<"), ("k_contract", "k_contract_"), ("k_eval", "k_eval<")]:
+    for name, key in [("k_bwd", "k_bwd<"), ("k_fwd", "k_fwd<"), ("k_contract", "k_contract_"), ("k_eval", "k_eval<"),
+                      ("k_step", "k_step<")]:
         fk = sorted(v for k, vs in fetch.items() if key in k for v in vs)
         wk = sorted(v for k, vs in write.items() if key in k for v in vs)
         if not fk or not wk:
@@ -336,11 +342,30 @@ def profile_batch_kernels(V, torch, b, s, T, M, Vv, step, losses, n_steps: int, 
         e1.record(s)
     torch.cuda.synchronize()
     over = sum(e0.elapsed_time(e1) for e0, e1 in empty) / n_steps
-    out = {name: max(0.0, sum(e[k].elapsed_time(e[k + 1]) for e in pev) / n_steps - over)
-           for k, name in enumerate(["k_fwd", "k_contract", "k_bwd", "k_fused_final"])}
+    ms = [max(0.0, sum(e[k].elapsed_time(e[k + 1]) for e in pev) / n_steps - over) for k in range(NE - 1)]
+    if V.vpinn_batch_get_tuning(b)[4]:
+        # the one-pass step: its kernel between the first two events, the reduction between the last two
+        out = {"k_step": ms[0], "k_fused_final": ms[3]}
+    else:
+        out = dict(zip(["k_fwd", "k_contract", "k_bwd", "k_fused_final"], ms))
     out["steps"] = n_steps
     out["event_overhead_ms"] = over
     return out
+
+
+def kernel_table(work, kms, extra=""):
+    """Per-kernel rates of the step's kernels (those kms times) and the dominant one."""
+    names = [k for k in ("k_step", "k_fwd", "k_contract", "k_bwd") if k in kms]
+    kernels = {}
+    for name in names:
+        ent = {"ms": round(kms[name], 5), "tflops": round(work[name]["flop"] / (kms[name] * 1e-3) / 1e12, 3)}
+        ent["frac_fp32_peak"] = round(ent["tflops"] / PEAK_FP32_TFLOPS, 4)
+        if "bytes" in work[name]:
+            ent["gbs"] = round(work[name]["bytes"] / (kms[name] * 1e-3) / 1e9, 1)
+            ent["frac_hbm_peak"] = round(ent["gbs"] / PEAK_HBM_GBS, 4)
+        kernels[name] = ent
+    kernels["k_fused_final"] = {"ms": round(kms["k_fused_final"], 5), "note": "reduction + Adam" + extra}
+    return kernels, max(names, key=lambda k: kms[k])
 
 
 def tune_batch(V, b, params, stream, fixed, reps):
@@ -546,15 +571,7 @@ def bench_batched(args, V, torch, gen):
             for key, val in w.items():
                 work.setdefault(name, {}).setdefault(key, 0.0)
                 work[name][key] += val
-    kernels = {}
-    for name in ("k_fwd", "k_contract", "k_bwd"):
-        ent = {"ms": round(kms[name], 4), "tflops": round(work[name]["flop"] / (kms[name] * 1e-3) / 1e12, 3)}
-        if "bytes" in work[name]:
-            ent["gbs"] = round(work[name]["bytes"] / (kms[name] * 1e-3) / 1e9, 1)
-            ent["frac_hbm_peak"] = round(ent["gbs"] / PEAK_HBM_GBS, 4)
-        kernels[name] = ent
-    kernels["k_fused_final"] = {"ms": round(kms["k_fused_final"], 4), "note": "reduction + Adam for 64 instances"}
-    dom = max(("k_fwd", "k_contract", "k_bwd"), key=lambda k: kms[k])
+    kernels, dom = kernel_table(work, kms, " for 64 instances")
     dom_tf = work[dom]["flop"] / (kms[dom] * 1e-3) / 1e12
     eps_s = 1e3 / ms
     flops = sum(flops_per_epoch(pr) for pr in probs)
@@ -675,11 +692,11 @@ def main():
                     help="counter runs: time only the tuned batch-of-one plan (no single-problem-API steps, no "
                          "loss check), so every fused kernel in the trace belongs to that plan; implies no CPU baseline")
     ap.add_argument("--tuning", type=lambda t: tuple(int(x) for x in t.split(",")), default=None,
-                    metavar="FWD_WAVES,CHUNK_SHIFT,ROWS_PER_PASS[,STORE_ACTIVATIONS]",
+                    metavar="FWD_WAVES,CHUNK_SHIFT,ROWS_PER_PASS[,STORE_ACTIVATIONS[,ONE_PASS]]",
                     help="use this tile-shape tuning instead of autotuning (profiling runs)")
     args = ap.parse_args()
-    if args.tuning is not None and len(args.tuning) not in (3, 4):
-        ap.error("--tuning takes 3 or 4 comma-separated integers")
+    if args.tuning is not None and len(args.tuning) not in (3, 4, 5):
+        ap.error("--tuning takes 3 to 5 comma-separated integers")
     if args.steps < 1 or args.warmup < 0:
         ap.error("--steps must be at least 1 and --warmup at least 0")
     if args.traffic_from:
@@ -899,16 +916,7 @@ def bench_single(args, V, torch, gen):
     kernels = {}
     if fused:
         km = res["kernel_ms"]
-        for name in ("k_fwd", "k_contract", "k_bwd"):
-            k_ms = km[name]
-            ent = {"ms": round(k_ms, 5), "tflops": round(work[name]["flop"] / (k_ms * 1e-3) / 1e12, 3)}
-            ent["frac_fp32_peak"] = round(ent["tflops"] / PEAK_FP32_TFLOPS, 4)
-            if "bytes" in work[name]:
-                ent["gbs"] = round(work[name]["bytes"] / (k_ms * 1e-3) / 1e9, 1)
-                ent["frac_hbm_peak"] = round(ent["gbs"] / PEAK_HBM_GBS, 4)
-            kernels[name] = ent
-        kernels["k_fused_final"] = {"ms": round(km["k_fused_final"], 5), "note": "reduction + Adam"}
-        dom = max(("k_fwd", "k_contract", "k_bwd"), key=lambda k: km[k])
+        kernels, dom = kernel_table(work, km)
         k_ms = km[dom]
         if dom == "k_contract" and mf:
             achieved = work[dom]["flop"] / (k_ms * 1e-3) / 1e12

@@ -434,13 +434,23 @@ void vpinn_batch_free(vpinn_batch *b);
  *                  (tanh included); 1: the forward pass stores them (L x 2 KB per
  *                  16 points of device memory, held by the plan) and the reverse
  *                  sweep reads them, recomputing only the tangents
- * A new batch starts with {12, 0, 4, 0}.
+ *   one_pass       1: one kernel per step runs the forward pass, the contraction and
+ *                  the reverse sweep (then the reduction): a block owns groups of
+ *                  whole elements (at most 128 points, one 16-point tile per
+ *                  wavefront) and keeps each tile's forward state in registers
+ *                  through the contraction, so nothing is recomputed or stored.
+ *                  The other fields are then ignored (store_activations must be 0).
+ *                  Needs every problem with stored G, N_quad <= 128, N_test <= 32,
+ *                  no shared points and one network output (else
+ *                  VPINN_E_UNSUPPORTED).  0: the four-kernel step.
+ * A new batch starts with {12, 0, 4, 0, 0}.
  */
 typedef struct {
     int32_t fwd_waves;
     int32_t chunk_shift;
     int32_t rows_per_pass;
     int32_t store_activations;
+    int32_t one_pass;
 } vpinn_tuning;
 
 /* The batch's current tuning.  Errors: VPINN_E_INVALID (null argument). */
@@ -455,14 +465,18 @@ vpinn_status vpinn_batch_set_tuning(vpinn_batch *b, const vpinn_tuning *t);
 
 /*
  * vpinn_batch_autotune -- the project's tile-shape autotuner.  Times every
- * tuning that matters for this batch (forward block sizes and storing
- * activations always; contraction chunking only if some problem has small
- * elements; rows per pass only if some problem streams rows) by `reps` loss-and-gradient evaluations at d_params
+ * tuning that matters for this batch (forward block sizes always; storing
+ * activations while they fit the 256 MB last-level cache; contraction chunking
+ * only if some problem has small elements; rows per pass only if some problem
+ * streams rows; the one-pass step where every problem fits it) by `reps`
+ * loss-and-gradient evaluations at d_params
  * (device [n][n_params], not modified) after one warm-up each, keeps the one
- * with the lowest median time, and returns it in *best (may be NULL).
+ * with the lowest median time, and returns it in *best (may be NULL).  A
+ * candidate whose plan does not fit in device memory is skipped.
  * Synchronous on `stream`; allocates scratch outputs and each candidate plan;
  * drops a captured graph like vpinn_batch_set_tuning.  Errors: VPINN_E_INVALID
- * (null batch or params, reps outside 1..100), VPINN_E_NOMEM, VPINN_E_DEVICE.
+ * (null batch or params, reps outside 1..100), VPINN_E_NOMEM (no candidate
+ * fits), VPINN_E_DEVICE.
  */
 vpinn_status vpinn_batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps, vpinn_tuning *best,
                                   void *stream);

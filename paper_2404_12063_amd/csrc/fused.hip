@@ -157,6 +157,7 @@ struct InstDesc {
     // (gblk0 ..), then one per contraction block
     int lrow0, ln_rows;
     int grow0, gblk0, gn_rows;  // gradient partial rows (tile blocks gblk0 ..)
+    int64_t grp0, n_grp;      // one-pass plans: the instance's groups grp0 .. of the global group list
     float two_cv, wb2, ws2;   // 2 c_v, 2 tau / N_D, 2 gamma / N_s
     float tau, gamma;
     double cv;
@@ -201,15 +202,17 @@ struct BwdArgs {
 };
 
 // ---------------------------------------------------------------------------
-// forward through the network for one tile.  If `keep` is non-null the
-// activations a_l and pre-activation tangents p_l (l >= 2) are stored there
-// (layer 1 keeps a_1 only; its tangent is s_1 times a weight column).
+// forward through the network for one tile.  With KEEP the activations a_l and
+// the tangents t_l = s_l p_l (s_l = 1 - a_l^2, p_l = W_l t_{l-1}; l >= 2) are kept
+// for the reverse sweep, which needs exactly these: t_{l-1} is the input of layer
+// l's weight gradient, and s_l sbar_l = tbar_l . t_l (layer 1 keeps a_1 only; its
+// tangent is s_1 times a weight column).
 // ---------------------------------------------------------------------------
 template <int L>
 struct Acts {
     Vec a[L];
-    Vec px[L];  // px[0], py[0] unused (layer 1)
-    Vec py[L];
+    Vec tx[L];  // tx[0], ty[0] unused (layer 1)
+    Vec ty[L];
 };
 
 // activations of one tile in the layout [layer][m][lane][4]: each lane's chained
@@ -219,15 +222,16 @@ constexpr int kActTile = 2 * 64 * 4;  // floats per layer and tile
 constexpr size_t kActStoreMaxBytes = (size_t)256 << 20;
 
 // tanh(x) = 1 - 2 / (1 + e^{2x}): one exponential, one reciprocal and three other
-// operations against five for the sign-split form tanh_f32 (largest error 1.8e-7
-// against 1.3e-7); the limits come out exactly (e = inf gives 1, e = 0 gives -1).
-// Used by the prediction kernel only, so the training kernels keep their rounding.
+// operations against five for the sign-split form tanh_f32 (largest absolute error
+// 1.8e-7 against 1.3e-7); the limits come out exactly (e = inf gives 1, e = 0
+// gives -1).  Every network kernel of this file uses it (the forward and reverse
+// sweeps therefore see the same activations); the plain path keeps tanh_f32.
 __device__ __forceinline__ float tanh_lean(float x) {
     const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
     return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
 }
 
-template <int L, bool KEEP, bool LEAN = false>
+template <int L, bool KEEP>
 __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane, float x, float y, Vec &A_, Vec &TX,
                                              Vec &TY, Acts<L> &keep, float *act = nullptr) {
     const int g = lane >> 4;
@@ -238,7 +242,7 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
             const int n = 16 * m + 4 * g + r;
             const float w0 = S.w1[n][0], w1v = S.w1[n][1];
             const float z = fmaf(w0, x, fmaf(w1v, y, S.b[0][n]));
-            const float a = LEAN ? tanh_lean(z) : tanh_f32(z);
+            const float a = tanh_lean(z);
             const float s = 1.0f - a * a;
             A_.v[m][r] = a;
             TX.v[m][r] = s * w0;
@@ -283,7 +287,7 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
         for (int m = 0; m < 2; ++m)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float a = LEAN ? tanh_lean(Z.v[m][r]) : tanh_f32(Z.v[m][r]);
+                const float a = tanh_lean(Z.v[m][r]);
                 const float s = 1.0f - a * a;
                 A_.v[m][r] = a;
                 TX.v[m][r] = s * PX.v[m][r];
@@ -296,14 +300,14 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
         }
         if (KEEP) {
             keep.a[l - 1] = A_;
-            keep.px[l - 1] = PX;
-            keep.py[l - 1] = PY;
+            keep.tx[l - 1] = TX;
+            keep.ty[l - 1] = TY;
         }
     }
 }
 
 // the reverse sweep's forward state from stored activations: a_l is read, s_l =
-// 1 - a_l^2, and only the tangent products are recomputed (no tanh, no value products)
+// 1 - a_l^2, and only the tangents are recomputed (no tanh, no value products)
 template <int L>
 __device__ __forceinline__ void tile_forward_loaded(const WeightsShared<L> &S, int lane, const float *act,
                                                     Acts<L> &K) {
@@ -354,8 +358,8 @@ __device__ __forceinline__ void tile_forward_loaded(const WeightsShared<L> &S, i
                 TX.v[m][r] = s * PX.v[m][r];
                 TY.v[m][r] = s * PY.v[m][r];
             }
-        K.px[l - 1] = PX;
-        K.py[l - 1] = PY;
+        K.tx[l - 1] = TX;
+        K.ty[l - 1] = TY;
     }
 }
 
@@ -429,18 +433,6 @@ struct GradAcc {
     f4 w[L > 1 ? L - 1 : 1][4];
 };
 
-// write the tangent s * p of a stored layer (s = 1 - a^2) transposed into T
-__device__ __forceinline__ void put_t_tangent(float (*T)[kTs], int lane, const Vec &a, const Vec &p) {
-    const int j = lane & 15, g = lane >> 4;
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        f4 t;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) t[r] = (1.0f - a.v[m][r] * a.v[m][r]) * p.v[m][r];
-        *reinterpret_cast<f4 *>(&T[j][16 * m + 4 * g]) = t;
-    }
-}
-
 // layer-1 tangent s_1 * W1[:, col] transposed into T
 template <int L>
 __device__ __forceinline__ void put_t_tangent1(float (*T)[kTs], int lane, const Vec &a, const WeightsShared<L> &S,
@@ -496,13 +488,13 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
             for (int r = 0; r < 4; ++r) {
                 const int n = 16 * m + 4 * g + r;
                 float tx, ty;
-                const float s = 1.0f - aL.v[m][r] * aL.v[m][r];
                 if (L == 1) {
+                    const float s = 1.0f - aL.v[m][r] * aL.v[m][r];
                     tx = s * S.w1[n][0];
                     ty = s * S.w1[n][1];
                 } else {
-                    tx = s * K.px[L - 1].v[m][r];
-                    ty = s * K.py[L - 1].v[m][r];
+                    tx = K.tx[L - 1].v[m][r];
+                    ty = K.ty[L - 1].v[m][r];
                 }
                 v.v[m][r] = ub * aL.v[m][r] + uxb * tx + uyb * ty;
                 const float w = S.wo[n];
@@ -531,12 +523,13 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
         for (int m = 0; m < 2; ++m)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                // z_bar = s (abar - 2 a sbar) with sbar = tbar . p, and s sbar = tbar . t
                 const float a = al.v[m][r];
                 const float s = 1.0f - a * a;
                 pxb.v[m][r] = s * txbar.v[m][r];
                 pyb.v[m][r] = s * tybar.v[m][r];
-                const float sbar = txbar.v[m][r] * K.px[l - 1].v[m][r] + tybar.v[m][r] * K.py[l - 1].v[m][r];
-                zb.v[m][r] = s * (abar.v[m][r] - 2.0f * a * sbar);
+                const float ssbar = txbar.v[m][r] * K.tx[l - 1].v[m][r] + tybar.v[m][r] * K.ty[l - 1].v[m][r];
+                zb.v[m][r] = fmaf(-2.0f * a, ssbar, s * abar.v[m][r]);
             }
         // weight gradient with the inputs of layer l: a_{l-1} and t_{l-1} = s_{l-1} p_{l-1}
         // (layer 1: s_1 times a W1 column), formed while writing the transpose tile
@@ -547,12 +540,12 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
         wave_sync();
         put_t(T0, lane, pxb);
         if (l - 1 == 1) put_t_tangent1<L>(T1, lane, K.a[0], S, 0);
-        else put_t_tangent(T1, lane, K.a[l - 2], K.px[l - 2]);
+        else put_t(T1, lane, K.tx[l - 2]);
         wgrad_from_tiles(T0, T1, lane, G.w[l - 2]);
         wave_sync();
         put_t(T0, lane, pyb);
         if (l - 1 == 1) put_t_tangent1<L>(T1, lane, K.a[0], S, 1);
-        else put_t_tangent(T1, lane, K.a[l - 2], K.py[l - 2]);
+        else put_t(T1, lane, K.ty[l - 2]);
         wgrad_from_tiles(T0, T1, lane, G.w[l - 2]);
         wave_sync();
         // propagate: abar = W_l^T zbar, tbar = W_l^T pbar
@@ -1310,9 +1303,9 @@ __device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const
 // Fixed order ((w0 + w1) + (w2 + w3)) + ((w4 + w5) + (w6 + w7)): odd wavefronts store
 // into four LDS regions (red, and three over the transpose tiles, idle here), even ones
 // add theirs, and the four regions are added on the way out.
-template <int L, int NH>
-__device__ __forceinline__ void flush_grad(BwdShared<L, NH> &S, const BwdArgs &A, int64_t row, GradAcc<L> &G,
-                                           int tid, int wave, int lane) {
+template <int L, int NH, class SH>
+__device__ __forceinline__ void flush_grad(SH &S, float *gpart, int64_t row, GradAcc<L> &G, int tid, int wave,
+                                           int lane) {
     static_assert(kBWaves == 8, "pairwise flush assumes eight wavefronts");
     float *mine = (wave >> 1) == 0 ? S.red : S.part[(wave >> 1) - 1];
     __syncthreads();
@@ -1321,7 +1314,7 @@ __device__ __forceinline__ void flush_grad(BwdShared<L, NH> &S, const BwdArgs &A
     if (!(wave & 1)) put_partial<L, true, NH>(mine, G, S.vacc[wave], lane);
     __syncthreads();
     for (int j = tid; j < n_pad_h(L, NH); j += kBThreads)
-        A.gpart[row * kMaxPadded + j] = (S.red[j] + S.part[0][j]) + (S.part[1][j] + S.part[2][j]);
+        gpart[row * kMaxPadded + j] = (S.red[j] + S.part[0][j]) + (S.part[1][j] + S.part[2][j]);
     zero_acc<L>(G);
     for (int t = tid; t < kBWaves * n_vslots(L, NH) * 64; t += kBThreads) (&S.vacc[0][0][0])[t] = 0.f;
     __syncthreads();
@@ -1400,8 +1393,227 @@ __global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
             }
             tile_backward<L, NH>(S.W, T0, T1, lane, p.x, p.y, ub, uxb, uyb, eb, K, G, S.vacc[wave]);
         }
-        flush_grad<L, NH>(S, A, row, G, tid, wave, lane);
+        flush_grad<L, NH>(S, A.gpart, row, G, tid, wave, lane);
         t = seg_end;
+        ++cur;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one launch for the forward pass, the contraction and the reverse sweep (the
+// one-pass tuning): a block of eight wavefronts owns groups of whole elements of
+// at most kGroupPts points, one 16-point tile per wavefront, and keeps each tile's
+// forward state (activations and post-activation tangents) in registers through
+// the contraction of its elements, so the reverse sweep starts from it: no forward
+// recomputation, no point buffer, no separate contraction launch.  Boundary and
+// sensor points come in groups of their own (mismatch terms, no contraction).
+// The contraction of a group: lane (point j, slice g) holds G_x, G_y of its point
+// for test functions k = g, g + 4, ... (loaded before the forward products, so
+// their latency hides behind them); the per-point terms go through LDS to
+// per-(element, test) row sums, eight lanes a row, added in a fixed order; 2 c_v R
+// comes back through LDS and each lane forms its slice of the adjoint, the four
+// slices added across lanes.  Limits: N_quad <= kGroupPts, N_test <= kKB, one
+// network output, no shared points, stored G.
+// ---------------------------------------------------------------------------
+constexpr int kGroupPts = 16 * kBWaves;          // points of a group: one tile per wavefront
+constexpr int kGroupMaxElem = kGroupPts / 4;     // elements of a group (N_quad >= 4)
+constexpr int kSlice = kKB / 4;                  // test functions a lane holds
+
+struct GroupDesc {
+    int64_t p0;  // first point of the group in the instance's point list
+    int64_t e0;  // first element (interior groups)
+    int np;      // points
+    int ne;      // elements; 0: boundary and sensor points
+};
+
+struct StepArgs {
+    const InstDesc *inst;
+    const GroupDesc *grp;
+    const int64_t *blk_grp;   // [blocks + 1] group range of each block
+    const int *blk_inst0;     // instance of each block's first group
+    const float *params;
+    int64_t param_stride;
+    int H;
+    const float *eps;         // [n_inst] or null (eps = 1)
+    int want_grad;
+    float *gpart;
+    double *lpart;
+    int64_t *step;            // optional step counter, incremented once per launch
+};
+
+template <int L>
+struct StepShared {
+    WeightsShared<L> W;
+    union {
+        float tt[kBWaves][2][16][kTs];
+        float part[3][n_pad_h(L, 1)];
+    };
+    float vacc[kBWaves][n_vslots(L, 1)][64];
+    float red[n_pad_h(L, 1)];
+    float cs[kGroupPts][kKB + 1];    // per-point terms u_x G_x + u_y G_y, by test function
+    float rb[kGroupMaxElem][kKB];    // 2 c_v R of the group's elements
+    float fs[kGroupMaxElem * kKB];   // F of the group's elements, [element][test]
+    // per-wavefront loss sums of the current instance (sum R^2, sum R A, boundary, sensor),
+    // one wavefront sum added per group, in group order
+    double lp[kBWaves][4];
+};
+
+// add this lane's loss terms of one group to its wavefront's running sums (lane 0 writes)
+__device__ __forceinline__ void add_loss(double (*lp)[4], int wave, int lane, int slot, double v0, double v1) {
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    if (lane == 0) {
+        lp[wave][slot] += v0;
+        lp[wave][slot + 1] += v1;
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(kBThreads, 1) void k_step(StepArgs A) {
+    __shared__ StepShared<L> S;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int j = lane & 15, gq = lane >> 4;
+    const int pl = 16 * wave + j;  // the lane's point within a group
+    if (A.step && blockIdx.x == 0 && tid == 0) *A.step += 1;
+    float(*T0)[kTs] = S.tt[wave][0];
+    float(*T1)[kTs] = S.tt[wave][1];
+    GradAcc<L> G;
+    zero_acc<L>(G);
+    for (int t = tid; t < kBWaves * n_vslots(L, 1) * 64; t += kBThreads) (&S.vacc[0][0][0])[t] = 0.f;
+    int64_t g = A.blk_grp[blockIdx.x];
+    const int64_t g_end = A.blk_grp[blockIdx.x + 1];
+    int cur = A.blk_inst0[blockIdx.x];
+    while (g < g_end) {
+        const InstDesc *Ip = A.inst + cur;
+        const int64_t seg_end = min(g_end, Ip->grp0 + Ip->n_grp);
+        const int64_t n_pts = Ip->n_pts, n_bnd = Ip->n_bnd;
+        const float2 *__restrict__ pts = Ip->pts;
+        const float *__restrict__ tgt = Ip->tgt;
+        const float *__restrict__ Gx = Ip->Gx;
+        const float *__restrict__ Gy = Ip->Gy;
+        const float *__restrict__ F = Ip->F;
+        const int nq = Ip->nq, ntest = Ip->ntest;
+        const int64_t gstride = Ip->gstride;
+        const float two_cv = Ip->two_cv, wb2 = Ip->wb2, ws2 = Ip->ws2;
+        const float eps = A.eps ? A.eps[cur] : 1.0f;
+        const int64_t rel = (int64_t)(blockIdx.x - Ip->gblk0);
+        __syncthreads();
+        load_weights<L, kBThreads, 1>(S.W, S.red, A.params + (int64_t)cur * A.param_stride, A.H, tid);
+        if (tid < kBWaves * 4) (&S.lp[0][0])[tid] = 0.0;
+        __syncthreads();
+        // the next group's point is loaded while this group computes
+        auto fetch = [&](int64_t gg) -> float2 {
+            if (gg >= seg_end) return make_float2(0.f, 0.f);
+            const GroupDesc D = A.grp[gg];
+            return pl < D.np ? pts[D.p0 + pl] : make_float2(0.f, 0.f);
+        };
+        float2 xyn = fetch(g);
+        for (; g < seg_end; ++g) {
+            const GroupDesc D = A.grp[g];
+            const bool valid = pl < D.np;
+            const bool active = 16 * wave < D.np;  // uniform in the wavefront
+            const bool interior = D.ne > 0;        // uniform in the block
+            const float2 xy = xyn;
+            const int el = interior ? pl / nq : 0, q = pl - el * nq;
+            float gx[kSlice], gy[kSlice];
+            const int64_t gb = (D.e0 + el) * gstride + q;
+#pragma unroll
+            for (int t = 0; t < kSlice; ++t) {
+                const int k = gq + 4 * t;
+                const bool ok = interior && valid && k < ntest;
+                gx[t] = ok ? Gx[gb + (int64_t)k * nq] : 0.f;
+                gy[t] = ok ? Gy[gb + (int64_t)k * nq] : 0.f;
+            }
+            xyn = fetch(g + 1);
+            // the group's rows of F (contiguous), loaded now and staged in LDS after the forward pass
+            constexpr int kFr = kGroupMaxElem * kKB / kBThreads;
+            float fr[kFr];
+#pragma unroll
+            for (int i = 0; i < kFr; ++i) {
+                const int f = tid + i * kBThreads;
+                fr[i] = (interior && f < D.ne * ntest) ? F[D.e0 * ntest + f] : 0.f;
+            }
+            Acts<L> K;
+            float u = 0.f, ux = 0.f, uy = 0.f;
+            if (active) {
+                Vec a, tx, ty;
+                tile_forward<L, true>(S.W, lane, xy.x, xy.y, a, tx, ty, K);
+                tile_outputs<L>(S.W, lane, a, tx, ty, u, ux, uy);
+            }
+            float ub = 0.f, uxb = 0.f, uyb = 0.f;
+            if (interior) {
+#pragma unroll
+                for (int t = 0; t < kSlice; ++t) {
+                    const int k = gq + 4 * t;
+                    if (valid && k < ntest) S.cs[pl][k] = fmaf(ux, gx[t], uy * gy[t]);
+                }
+#pragma unroll
+                for (int i = 0; i < kFr; ++i) {
+                    const int f = tid + i * kBThreads;
+                    if (f < D.ne * ntest) S.fs[f] = fr[i];
+                }
+                __syncthreads();
+                double lrr = 0.0, lra = 0.0;
+                for (int r8 = tid; r8 < 8 * D.ne * ntest; r8 += kBThreads) {
+                    const int r = r8 >> 3, part = r8 & 7;
+                    const int e2 = r / ntest, k = r - e2 * ntest;
+                    float a = 0.f;
+                    for (int qq = part; qq < nq; qq += 8) a += S.cs[e2 * nq + qq][k];
+                    a += __shfl_xor(a, 4, 8);
+                    a += __shfl_xor(a, 2, 8);
+                    a += __shfl_xor(a, 1, 8);
+                    if (part == 0) {
+                        const float R = eps * a - S.fs[e2 * ntest + k];
+                        S.rb[e2][k] = two_cv * R;
+                        lrr += (double)R * (double)R;
+                        lra += (double)R * (double)a;
+                    }
+                }
+                add_loss(S.lp, wave, lane, 0, lrr, lra);
+                __syncthreads();
+                // dL/du_x = eps sum_k 2 c_v R_k G_x[k, q]: this lane's slice, then the four slices
+                float bx = 0.f, by = 0.f;
+#pragma unroll
+                for (int t = 0; t < kSlice; ++t) {
+                    const int k = gq + 4 * t;
+                    if (k < ntest) {
+                        const float rk = S.rb[el][k];
+                        bx = fmaf(rk, gx[t], bx);
+                        by = fmaf(rk, gy[t], by);
+                    }
+                }
+                bx = group_sum(bx);
+                by = group_sum(by);
+                if (valid) {
+                    uxb = eps * bx;
+                    uyb = eps * by;
+                }
+            } else {
+                // boundary (Sec. 2.3) or sensor (Sec. 4.7) mismatch: loss term and its adjoint
+                double lbb = 0.0, lss = 0.0;
+                if (valid) {
+                    const int64_t xi = D.p0 + pl - n_pts;
+                    const float d = u - tgt[xi];
+                    const bool bnd = xi < n_bnd;
+                    if (gq == 0) {
+                        if (bnd) lbb = (double)d * (double)d;
+                        else lss = (double)d * (double)d;
+                    }
+                    ub = (bnd ? wb2 : ws2) * d;
+                }
+                add_loss(S.lp, wave, lane, 2, lbb, lss);
+            }
+            if (A.want_grad && active)
+                tile_backward<L, 1>(S.W, T0, T1, lane, xy.x, xy.y, ub, uxb, uyb, 0.f, K, G, S.vacc[wave]);
+        }
+        // the block's loss sums for this instance, wavefronts added in order -> its loss row
+        __syncthreads();
+        if (tid < 4) {
+            double v = 0.0;
+            for (int w = 0; w < kBWaves; ++w) v += S.lp[w][tid];
+            A.lpart[(Ip->lrow0 + rel) * 4 + tid] = v;
+        }
+        if (A.want_grad) flush_grad<L, 1>(S, A.gpart, Ip->grow0 + rel, G, tid, wave, lane);
         ++cur;
     }
 }
@@ -1616,7 +1828,7 @@ __global__ __launch_bounds__(kEvalWaves * 64, 1) void k_eval(EvalArgs A) {
         if (TAN) {
             Vec tx, ty;
             Acts<L> unused;
-            tile_forward<L, false, true>(S.W, lane, p.x, p.y, a, tx, ty, unused);
+            tile_forward<L, false>(S.W, lane, p.x, p.y, a, tx, ty, unused);
             tile_outputs<L>(S.W, lane, a, tx, ty, u, ux, uy);
         } else {
             tile_values<L>(S.W, lane, p.x, p.y, a);
@@ -1692,11 +1904,12 @@ static int cu_count(int dev) {
 // tile shapes a plan is built with (vpinn_tuning): forward wavefronts per block,
 // elements per small-element contraction block (shift), rows per pass of the
 // row-streaming contraction
-static const vpinn_tuning kDefaultTuning = {12, 0, 4, 0};
+static const vpinn_tuning kDefaultTuning = {12, 0, 4, 0, 0};
 static bool tuning_valid(const vpinn_tuning &t) {
     return (t.fwd_waves == 8 || t.fwd_waves == 12 || t.fwd_waves == 16) && t.chunk_shift >= 0 && t.chunk_shift <= 2 &&
            (t.rows_per_pass == 2 || t.rows_per_pass == 4 || t.rows_per_pass == 8) &&
-           (t.store_activations == 0 || t.store_activations == 1);
+           (t.store_activations == 0 || t.store_activations == 1) && (t.one_pass == 0 || t.one_pass == 1) &&
+           !(t.one_pass && t.store_activations);
 }
 
 struct FusedPlan {
@@ -1706,6 +1919,8 @@ struct FusedPlan {
     DevBuf dpts, abuf, eabuf;
     DevBuf act;  // store_activations: [tiles][L][kActTile]
     DevBuf rblk_inst, apart;  // large elements: instance of each row-sum block; partial row sums
+    DevBuf grp;               // one-pass: the group list (GroupDesc); blk_tiles then holds group ranges
+    int64_t n_grp = 0;
     int64_t rblocks = 0;
     int nh = 1;   // network outputs
     vpinn_tuning tune = kDefaultTuning;
@@ -1716,6 +1931,89 @@ struct FusedPlan {
     size_t cdyn_fast = 0, cdyn_generic = 0;  // dynamic LDS of k_contract_fast / k_split_adj
     size_t cdyn_mf = 0;                      // and of k_contract_mf
 };
+
+// which of the four-kernel plan's contraction kernels takes a problem's elements
+static int contraction_path(const vpinn_problem *p) {
+    return p->matfree                               ? kPathMF
+           : (p->nq <= kCThreads && p->ntest <= kKB) ? kPathFast
+           : (p->nq <= 64)                          ? kPathRows1
+           : (p->nq <= 128)                         ? kPathRows2
+           : (p->nq <= 64 * kRowQ)                  ? kPathRows4
+                                                    : kPathGeneric;
+}
+
+// One-pass plan: every instance's elements in groups of whole elements of at most
+// kGroupPts points (floor(kGroupPts / N_quad) elements each, the last one shorter),
+// then its boundary and sensor points in groups of kGroupPts; the global group list
+// is dealt in equal contiguous shares to one block per CU, and instance i gets one
+// loss row and one gradient row per block whose share meets its groups.
+static vpinn_status build_one_pass(vpinn_problem *const *probs, int n, int nh, int cus, std::vector<InstDesc> &D,
+                                   FusedPlan &P) {
+    if (nh != 1) return fail(VPINN_E_UNSUPPORTED, "the one-pass step has one network output");
+    std::vector<GroupDesc> grp;
+    for (int i = 0; i < n; ++i) {
+        const vpinn_problem *p = probs[i];
+        if (p->matfree || p->n_uniq > 0 || p->nq > kGroupPts || p->ntest > kKB)
+            return fail(VPINN_E_UNSUPPORTED, "problem " + std::to_string(i) +
+                                                 ": the one-pass step needs stored G, no shared points, N_quad <= " +
+                                                 std::to_string(kGroupPts) + " and N_test <= " + std::to_string(kKB));
+        InstDesc &d = D[i];
+        d.grp0 = (int64_t)grp.size();
+        const int epg = std::min(kGroupMaxElem, kGroupPts / p->nq);
+        for (int64_t e0 = 0; e0 < p->n_elem; e0 += epg) {
+            const int ne = (int)std::min<int64_t>(epg, p->n_elem - e0);
+            grp.push_back(GroupDesc{e0 * p->nq, e0, ne * p->nq, ne});
+        }
+        const int64_t nx = p->n_bnd + p->n_sen;
+        for (int64_t x0 = 0; x0 < nx; x0 += kGroupPts)
+            grp.push_back(GroupDesc{p->n_pts + x0, 0, (int)std::min<int64_t>(kGroupPts, nx - x0), 0});
+        d.n_grp = (int64_t)grp.size() - d.grp0;
+    }
+    const int64_t ng = (int64_t)grp.size();
+    const int nblk = (int)std::min<int64_t>(std::min<int64_t>((int64_t)cus, kMaxBlocks), ng);
+    std::vector<int64_t> bg(nblk + 1);
+    std::vector<int> binst(nblk);
+    for (int b = 0; b <= nblk; ++b) bg[b] = (int64_t)b * ng / nblk;
+    int rows = 0, bb = 0;
+    for (int i = 0; i < n; ++i) {
+        InstDesc &d = D[i];
+        const int64_t gf = d.grp0, gl = d.grp0 + d.n_grp - 1;
+        while (bg[bb + 1] <= gf) ++bb;
+        int bl = bb;
+        while (bg[bl + 1] <= gl) ++bl;
+        d.gblk0 = bb;
+        d.gn_rows = bl - bb + 1;
+        d.grow0 = rows;
+        d.lrow0 = rows;
+        d.ln_rows = d.gn_rows;
+        rows += d.gn_rows;
+    }
+    for (int b = 0, i = 0; b < nblk; ++b) {
+        while (D[i].grp0 + D[i].n_grp <= bg[b]) ++i;
+        binst[b] = i;
+    }
+    VP_ALLOC(P.inst.reserve(sizeof(InstDesc) * n));
+    VP_ALLOC(P.grp.reserve(sizeof(GroupDesc) * (size_t)ng));
+    VP_ALLOC(P.blk_tiles.reserve(sizeof(int64_t) * (nblk + 1)));
+    VP_ALLOC(P.blk_inst0.reserve(sizeof(int) * nblk));
+    VP_ALLOC(P.gpart.reserve(sizeof(float) * kMaxPadded * (size_t)rows));
+    VP_ALLOC(P.lpart.reserve(sizeof(double) * 4 * (size_t)rows));
+    VP_HIP(hipMemcpy(P.inst.ptr, D.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(P.grp.ptr, grp.data(), sizeof(GroupDesc) * (size_t)ng, hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(P.blk_tiles.ptr, bg.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice));
+    VP_HIP(hipMemcpy(P.blk_inst0.ptr, binst.data(), sizeof(int) * nblk, hipMemcpyHostToDevice));
+    P.host_inst = D;
+    P.tblocks = nblk;
+    P.cblocks = 0;
+    P.n_inst = n;
+    P.grows = rows;
+    P.lrows = rows;
+    P.n_grp = ng;
+    P.tiles = 0;
+    P.rblocks = 0;
+    for (int k = 0; k < kNumPaths; ++k) P.cpath_blocks[k] = 0;
+    return VPINN_OK;
+}
 
 static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_loss_cfg *cfg, int dev,
                                const vpinn_tuning &tune, FusedPlan &P) {
@@ -1783,12 +2081,7 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
             d.qn = p->n;
             d.tn = p->nt;
         }
-        d.path = p->matfree                               ? kPathMF
-                 : (p->nq <= kCThreads && p->ntest <= kKB) ? kPathFast
-                 : (p->nq <= 64)                          ? kPathRows1
-                 : (p->nq <= 128)                         ? kPathRows2
-                 : (p->nq <= 64 * kRowQ)                  ? kPathRows4
-                                                          : kPathGeneric;
+        d.path = contraction_path(p);
         d.epc = d.path == kPathFast ? std::max(1, (kCThreads / p->nq) >> tune.chunk_shift)
                 : d.path == kPathMF ? kCWaves
                                     : 1;
@@ -1823,6 +2116,16 @@ static vpinn_status build_plan(vpinn_problem *const *probs, int n, const vpinn_l
         d.ws2 = p->n_sen ? (float)(2.0 * cfg->gamma / (double)p->n_sen) : 0.f;
         d.tau = cfg->tau;
         d.gamma = cfg->gamma;
+    }
+    if (tune.one_pass) {
+        vpinn_status st = build_one_pass(probs, n, nh, cus, D, P);
+        if (st) return st;
+        P.tiles = tiles;  // the four-kernel tile count, for the stored-activation footprint
+        P.L = L;
+        P.H = H;
+        P.nh = nh;
+        P.npf = vpinn_n_params_out(H, L, nh);
+        return VPINN_OK;
     }
     // contraction blocks grouped by path (one launch each), instance order within a path
     int64_t cpath_blocks[kNumPaths] = {};
@@ -2036,6 +2339,40 @@ static vpinn_status run_plan(const FusedPlan &P, const float *params, const floa
     ba.act = P.act.as<float>();
     const dim3 fg((unsigned)std::max<int64_t>(1, (P.npf + kFinCols - 1) / kFinCols), (unsigned)P.n_inst);
     const int ft = kFinThreads;
+    if (P.tune.one_pass) {
+        StepArgs sa{};
+        sa.inst = P.inst.as<InstDesc>();
+        sa.grp = P.grp.as<GroupDesc>();
+        sa.blk_grp = P.blk_tiles.as<int64_t>();
+        sa.blk_inst0 = P.blk_inst0.as<int>();
+        sa.params = params;
+        sa.param_stride = P.npf;
+        sa.H = P.H;
+        sa.eps = eps;
+        sa.want_grad = want_grad ? 1 : 0;
+        sa.gpart = P.gpart.as<float>();
+        sa.lpart = P.lpart.as<double>();
+        sa.step = step;
+        // profiling events: the one kernel is timed between the first two, the reduction between the last two
+        if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
+        switch (P.L) {
+        case 1: k_step<1><<<P.tblocks, kBThreads, 0, s>>>(sa); break;
+        case 2: k_step<2><<<P.tblocks, kBThreads, 0, s>>>(sa); break;
+        case 3: k_step<3><<<P.tblocks, kBThreads, 0, s>>>(sa); break;
+        default: k_step<4><<<P.tblocks, kBThreads, 0, s>>>(sa); break;
+        }
+        for (int k = 1; k <= 3; ++k)
+            if (ev && ev[k]) (void)hipEventRecord(ev[k], s);
+        switch (P.L) {
+        case 1: k_fused_final<1, 1><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf, loss, grad, grad_eps, ad); break;
+        case 2: k_fused_final<2, 1><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf, loss, grad, grad_eps, ad); break;
+        case 3: k_fused_final<3, 1><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf, loss, grad, grad_eps, ad); break;
+        default: k_fused_final<4, 1><<<fg, ft, 0, s>>>(P.inst.as<InstDesc>(), P.gpart.as<float>(), P.lpart.as<double>(), P.H, P.npf, loss, grad, grad_eps, ad); break;
+        }
+        if (ev && ev[4]) (void)hipEventRecord(ev[4], s);
+        VP_HIP(hipGetLastError());
+        return VPINN_OK;
+    }
     switch (P.L * 2 + P.nh - 1) {
     case 2: launch_all<1, 1>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
     case 3: launch_all<1, 2>(P, fa, ca, ba, want_grad, fg, ft, loss, grad, grad_eps, ad, ev, s); break;
@@ -2247,8 +2584,12 @@ vpinn_status batch_set_tuning(vpinn_batch *b, const vpinn_tuning *t) {
 vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps, vpinn_tuning *best_out,
                             hipStream_t s) {
     const FusedPlan &P0 = b->plan;
-    const bool has_fast = P0.cpath_blocks[kPathFast] > 0;
-    const bool has_rows = P0.cpath_blocks[kPathRows1] + P0.cpath_blocks[kPathRows2] + P0.cpath_blocks[kPathRows4] > 0;
+    bool has_fast = false, has_rows = false;
+    for (const vpinn_problem *p : b->probs) {
+        const int path = contraction_path(p);
+        has_fast = has_fast || path == kPathFast;
+        has_rows = has_rows || path == kPathRows1 || path == kPathRows2 || path == kPathRows4;
+    }
     // storing the activations is a candidate only while their buffer fits the last-level cache: beyond
     // it the round trip is HBM traffic, and the reverse sweep recomputes them instead
     const bool may_store = (size_t)P0.tiles * P0.L * kActTile * sizeof(float) <= kActStoreMaxBytes;
@@ -2257,7 +2598,12 @@ vpinn_status batch_autotune(vpinn_batch *b, const float *d_params, int32_t reps,
         for (int cs = 0; cs <= (has_fast ? 2 : 0); ++cs)
             for (int rp : {2, 4, 8})
                 for (int sa : {0, 1})
-                    if ((has_rows || rp == 4) && (sa == 0 || may_store)) cand.push_back(vpinn_tuning{fw, cs, rp, sa});
+                    if ((has_rows || rp == 4) && (sa == 0 || may_store)) cand.push_back(vpinn_tuning{fw, cs, rp, sa, 0});
+    // the one-pass step (its kernels ignore the other fields) where every problem fits it
+    bool one_pass_ok = b->cfg.n_outputs != 2;
+    for (const vpinn_problem *p : b->probs)
+        one_pass_ok = one_pass_ok && !p->matfree && p->n_uniq == 0 && p->nq <= kGroupPts && p->ntest <= kKB;
+    if (one_pass_ok) cand.push_back(vpinn_tuning{12, 0, 4, 0, 1});
     const int n = (int)b->probs.size();
     DevBuf losses, grads;
     VP_ALLOC(losses.reserve(sizeof(float) * 4 * (size_t)n));

@@ -64,10 +64,10 @@ class vpinn_loss_cfg(C.Structure):
 
 class vpinn_tuning(C.Structure):
     _fields_ = [("fwd_waves", C.c_int32), ("chunk_shift", C.c_int32), ("rows_per_pass", C.c_int32),
-                ("store_activations", C.c_int32)]
+                ("store_activations", C.c_int32), ("one_pass", C.c_int32)]
 
     def as_tuple(self):
-        return (self.fwd_waves, self.chunk_shift, self.rows_per_pass, self.store_activations)
+        return (self.fwd_waves, self.chunk_shift, self.rows_per_pass, self.store_activations, self.one_pass)
 
 
 class VpinnError(RuntimeError):
@@ -387,15 +387,15 @@ def vpinn_batch_replay(b: Batch, stream=None):
 
 
 def vpinn_batch_get_tuning(b: Batch):
-    """(fwd_waves, chunk_shift, rows_per_pass, store_activations) of the batch's plan."""
+    """(fwd_waves, chunk_shift, rows_per_pass, store_activations, one_pass) of the batch's plan."""
     t = vpinn_tuning()
     _check(lib().vpinn_batch_get_tuning(b.handle, C.byref(t)))
     return t.as_tuple()
 
 
 def vpinn_batch_set_tuning(b: Batch, fwd_waves: int, chunk_shift: int, rows_per_pass: int,
-                           store_activations: int = 0):
-    t = vpinn_tuning(fwd_waves, chunk_shift, rows_per_pass, store_activations)
+                           store_activations: int = 0, one_pass: int = 0):
+    t = vpinn_tuning(fwd_waves, chunk_shift, rows_per_pass, store_activations, one_pass)
     _check(lib().vpinn_batch_set_tuning(b.handle, C.byref(t)))
 
 

@@ -28,7 +28,11 @@ def test_c2_algorithmic_counts():
     assert (prob.width, prob.n_hidden, prob.test_order ** 2, prob.n_points, len(prob.bnd_xy)) == (30, 3, 25, 102400, 1600)
     assert bench.flops_per_epoch(prob) == 33200 * 102400 + 11160 * 1600 == 3417536000
     work = bench.kernel_work(prob)
-    assert sum(w["flop"] for w in work.values()) == bench.flops_per_epoch(prob)
+    four = ("k_fwd", "k_contract", "k_bwd")
+    assert sum(work[k]["flop"] for k in four) == bench.flops_per_epoch(prob)
+    # the one-pass kernel does the three kernels' work and reads G, F and the points once
+    assert work["k_step"]["flop"] == bench.flops_per_epoch(prob)
+    assert work["k_step"]["bytes"] == 8 * 25 * 102400 + 4 * 25 * 1024 + 8 * 102400 + 12 * 1600
     assert work["k_fwd"]["flop"] == 2 * (5520 * 102400 + 1890 * 1600)
     assert work["k_bwd"]["flop"] == 2 * (10980 * 102400 + 3690 * 1600)
     # G_x and G_y once, F, the point buffer in and out
@@ -74,7 +78,7 @@ def test_traffic_needs_the_measured_sources_and_tuning(tmp_path, monkeypatch):
     assert bench.traffic_from_profile("c2", "k_bwd", (16, 2, 4, 1)) is None
 
 
-@pytest.mark.parametrize("args", [["--tuning", "1,2"], ["--tuning", "1,2,3,4,5"], ["--workload", "nope"],
+@pytest.mark.parametrize("args", [["--tuning", "1,2"], ["--tuning", "1,2,3,4,5,6"], ["--workload", "nope"],
                                   ["--steps", "0"], ["--warmup", "-1"]])
 def test_argument_errors_exit_before_any_device_work(args):
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args, capture_output=True, text=True,

@@ -283,12 +283,12 @@ def test_tunings_agree_with_oracle(V, torch):
     probs = _all_shapes()
     gp = [_gpu(V, p) for p in probs]
     b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
-    assert V.vpinn_batch_get_tuning(b) == (12, 0, 4, 0)
+    assert V.vpinn_batch_get_tuning(b) == (12, 0, 4, 0, 0)
     n = V.vpinn_n_params(30, 3)
     th = _params(probs)
     T = torch.tensor(th, dtype=torch.float32, device="cuda:0")
     refs = [O.problem_loss_grad(p, O.assemble_problem(p), th[i]) for i, p in enumerate(probs)]
-    for tune in [(8, 2, 2, 0), (16, 1, 8, 1), (12, 0, 4, 1), (12, 0, 4, 0)]:
+    for tune in [(8, 2, 2, 0, 0), (16, 1, 8, 1, 0), (12, 0, 4, 1, 0), (12, 0, 4, 0, 0)]:
         V.vpinn_batch_set_tuning(b, *tune)
         assert V.vpinn_batch_get_tuning(b) == tune
         L, G = _batch_eval(V, torch, b, T, len(probs), n)
@@ -310,6 +310,7 @@ def test_autotune_picks_a_valid_tuning_and_keeps_parity(V, torch):
     best = V.vpinn_batch_autotune(b, T, reps=2)
     assert best == V.vpinn_batch_get_tuning(b)
     assert best[0] in (8, 12, 16) and 0 <= best[1] <= 2 and best[2] in (2, 4, 8) and best[3] in (0, 1)
+    assert best[4] == 0  # the batch has shapes the one-pass step does not take
     L1, G1 = _batch_eval(V, torch, b, T, len(probs), n)
     np.testing.assert_allclose(L1, L0, rtol=1e-5)
     for i in range(len(probs)):
@@ -575,3 +576,143 @@ def test_c4_in_the_bench_launch_configuration(V, torch):
     ref2 = O.problem_loss_grad(prob, asm, th_after, eps=e_after, want_grad=False)
     assert abs(losses[0, 0].item() - ref2.loss[0]) / ref2.loss[0] < 1e-5
     assert int(step.item()) == 2
+
+
+def _one_pass_shapes():
+    """Instances the one-pass step takes, chosen to exercise its grouping: N_quad from 4 (32 elements a group) to
+    121 (one element of eight tiles, the last with nine points), element counts that do not fill the last group, no
+    boundary points, boundary sets of one and of three groups, sensors, and a uniform mesh (one shared G)."""
+    specs = [  # (mx, my, n, N_t, k, boundary points, jitter)
+        (3, 4, 2, 1, 1, 40, 0.2), (5, 3, 3, 2, 2, 0, 0.2), (7, 5, 6, 5, 3, 300, 0.2), (1, 1, 11, 5, 2, 40, 0.2),
+        (2, 3, 4, 3, 4, 128, 0.2), (9, 7, 5, 5, 5, 44, 0.2), (4, 4, 6, 4, 1, 40, 0.0)]
+    out = []
+    for i, (mx, my, n, nt, k, nd, jit) in enumerate(specs):
+        p = gen.poisson_sinsin_square(f"op{i}", 1, n, nt, k, max(nd, 4), jit, seed=300 + i)
+        p.mesh = gen.square_mesh(mx, my, jit, seed=300 + i)
+        if nd == 0:
+            p.bnd_xy, p.bnd_g = np.zeros((0, 2)), np.zeros(0)
+        out.append(p)
+    out[2].sens_xy = gen.sensor_points(70, 5)
+    out[2].sens_u = gen.uniform(5, "su", 70, -1, 1)
+    for p in out:
+        p.gamma = 5.0
+    return out
+
+
+def test_one_pass_matches_oracle_and_four_kernels(V, torch):
+    """The one-pass step (forward, contraction and reverse sweep in one kernel) computes each instance's loss and
+    gradient to the oracle's tolerances, and agrees with the four-kernel step to FP32 summation order; a fixed
+    tuning is bitwise reproducible, and a loss-only call gives the same losses."""
+    from oracle import oracle as O
+    probs = _one_pass_shapes()
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
+    n = V.vpinn_n_params(30, 3)
+    th = _params(probs)
+    T = torch.tensor(th, dtype=torch.float32, device="cuda:0")
+    L4, G4 = _batch_eval(V, torch, b, T, len(probs), n)
+    V.vpinn_batch_set_tuning(b, 12, 0, 4, 0, 1)
+    assert V.vpinn_batch_get_tuning(b) == (12, 0, 4, 0, 1)
+    L1, G1 = _batch_eval(V, torch, b, T, len(probs), n)
+    for i, p in enumerate(probs):
+        print(f"one-pass instance {i}: n={p.quad_order} N_t={p.test_order} elements={p.n_elem}", flush=True)
+        ref = O.problem_loss_grad(p, O.assemble_problem(p), th[i])
+        for k in range(4):
+            assert abs(L1[i, k] - ref.loss[k]) <= 1e-5 * abs(ref.loss[k]) + 1e-12, (i, k, L1[i, k], ref.loss[k])
+        assert np.linalg.norm(G1[i] - ref.grad) / np.linalg.norm(ref.grad) < 1e-4, i
+        np.testing.assert_allclose(L1[i], L4[i], rtol=2e-6, atol=1e-12)
+        assert np.linalg.norm(G1[i] - G4[i]) <= 1e-5 * np.linalg.norm(G4[i]), i
+    L2, G2 = _batch_eval(V, torch, b, T, len(probs), n)
+    assert np.array_equal(L1, L2) and np.array_equal(G1, G2)
+    lo = torch.zeros((len(probs), 4), device="cuda:0")
+    V.vpinn_batch_loss_and_grad(b, T, losses=lo)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(lo.cpu().double().numpy(), L1)
+
+
+def test_one_pass_step_with_eps_matches_eager_and_graph(V, torch):
+    """The one-pass batched step training eps beside the weights: three eager steps against three replays of the
+    captured step (bitwise); and one step against the four-kernel step: the same losses and the same first Adam
+    moment (a tenth of the gradient) to FP32 summation order."""
+    probs = _one_pass_shapes()[:5]
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 5.0))
+    th = _params(probs)
+    dev = torch.device("cuda:0")
+    eps0 = np.array([2.0, 0.5, 1.0, 1.5, 0.8], dtype=np.float32)
+
+    def run(one_pass, graph, steps=3):
+        V.vpinn_batch_set_tuning(b, 12, 0, 4, 0, one_pass)
+        T = torch.tensor(th, dtype=torch.float32, device=dev)
+        M, Vv = torch.zeros_like(T), torch.zeros_like(T)
+        E = torch.tensor(eps0, device=dev)
+        Em, Ev = torch.zeros_like(E), torch.zeros_like(E)
+        S = torch.zeros(1, dtype=torch.int64, device=dev)
+        Ls = torch.zeros((len(probs), 4), device=dev)
+        s = torch.cuda.Stream()
+        kw = dict(lr=1e-3, losses=Ls, stream=s, diff=E, diff_m=Em, diff_v=Ev)
+        if graph:
+            V.vpinn_batch_capture(b, T, M, Vv, S, **kw)
+        seen = []
+        for _ in range(steps):
+            if graph:
+                V.vpinn_batch_replay(b, stream=s)
+            else:
+                V.vpinn_batch_step(b, T, M, Vv, S, **kw)
+            s.synchronize()
+            seen.append(Ls.cpu().numpy().copy())
+        assert int(S.item()) == steps
+        return T.cpu().numpy(), E.cpu().numpy(), np.stack(seen), M.cpu().double().numpy()
+
+    Te, Ee, Le, _ = run(1, False)
+    Tg, Eg, Lg, _ = run(1, True)
+    np.testing.assert_array_equal(Tg, Te)
+    np.testing.assert_array_equal(Eg, Ee)
+    np.testing.assert_array_equal(Lg, Le)
+    # instance 0 has two GLL points per direction, the element corners, where every test function vanishes:
+    # G = F = 0, so R = 0 and dL/deps = 0 and Adam leaves its eps; every other eps moves
+    assert Ee[0] == eps0[0] and np.all(Ee[1:] != eps0[1:])
+    _, _, L1, M1 = run(1, False, steps=1)
+    _, _, L4, M4 = run(0, False, steps=1)
+    np.testing.assert_allclose(L1, L4, rtol=2e-6)
+    for i in range(len(probs)):
+        assert np.linalg.norm(M1[i] - M4[i]) <= 1e-5 * np.linalg.norm(M4[i]), i
+
+
+def test_one_pass_refuses_what_it_does_not_take(V, torch):
+    """Elements above 128 points, more than 32 test functions and shared points make the one-pass tuning
+    unsupported; the batch keeps its plan."""
+    for n, nt in ((12, 3), (6, 7)):
+        p = gen.poisson_sinsin_square("big", 2, n, nt, 2, 40, 0.2, seed=9)
+        b = V.vpinn_batch_create([_gpu(V, p)], V.loss_cfg(30, 3, 10.0, 0.0))
+        with pytest.raises(V.VpinnError) as ei:
+            V.vpinn_batch_set_tuning(b, 12, 0, 4, 0, 1)
+        assert ei.value.code == V.VPINN_E_UNSUPPORTED
+        assert V.vpinn_batch_get_tuning(b) == (12, 0, 4, 0, 0)
+    p = gen.poisson_sinsin_square("shared", 3, 5, 3, 2, 40, 0.2, seed=9)
+    g = _gpu(V, p)
+    V.vpinn_set_shared_points(g, p.mesh.xy, p.mesh.quad)
+    b = V.vpinn_batch_create([g], V.loss_cfg(30, 3, 10.0, 0.0))
+    with pytest.raises(V.VpinnError) as ei:
+        V.vpinn_batch_set_tuning(b, 12, 0, 4, 0, 1)
+    assert ei.value.code == V.VPINN_E_UNSUPPORTED
+    with pytest.raises(V.VpinnError) as ei:
+        V.vpinn_batch_set_tuning(b, 12, 0, 4, 1, 1)  # nothing to store in the one-pass step
+    assert ei.value.code == V.VPINN_E_INVALID
+
+
+@pytest.mark.slow
+def test_c5_one_pass_full(V, torch, c5_oracle):
+    """The 64-instance workload with the one-pass step: every instance's loss and gradient against the oracle."""
+    probs, th, refs = c5_oracle
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(30, 3, 10.0, 0.0))
+    V.vpinn_batch_set_tuning(b, 12, 0, 4, 0, 1)
+    n = V.vpinn_n_params(30, 3)
+    T = torch.tensor(th, dtype=torch.float32, device="cuda:0")
+    L, Gd = _batch_eval(V, torch, b, T, 64, n)
+    lerr = [abs(L[i, 0] - refs[i].loss[0]) / refs[i].loss[0] for i in range(64)]
+    gerr = [np.linalg.norm(Gd[i] - refs[i].grad) / np.linalg.norm(refs[i].grad) for i in range(64)]
+    print(f"c5 one-pass: max loss rel err {max(lerr):.2e}, max grad rel L2 err {max(gerr):.2e}")
+    assert max(lerr) < 1e-5, int(np.argmax(lerr))
+    assert max(gerr) < 1e-4, int(np.argmax(gerr))
