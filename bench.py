@@ -219,8 +219,10 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str, tuning=None):
     fetch = per_kernel(fetch_csv, "FETCH_SIZE")
     write = per_kernel(write_csv, "WRITE_SIZE")
     def copy_kib(vals):
-        # the copy dispatches are the ones near 256 MiB; take their median
-        cand = sorted(v for k, vs in vals.items() for v in vs if 0.5 * (COPY_PROBE_BYTES >> 10) < v < 2.0 * (COPY_PROBE_BYTES >> 10))
+        # the probe's copy dispatches: the runtime's copy kernel reading more than a quarter of the probe's bytes
+        # (the other copies are small uploads); their median
+        cand = sorted(v for k, vs in vals.items() if "copyBuffer" in k for v in vs
+                      if v > 0.25 * (COPY_PROBE_BYTES >> 10))
         return cand[len(cand) // 2]
     f_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(fetch)
     w_scale = (COPY_PROBE_BYTES / 1024.0) / copy_kib(write)
