@@ -472,10 +472,12 @@ __device__ __forceinline__ void wgrad_from_tiles(float (*T0)[kTs], float (*T1)[k
     __builtin_amdgcn_s_setprio(0);
 }
 
+// padb (width below 32): the hidden layers' bias gradients come out of the weight-gradient
+// products as column 31 (see tile_backward); otherwise they are column sums in VA
 template <int L, int NH>
 __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[kTs], float (*T1)[kTs], int lane,
                                               float x, float y, float ub, float uxb, float uyb, float eb,
-                                              const Acts<L> &K, GradAcc<L> &G, float (*VA)[64]) {
+                                              const Acts<L> &K, GradAcc<L> &G, float (*VA)[64], bool padb) {
     const int g = lane >> 4;
     Vec abar, txbar, tybar;
     {
@@ -532,11 +534,20 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
                 zb.v[m][r] = fmaf(-2.0f * a, ssbar, s * abar.v[m][r]);
             }
         // weight gradient with the inputs of layer l: a_{l-1} and t_{l-1} = s_{l-1} p_{l-1}
-        // (layer 1: s_1 times a W1 column), formed while writing the transpose tile
+        // (layer 1: s_1 times a W1 column), formed while writing the transpose tile.  With a
+        // padding neuron (width below 32) its input slot 31 is set to 1 in the transpose tile
+        // of the value stream, so dW_l[:, 31] = sum_p zbar = db_l comes out of the same
+        // products (the slot's weights are zero and its gradient is otherwise unused)
         put_t(T0, lane, zb);
-        put_t(T1, lane, K.a[l - 2]);
+        if (padb) {
+            Vec ab = K.a[l - 2];
+            if ((lane >> 4) == 3) ab.v[1][3] = 1.0f;  // neuron 16 + 4*3 + 3 = 31
+            put_t(T1, lane, ab);
+        } else {
+            put_t(T1, lane, K.a[l - 2]);
+        }
         wgrad_from_tiles(T0, T1, lane, G.w[l - 2]);
-        VA[l - 1][lane] += col_sum(T0, lane);
+        if (!padb) VA[l - 1][lane] += col_sum(T0, lane);
         wave_sync();
         put_t(T0, lane, pxb);
         if (l - 1 == 1) put_t_tangent1<L>(T1, lane, K.a[0], S, 0);
@@ -1233,9 +1244,11 @@ __global__ __launch_bounds__(kCThreads) void k_contract_mf(ContractArgs A) {
     contract_flush(A, c, lrr, lra, lp, tid, wave, lane);
 }
 
-// one wavefront's gradient sums in padded order -> P (op: store, or add to what P holds)
+// one wavefront's gradient sums in padded order -> P (op: store, or add to what P holds).
+// padb: the biases of layers 2..L are column 31 of the weight-gradient tiles (tile_backward)
 template <int L, bool ADD, int NH>
-__device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const float (*VA)[64], int lane) {
+__device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const float (*VA)[64], int lane,
+                                            bool padb) {
     const int g = lane >> 4, c = lane & 15, hi = lane ^ 32;
     const bool lo = lane < 32;
     constexpr int NW = 16 * (L > 1 ? L - 1 : 0);
@@ -1277,9 +1290,22 @@ __device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const
             for (int r = 0; r < 4; ++r)
                 P[off_w(l) + (16 * (t >> 1) + 4 * g + r) * PW + 16 * (t & 1) + c] =
                     ADD ? G.w[l - 2][t][r] + cw[16 * (l - 2) + 4 * t + r] : G.w[l - 2][t][r];
+    if (padb && c == 15) {
+        // column 31 (t odd, c = 15) of layer l's tile is db_l at row 16 (t >> 1) + 4 g + r
+#pragma unroll
+        for (int l = 2; l <= L; ++l)
+#pragma unroll
+            for (int t = 1; t < 4; t += 2)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float *d = P + off_b(l) + 16 * (t >> 1) + 4 * g + r;
+                    *d = ADD ? G.w[l - 2][t][r] + *d : G.w[l - 2][t][r];
+                }
+    }
     if (lo) {
 #pragma unroll
         for (int l = 1; l <= L; ++l) {
+            if (padb && l >= 2) continue;
             const float v = VA[l - 1][lane] + VA[l - 1][hi];
             P[off_b(l) + lane] = ADD ? v + cv[l - 1] : v;
         }
@@ -1305,13 +1331,13 @@ __device__ __forceinline__ void put_partial(float *P, const GradAcc<L> &G, const
 // add theirs, and the four regions are added on the way out.
 template <int L, int NH, class SH>
 __device__ __forceinline__ void flush_grad(SH &S, float *gpart, int64_t row, GradAcc<L> &G, int tid, int wave,
-                                           int lane) {
+                                           int lane, bool padb) {
     static_assert(kBWaves == 8, "pairwise flush assumes eight wavefronts");
     float *mine = (wave >> 1) == 0 ? S.red : S.part[(wave >> 1) - 1];
     __syncthreads();
-    if (wave & 1) put_partial<L, false, NH>(mine, G, S.vacc[wave], lane);
+    if (wave & 1) put_partial<L, false, NH>(mine, G, S.vacc[wave], lane, padb);
     __syncthreads();
-    if (!(wave & 1)) put_partial<L, true, NH>(mine, G, S.vacc[wave], lane);
+    if (!(wave & 1)) put_partial<L, true, NH>(mine, G, S.vacc[wave], lane, padb);
     __syncthreads();
     for (int j = tid; j < n_pad_h(L, NH); j += kBThreads)
         gpart[row * kMaxPadded + j] = (S.red[j] + S.part[0][j]) + (S.part[1][j] + S.part[2][j]);
@@ -1391,9 +1417,9 @@ __global__ __launch_bounds__(kBThreads, 1) void k_bwd(BwdArgs A) {
                 Vec a, tx, ty;
                 tile_forward<L, true>(S.W, lane, p.x, p.y, a, tx, ty, K);
             }
-            tile_backward<L, NH>(S.W, T0, T1, lane, p.x, p.y, ub, uxb, uyb, eb, K, G, S.vacc[wave]);
+            tile_backward<L, NH>(S.W, T0, T1, lane, p.x, p.y, ub, uxb, uyb, eb, K, G, S.vacc[wave], A.H < PW);
         }
-        flush_grad<L, NH>(S, A.gpart, row, G, tid, wave, lane);
+        flush_grad<L, NH>(S, A.gpart, row, G, tid, wave, lane, A.H < PW);
         t = seg_end;
         ++cur;
     }
@@ -1604,7 +1630,8 @@ __global__ __launch_bounds__(kBThreads, 1) void k_step(StepArgs A) {
                 add_loss(S.lp, wave, lane, 2, lbb, lss);
             }
             if (A.want_grad && active)
-                tile_backward<L, 1>(S.W, T0, T1, lane, xy.x, xy.y, ub, uxb, uyb, 0.f, K, G, S.vacc[wave]);
+                tile_backward<L, 1>(S.W, T0, T1, lane, xy.x, xy.y, ub, uxb, uyb, 0.f, K, G, S.vacc[wave],
+                                    A.H < PW);
         }
         // the block's loss sums for this instance, wavefronts added in order -> its loss row
         __syncthreads();
@@ -1613,7 +1640,7 @@ __global__ __launch_bounds__(kBThreads, 1) void k_step(StepArgs A) {
             for (int w = 0; w < kBWaves; ++w) v += S.lp[w][tid];
             A.lpart[(Ip->lrow0 + rel) * 4 + tid] = v;
         }
-        if (A.want_grad) flush_grad<L, 1>(S, A.gpart, Ip->grow0 + rel, G, tid, wave, lane);
+        if (A.want_grad) flush_grad<L, 1>(S, A.gpart, Ip->grow0 + rel, G, tid, wave, lane, A.H < PW);
         ++cur;
     }
 }

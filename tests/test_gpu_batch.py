@@ -716,3 +716,25 @@ def test_c5_one_pass_full(V, torch, c5_oracle):
     print(f"c5 one-pass: max loss rel err {max(lerr):.2e}, max grad rel L2 err {max(gerr):.2e}")
     assert max(lerr) < 1e-5, int(np.argmax(lerr))
     assert max(gerr) < 1e-4, int(np.argmax(gerr))
+
+
+@pytest.mark.parametrize("width,n_hidden", [(32, 3), (31, 2), (16, 4), (30, 1)])
+def test_widths_without_and_with_a_padding_neuron(V, torch, width, n_hidden):
+    """The hidden layers' bias gradients come out of the weight-gradient products through padding slot 31 when the
+    width is below 32, and out of column sums at width 32: both against the oracle, on both step kernels."""
+    from oracle import oracle as O
+    probs = _mixed_instances()[:3]
+    for p in probs:
+        p.width, p.n_hidden = width, n_hidden
+    gp = [_gpu(V, p) for p in probs]
+    b = V.vpinn_batch_create(gp, V.loss_cfg(width, n_hidden, 10.0, 5.0))
+    n = V.vpinn_n_params(width, n_hidden)
+    th = np.stack([gen.glorot_params(width, n_hidden, 40 + i, 0.1, name=f"w{width}") for i in range(len(probs))])
+    T = torch.tensor(th, dtype=torch.float32, device="cuda:0")
+    refs = [O.problem_loss_grad(p, O.assemble_problem(p), th[i]) for i, p in enumerate(probs)]
+    for one_pass in (0, 1):
+        V.vpinn_batch_set_tuning(b, 12, 0, 4, 0, one_pass)
+        L, G = _batch_eval(V, torch, b, T, len(probs), n)
+        for i, ref in enumerate(refs):
+            assert abs(L[i, 0] - ref.loss[0]) / ref.loss[0] < 1e-5, (one_pass, i)
+            assert np.linalg.norm(G[i] - ref.grad) / np.linalg.norm(ref.grad) < 1e-4, (one_pass, i)
