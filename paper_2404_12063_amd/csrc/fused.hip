@@ -447,28 +447,53 @@ __device__ __forceinline__ void put_t_tangent1(float (*T)[kTs], int lane, const 
     }
 }
 
-// T0 holds the out-side vector, T1 the in-side one: dW += sum over points (MFMA, K = points)
-__device__ __forceinline__ void wgrad_from_tiles(float (*T0)[kTs], float (*T1)[kTs], int lane, f4 acc[4]) {
+// operands of one weight-gradient product, read from the transpose tiles (T0 the out-side
+// vector, T1 the in-side one; K = the tile's 16 points)
+struct WOps {
+    float a0[4], a1[4], b0[4], b1[4];
+};
+
+__device__ __forceinline__ void wgrad_read(float (*T0)[kTs], float (*T1)[kTs], int lane, WOps &o) {
     wave_sync();
     const int c = lane & 15, k = lane >> 4;
-    // every operand read is issued before the first product
-    float a0[4], a1[4], b0[4], b1[4];
 #pragma unroll
     for (int kp = 0; kp < 4; ++kp) {
-        a0[kp] = T0[4 * kp + k][c];
-        a1[kp] = T0[4 * kp + k][16 + c];
-        b0[kp] = T1[4 * kp + k][c];
-        b1[kp] = T1[4 * kp + k][16 + c];
+        o.a0[kp] = T0[4 * kp + k][c];
+        o.a1[kp] = T0[4 * kp + k][16 + c];
+        o.b0[kp] = T1[4 * kp + k][c];
+        o.b1[kp] = T1[4 * kp + k][16 + c];
     }
+}
+
+// dW += sum over points (MFMA, K = points)
+__device__ __forceinline__ void wgrad_mma(const WOps &o, f4 acc[4]) {
+#pragma unroll
+    for (int kp = 0; kp < 4; ++kp) {
+        acc[0] = mfma(o.a0[kp], o.b0[kp], acc[0]);
+        acc[1] = mfma(o.a0[kp], o.b1[kp], acc[1]);
+        acc[2] = mfma(o.a1[kp], o.b0[kp], acc[2]);
+        acc[3] = mfma(o.a1[kp], o.b1[kp], acc[3]);
+    }
+}
+
+// one stream of a layer's reverse sweep: its propagation W_l^T vbar (into out) and its
+// weight gradient vbar x in (into acc).  The transpose tiles are read first and the
+// propagation's products, which need no LDS, run while those reads are in flight.
+__device__ __forceinline__ void stream_back(float (*T0)[kTs], float (*T1)[kTs], int lane, const float (&wv)[2][8],
+                                            const Vec &vb, f4 (&out)[2], f4 acc[4]) {
+    WOps o;
+    wgrad_read(T0, T1, lane, o);
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-    for (int kp = 0; kp < 4; ++kp) {
-        acc[0] = mfma(a0[kp], b0[kp], acc[0]);
-        acc[1] = mfma(a0[kp], b1[kp], acc[1]);
-        acc[2] = mfma(a1[kp], b0[kp], acc[2]);
-        acc[3] = mfma(a1[kp], b1[kp], acc[3]);
+    for (int mi = 0; mi < 2; ++mi) {
+        f4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v = mfma(wv[mi][s], vb.v[s >> 2][s & 3], v);
+        out[mi] = v;
     }
+    __builtin_amdgcn_sched_barrier(0);
+    wgrad_mma(o, acc);
     __builtin_amdgcn_s_setprio(0);
 }
 
@@ -538,6 +563,15 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
         // padding neuron (width below 32) its input slot 31 is set to 1 in the transpose tile
         // of the value stream, so dW_l[:, 31] = sum_p zbar = db_l comes out of the same
         // products (the slot's weights are zero and its gradient is otherwise unused)
+        // W_l^T fragments of the propagation (abar = W_l^T zbar, tbar = W_l^T pbar), read once
+        // for the three streams
+        float wv[2][8];
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) wv[mi][s] = S.wf[l - 2][1][mi][s][lane];
+        f4 pa[2], px[2], py[2];
+        // stream 1: zbar with a_{l-1}; 2: pbar^x with t^x_{l-1}; 3: pbar^y with t^y_{l-1}
         put_t(T0, lane, zb);
         if (padb) {
             Vec ab = K.a[l - 2];
@@ -546,39 +580,24 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
         } else {
             put_t(T1, lane, K.a[l - 2]);
         }
-        wgrad_from_tiles(T0, T1, lane, G.w[l - 2]);
+        stream_back(T0, T1, lane, wv, zb, pa, G.w[l - 2]);
         if (!padb) VA[l - 1][lane] += col_sum(T0, lane);
         wave_sync();
         put_t(T0, lane, pxb);
         if (l - 1 == 1) put_t_tangent1<L>(T1, lane, K.a[0], S, 0);
         else put_t(T1, lane, K.tx[l - 2]);
-        wgrad_from_tiles(T0, T1, lane, G.w[l - 2]);
+        stream_back(T0, T1, lane, wv, pxb, px, G.w[l - 2]);
         wave_sync();
         put_t(T0, lane, pyb);
         if (l - 1 == 1) put_t_tangent1<L>(T1, lane, K.a[0], S, 1);
         else put_t(T1, lane, K.ty[l - 2]);
-        wgrad_from_tiles(T0, T1, lane, G.w[l - 2]);
+        stream_back(T0, T1, lane, wv, pyb, py, G.w[l - 2]);
         wave_sync();
-        // propagate: abar = W_l^T zbar, tbar = W_l^T pbar
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
-            f4 sa = {0.f, 0.f, 0.f, 0.f}, sx = {0.f, 0.f, 0.f, 0.f}, sy = {0.f, 0.f, 0.f, 0.f};
-            float wv[8];
-#pragma unroll
-            for (int s = 0; s < 8; ++s) wv[s] = S.wf[l - 2][1][mi][s][lane];
-            __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const float w = wv[s];
-                sa = mfma(w, zb.v[s >> 2][s & 3], sa);
-                sx = mfma(w, pxb.v[s >> 2][s & 3], sx);
-                sy = mfma(w, pyb.v[s >> 2][s & 3], sy);
-            }
-            __builtin_amdgcn_s_setprio(0);
-            abar.v[mi] = sa;
-            txbar.v[mi] = sx;
-            tybar.v[mi] = sy;
+            abar.v[mi] = pa[mi];
+            txbar.v[mi] = px[mi];
+            tybar.v[mi] = py[mi];
         }
     }
     // layer 1: t_1 = s_1 W1[:, c], z_1 = W1 (x, y) + b_1
