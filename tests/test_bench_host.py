@@ -84,3 +84,22 @@ def test_argument_errors_exit_before_any_device_work(args):
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args, capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and r.stdout == "" and "error" in r.stderr
+
+
+def test_oracle_pool_equals_the_oracle_called_in_turn():
+    """The CPU baseline of the batched workload runs the unchanged oracle one instance per task on host threads:
+    each instance's loss and gradient must be exactly those of a plain call (threads change nothing in FP64), the
+    epoch's wall time positive and the one-thread time the sum of the instances' times."""
+    from oracle import oracle as O
+    import numpy as np
+    probs = gen.batched_instances(3, seed=4, lo=16, hi=48)
+    th = np.stack([p.params(seed=11 + i, bias_scale=0.1) for i, p in enumerate(probs)])
+    ref, wall, osum = bench.oracle_batched(probs, th, threads=2)
+    assert wall > 0 and osum > 0
+    for i, p in enumerate(probs):
+        r = O.problem_loss_grad(p, O.assemble_problem(p), th[i])
+        assert np.array_equal(ref[i].loss, r.loss) and np.array_equal(ref[i].grad, r.grad), i
+
+
+def test_pool_threads_stay_within_one_gpu_share():
+    assert 1 <= bench.pool_threads() <= 16

@@ -432,3 +432,37 @@ def test_large_element_loss_without_gradient(V, torch, m, n, nt):
     ref = O.problem_loss_grad(prob, O.assemble_problem(prob), theta, want_grad=False)
     assert abs(float(l1[0]) - ref.loss[0]) <= LOSS_RTOL * abs(ref.loss[0])
     assert torch.equal(l1, l2)
+
+
+def test_changed_weighting_on_another_stream_keeps_earlier_results(V, torch):
+    """A problem's cached plan is rebuilt when tau changes; the rebuild rewrites device descriptors, so it must wait
+    for earlier calls still running on other streams: a call with tau = 10 on one stream, followed at once by a call
+    with tau = 1 on another, gives each its own loss (each against its own solitary evaluation)."""
+    prob = gen.config_c4()
+    p = V.assemble_problem(prob)
+    dev = torch.device("cuda:0")
+    th = torch.tensor(prob.params(bias_scale=0.1), dtype=torch.float32, device=dev)
+    eps = torch.tensor([0.7], device=dev)
+    n = th.numel()
+
+    def solo(tau):
+        l, g = torch.zeros(4, device=dev), torch.zeros(n, device=dev)
+        V.vpinn_loss_and_grad(p, V.loss_cfg(30, 3, tau, 10.0), th, eps=eps, loss=l, grad=g)
+        torch.cuda.synchronize()
+        return l.cpu().numpy(), g.cpu().numpy()
+
+    want10, want1 = solo(10.0), solo(1.0)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for _ in range(3):
+        l10, g10 = torch.zeros(4, device=dev), torch.zeros(n, device=dev)
+        l1, g1 = torch.zeros(4, device=dev), torch.zeros(n, device=dev)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s1):
+            V.vpinn_loss_and_grad(p, V.loss_cfg(30, 3, 10.0, 10.0), th, eps=eps, loss=l10, grad=g10, stream=s1)
+        with torch.cuda.stream(s2):
+            V.vpinn_loss_and_grad(p, V.loss_cfg(30, 3, 1.0, 10.0), th, eps=eps, loss=l1, grad=g1, stream=s2)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(l10.cpu().numpy(), want10[0])
+        np.testing.assert_array_equal(g10.cpu().numpy(), want10[1])
+        np.testing.assert_array_equal(l1.cpu().numpy(), want1[0])
+        np.testing.assert_array_equal(g1.cpu().numpy(), want1[1])
