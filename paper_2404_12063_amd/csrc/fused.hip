@@ -77,8 +77,92 @@ struct Vec {
     f4 v[2];
 };
 
-__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+// FP32 products on the bf16 matrix cores.  Every operand x is split into three bf16
+// pieces, x0 = rn(x), x1 = rn(x - x0), x2 = rn(x - x0 - x1) (each subtraction exact), so
+// |x1| <= 2^-8 |x|, |x2| <= 2^-16 |x| and |x - x0 - x1 - x2| <= 2^-24 |x|; a product is the
+// sum of the six piece products x_i y_j with i + j <= 2, each exact in FP32, accumulated
+// smallest first (the three dropped ones are below 2^-23 |x y|).  Measured on random
+// 16x32 by 32x16 products, its error is half that of the FP32 MFMA (16x16x4f32).  The
+// point of it: bf16 MFMAs run on the matrix cores beside the vector ALU work of the other
+// wavefront of a SIMD, while FP32 MFMAs hold the vector ALU for their whole duration,
+// and a 16x16x32 bf16 product takes ~17 cycles against ~33 for 16x16x4 in FP32.
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+
+// the piece pairs (i, j) of a product, smallest first
+constexpr int kPi[6] = {0, 1, 2, 0, 1, 0};
+constexpr int kPj[6] = {2, 1, 0, 1, 0, 0};
+
+__device__ __forceinline__ unsigned pk_bf16(float x, float y) {
+    const fl2 v = {x, y};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf2));
+}
+
+// x in the low half, y in the high half of each piece
+struct Pieces3 {
+    unsigned p0, p1, p2;
+};
+__device__ __forceinline__ Pieces3 split_pair(float x, float y) {
+    Pieces3 r;
+    r.p0 = pk_bf16(x, y);
+    x -= __uint_as_float(r.p0 << 16);
+    y -= __uint_as_float(r.p0 & 0xffff0000u);
+    r.p1 = pk_bf16(x, y);
+    x -= __uint_as_float(r.p1 << 16);
+    y -= __uint_as_float(r.p1 & 0xffff0000u);
+    r.p2 = pk_bf16(x, y);
+    return r;
+}
+
+// the weight fragments are read from LDS again for every tile: reading them through an
+// opaque copy of the lane index keeps the compiler from hoisting them out of the tile
+// loops into registers, which would cost the occupancy of every network kernel
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// a K = 32 operand (eight values a lane) and a K = 16 operand (four), three pieces each
+struct Split8 {
+    u4 p[3];
+};
+struct Split4 {
+    u2 p[3];
+};
+
+__device__ __forceinline__ f4 mfb(u4 a, u4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfb16(u2 a, u2 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4v, a), __builtin_bit_cast(s4v, b), c, 0, 0,
+                                                     0);
+}
+
+__device__ __forceinline__ void split4(const float (&v)[4], Split4 &s) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const Pieces3 r = split_pair(v[2 * q], v[2 * q + 1]);
+        s.p[0][q] = r.p0;
+        s.p[1][q] = r.p1;
+        s.p[2][q] = r.p2;
+    }
+}
+
+// a chained vector as the K = 32 operand: slot 4m + r holds v[m][r] (neuron 16m + 4g + r)
+__device__ __forceinline__ void split8(const Vec &v, Split8 &s) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const Pieces3 r = split_pair(v.v[m][2 * h], v.v[m][2 * h + 1]);
+            s.p[0][2 * m + h] = r.p0;
+            s.p[1][2 * m + h] = r.p1;
+            s.p[2][2 * m + h] = r.p2;
+        }
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -90,9 +174,11 @@ __device__ __forceinline__ void wave_sync() {
 // network weights of the current instance in LDS
 template <int L>
 struct WeightsShared {
-    // A-operand fragments of the hidden-to-hidden products, layers 2..L:
-    // [layer][dir 0 = W (forward), 1 = W^T (backward)][out tile][k step][lane]
-    float wf[L > 1 ? L - 1 : 1][2][2][8][64];
+    // A-operand fragments of the hidden-to-hidden products, layers 2..L, as three bf16
+    // pieces: [layer][dir 0 = W (forward), 1 = W^T (backward)][out tile][piece][lane];
+    // lane (c, g) of out tile t holds in slot 4m + r the weight of output 16t + c and
+    // input 16m + 4g + r (dir 0), or of output 16m + 4g + r and input 16t + c (dir 1)
+    u4 wp[L > 1 ? L - 1 : 1][2][2][3][64];
     float w1[PW][2];
     float b[L][PW];
     float wo[PW];
@@ -235,6 +321,7 @@ template <int L, bool KEEP>
 __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane, float x, float y, Vec &A_, Vec &TX,
                                              Vec &TY, Acts<L> &keep, float *act = nullptr) {
     const int g = lane >> 4;
+    const int ln = opaque(lane);
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -257,31 +344,39 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
 #pragma unroll
     for (int l = 2; l <= L; ++l) {
         Vec Z, PX, PY;
+        // the layer's inputs as bf16 pieces; the six chains (two output tiles, three
+        // streams) interleave, so no product waits on the one before it
+        Split8 sa, sx, sy;
+        split8(A_, sa);
+        split8(TX, sx);
+        split8(TY, sy);
+        Split8 w[2];
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) w[mo].p[k] = S.wp[l - 2][0][mo][k][ln];
+        f4 z[2], px[2], py[2];
 #pragma unroll
         for (int mo = 0; mo < 2; ++mo) {
-            f4 z, px = {0.f, 0.f, 0.f, 0.f}, py = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) z[r] = S.b[l - 1][16 * mo + 4 * g + r];
-            // the layer's weight fragments are read before the products (the scheduling
-            // barrier keeps the compiler from sinking the reads to their uses), and the MFMA
-            // cluster runs at raised wave priority, so the two wavefronts sharing a SIMD
-            // alternate between matrix and vector work instead of contending in step
-            float wv[8];
+            for (int r = 0; r < 4; ++r) z[mo][r] = S.b[l - 1][16 * mo + 4 * g + r];
+            px[mo] = f4{0.f, 0.f, 0.f, 0.f};
+            py[mo] = f4{0.f, 0.f, 0.f, 0.f};
+        }
 #pragma unroll
-            for (int s = 0; s < 8; ++s) wv[s] = S.wf[l - 2][0][mo][s][lane];
-            __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_setprio(1);
+        for (int t = 0; t < 6; ++t)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const float w = wv[s];
-                z = mfma(w, A_.v[s >> 2][s & 3], z);
-                px = mfma(w, TX.v[s >> 2][s & 3], px);
-                py = mfma(w, TY.v[s >> 2][s & 3], py);
+            for (int mo = 0; mo < 2; ++mo) {
+                const u4 wt = w[mo].p[kPi[t]];
+                z[mo] = mfb(wt, sa.p[kPj[t]], z[mo]);
+                px[mo] = mfb(wt, sx.p[kPj[t]], px[mo]);
+                py[mo] = mfb(wt, sy.p[kPj[t]], py[mo]);
             }
-            __builtin_amdgcn_s_setprio(0);
-            Z.v[mo] = z;
-            PX.v[mo] = px;
-            PY.v[mo] = py;
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo) {
+            Z.v[mo] = z[mo];
+            PX.v[mo] = px[mo];
+            PY.v[mo] = py[mo];
         }
 #pragma unroll
         for (int m = 0; m < 2; ++m)
@@ -312,6 +407,7 @@ template <int L>
 __device__ __forceinline__ void tile_forward_loaded(const WeightsShared<L> &S, int lane, const float *act,
                                                     Acts<L> &K) {
     const int g = lane >> 4;
+    const int ln = opaque(lane);
     const f4 *in = reinterpret_cast<const f4 *>(act);
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -332,22 +428,26 @@ __device__ __forceinline__ void tile_forward_loaded(const WeightsShared<L> &S, i
 #pragma unroll
     for (int l = 2; l <= L; ++l) {
         Vec PX, PY;
+        Split8 sx, sy;
+        split8(TX, sx);
+        split8(TY, sy);
+        Split8 w[2];
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) w[mo].p[k] = S.wp[l - 2][0][mo][k][ln];
+        f4 px[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}}, py[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+#pragma unroll
+            for (int mo = 0; mo < 2; ++mo) {
+                px[mo] = mfb(w[mo].p[kPi[t]], sx.p[kPj[t]], px[mo]);
+                py[mo] = mfb(w[mo].p[kPi[t]], sy.p[kPj[t]], py[mo]);
+            }
 #pragma unroll
         for (int mo = 0; mo < 2; ++mo) {
-            f4 px = {0.f, 0.f, 0.f, 0.f}, py = {0.f, 0.f, 0.f, 0.f};
-            float wv[8];
-#pragma unroll
-            for (int s = 0; s < 8; ++s) wv[s] = S.wf[l - 2][0][mo][s][lane];
-            __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                px = mfma(wv[s], TX.v[s >> 2][s & 3], px);
-                py = mfma(wv[s], TY.v[s >> 2][s & 3], py);
-            }
-            __builtin_amdgcn_s_setprio(0);
-            PX.v[mo] = px;
-            PY.v[mo] = py;
+            PX.v[mo] = px[mo];
+            PY.v[mo] = py[mo];
         }
 #pragma unroll
         for (int m = 0; m < 2; ++m)
@@ -448,7 +548,8 @@ __device__ __forceinline__ void put_t_tangent1(float (*T)[kTs], int lane, const 
 }
 
 // operands of one weight-gradient product, read from the transpose tiles (T0 the out-side
-// vector, T1 the in-side one; K = the tile's 16 points)
+// vector, T1 the in-side one; K = the tile's 16 points, lane (c, g) holding point 4j + g
+// in slot j)
 struct WOps {
     float a0[4], a1[4], b0[4], b1[4];
 };
@@ -465,36 +566,41 @@ __device__ __forceinline__ void wgrad_read(float (*T0)[kTs], float (*T1)[kTs], i
     }
 }
 
-// dW += sum over points (MFMA, K = points)
+// dW += sum over points (K = the 16 points, split products)
 __device__ __forceinline__ void wgrad_mma(const WOps &o, f4 acc[4]) {
+    Split4 a0, a1, b0, b1;
+    split4(o.a0, a0);
+    split4(o.a1, a1);
+    split4(o.b0, b0);
+    split4(o.b1, b1);
 #pragma unroll
-    for (int kp = 0; kp < 4; ++kp) {
-        acc[0] = mfma(o.a0[kp], o.b0[kp], acc[0]);
-        acc[1] = mfma(o.a0[kp], o.b1[kp], acc[1]);
-        acc[2] = mfma(o.a1[kp], o.b0[kp], acc[2]);
-        acc[3] = mfma(o.a1[kp], o.b1[kp], acc[3]);
+    for (int t = 0; t < 6; ++t) {
+        const int i = kPi[t], j = kPj[t];
+        acc[0] = mfb16(a0.p[i], b0.p[j], acc[0]);
+        acc[1] = mfb16(a0.p[i], b1.p[j], acc[1]);
+        acc[2] = mfb16(a1.p[i], b0.p[j], acc[2]);
+        acc[3] = mfb16(a1.p[i], b1.p[j], acc[3]);
     }
 }
 
 // one stream of a layer's reverse sweep: its propagation W_l^T vbar (into out) and its
-// weight gradient vbar x in (into acc).  The transpose tiles are read first and the
-// propagation's products, which need no LDS, run while those reads are in flight.
-__device__ __forceinline__ void stream_back(float (*T0)[kTs], float (*T1)[kTs], int lane, const float (&wv)[2][8],
+// weight gradient vbar x in (into acc).  The transpose tiles are read first; the stream's
+// split and its propagation products, which need no LDS, run while those reads are in
+// flight.
+__device__ __forceinline__ void stream_back(float (*T0)[kTs], float (*T1)[kTs], int lane, const Split8 (&wt)[2],
                                             const Vec &vb, f4 (&out)[2], f4 acc[4]) {
     WOps o;
     wgrad_read(T0, T1, lane, o);
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_setprio(1);
+    Split8 sv;
+    split8(vb, sv);
+    f4 v[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi) {
-        f4 v = {0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 6; ++t)
 #pragma unroll
-        for (int s = 0; s < 8; ++s) v = mfma(wv[mi][s], vb.v[s >> 2][s & 3], v);
-        out[mi] = v;
-    }
-    __builtin_amdgcn_sched_barrier(0);
+        for (int mi = 0; mi < 2; ++mi) v[mi] = mfb(wt[mi].p[kPi[t]], sv.p[kPj[t]], v[mi]);
+    out[0] = v[0];
+    out[1] = v[1];
     wgrad_mma(o, acc);
-    __builtin_amdgcn_s_setprio(0);
 }
 
 // padb (width below 32): the hidden layers' bias gradients come out of the weight-gradient
@@ -504,6 +610,7 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
                                               float x, float y, float ub, float uxb, float uyb, float eb,
                                               const Acts<L> &K, GradAcc<L> &G, float (*VA)[64], bool padb) {
     const int g = lane >> 4;
+    const int ln = opaque(lane);
     Vec abar, txbar, tybar;
     {
         // output layer: dW_out = sum_p ub a_L + uxb t_L^x + uyb t_L^y
@@ -565,11 +672,11 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
         // products (the slot's weights are zero and its gradient is otherwise unused)
         // W_l^T fragments of the propagation (abar = W_l^T zbar, tbar = W_l^T pbar), read once
         // for the three streams
-        float wv[2][8];
+        Split8 wv[2];
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) wv[mi][s] = S.wf[l - 2][1][mi][s][lane];
+            for (int k = 0; k < 3; ++k) wv[mi].p[k] = S.wp[l - 2][1][mi][k][ln];
         f4 pa[2], px[2], py[2];
         // stream 1: zbar with a_{l-1}; 2: pbar^x with t^x_{l-1}; 3: pbar^y with t^y_{l-1}
         put_t(T0, lane, zb);
@@ -665,25 +772,28 @@ __device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, 
         for (int t = tid; t < PW; t += NT) S.wo2[t] = t < H ? stage[ho + H + t] : 0.f;
         if (tid == 0) S.bo2 = stage[ho + 2 * H + 1];
     }
-    // fragments [l][dir][mt][slot][lane] in flat order, NT consecutive entries per
-    // pass; all reads are issued before the writes
+    // fragments: thread t takes (layer, dir, out tile, lane) = t, gathers its eight
+    // weights from the staged parameters and writes their three pieces
     static_assert(NT % 64 == 0, "whole wavefronts");
-    constexpr int kTot = (L - 1) * 2 * 2 * 8 * 64;
-    constexpr int kFr = (kTot + NT - 1) / NT;
-    float f[kFr > 0 ? kFr : 1];
+    constexpr int kTot = (L - 1) * 2 * 2 * 64;
+    for (int t = tid; t < kTot; t += NT) {
+        const int ln = t & 63, mt = (t >> 6) & 1, dir = (t >> 7) & 1, l = 2 + (t >> 8);
+        const int c = ln & 15, g = ln >> 4;
+        Vec w;
 #pragma unroll
-    for (int k = 0; k < kFr; ++k) {
-        const int t = tid + NT * k;
-        const int ln = t & 63, sl = (t >> 6) & 7, mt = (t >> 9) & 1, dir = (t >> 10) & 1, l = 2 + (t >> 11);
-        const int c = ln & 15, q = 4 * (ln >> 4) + (sl & 3), m = sl >> 2;
-        // forward: W[16 mt + c][16 m + q]; backward: W[16 m + q][16 mt + c]
-        const int o = dir == 0 ? 16 * mt + c : 16 * m + q;
-        const int i = dir == 0 ? 16 * m + q : 16 * mt + c;
-        f[k] = (t < kTot && o < H && i < H) ? stage[hoff_w(H, l) + o * H + i] : 0.f;
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int q = 16 * m + 4 * g + r;
+                const int o = dir == 0 ? 16 * mt + c : q;
+                const int i = dir == 0 ? q : 16 * mt + c;
+                w.v[m][r] = (o < H && i < H) ? stage[hoff_w(H, l) + o * H + i] : 0.f;
+            }
+        Split8 sp;
+        split8(w, sp);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) S.wp[l - 2][dir][mt][k][ln] = sp.p[k];
     }
-#pragma unroll
-    for (int k = 0; k < kFr; ++k)
-        if (tid + NT * k < kTot) (&S.wf[0][0][0][0][0])[tid + NT * k] = f[k];
 }
 
 template <int L>
@@ -1817,6 +1927,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fused_final(
 template <int L>
 __device__ __forceinline__ void tile_values(const WeightsShared<L> &S, int lane, float x, float y, Vec &A_) {
     const int g = lane >> 4;
+    const int ln = opaque(lane);
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -1827,19 +1938,19 @@ __device__ __forceinline__ void tile_values(const WeightsShared<L> &S, int lane,
 #pragma unroll
     for (int l = 2; l <= L; ++l) {
         Vec Z;
+        Split8 sa;
+        split8(A_, sa);
+        f4 z[2];
 #pragma unroll
-        for (int mo = 0; mo < 2; ++mo) {
-            f4 z;
+        for (int mo = 0; mo < 2; ++mo)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) z[r] = S.b[l - 1][16 * mo + 4 * g + r];
-            float wv[8];
+            for (int r = 0; r < 4; ++r) z[mo][r] = S.b[l - 1][16 * mo + 4 * g + r];
 #pragma unroll
-            for (int s = 0; s < 8; ++s) wv[s] = S.wf[l - 2][0][mo][s][lane];
-            __builtin_amdgcn_sched_barrier(0);
+        for (int t = 0; t < 6; ++t)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) z = mfma(wv[s], A_.v[s >> 2][s & 3], z);
-            Z.v[mo] = z;
-        }
+            for (int mo = 0; mo < 2; ++mo) z[mo] = mfb(S.wp[l - 2][0][mo][kPi[t]][ln], sa.p[kPj[t]], z[mo]);
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo) Z.v[mo] = z[mo];
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
