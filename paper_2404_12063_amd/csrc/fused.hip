@@ -547,50 +547,48 @@ __device__ __forceinline__ void put_t_tangent1(float (*T)[kTs], int lane, const 
     }
 }
 
-// operands of one weight-gradient product, read from the transpose tiles (T0 the out-side
-// vector, T1 the in-side one; K = the tile's 16 points, lane (c, g) holding point 4j + g
-// in slot j)
-struct WOps {
-    float a0[4], a1[4], b0[4], b1[4];
-};
-
-__device__ __forceinline__ void wgrad_read(float (*T0)[kTs], float (*T1)[kTs], int lane, WOps &o) {
-    wave_sync();
-    const int c = lane & 15, k = lane >> 4;
-#pragma unroll
-    for (int kp = 0; kp < 4; ++kp) {
-        o.a0[kp] = T0[4 * kp + k][c];
-        o.a1[kp] = T0[4 * kp + k][16 + c];
-        o.b0[kp] = T1[4 * kp + k][c];
-        o.b1[kp] = T1[4 * kp + k][16 + c];
-    }
+// identity operand of the in-register transposes (K = 16): lane (n, g) holds 1 in slot j
+// where 4g + j = n
+__device__ __forceinline__ u2 ident16(int lane) {
+    const int j = (lane & 15) - 4 * (lane >> 4);
+    const unsigned one = 0x3f80u;  // bf16 1.0
+    return u2{(j == 0 ? one : 0u) | (j == 1 ? one << 16 : 0u), (j == 2 ? one : 0u) | (j == 3 ? one << 16 : 0u)};
 }
 
-// dW += sum over points (K = the 16 points, split products)
-__device__ __forceinline__ void wgrad_mma(const WOps &o, f4 acc[4]) {
-    Split4 a0, a1, b0, b1;
-    split4(o.a0, a0);
-    split4(o.a1, a1);
-    split4(o.b0, b0);
-    split4(o.b1, b1);
+// a split chained vector transposed in registers: per half m and piece k, D = A I with A
+// the piece's half (rows = the 16 points, K = the half's 16 neurons), so lane (n, g) gets
+// neuron 16m + n at points 4g + r, the K = points operand of the weight-gradient products
+// (slot r = point 4g + r).  Every value is a bf16 times 1, so D and its repacking are exact.
+__device__ __forceinline__ void transpose_split(const Split8 &s, u2 id, Split4 (&t)[2]) {
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        const int i = kPi[t], j = kPj[t];
-        acc[0] = mfb16(a0.p[i], b0.p[j], acc[0]);
-        acc[1] = mfb16(a0.p[i], b1.p[j], acc[1]);
-        acc[2] = mfb16(a1.p[i], b0.p[j], acc[2]);
-        acc[3] = mfb16(a1.p[i], b1.p[j], acc[3]);
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const f4 d = mfb16(u2{s.p[k][2 * m], s.p[k][2 * m + 1]}, id, f4{0.f, 0.f, 0.f, 0.f});
+            t[m].p[k] = u2{pk_bf16(d[0], d[1]), pk_bf16(d[2], d[3])};
+        }
+}
+
+// the in-side operand of one weight-gradient product from the transpose tile T1[point][n]:
+// lane (c, g) holds neurons c and 16 + c at points 4g + j (slot j)
+__device__ __forceinline__ void wgrad_read(float (*T1)[kTs], int lane, float (&b0)[4], float (&b1)[4]) {
+    wave_sync();
+    const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        b0[j] = T1[4 * g + j][c];
+        b1[j] = T1[4 * g + j][16 + c];
     }
 }
 
 // one stream of a layer's reverse sweep: its propagation W_l^T vbar (into out) and its
-// weight gradient vbar x in (into acc).  The transpose tiles are read first; the stream's
-// split and its propagation products, which need no LDS, run while those reads are in
-// flight.
-__device__ __forceinline__ void stream_back(float (*T0)[kTs], float (*T1)[kTs], int lane, const Split8 (&wt)[2],
-                                            const Vec &vb, f4 (&out)[2], f4 acc[4]) {
-    WOps o;
-    wgrad_read(T0, T1, lane, o);
+// weight gradient vbar x in (into acc, K = the tile's 16 points).  The transpose tile of
+// the in-side vector is read first; the split of vbar, its propagation products and its
+// in-register transpose, which need no LDS, run while those reads are in flight.
+__device__ __forceinline__ void stream_back(float (*T1)[kTs], int lane, u2 id, const Split8 (&wt)[2], const Vec &vb,
+                                            f4 (&out)[2], f4 acc[4]) {
+    float b0[4], b1[4];
+    wgrad_read(T1, lane, b0, b1);
     Split8 sv;
     split8(vb, sv);
     f4 v[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
@@ -600,7 +598,18 @@ __device__ __forceinline__ void stream_back(float (*T0)[kTs], float (*T1)[kTs], 
         for (int mi = 0; mi < 2; ++mi) v[mi] = mfb(wt[mi].p[kPi[t]], sv.p[kPj[t]], v[mi]);
     out[0] = v[0];
     out[1] = v[1];
-    wgrad_mma(o, acc);
+    Split4 a[2], sb0, sb1;
+    transpose_split(sv, id, a);
+    split4(b0, sb0);
+    split4(b1, sb1);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const int i = kPi[t], j = kPj[t];
+        acc[0] = mfb16(a[0].p[i], sb0.p[j], acc[0]);
+        acc[1] = mfb16(a[0].p[i], sb1.p[j], acc[1]);
+        acc[2] = mfb16(a[1].p[i], sb0.p[j], acc[2]);
+        acc[3] = mfb16(a[1].p[i], sb1.p[j], acc[3]);
+    }
 }
 
 // padb (width below 32): the hidden layers' bias gradients come out of the weight-gradient
@@ -611,6 +620,7 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
                                               const Acts<L> &K, GradAcc<L> &G, float (*VA)[64], bool padb) {
     const int g = lane >> 4;
     const int ln = opaque(lane);
+    const u2 id = ident16(lane);
     Vec abar, txbar, tybar;
     {
         // output layer: dW_out = sum_p ub a_L + uxb t_L^x + uyb t_L^y
@@ -679,26 +689,23 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
             for (int k = 0; k < 3; ++k) wv[mi].p[k] = S.wp[l - 2][1][mi][k][ln];
         f4 pa[2], px[2], py[2];
         // stream 1: zbar with a_{l-1}; 2: pbar^x with t^x_{l-1}; 3: pbar^y with t^y_{l-1}
-        put_t(T0, lane, zb);
         if (padb) {
             Vec ab = K.a[l - 2];
             if ((lane >> 4) == 3) ab.v[1][3] = 1.0f;  // neuron 16 + 4*3 + 3 = 31
             put_t(T1, lane, ab);
         } else {
             put_t(T1, lane, K.a[l - 2]);
+            VA[l - 1][lane] += colsum_vec(T0, lane, zb);
         }
-        stream_back(T0, T1, lane, wv, zb, pa, G.w[l - 2]);
-        if (!padb) VA[l - 1][lane] += col_sum(T0, lane);
+        stream_back(T1, lane, id, wv, zb, pa, G.w[l - 2]);
         wave_sync();
-        put_t(T0, lane, pxb);
         if (l - 1 == 1) put_t_tangent1<L>(T1, lane, K.a[0], S, 0);
         else put_t(T1, lane, K.tx[l - 2]);
-        stream_back(T0, T1, lane, wv, pxb, px, G.w[l - 2]);
+        stream_back(T1, lane, id, wv, pxb, px, G.w[l - 2]);
         wave_sync();
-        put_t(T0, lane, pyb);
         if (l - 1 == 1) put_t_tangent1<L>(T1, lane, K.a[0], S, 1);
         else put_t(T1, lane, K.ty[l - 2]);
-        stream_back(T0, T1, lane, wv, pyb, py, G.w[l - 2]);
+        stream_back(T1, lane, id, wv, pyb, py, G.w[l - 2]);
         wave_sync();
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) {
