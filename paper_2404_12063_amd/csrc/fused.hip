@@ -179,6 +179,9 @@ struct WeightsShared {
     // lane (c, g) of out tile t holds in slot 4m + r the weight of output 16t + c and
     // input 16m + 4g + r (dir 0), or of output 16m + 4g + r and input 16t + c (dir 1)
     u4 wp[L > 1 ? L - 1 : 1][2][2][3][64];
+    // layer 2's tangent products from s_1 = 1 - a_1^2: p_2 = W_2 (s_1 W_1[:, c]) =
+    // (W_2 diag(W_1[:, c])) s_1, so both tangents share one split; [c][out tile][piece][lane]
+    u4 wt2[2][2][3][64];
     float w1[PW][2];
     float b[L][PW];
     float wo[PW];
@@ -332,8 +335,12 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
             const float a = tanh_lean(z);
             const float s = 1.0f - a * a;
             A_.v[m][r] = a;
-            TX.v[m][r] = s * w0;
-            TY.v[m][r] = s * w1v;
+            if (L == 1) {
+                TX.v[m][r] = s * w0;
+                TY.v[m][r] = s * w1v;
+            } else {
+                TX.v[m][r] = s;  // s_1: layer 2 forms both tangents from it
+            }
         }
     if (act) {
         f4 *o = reinterpret_cast<f4 *>(act);
@@ -344,17 +351,15 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
 #pragma unroll
     for (int l = 2; l <= L; ++l) {
         Vec Z, PX, PY;
-        // the layer's inputs as bf16 pieces; the six chains (two output tiles, three
-        // streams) interleave, so no product waits on the one before it
+        // the layer's inputs as bf16 pieces.  Layer 2's TX holds s_1 and its tangents use the two scaled weight sets.  One output
+        // tile at a time (its three chains interleaved), its weights read just before its
+        // products; in the forward pass alone a scheduling barrier keeps the next tile's reads
+        // from being hoisted, which would hold every weight set in registers at once.
+        const bool s1 = l == 2;
         Split8 sa, sx, sy;
         split8(A_, sa);
         split8(TX, sx);
-        split8(TY, sy);
-        Split8 w[2];
-#pragma unroll
-        for (int mo = 0; mo < 2; ++mo)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) w[mo].p[k] = S.wp[l - 2][0][mo][k][ln];
+        if (!s1) split8(TY, sy);
         f4 z[2], px[2], py[2];
 #pragma unroll
         for (int mo = 0; mo < 2; ++mo) {
@@ -364,14 +369,29 @@ __device__ __forceinline__ void tile_forward(const WeightsShared<L> &S, int lane
             py[mo] = f4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
-        for (int t = 0; t < 6; ++t)
+        for (int mo = 0; mo < 2; ++mo) {
+            Split8 w, wx, wy;
 #pragma unroll
-            for (int mo = 0; mo < 2; ++mo) {
-                const u4 wt = w[mo].p[kPi[t]];
-                z[mo] = mfb(wt, sa.p[kPj[t]], z[mo]);
-                px[mo] = mfb(wt, sx.p[kPj[t]], px[mo]);
-                py[mo] = mfb(wt, sy.p[kPj[t]], py[mo]);
+            for (int k = 0; k < 3; ++k) {
+                w.p[k] = S.wp[l - 2][0][mo][k][ln];
+                if (s1) {
+                    wx.p[k] = S.wt2[0][mo][k][ln];
+                    wy.p[k] = S.wt2[1][mo][k][ln];
+                }
             }
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+                z[mo] = mfb(w.p[kPi[t]], sa.p[kPj[t]], z[mo]);
+                if (s1) {
+                    px[mo] = mfb(wx.p[kPi[t]], sx.p[kPj[t]], px[mo]);
+                    py[mo] = mfb(wy.p[kPi[t]], sx.p[kPj[t]], py[mo]);
+                } else {
+                    px[mo] = mfb(w.p[kPi[t]], sx.p[kPj[t]], px[mo]);
+                    py[mo] = mfb(w.p[kPi[t]], sy.p[kPj[t]], py[mo]);
+                }
+            }
+            if (!KEEP) __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll
         for (int mo = 0; mo < 2; ++mo) {
             Z.v[mo] = z[mo];
@@ -598,17 +618,22 @@ __device__ __forceinline__ void stream_back(float (*T1)[kTs], int lane, u2 id, c
         for (int mi = 0; mi < 2; ++mi) v[mi] = mfb(wt[mi].p[kPi[t]], sv.p[kPj[t]], v[mi]);
     out[0] = v[0];
     out[1] = v[1];
-    Split4 a[2], sb0, sb1;
+    Split4 a[2], sb[2];
     transpose_split(sv, id, a);
-    split4(b0, sb0);
-    split4(b1, sb1);
+    split4(b0, sb[0]);
+    split4(b1, sb[1]);
+    // two piece products per K = 32 product (slots 0-3 one pair of pieces, 4-7 the other),
+    // smallest first: (0,2)+(2,0), (1,1)+(0,1), (1,0)+(0,0)
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        const int i = kPi[t], j = kPj[t];
-        acc[0] = mfb16(a[0].p[i], sb0.p[j], acc[0]);
-        acc[1] = mfb16(a[0].p[i], sb1.p[j], acc[1]);
-        acc[2] = mfb16(a[1].p[i], sb0.p[j], acc[2]);
-        acc[3] = mfb16(a[1].p[i], sb1.p[j], acc[3]);
+    for (int q = 0; q < 3; ++q) {
+        const int i0 = kPi[2 * q], j0 = kPj[2 * q], i1 = kPi[2 * q + 1], j1 = kPj[2 * q + 1];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+                acc[2 * m + n] = mfb(u4{a[m].p[i0][0], a[m].p[i0][1], a[m].p[i1][0], a[m].p[i1][1]},
+                                     u4{sb[n].p[j0][0], sb[n].p[j0][1], sb[n].p[j1][0], sb[n].p[j1][1]},
+                                     acc[2 * m + n]);
     }
 }
 
@@ -748,6 +773,9 @@ __device__ __forceinline__ void tile_backward(WeightsShared<L> &S, float (*T0)[k
 template <int L, int NT, int NH>
 __device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, const float *__restrict__ P, int H,
                                              int tid) {
+    // addresses are formed here at every call: hoisted to the kernel's start, they would be
+    // spilled by the tile loops and reloaded at every instance change
+    tid = opaque(tid);
     // flat tail: W_out[NH][H], b_out[NH]
     const int npf = 3 * H + (L - 1) * (H * H + H) + NH * (H + 1);
     constexpr int kLoads = (n_pad_h(L, NH) + NT - 1) / NT;
@@ -800,6 +828,24 @@ __device__ __forceinline__ void load_weights(WeightsShared<L> &S, float *stage, 
         split8(w, sp);
 #pragma unroll
         for (int k = 0; k < 3; ++k) S.wp[l - 2][dir][mt][k][ln] = sp.p[k];
+    }
+    if (L >= 2) {
+        for (int t = tid; t < 2 * 2 * 64; t += NT) {
+            const int ln = t & 63, mt = (t >> 6) & 1, col = t >> 7;
+            const int c = ln & 15, g = ln >> 4, o = 16 * mt + c;
+            Vec w;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int q = 16 * m + 4 * g + r;
+                    w.v[m][r] = (o < H && q < H) ? stage[hoff_w(H, 2) + o * H + q] * stage[2 * q + col] : 0.f;
+                }
+            Split8 sp;
+            split8(w, sp);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) S.wt2[col][mt][k][ln] = sp.p[k];
+        }
     }
 }
 
