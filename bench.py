@@ -43,6 +43,18 @@ PAPER_CONTEXT = {
                                 "(Sec. 4.7.2 and the conclusions; quadrature and test orders not stated)"},
 }
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 (vector and matrix) peak
+# how the network kernels compute: every line carries it
+ARITHMETIC = {
+    "products": ("FP32: each operand split exactly into three bf16 pieces, the six piece products of an FP32 "
+                 "product accumulated in FP32 on the bf16 matrix cores (16x16x32 and 16x16x16 MFMAs); error "
+                 "below that of the FP32 MFMA"),
+    "elementwise": "FP32 vector ALU (tanh, derivatives, the splitting itself)",
+    "reductions": "losses summed in FP64, gradient partials in FP32, both in a fixed order",
+}
+# roofline note of the network kernels: what `achieved` counts and what bounds them
+ROOF_NOTE = ("achieved counts the algorithmic FP32 multiply-adds (the network's own width, no padding, no "
+             "recomputation) against the FP32 matrix peak; the matrix cores execute six bf16 products per FP32 "
+             "product, and what bounds the kernel is vector-ALU issue (the splitting and the elementwise work)")
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # VALU FP32 without packed instructions (they are switched off at build time):
 # 256 CUs x 64 lanes x 2 FLOP per FMA x 2.4 GHz
@@ -592,7 +604,9 @@ def bench_batched(args, V, torch, gen):
                      "achieved": round(dom_tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(dom_tf / PEAK_FP32_TFLOPS, 4),
                      "traffic": traffic_from_profile("c5", dom, tuning),
-                     "algorithmic_flop_per_launch": work[dom]["flop"], "launch_ms_mean": round(kms[dom], 4)},
+                     "algorithmic_flop_per_launch": work[dom]["flop"], "launch_ms_mean": round(kms[dom], 4),
+                     "note": ROOF_NOTE},
+        "arithmetic": ARITHMETIC,
         "whole_step": whole_step_rates(flops, sum(bytes_per_epoch(pr) for pr in probs), ms),
         "kernels": kernels,
         "kernels_note": ("mean durations over eager batched steps of the same tuned plan as the timed graph, "
@@ -806,7 +820,9 @@ def bench_predict(args, V, torch, gen):
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": traffic_from_profile("predict", "k_eval"),
                      "algorithmic_bytes_per_point": 12, "algorithmic_flop_per_point": fpp,
-                     "algorithmic_flop_per_launch": fpp * big["n_points"], "launch_ms_mean": big["kernel_ms"]},
+                     "algorithmic_flop_per_launch": fpp * big["n_points"], "launch_ms_mean": big["kernel_ms"],
+                     "note": ROOF_NOTE},
+        "arithmetic": ARITHMETIC,
         "paper_context": {"hardware": "NVIDIA RTX A6000, TensorFlow", "seconds_at_largest": PREDICT_PAPER_S[-1],
                           "note": "the paper does not state the network used for the timing"},
     }
@@ -934,7 +950,7 @@ def bench_single(args, V, torch, gen):
             achieved = work[dom]["flop"] / (k_ms * 1e-3) / 1e12
             roof = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                    "algorithmic_flop_per_launch": work[dom]["flop"]}
+                    "algorithmic_flop_per_launch": work[dom]["flop"], "note": ROOF_NOTE}
         roof["traffic"] = traffic_from_profile(args.workload, dom, res.get("tuning"))
         roof["launch_ms_mean"] = round(k_ms, 5)
     else:
@@ -966,6 +982,7 @@ def bench_single(args, V, torch, gen):
                    "boundary_points": len(prob.bnd_xy), "parallelism": "single GPU"},
         "mquadpts_per_s": round(prob.n_points * eps_s / 1e6, 2),
         "roofline": roof,
+        "arithmetic": ARITHMETIC,
         "whole_step": whole_step_rates(flops, bytes_per_epoch(prob, mf), ms),
     }
     if graph:
