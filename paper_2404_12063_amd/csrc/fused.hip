@@ -603,25 +603,30 @@ __device__ __forceinline__ void wgrad_read(float (*T1)[kTs], int lane, float (&b
 
 // one stream of a layer's reverse sweep: its propagation W_l^T vbar (into out) and its
 // weight gradient vbar x in (into acc, K = the tile's 16 points).  The transpose tile of
-// the in-side vector is read first; the split of vbar, its propagation products and its
-// in-register transpose, which need no LDS, run while those reads are in flight.
+// the in-side vector is read first and the split of vbar, which needs no LDS, runs while
+// those reads are in flight; then the in-side split, and then every product of the stream
+// (propagation, the in-register transpose, the weight gradient) as one cluster at raised
+// wave priority, so the matrix cores are fed while the other wavefront of the SIMD issues
+// its vector work beside them.
 __device__ __forceinline__ void stream_back(float (*T1)[kTs], int lane, u2 id, const Split8 (&wt)[2], const Vec &vb,
                                             f4 (&out)[2], f4 acc[4]) {
     float b0[4], b1[4];
     wgrad_read(T1, lane, b0, b1);
     Split8 sv;
     split8(vb, sv);
+    Split4 a[2], sb[2];
+    split4(b0, sb[0]);
+    split4(b1, sb[1]);
     f4 v[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int t = 0; t < 6; ++t)
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi) v[mi] = mfb(wt[mi].p[kPi[t]], sv.p[kPj[t]], v[mi]);
     out[0] = v[0];
     out[1] = v[1];
-    Split4 a[2], sb[2];
     transpose_split(sv, id, a);
-    split4(b0, sb[0]);
-    split4(b1, sb[1]);
     // two piece products per K = 32 product (slots 0-3 one pair of pieces, 4-7 the other),
     // smallest first: (0,2)+(2,0), (1,1)+(0,1), (1,0)+(0,0)
 #pragma unroll
@@ -635,6 +640,7 @@ __device__ __forceinline__ void stream_back(float (*T1)[kTs], int lane, u2 id, c
                                      u4{sb[n].p[j0][0], sb[n].p[j0][1], sb[n].p[j1][0], sb[n].p[j1][1]},
                                      acc[2 * m + n]);
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // padb (width below 32): the hidden layers' bias gradients come out of the weight-gradient
