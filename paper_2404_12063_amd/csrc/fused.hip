@@ -22,13 +22,15 @@
 //
 // Register layout of a 32-neuron vector over a 16-point tile ("chained"):
 // lane l holds point j = l % 16 and neurons 16 m + 4 g + r (g = l / 16,
-// m = 0..1, r = 0..3) in v[m][r].  This is exactly the output layout of
-// V_MFMA_F32_16X16X4F32 for two 16-row tiles, and also the B-operand layout of
-// the next product when its K index is walked as (m, r) with K-slot g, so every
-// hidden-to-hidden product (forward, and backward with W transposed) chains
-// from registers to registers.  Only the weight-gradient products, which
-// contract over points, need the vectors transposed; that goes through a small
-// per-wavefront LDS tile.
+// m = 0..1, r = 0..3) in v[m][r].  This is exactly the output layout of a
+// 16x16 MFMA for two 16-row tiles, and, read as the eight K slots 4m + r of
+// lane group g, the B-operand layout of V_MFMA_F32_16X16X32_BF16 with K = all
+// 32 inputs, so every hidden-to-hidden product (forward, and backward with W
+// transposed) chains from registers to registers.  The products are FP32
+// products evaluated as split-bf16 MFMAs (see split_pair).  Only the
+// weight-gradient products, which contract over points, need their operands
+// transposed: the adjoint in registers (identity MFMAs), the layer input
+// through a small per-wavefront LDS tile.
 #include <algorithm>
 #include <cstdint>
 #include <new>
@@ -42,8 +44,8 @@ namespace vp {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // forward: one block per CU of 8, 12 or 16 wavefronts (a tuning choice); the
-// forward alone needs few registers (~126), so up to four wavefronts per SIMD
-// hide each other's LDS and MFMA latencies
+// forward alone needs ~140 registers (the 16-wavefront build is held to 128), so
+// three or four wavefronts per SIMD hide each other's LDS and MFMA latencies
 // contraction: many small blocks, one chunk of whole elements each
 constexpr int kCThreads = 256;
 constexpr int kCWaves = kCThreads / 64;
