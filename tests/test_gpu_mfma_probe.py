@@ -1,0 +1,84 @@
+"""The measurements behind the network kernels' products (paper_2404_12063_amd/probe/mfma_probe.hip).
+
+1. Split-bf16 products (three round-to-nearest pieces per FP32 operand, six piece products
+   accumulated in FP32 on 16x16x32 bf16 MFMAs) are at least as accurate as the FP32 MFMA
+   (16x16x4) on random 16x32 by 32x16 products, against the FP64 product.
+2. bf16 MFMAs run beside another wavefront's vector instructions on the same SIMD, FP32 MFMAs
+   do not: with an MFMA wavefront and a v_fma_f32 wavefront sharing a SIMD, the fraction of
+   the shorter solo time hidden when both run is near 0 for FP32 and large for bf16.
+
+Run with -s to see the numbers.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2404_12063_amd", "probe", "libmfma_probe.so")
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        raise RuntimeError(f"{LIB} is not built (run __graft_entry__.build())")
+    L = C.CDLL(LIB)
+    fp = C.POINTER(C.c_float)
+    L.mfma_probe_products.argtypes = [C.c_int, fp, fp, fp, fp, fp]
+    L.mfma_probe_products.restype = C.c_int
+    L.mfma_probe_coexec.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    L.mfma_probe_coexec.restype = C.c_int
+    return L
+
+
+def test_probe_library_loads_and_exports_its_calls():
+    L = _lib()
+    assert hasattr(L, "mfma_probe_products") and hasattr(L, "mfma_probe_coexec")
+    d = C.c_double()
+    assert L.mfma_probe_coexec(7, 1, 1, 1, C.byref(d)) == 1  # bad kind: refused before any device call
+
+
+@pytest.mark.gpu
+def test_split_bf16_products_are_at_least_as_accurate_as_the_fp32_mfma():
+    L = _lib()
+    n = 4096
+    rng = np.random.default_rng(20261203)
+    W = rng.standard_normal((n, 16, 32))
+    V = rng.standard_normal((n, 32, 16))
+    # half the blocks with magnitudes spread over 2^-6 .. 2^6
+    W[1::2] *= np.exp2(rng.uniform(-6, 6, size=W[1::2].shape))
+    V[1::2] *= np.exp2(rng.uniform(-6, 6, size=V[1::2].shape))
+    W = W.astype(np.float32)
+    V = V.astype(np.float32)
+    outs = [np.empty((n, 16, 16), dtype=np.float32) for _ in range(3)]
+    fp = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))
+    assert L.mfma_probe_products(n, fp(W), fp(V), *(fp(o) for o in outs)) == 0
+    w64, v64 = W.astype(np.float64), V.astype(np.float64)
+    ref = w64 @ v64
+    mag = np.abs(w64) @ np.abs(v64)
+    u = 2.0 ** -24
+    err = [np.abs(o.astype(np.float64) - ref) / mag / u for o in outs]
+    names = ("FP32 MFMA", "split bf16, 6 products", "split bf16, 9 products")
+    for nm, e in zip(names, err):
+        print(f"{nm:24s} error / sum|w v| in units of 2^-24: max {e.max():.2f}, mean {e.mean():.3f}")
+    assert err[1].max() <= err[0].max() and err[1].mean() <= err[0].mean()
+    assert err[1].max() < 8.0
+
+
+@pytest.mark.gpu
+def test_bf16_mfma_runs_beside_vector_work_and_fp32_mfma_does_not():
+    L = _lib()
+    im, iv = 1024, 512
+    hidden = {}
+    for kind, name in ((0, "FP32 16x16x4"), (1, "bf16 16x16x32"), (2, "bf16 16x16x16")):
+        cyc = {}
+        for mode in (1, 2, 3):
+            d = C.c_double()
+            assert L.mfma_probe_coexec(kind, mode, im, iv, C.byref(d)) == 0
+            cyc[mode] = d.value
+        m, v, both = cyc[1], cyc[2], cyc[3]
+        hidden[kind] = (m + v - both) / min(m, v)
+        print(f"{name:14s} MFMA alone {m:9.0f} cycles ({m / (8 * im):.1f} per MFMA), VALU alone {v:9.0f} "
+              f"({v / (64 * iv):.2f} per FMA), both {both:9.0f}: hidden fraction {hidden[kind]:.2f}")
+    assert hidden[0] < 0.15
+    assert hidden[1] > 0.5 and hidden[2] > 0.5
