@@ -80,5 +80,6 @@ def test_bf16_mfma_runs_beside_vector_work_and_fp32_mfma_does_not():
         hidden[kind] = (m + v - both) / min(m, v)
         print(f"{name:14s} MFMA alone {m:9.0f} cycles ({m / (8 * im):.1f} per MFMA), VALU alone {v:9.0f} "
               f"({v / (64 * iv):.2f} per FMA), both {both:9.0f}: hidden fraction {hidden[kind]:.2f}")
+    # measured 0.01 (FP32), 0.59 (16x16x32) and 0.81 (16x16x16); the bounds leave room for box-to-box spread
     assert hidden[0] < 0.15
-    assert hidden[1] > 0.5 and hidden[2] > 0.5
+    assert hidden[1] > 0.3 and hidden[2] > 0.3
