@@ -263,6 +263,11 @@ int64_t vpinn_n_params_out(int32_t width, int32_t n_hidden, int32_t n_outputs);
  * The problem keeps a device workspace that the first call of each path
  * allocates (and a call with more boundary or sensor points grows); later calls
  * allocate nothing.  Deterministic: fixed-order reductions, no float atomics.
+ * Arithmetic: FP32 throughout, loss totals in FP64.  The fused path evaluates the
+ * network's dense products on the bf16 matrix cores as FP32 products: each operand
+ * split exactly into three bf16 pieces, the six significant piece products
+ * accumulated in FP32 (no less accurate than an FP32 matrix product); the plain
+ * path uses FP32 vector multiply-adds.
  */
 vpinn_status vpinn_loss_and_grad(vpinn_problem *p, const vpinn_loss_cfg *cfg, const float *d_params,
                                  const float *d_eps, float *d_loss, float *d_grad, float *d_grad_eps,
