@@ -38,6 +38,20 @@ def test_probe_library_loads_and_exports_its_calls():
     assert L.mfma_probe_coexec(7, 1, 1, 1, C.byref(d)) == 1  # bad kind: refused before any device call
 
 
+def _product_errors(L, W, V):
+    n = W.shape[0]
+    W = W.astype(np.float32)
+    V = V.astype(np.float32)
+    outs = [np.empty((n, 16, 16), dtype=np.float32) for _ in range(3)]
+    fp = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))
+    assert L.mfma_probe_products(n, fp(W), fp(V), *(fp(o) for o in outs)) == 0
+    w64, v64 = W.astype(np.float64), V.astype(np.float64)
+    ref = w64 @ v64
+    mag = np.abs(w64) @ np.abs(v64)
+    u = 2.0 ** -24
+    return [np.abs(o.astype(np.float64) - ref) / mag / u for o in outs]
+
+
 @pytest.mark.gpu
 def test_split_bf16_products_are_at_least_as_accurate_as_the_fp32_mfma():
     L = _lib()
@@ -48,21 +62,26 @@ def test_split_bf16_products_are_at_least_as_accurate_as_the_fp32_mfma():
     # half the blocks with magnitudes spread over 2^-6 .. 2^6
     W[1::2] *= np.exp2(rng.uniform(-6, 6, size=W[1::2].shape))
     V[1::2] *= np.exp2(rng.uniform(-6, 6, size=V[1::2].shape))
-    W = W.astype(np.float32)
-    V = V.astype(np.float32)
-    outs = [np.empty((n, 16, 16), dtype=np.float32) for _ in range(3)]
-    fp = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))
-    assert L.mfma_probe_products(n, fp(W), fp(V), *(fp(o) for o in outs)) == 0
-    w64, v64 = W.astype(np.float64), V.astype(np.float64)
-    ref = w64 @ v64
-    mag = np.abs(w64) @ np.abs(v64)
-    u = 2.0 ** -24
-    err = [np.abs(o.astype(np.float64) - ref) / mag / u for o in outs]
+    err = _product_errors(L, W, V)
     names = ("FP32 MFMA", "split bf16, 6 products", "split bf16, 9 products")
     for nm, e in zip(names, err):
         print(f"{nm:24s} error / sum|w v| in units of 2^-24: max {e.max():.2f}, mean {e.mean():.3f}")
     assert err[1].max() <= err[0].max() and err[1].mean() <= err[0].mean()
     assert err[1].max() < 8.0
+
+
+@pytest.mark.gpu
+def test_split_bf16_products_keep_their_accuracy_over_a_wide_exponent_range():
+    # whole blocks scaled by 2^-60 .. 2^60 (bf16 pieces share FP32's exponent range; the
+    # smallest piece stays a normal number while |x| > 2^-110)
+    L = _lib()
+    n = 1024
+    rng = np.random.default_rng(7)
+    W = rng.standard_normal((n, 16, 32)) * np.exp2(rng.uniform(-60, 60, size=(n, 1, 1)))
+    V = rng.standard_normal((n, 32, 16)) * np.exp2(rng.uniform(-60, 60, size=(n, 1, 1)))
+    err = _product_errors(L, W, V)
+    print(f"scaled blocks: FP32 MFMA max {err[0].max():.2f}, split bf16 max {err[1].max():.2f} units of 2^-24")
+    assert err[1].max() < 8.0 and err[1].max() <= err[0].max() + 1.0
 
 
 @pytest.mark.gpu
